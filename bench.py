@@ -1,0 +1,267 @@
+"""Benchmark of the lattice-Boltzmann stream-and-collide step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick] [--no-cpu-baseline]
+
+Workload (headline line): D3Q27 BGK Taylor-Green vortex on a 256^3 periodic grid,
+FP32 populations, tau = 0.51, u0 = 0.05, populations initialised to equilibrium.
+One benchmark step is one lattice update of the whole grid (lbm_step with
+n_steps = 1: pull streaming, moments, equilibrium, BGK relaxation, store).  The
+inputs are resident in HBM before the timed region; the timed region is K
+back-to-back steps bracketed by HIP events on the stream the kernels run on.
+
+Printed: one JSON line with MLUPS as `value`, the HBM roofline of the step kernel
+(algorithmic bytes 2*Q*sizeof(storage) per cell), the oracle's CPU throughput on a
+bounded sample, and in `detail` the other storage formats (FP64, shifted FP32,
+shifted FP16/BF16), the adjoint step, the moments kernel, a plain device copy for
+the practical bandwidth ceiling, and the velocity error of each format against the
+FP64 run after 1000 steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E nominal
+N = 256
+TAU = 0.51
+U0 = 0.05
+WORKLOAD = f"D3Q27 BGK Taylor-Green vortex {N}^3 periodic, FP32 populations, tau={TAU}, u0={U0}"
+METRIC = "MLUPS & HBM GB/s (% of peak) fwd/adjoint, FP32 vs FP16-shifted at stated err"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_launches(fn, steps: int, warmup: int) -> float:
+    """Average milliseconds per call of fn() over `steps` calls, HIP events on the
+    current stream (the one the binding launches on)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def run_forward(B, storage: str, steps: int, warmup: int, u_dev):
+    grid = B.Grid("D3Q27", storage, N, N, N)
+    bufs = [grid.empty_populations(), grid.empty_populations()]
+    B.lbm_init_equilibrium(grid, None, u_dev, bufs[0])
+    cur = [0]
+
+    def one():
+        B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, None, 1)
+        cur[0] ^= 1
+
+    ms = time_launches(one, steps, warmup)
+    bpc = B.bytes_per_cell_step(grid)
+    out = {
+        "storage": storage,
+        "ms_per_step": ms,
+        "mlups": grid.ncells / (ms * 1e-3) / 1e6,
+        "bytes_per_cell": bpc,
+        "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9,
+    }
+    out["hbm_frac"] = out["hbm_gbs"] / PEAK_HBM_GBS
+    del bufs
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_adjoint(B, storage: str, steps: int, warmup: int, u_dev):
+    grid = B.Grid("D3Q27", storage, N, N, N)
+    g = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u_dev, g)
+    lam = [torch.zeros(grid.population_shape(), dtype=grid.real_dtype, device="cuda") for _ in range(2)]
+    lam[0].normal_()
+    cur = [0]
+
+    def one():
+        B.lbm_adjoint_step(grid, g, lam[cur[0]], lam[1 - cur[0]], TAU)
+        cur[0] ^= 1
+
+    ms = time_launches(one, steps, warmup)
+    wb = torch.tensor([], dtype=grid.word_dtype).element_size()
+    rb = torch.tensor([], dtype=grid.real_dtype).element_size()
+    bpc = grid.Q * (wb + 2 * rb)
+    out = {"storage": storage, "ms_per_step": ms, "mlups": grid.ncells / (ms * 1e-3) / 1e6,
+           "bytes_per_cell": bpc, "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9}
+    out["hbm_frac"] = out["hbm_gbs"] / PEAK_HBM_GBS
+    del g, lam
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_moments(B, steps: int, warmup: int, u_dev):
+    grid = B.Grid("D3Q27", "f32", N, N, N)
+    g = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u_dev, g)
+    rho = grid.empty_real(0)
+    u = grid.empty_real(3)
+    red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
+    ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
+    ms = time_launches(lambda: B.lbm_moments(grid, g, None, rho, u, red, ws), steps, warmup)
+    bpc = 27 * 4 + 4 * 4
+    out = {"ms": ms, "bytes_per_cell": bpc, "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9,
+           "reductions": dict(zip(B.RED_NAMES, red.cpu().tolist()))}
+    del g, rho, u
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_copy(steps: int, warmup: int):
+    nbytes = 2 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    ms = time_launches(lambda: b.copy_(a), steps, warmup)
+    out = {"bytes": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def accuracy_vs_fp64(B, u_dev, n_steps: int):
+    """Velocity relative L2 error (and kinetic-energy relative error) of each storage
+    format against the FP64 run after n_steps, all on the GPU."""
+    res = {}
+    ref_u = None
+    ref_ke = None
+    for storage in ("f64", "f32", "f32s", "f16s", "bf16s"):
+        grid = B.Grid("D3Q27", storage, N, N, N)
+        a, b = grid.empty_populations(), grid.empty_populations()
+        B.lbm_init_equilibrium(grid, None, u_dev, a)
+        where = B.lbm_step(grid, a, b, TAU, None, n_steps)
+        f = b if where == 0 else a
+        u = grid.empty_real(3)
+        red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
+        ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
+        B.lbm_moments(grid, f, None, None, u, red, ws)
+        ke = float(red[4].cpu())
+        del a, b
+        u = u.double()
+        if storage == "f64":
+            ref_u, ref_ke = u, ke
+            res[storage] = {"kinetic_energy": ke}
+        else:
+            res[storage] = {"u_rel_l2": float((u - ref_u).norm() / ref_u.norm()),
+                            "ke_rel_err": abs(ke - ref_ke) / ref_ke, "kinetic_energy": ke}
+        del u
+        torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(seconds_budget: float = 20.0):
+    """The FP64 oracle (plain torch CPU ops) on a bounded sample of the same
+    workload: the D3Q27 Taylor-Green vortex at tau=0.51 on a 64^3 grid (the
+    256^3 grid's per-cell work, 1/64 of its cells), a few steps, all host threads."""
+    from oracle import lbm as olbm
+    import synthetic
+
+    threads = os.cpu_count() or 1
+    torch.set_num_threads(threads)
+    n = 64
+    st = olbm.stencil("D3Q27")
+    u = synthetic.taylor_green_3d(n, n, n, U0)
+    g = olbm.equilibrium(torch.ones(n, n, n, dtype=torch.float64), u, st)
+    g = olbm.step(g, TAU, st)  # warm-up
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds_budget and steps < 200:
+        g = olbm.step(g, TAU, st)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 torch-CPU oracle, D3Q27 TGV tau={TAU} on {n}^3 cells, {steps} steps "
+                      f"({dt:.1f} s), same per-cell work as the {N}^3 run"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--quick", action="store_true", help="headline kernel only (for profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy-steps", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the step runs on a single MI355X and this build has no "
+              "multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2106_12929_amd import binding as B
+    from synthetic import taylor_green_3d
+
+    torch.cuda.set_device(0)
+    u_dev = taylor_green_3d(N, N, N, U0).cuda()
+    log(f"[bench] lib {B.LIB_PATH} version {B.lbm_version()}")
+
+    log("[bench] forward f32")
+    head = run_forward(B, "f32", args.steps, args.warmup, u_dev)
+    detail = {"forward": {"f32": head}}
+    if not args.quick:
+        for storage in ("f16s", "bf16s", "f32s", "f64"):
+            log(f"[bench] forward {storage}")
+            detail["forward"][storage] = run_forward(B, storage, args.steps, args.warmup, u_dev)
+        detail["fp16s_speedup_vs_f32"] = detail["forward"]["f16s"]["mlups"] / head["mlups"]
+        log("[bench] adjoint")
+        detail["adjoint"] = {s: run_adjoint(B, s, max(20, args.steps // 4), 5, u_dev) for s in ("f32", "f16s")}
+        log("[bench] moments")
+        detail["moments_f32"] = run_moments(B, 20, 3, u_dev)
+        log("[bench] copy")
+        detail["device_copy"] = run_copy(20, 3)
+        head["frac_of_copy"] = head["hbm_gbs"] / detail["device_copy"]["gbs"]
+        log(f"[bench] accuracy after {args.accuracy_steps} steps")
+        detail["accuracy_vs_f64_gpu"] = {"steps": args.accuracy_steps,
+                                         "errors": accuracy_vs_fp64(B, u_dev, args.accuracy_steps)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": METRIC,
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "lattice": "D3Q27", "grid": [N, N, N], "storage": "f32",
+                   "tau": TAU, "u0": U0, "cells": N ** 3},
+        "roofline": {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": head["hbm_frac"], "traffic": None,
+                     "kernel": "lbm::step_kernel<D3Q27, F32, unforced>",
+                     "algorithmic_bytes_per_launch": head["bytes_per_cell"] * N ** 3},
+        "cpu_baseline": cpu,
+        "detail": detail,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) lattice-Boltzmann stream-and-collide library.
+ *
+ * The library implements one time step of the lattice Boltzmann method with the BGK
+ * collision operator (Bedrunka et al., "Lettuce: PyTorch-based Lattice Boltzmann
+ * Framework", arXiv:2106.12929, Sec. 2.1):
+ *   Eq. 1  f_i(x + c_i, t + 1) = f_i(x, t) + Omega_i(f(x, t))        (stream + collide)
+ *   Eq. 2  Omega_i = -(f_i - f_i^eq) / tau                            (BGK)
+ *   Eq. 3  f_i^eq = w_i rho (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)   (c_s^2 = 1/3)
+ *   Eq. 4  rho = sum_i f_i,   rho u = sum_i c_i f_i
+ * on fully periodic D2Q9 and D3Q27 grids, with an optional per-cell body force (Guo
+ * scheme, textbook), plus the reverse-mode derivative of the step (the automatic
+ * differentiation of Sec. 3.2, written by hand).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice velocity order: c_i in {-1,0,1}^D with c_x fastest, then c_y, then c_z:
+ *   i = 3(c_y+1) + (c_x+1)  (D2Q9),   i = 9(c_z+1) + 3(c_y+1) + (c_x+1)  (D3Q27).
+ *   The rest velocity is i = Q/2 and the opposite of i is Q-1-i.  lbm_lattice_info()
+ *   publishes c and w.
+ *
+ * Grid: nx, ny, nz >= 1 cells (nz = 1 for D2Q9), N = nx*ny*nz <= 2^31 - 1.
+ *   Cell (x, y, z) has linear index n = (z*ny + y)*nx + x (x fastest).
+ *
+ * Population buffers ("f", "g", SoA): element (i, n) at word offset i*N + n, Q*N words.
+ *   The word type and meaning depend on the storage kind:
+ *     LBM_F64    double   f_i
+ *     LBM_F32    float    f_i
+ *     LBM_F32S   float    f_i - w_i         ("shifted": the deviation from rest)
+ *     LBM_F16S   binary16 f_i - w_i  (raw 16-bit words, IEEE half)
+ *     LBM_BF16S  bfloat16 f_i - w_i  (raw 16-bit words)
+ *   Arithmetic runs in FP64 for LBM_F64 and in FP32 otherwise; every value written is
+ *   rounded once to the storage format, to nearest even, subnormals kept.
+ *
+ * Real arrays (force, rho, u, adjoint populations, force gradients) use the "real"
+ *   type of the storage kind: double for LBM_F64, float for every other kind.  Vector
+ *   fields are SoA [D][N] (component a = x, y, z at offset a*N + n).
+ *
+ * State: a population buffer holds the post-collision populations g(t) = C(f(t)) of
+ *   Eq. 1's state f(t); one step maps g(t) to g(t+1) = C(S g(t)) where S is the
+ *   periodic pull streaming (S g)_i(x) = g_i(x - c_i).  This is Eq. 1 regrouped so
+ *   that one kernel reads each population once and writes it once.
+ *
+ * Memory and streams: every pointer argument is a device pointer owned by the caller
+ *   (nothing is retained after a call returns), aligned to 16 bytes.  The library
+ *   allocates no device memory.  `stream` is a hipStream_t (NULL = the null stream);
+ *   all work is enqueued asynchronously on it and no call synchronises.
+ *
+ * Errors: every entry point validates its arguments on the host before any HIP call
+ *   and returns a negative lbm_status without touching device memory when they are
+ *   invalid.  A failed kernel launch returns LBM_EHIP; faults inside kernels surface at
+ *   the caller's next synchronisation.  lbm_strerror()/lbm_last_error() describe codes.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lbm_lattice { LBM_D2Q9 = 0, LBM_D3Q27 = 1 };
+
+enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_F16S = 3, LBM_BF16S = 4 };
+
+enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1, /* bad scalar argument: tau <= 1/2 or not finite, n_steps < 1,
+                      dims < 1, nz != 1 for D2Q9, unknown lattice or storage,
+                      workspace too small */
+  LBM_ENULL = -2,  /* a required pointer is NULL */
+  LBM_EALIGN = -3, /* a pointer is not 16-byte aligned */
+  LBM_EALIAS = -4, /* an output buffer overlaps an input buffer it must not overlap */
+  LBM_EUNSUP = -5, /* unsupported combination of arguments */
+  LBM_ERANGE = -6, /* grid too large: N > 2^31 - 1 or a dimension > 2^31 - 1 */
+  LBM_EHIP = -7    /* a HIP runtime call failed; lbm_last_error() has the text */
+};
+
+/* Grid descriptor.  lattice: enum lbm_lattice; storage: enum lbm_storage. */
+typedef struct lbm_grid {
+  int32_t lattice;
+  int32_t storage;
+  int64_t nx, ny, nz;
+} lbm_grid;
+
+/* Number of reduction results written by lbm_moments (see there). */
+#define LBM_NRED 8
+
+/* Static description of a status code (never NULL). */
+const char* lbm_strerror(int status);
+
+/* Text of the most recent failure on the calling thread (validation detail or HIP
+ * error string); "" if none. */
+const char* lbm_last_error(void);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int lbm_version(void);
+
+/* Velocity set of a lattice (Sec. 2.1: c_i, w_i; the values are the textbook D2Q9 and
+ * D3Q27 tables, the order is the library's).  Host pointers; any may be NULL.
+ * D, Q: dimension and number of velocities.  c: Q*D ints, row i = (c_x, c_y[, c_z]).
+ * w: Q doubles.  Returns LBM_OK or LBM_EINVAL for an unknown lattice. */
+int lbm_lattice_info(int lattice, int* D, int* Q, int* c, double* w);
+
+/* Writes the equilibrium populations f^eq(rho, u) (Eq. 3) of every cell into f_out,
+ * which is then g(0): an equilibrium is a fixed point of the BGK collision, so it is
+ * both the pre- and the post-collision state at t = 0.
+ * rho: N doubles, or NULL for rho = 1 everywhere.  u: D*N doubles (SoA), required.
+ * f_out: Q*N storage words.  f^eq is evaluated in FP64 and rounded once. */
+int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* u,
+                         void* f_out, void* stream);
+
+/* Advances the populations by n_steps time steps g <- C(S g) (Eqs. 1-4), ping-ponging
+ * between f_in and f_out: step k reads one buffer and writes the other, starting with
+ * f_in -> f_out.  For n_steps > 1 both buffers are overwritten.
+ * tau: BGK relaxation time (Eq. 2), tau > 1/2; the kinematic viscosity is
+ *   nu = (tau - 1/2)/3 (Sec. 3.1).
+ * force: D*N reals (SoA), or NULL for no force.  With a force the collision uses the
+ *   Guo scheme: u = (sum c_i f_i + F/2)/rho in f^eq, plus the source
+ *   (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F.
+ * f_in and f_out must not overlap; force must not overlap either.
+ * Returns 0 if the result is in f_out (odd n_steps), 1 if it is in f_in (even
+ * n_steps), or a negative lbm_status. */
+int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force,
+             int n_steps, void* stream);
+
+/* Streaming only: f_out_i(x) = f_in_i(x - c_i), periodic (Eq. 1's shift), copying the
+ * raw storage words (a permutation: bit-exact for every storage kind).  Buffers must not
+ * overlap. */
+int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* stream);
+
+/* Bytes of device workspace lbm_moments needs when it computes reductions. */
+int lbm_moments_workspace_size(const lbm_grid* grid, size_t* bytes);
+
+/* Macroscopic fields of the state g (Eq. 4) and FP64 reductions over the grid.
+ * rho_out: N reals or NULL.  u_out: D*N reals or NULL.
+ *   rho = sum_i g_i; u = (sum_i c_i g_i - F/2)/rho, i.e. the density and the (Guo)
+ *   velocity of the pre-collision state f(t) whose collision produced g(t).
+ * force: D*N reals or NULL (must match what the steps used).
+ * red: NULL, or a device array of LBM_NRED doubles receiving, in FP64:
+ *   [0] sum rho   [1..3] sum rho u_a (z = 0 in 2D)   [4] kinetic energy 1/2 sum |u|^2
+ *   [5] number of cells whose rho or u is not finite   [6] max |u|   [7] min rho
+ *   The reduction order is fixed, so results are bitwise reproducible.
+ * workspace: device scratch of lbm_moments_workspace_size() bytes, required iff red is
+ *   not NULL; its contents are clobbered. */
+int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rho_out,
+                void* u_out, double* red, void* workspace, size_t workspace_bytes,
+                void* stream);
+
+/* Reverse-mode derivative of one lbm_step (hand-written adjoint; the paper obtains the
+ * same quantity by automatic differentiation, Sec. 3.2).  With g' = C(S g_t; F):
+ *   lam_out = (dg'/dg_t)^T lam_next          (overwritten, Q*N reals)
+ *   dforce += (dg'/dF)^T lam_next            (accumulated, D*N reals; may be NULL)
+ * g_t: the state the forward step started from (storage words).  lam_next: Q*N reals,
+ * dL/dg(t+1).  For shifted storage the derivative is taken with respect to f_i (equal to
+ * the one with respect to f_i - w_i); rounding to storage is not differentiated.
+ * tau and force as in lbm_step; dforce requires force.  lam_out must not overlap g_t,
+ * lam_next, force or dforce. */
+int lbm_adjoint_step(const lbm_grid* grid, const void* g_t, const void* lam_next, void* lam_out,
+                     double tau, const void* force, void* dforce, void* stream);
+
+/* Reverse-mode derivative of lbm_moments' fields: with (rho, u) = moments(g; F),
+ *   lam_out = (drho/dg)^T dL_drho + (du/dg)^T dL_du       (overwritten, Q*N reals)
+ *   dforce += (du/dF)^T dL_du = -dL_du / (2 rho)           (accumulated, may be NULL)
+ * dL_drho: N reals or NULL (zero); dL_du: D*N reals or NULL (zero). */
+int lbm_moments_adjoint(const lbm_grid* grid, const void* g, const void* force,
+                        const void* dL_drho, const void* dL_du, void* lam_out, void* dforce,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -208,14 +208,10 @@ def nu_from_tau(tau: float) -> float:
 # Pointwise evaluation for sampled parity at large grids
 # --------------------------------------------------------------------------------------
 
-def step_at_cells(g: torch.Tensor, tau: float, st: Stencil, cells: torch.Tensor,
-                  force: torch.Tensor | None = None) -> torch.Tensor:
-    """`step` evaluated only at the listed cells.
-
-    cells: [M, D] int64 coordinates (x, y[, z]).  g may be any float tensor (it is
-    read in FP64).  Returns [Q, M] float64: the populations C(S g) at those cells.
-    Streaming is the same rule as `stream`: h_i(x) = g_i(x - c_i), periodic.
-    """
+def gather_at_cells(g: torch.Tensor, st: Stencil, cells: torch.Tensor) -> torch.Tensor:
+    """The streamed populations h_i(x) = g_i(x - c_i) (periodic, as in `stream`) at
+    the listed cells only.  cells: [M, D] int64 coordinates (x, y[, z]).  Returns
+    [Q, M] float64 (g may have any dtype; values are converted exactly)."""
     spatial = g.shape[1:]
     sizes = [spatial[-1 - a] for a in range(st.D)]   # (nx, ny[, nz])
     M = cells.shape[0]
@@ -224,8 +220,19 @@ def step_at_cells(g: torch.Tensor, tau: float, st: Stencil, cells: torch.Tensor,
         src = [(cells[:, a] - int(st.c[i, a])) % sizes[a] for a in range(st.D)]
         idx = tuple(reversed(src))                      # (z, y, x) order for indexing
         h[i] = g[i][idx].to(F64)
-    F = None
-    if force is not None:
-        idx = tuple(cells[:, a] for a in reversed(range(st.D)))
-        F = torch.stack([force[a][idx].to(F64) for a in range(st.D)])
+    return h
+
+
+def force_at_cells(force: torch.Tensor, st: Stencil, cells: torch.Tensor) -> torch.Tensor:
+    """force[a](x) at the listed cells: [D, M] float64."""
+    idx = tuple(cells[:, a] for a in reversed(range(st.D)))
+    return torch.stack([force[a][idx].to(F64) for a in range(st.D)])
+
+
+def step_at_cells(g: torch.Tensor, tau: float, st: Stencil, cells: torch.Tensor,
+                  force: torch.Tensor | None = None) -> torch.Tensor:
+    """`step` evaluated only at the listed cells: returns [Q, M] float64, the
+    populations C(S g) there."""
+    h = gather_at_cells(g, st, cells)
+    F = None if force is None else force_at_cells(force, st, cells)
     return bgk_collide(h, tau, st, F)

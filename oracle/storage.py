@@ -59,6 +59,18 @@ def step_emulated(s: torch.Tensor, tau: float, st: lbm.Stencil, kind: str,
     return quantize(lbm.step(dequantize(s, st, kind), tau, st, force), st, kind)
 
 
+def step_at_cells_emulated(s: torch.Tensor, tau: float, st: lbm.Stencil, kind: str, cells: torch.Tensor,
+                           force: torch.Tensor | None = None) -> torch.Tensor:
+    """`step_emulated` evaluated at the listed cells only ([M, D] coordinates):
+    gathers the streamed stored words, dequantises, takes the FP64 collision and
+    returns the FP64 populations [Q, M] (before the final rounding to storage)."""
+    h = lbm.gather_at_cells(s, st, cells)
+    if is_shifted(kind):
+        h = h + st.w.reshape(st.Q, 1)
+    F = None if force is None else lbm.force_at_cells(force, st, cells)
+    return lbm.bgk_collide(h, tau, st, F)
+
+
 def stream_stored(s: torch.Tensor, st: lbm.Stencil) -> torch.Tensor:
     """Streaming applied to the stored words themselves: a permutation, so no
     arithmetic and no rounding is involved, whatever the storage dtype."""

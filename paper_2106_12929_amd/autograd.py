@@ -1,0 +1,107 @@
+"""torch.autograd wrappers of the hand-written adjoint kernels.
+
+The paper differentiates its solver by PyTorch autograd through every tensor
+operation (Sec. 3.2).  Here the derivative of a whole rollout comes from the
+library's adjoint kernels instead:
+
+  LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every) -> g_T
+      forward: n_steps lbm_step calls, keeping a copy of the state every K steps;
+      backward: for each K-step segment, last to first, replay the segment from
+      its checkpoint (keeping its K states), then run K lbm_adjoint_step calls
+      backwards; the force gradient accumulates in place in the kernels.
+      Memory: ceil(n/K) checkpoints + K segment states + 2 adjoint buffers.
+      Forward and adjoint kernels are deterministic (no atomics), so the gradient
+      is bitwise independent of K.
+
+  LBMMoments.apply(g, force, grid) -> (rho, u)
+      forward: lbm_moments; backward: lbm_moments_adjoint.
+
+The derivative is that of the exact-arithmetic step at the stored state: rounding
+to a reduced-precision storage format is not differentiated.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+def _real(grid: B.Grid, t: torch.Tensor | None) -> torch.Tensor | None:
+    if t is None:
+        return None
+    return t.detach().to(grid.real_dtype).contiguous()
+
+
+class LBMRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, g0, force, grid: B.Grid, tau: float, n_steps: int, checkpoint_every: int):
+        if n_steps < 1 or checkpoint_every < 1:
+            raise ValueError("n_steps and checkpoint_every must be >= 1")
+        F = _real(grid, force)
+        a = g0.detach().contiguous().clone()
+        b = torch.empty_like(a)
+        ckpts = []
+        for t in range(n_steps):
+            if t % checkpoint_every == 0:
+                ckpts.append(a.clone())
+            B.lbm_step(grid, a, b, tau, F, 1)
+            a, b = b, a
+        ctx.grid, ctx.tau, ctx.n, ctx.K = grid, tau, n_steps, checkpoint_every
+        ctx.ckpts = ckpts
+        ctx.force = F
+        ctx.force_needs_grad = force is not None and ctx.needs_input_grad[1]
+        return a
+
+    @staticmethod
+    def backward(ctx, lam_T):
+        grid, tau, n, K, F = ctx.grid, ctx.tau, ctx.n, ctx.K, ctx.force
+        lam = lam_T.detach().to(grid.real_dtype).contiguous().clone()
+        lam_out = torch.empty_like(lam)
+        dF = torch.zeros_like(F) if ctx.force_needs_grad else None
+        n_seg = len(ctx.ckpts)
+        states = [torch.empty_like(ctx.ckpts[0]) for _ in range(min(K, n))]
+        for seg in reversed(range(n_seg)):
+            t0 = seg * K
+            t1 = min(t0 + K, n)
+            states[0].copy_(ctx.ckpts[seg])
+            for t in range(t0 + 1, t1):
+                B.lbm_step(grid, states[t - 1 - t0], states[t - t0], tau, F, 1)
+            for t in reversed(range(t0, t1)):
+                B.lbm_adjoint_step(grid, states[t - t0], lam, lam_out, tau, F, dF)
+                lam, lam_out = lam_out, lam
+            ctx.ckpts[seg] = None  # release the checkpoint once its segment is done
+        return lam, dF, None, None, None, None
+
+
+class LBMMoments(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, g, force, grid: B.Grid):
+        F = _real(grid, force)
+        gc = g.detach().contiguous()
+        rho = grid.empty_real(0, g.device)
+        u = grid.empty_real(grid.D, g.device)
+        B.lbm_moments(grid, gc, F, rho, u)
+        ctx.save_for_backward(gc)
+        ctx.grid, ctx.force = grid, F
+        ctx.force_needs_grad = force is not None and ctx.needs_input_grad[1]
+        return rho, u
+
+    @staticmethod
+    def backward(ctx, drho, du):
+        (g,) = ctx.saved_tensors
+        grid, F = ctx.grid, ctx.force
+        lam = torch.empty(grid.population_shape(), dtype=grid.real_dtype, device=g.device)
+        dF = torch.zeros_like(F) if ctx.force_needs_grad else None
+        B.lbm_moments_adjoint(grid, g, F, _real(grid, drho), _real(grid, du), lam, dF)
+        return lam, dF, None
+
+
+def rollout(grid: B.Grid, g0: torch.Tensor, force: torch.Tensor | None, tau: float, n_steps: int,
+            checkpoint_every: int = 10) -> torch.Tensor:
+    """Differentiable n-step rollout from g0 under a constant force field."""
+    return LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every)
+
+
+def moments(grid: B.Grid, g: torch.Tensor, force: torch.Tensor | None = None):
+    """Differentiable (rho, u) of a state."""
+    return LBMMoments.apply(g, force, grid)

@@ -1,0 +1,275 @@
+"""Thin ctypes binding of liblbm.so (the C ABI in include/lbm.h).
+
+Each function has the name of the C entry point it calls and only marshals
+arguments: it checks that every tensor lives on the GPU, is contiguous and has the
+dtype and element count the call reads or writes (so the kernels never index past
+a buffer), then passes raw device pointers and the current HIP stream.  All
+arithmetic happens in the HIP kernels.  There is no fallback: if the library is
+missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LATTICES = {"D2Q9": 0, "D3Q27": 1}
+STORAGES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3, "bf16s": 4}
+STORAGE_DTYPE = {"f64": torch.float64, "f32": torch.float32, "f32s": torch.float32,
+                 "f16s": torch.float16, "bf16s": torch.bfloat16}
+NRED = 8
+RED_NAMES = ("mass", "momentum_x", "momentum_y", "momentum_z", "kinetic_energy",
+             "nonfinite_cells", "max_speed", "min_density")
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.lbm_strerror(status).decode()
+        detail = _lib.lbm_last_error().decode()
+        super().__init__(f"{where}: {msg} ({status}){': ' + detail if detail else ''}")
+
+
+class _CGrid(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2106_12929_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    gp = ctypes.POINTER(_CGrid)
+    sigs = {
+        "lbm_strerror": (ctypes.c_char_p, [i32]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+        "lbm_version": (i32, []),
+        "lbm_lattice_info": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(dbl)]),
+        "lbm_init_equilibrium": (i32, [gp, vp, vp, vp, vp]),
+        "lbm_step": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
+        "lbm_stream_only": (i32, [gp, vp, vp, vp]),
+        "lbm_moments_workspace_size": (i32, [gp, ctypes.POINTER(sz)]),
+        "lbm_moments": (i32, [gp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lbm_adjoint_step": (i32, [gp, vp, vp, vp, dbl, vp, vp, vp]),
+        "lbm_moments_adjoint": (i32, [gp, vp, vp, vp, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Grid descriptor: lattice "D2Q9"/"D3Q27", storage kind, and nx, ny, nz cells."""
+
+    lattice: str
+    storage: str
+    nx: int
+    ny: int
+    nz: int = 1
+
+    @property
+    def D(self) -> int:
+        return 2 if self.lattice == "D2Q9" else 3
+
+    @property
+    def Q(self) -> int:
+        return 9 if self.lattice == "D2Q9" else 27
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def spatial(self) -> tuple:
+        return (self.ny, self.nx) if self.D == 2 else (self.nz, self.ny, self.nx)
+
+    @property
+    def word_dtype(self) -> torch.dtype:
+        return STORAGE_DTYPE[self.storage]
+
+    @property
+    def real_dtype(self) -> torch.dtype:
+        return torch.float64 if self.storage == "f64" else torch.float32
+
+    def population_shape(self) -> tuple:
+        return (self.Q,) + self.spatial
+
+    def vector_shape(self) -> tuple:
+        return (self.D,) + self.spatial
+
+    def c_struct(self) -> _CGrid:
+        if self.lattice not in LATTICES:
+            raise ValueError(f"unknown lattice {self.lattice!r}")
+        if self.storage not in STORAGES:
+            raise ValueError(f"unknown storage {self.storage!r}")
+        return _CGrid(LATTICES[self.lattice], STORAGES[self.storage], self.nx, self.ny, self.nz)
+
+    def empty_populations(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.population_shape(), dtype=self.word_dtype, device=device)
+
+    def empty_real(self, components: int, device="cuda") -> torch.Tensor:
+        shape = self.spatial if components == 0 else (components,) + self.spatial
+        return torch.empty(shape, dtype=self.real_dtype, device=device)
+
+
+def _dev_ptr(t: torch.Tensor | None, name: str, dtype: torch.dtype, numel: int, required: bool = True):
+    if t is None:
+        if required:
+            raise ValueError(f"{name} is required")
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype} (got {t.dtype})")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements (got {t.numel()})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise LbmError(rc, where)
+    return rc
+
+
+def lbm_version() -> int:
+    return _lib.lbm_version()
+
+
+def lbm_lattice_info(lattice: str):
+    """(D, Q, c [Q][D] as a list of tuples, w [Q]) of a lattice."""
+    D, Q = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.lbm_lattice_info(LATTICES[lattice], ctypes.byref(D), ctypes.byref(Q), None, None),
+           "lbm_lattice_info")
+    c = (ctypes.c_int * (Q.value * D.value))()
+    w = (ctypes.c_double * Q.value)()
+    _check(_lib.lbm_lattice_info(LATTICES[lattice], None, None, c, w), "lbm_lattice_info")
+    rows = [tuple(c[i * D.value:(i + 1) * D.value]) for i in range(Q.value)]
+    return D.value, Q.value, rows, list(w)
+
+
+def lbm_init_equilibrium(grid: Grid, rho: torch.Tensor | None, u: torch.Tensor, f_out: torch.Tensor,
+                         stream=None) -> None:
+    """f_out <- f^eq(rho, u); rho (or None for 1) and u are float64 GPU tensors."""
+    N = grid.ncells
+    g = grid.c_struct()
+    args = (_dev_ptr(rho, "rho", torch.float64, N, required=False),
+            _dev_ptr(u, "u", torch.float64, grid.D * N),
+            _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N))
+    _check(_lib.lbm_init_equilibrium(ctypes.byref(g), *args, _stream(stream)), "lbm_init_equilibrium")
+
+
+def lbm_step(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: float,
+             force: torch.Tensor | None = None, n_steps: int = 1, stream=None) -> int:
+    """n_steps ping-pong steps; returns 0 if the result is in f_out, 1 if in f_in."""
+    N = grid.ncells
+    g = grid.c_struct()
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    F = _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False)
+    return _check(_lib.lbm_step(ctypes.byref(g), a, b, float(tau), F, int(n_steps), _stream(stream)), "lbm_step")
+
+
+def lbm_stream_only(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, stream=None) -> None:
+    N = grid.ncells
+    g = grid.c_struct()
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    _check(_lib.lbm_stream_only(ctypes.byref(g), a, b, _stream(stream)), "lbm_stream_only")
+
+
+def lbm_moments_workspace_size(grid: Grid) -> int:
+    g = grid.c_struct()
+    n = ctypes.c_size_t()
+    _check(_lib.lbm_moments_workspace_size(ctypes.byref(g), ctypes.byref(n)), "lbm_moments_workspace_size")
+    return n.value
+
+
+def lbm_moments(grid: Grid, f: torch.Tensor, force: torch.Tensor | None = None,
+                rho_out: torch.Tensor | None = None, u_out: torch.Tensor | None = None,
+                red: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None) -> None:
+    """Density/velocity fields and (if red is given) the 8 FP64 reductions.
+
+    red: float64 GPU tensor of 8 elements.  workspace: uint8 GPU tensor of at least
+    lbm_moments_workspace_size(grid) bytes (required with red).
+    """
+    N = grid.ncells
+    g = grid.c_struct()
+    ws_ptr, ws_bytes = None, 0
+    if red is not None:
+        need = lbm_moments_workspace_size(grid)
+        if workspace is None or workspace.dtype != torch.uint8 or workspace.numel() < need:
+            raise ValueError(f"workspace must be a uint8 GPU tensor of >= {need} bytes")
+        ws_ptr = _dev_ptr(workspace, "workspace", torch.uint8, workspace.numel())
+        ws_bytes = workspace.numel()
+    args = (_dev_ptr(f, "f", grid.word_dtype, grid.Q * N),
+            _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False),
+            _dev_ptr(rho_out, "rho_out", grid.real_dtype, N, required=False),
+            _dev_ptr(u_out, "u_out", grid.real_dtype, grid.D * N, required=False),
+            _dev_ptr(red, "red", torch.float64, NRED, required=False))
+    _check(_lib.lbm_moments(ctypes.byref(g), *args, ws_ptr, ctypes.c_size_t(ws_bytes), _stream(stream)),
+           "lbm_moments")
+
+
+def lbm_adjoint_step(grid: Grid, g_t: torch.Tensor, lam_next: torch.Tensor, lam_out: torch.Tensor, tau: float,
+                     force: torch.Tensor | None = None, dforce: torch.Tensor | None = None, stream=None) -> None:
+    """lam_out <- (dg'/dg_t)^T lam_next; dforce += (dg'/dF)^T lam_next."""
+    N = grid.ncells
+    g = grid.c_struct()
+    args = (_dev_ptr(g_t, "g_t", grid.word_dtype, grid.Q * N),
+            _dev_ptr(lam_next, "lam_next", grid.real_dtype, grid.Q * N),
+            _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.Q * N))
+    F = _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False)
+    dF = _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False)
+    _check(_lib.lbm_adjoint_step(ctypes.byref(g), *args, float(tau), F, dF, _stream(stream)), "lbm_adjoint_step")
+
+
+def lbm_moments_adjoint(grid: Grid, f: torch.Tensor, force: torch.Tensor | None,
+                        dL_drho: torch.Tensor | None, dL_du: torch.Tensor | None, lam_out: torch.Tensor,
+                        dforce: torch.Tensor | None = None, stream=None) -> None:
+    """lam_out <- d(rho, u)/dg ^T (dL_drho, dL_du); dforce += -dL_du/(2 rho)."""
+    N = grid.ncells
+    g = grid.c_struct()
+    args = (_dev_ptr(f, "f", grid.word_dtype, grid.Q * N),
+            _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False),
+            _dev_ptr(dL_drho, "dL_drho", grid.real_dtype, N, required=False),
+            _dev_ptr(dL_du, "dL_du", grid.real_dtype, grid.D * N, required=False),
+            _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.Q * N),
+            _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False))
+    _check(_lib.lbm_moments_adjoint(ctypes.byref(g), *args, _stream(stream)), "lbm_moments_adjoint")
+
+
+def bytes_per_cell_step(grid: Grid) -> int:
+    """Algorithmic HBM bytes of one step per cell: read and write Q stored words."""
+    return 2 * grid.Q * torch.tensor([], dtype=grid.word_dtype).element_size()
+
+
+def mlups(grid: Grid, steps: int, seconds: float) -> float:
+    return grid.ncells * steps / seconds / 1e6
+
+
+__all__ = [n for n in dir() if n.startswith("lbm_")] + ["Grid", "LbmError", "NRED", "RED_NAMES", "LIB_PATH",
+                                                        "bytes_per_cell_step", "mlups"]

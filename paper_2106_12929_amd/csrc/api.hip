@@ -1,0 +1,294 @@
+// C ABI of the library (declared in include/lbm.h): host-side argument validation and
+// dispatch to the kernels.  Every check runs before the first HIP call, so invalid
+// arguments never reach the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "kernels.h"
+#include "lattice.h"
+#include "lbm.h"
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(LBM_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+struct Geometry {
+  int D = 0, Q = 0;
+  size_t word = 0;  // bytes per stored population
+  size_t real = 0;  // bytes per real (force, rho, u, adjoint)
+  lbm::GridArgs args{};
+};
+
+uint32_t pick_block_x(int64_t nx) {
+  // The row segment per block that leaves the fewest idle threads (ties: the longer).
+  uint32_t best = 256;
+  int64_t best_waste = -1;
+  for (uint32_t bx : {256u, 128u, 64u}) {
+    const int64_t waste = ((nx + bx - 1) / bx) * bx - nx;
+    if (best_waste < 0 || waste < best_waste) {
+      best = bx;
+      best_waste = waste;
+    }
+  }
+  return best;
+}
+
+int check_grid(const lbm_grid* g, Geometry* geo) {
+  if (!g) return fail(LBM_ENULL, "grid is NULL");
+  if (g->lattice != LBM_D2Q9 && g->lattice != LBM_D3Q27) return fail(LBM_EINVAL, "unknown lattice %d", g->lattice);
+  if (g->storage < LBM_F64 || g->storage > LBM_BF16S) return fail(LBM_EINVAL, "unknown storage %d", g->storage);
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+    return fail(LBM_EINVAL, "grid dimensions must be >= 1 (got %lld x %lld x %lld)", (long long)g->nx,
+                (long long)g->ny, (long long)g->nz);
+  if (g->lattice == LBM_D2Q9 && g->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1 (got %lld)", (long long)g->nz);
+  const int64_t lim = 2147483647;
+  if (g->nx > lim || g->ny > lim || g->nz > lim) return fail(LBM_ERANGE, "a grid dimension exceeds 2^31-1");
+  if (g->nx * g->ny > lim || (g->nx * g->ny) * g->nz > lim)
+    return fail(LBM_ERANGE, "grid has more than 2^31-1 cells");
+  geo->D = g->lattice == LBM_D2Q9 ? 2 : 3;
+  geo->Q = g->lattice == LBM_D2Q9 ? 9 : 27;
+  geo->word = g->storage == LBM_F64 ? 8 : (g->storage == LBM_F32 || g->storage == LBM_F32S) ? 4 : 2;
+  geo->real = g->storage == LBM_F64 ? 8 : 4;
+  geo->args.nx = (uint32_t)g->nx;
+  geo->args.ny = (uint32_t)g->ny;
+  geo->args.nz = (uint32_t)g->nz;
+  geo->args.ncells = (uint64_t)(g->nx * g->ny * g->nz);
+  geo->args.block_x = pick_block_x(g->nx);
+  return LBM_OK;
+}
+
+int check_ptr(const void* p, const char* name, bool required) {
+  if (!p) return required ? fail(LBM_ENULL, "%s is NULL", name) : LBM_OK;
+  if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(LBM_EALIGN, "%s is not 16-byte aligned", name);
+  return LBM_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+int check_tau(double tau) {
+  if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_EINVAL, "tau must be finite and > 1/2 (got %g)", tau);
+  return LBM_OK;
+}
+
+int reduce_blocks(const Geometry& geo) {
+  const uint64_t b = (geo.args.ncells + 255) / 256;
+  return (int)(b < (uint64_t)lbm::kMaxReduceBlocks ? b : (uint64_t)lbm::kMaxReduceBlocks);
+}
+
+#define LBM_TRY(expr)          \
+  do {                         \
+    const int rc_ = (expr);    \
+    if (rc_ != LBM_OK) return rc_; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_strerror(int status) {
+  switch (status) {
+    case LBM_OK: return "success";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENULL: return "required pointer is NULL";
+    case LBM_EALIGN: return "pointer is not 16-byte aligned";
+    case LBM_EALIAS: return "output buffer overlaps an input buffer";
+    case LBM_EUNSUP: return "unsupported combination of arguments";
+    case LBM_ERANGE: return "grid too large";
+    case LBM_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* lbm_last_error(void) { return g_last_error; }
+
+int lbm_version(void) { return 10000; }
+
+int lbm_lattice_info(int lattice, int* D, int* Q, int* c, double* w) {
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q27) return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+  const int d = lattice == LBM_D2Q9 ? 2 : 3;
+  const int q = lattice == LBM_D2Q9 ? 9 : 27;
+  if (D) *D = d;
+  if (Q) *Q = q;
+  for (int i = 0; i < q; ++i) {
+    if (lattice == LBM_D2Q9) {
+      using LT = lbm::Lattice<lbm::kD2Q9>;
+      if (c) {
+        c[i * 2 + 0] = LT::cx(i);
+        c[i * 2 + 1] = LT::cy(i);
+      }
+      if (w) w[i] = LT::w(i);
+    } else {
+      using LT = lbm::Lattice<lbm::kD3Q27>;
+      if (c) {
+        c[i * 3 + 0] = LT::cx(i);
+        c[i * 3 + 1] = LT::cy(i);
+        c[i * 3 + 2] = LT::cz(i);
+      }
+      if (w) w[i] = LT::w(i);
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* u, void* f_out, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_ptr(rho, "rho", false));
+  LBM_TRY(check_ptr(u, "u", true));
+  LBM_TRY(check_ptr(f_out, "f_out", true));
+  const size_t N = geo.args.ncells;
+  const size_t fbytes = geo.Q * N * geo.word;
+  if (overlap(f_out, fbytes, rho, N * 8) || overlap(f_out, fbytes, u, geo.D * N * 8))
+    return fail(LBM_EALIAS, "f_out overlaps rho or u");
+  const hipError_t e = lbm::launch_init(grid->lattice, grid->storage, rho, u, f_out, geo.args, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init_equilibrium launch");
+}
+
+int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force, int n_steps,
+             void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_tau(tau));
+  if (n_steps < 1) return fail(LBM_EINVAL, "n_steps must be >= 1 (got %d)", n_steps);
+  LBM_TRY(check_ptr(f_in, "f_in", true));
+  LBM_TRY(check_ptr(f_out, "f_out", true));
+  LBM_TRY(check_ptr(force, "force", false));
+  const size_t N = geo.args.ncells;
+  const size_t fbytes = geo.Q * N * geo.word;
+  if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
+  if (overlap(force, geo.D * N * geo.real, f_in, fbytes) || overlap(force, geo.D * N * geo.real, f_out, fbytes))
+    return fail(LBM_EALIAS, "force overlaps a population buffer");
+  const double omega = 1.0 / tau;
+  void* bufs[2] = {f_in, f_out};
+  for (int k = 0; k < n_steps; ++k) {
+    const hipError_t e = lbm::launch_step(grid->lattice, grid->storage, bufs[k & 1], bufs[(k + 1) & 1], force,
+                                          geo.args, omega, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step launch");
+  }
+  return (n_steps & 1) ? 0 : 1;
+}
+
+int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_ptr(f_in, "f_in", true));
+  LBM_TRY(check_ptr(f_out, "f_out", true));
+  const size_t fbytes = geo.Q * geo.args.ncells * geo.word;
+  if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
+  const hipError_t e = lbm::launch_stream(grid->lattice, (int)geo.word, f_in, f_out, geo.args, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_stream_only launch");
+}
+
+int lbm_moments_workspace_size(const lbm_grid* grid, size_t* bytes) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  if (!bytes) return fail(LBM_ENULL, "bytes is NULL");
+  *bytes = (size_t)reduce_blocks(geo) * lbm::kNred * sizeof(double);
+  return LBM_OK;
+}
+
+int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rho_out, void* u_out, double* red,
+                void* workspace, size_t workspace_bytes, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_ptr(g, "g", true));
+  LBM_TRY(check_ptr(force, "force", false));
+  LBM_TRY(check_ptr(rho_out, "rho_out", false));
+  LBM_TRY(check_ptr(u_out, "u_out", false));
+  LBM_TRY(check_ptr(red, "red", false));
+  const int nblocks = reduce_blocks(geo);
+  const size_t need = (size_t)nblocks * lbm::kNred * sizeof(double);
+  if (red) {
+    LBM_TRY(check_ptr(workspace, "workspace", true));
+    if (workspace_bytes < need)
+      return fail(LBM_EINVAL, "workspace has %zu bytes, lbm_moments needs %zu", workspace_bytes, need);
+  }
+  const size_t N = geo.args.ncells;
+  const size_t fbytes = geo.Q * N * geo.word;
+  const size_t rbytes = N * geo.real, ubytes = geo.D * N * geo.real;
+  const void* ins[2] = {g, force};
+  const size_t insz[2] = {fbytes, geo.D * N * geo.real};
+  void* outs[4] = {rho_out, u_out, red, red ? workspace : nullptr};
+  const size_t outsz[4] = {rbytes, ubytes, lbm::kNred * sizeof(double), need};
+  for (int a = 0; a < 4; ++a) {
+    for (int b = 0; b < 2; ++b)
+      if (overlap(outs[a], outsz[a], ins[b], insz[b])) return fail(LBM_EALIAS, "an output of lbm_moments overlaps an input");
+    for (int b = a + 1; b < 4; ++b)
+      if (overlap(outs[a], outsz[a], outs[b], outsz[b])) return fail(LBM_EALIAS, "two outputs of lbm_moments overlap");
+  }
+  const hipError_t e = lbm::launch_moments(grid->lattice, grid->storage, g, force, rho_out, u_out,
+                                           red ? (double*)workspace : nullptr, nblocks, red, geo.args,
+                                           (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments launch");
+}
+
+int lbm_adjoint_step(const lbm_grid* grid, const void* g_t, const void* lam_next, void* lam_out, double tau,
+                     const void* force, void* dforce, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_tau(tau));
+  LBM_TRY(check_ptr(g_t, "g_t", true));
+  LBM_TRY(check_ptr(lam_next, "lam_next", true));
+  LBM_TRY(check_ptr(lam_out, "lam_out", true));
+  LBM_TRY(check_ptr(force, "force", false));
+  LBM_TRY(check_ptr(dforce, "dforce", false));
+  if (dforce && !force) return fail(LBM_EUNSUP, "dforce needs the force the step used");
+  const size_t N = geo.args.ncells;
+  const size_t gbytes = geo.Q * N * geo.word, lbytes = geo.Q * N * geo.real, fbytes = geo.D * N * geo.real;
+  if (overlap(lam_out, lbytes, g_t, gbytes) || overlap(lam_out, lbytes, lam_next, lbytes) ||
+      overlap(lam_out, lbytes, force, fbytes) || overlap(lam_out, lbytes, dforce, fbytes))
+    return fail(LBM_EALIAS, "lam_out overlaps another argument");
+  if (overlap(dforce, fbytes, g_t, gbytes) || overlap(dforce, fbytes, lam_next, lbytes) ||
+      overlap(dforce, fbytes, force, fbytes))
+    return fail(LBM_EALIAS, "dforce overlaps another argument");
+  const hipError_t e = lbm::launch_adjoint(grid->lattice, grid->storage, g_t, lam_next, lam_out, force, dforce,
+                                           geo.args, 1.0 / tau, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step launch");
+}
+
+int lbm_moments_adjoint(const lbm_grid* grid, const void* g, const void* force, const void* dL_drho,
+                        const void* dL_du, void* lam_out, void* dforce, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_ptr(g, "g", true));
+  LBM_TRY(check_ptr(force, "force", false));
+  LBM_TRY(check_ptr(dL_drho, "dL_drho", false));
+  LBM_TRY(check_ptr(dL_du, "dL_du", false));
+  LBM_TRY(check_ptr(lam_out, "lam_out", true));
+  LBM_TRY(check_ptr(dforce, "dforce", false));
+  if (dforce && !force) return fail(LBM_EUNSUP, "dforce needs the force the moments used");
+  const size_t N = geo.args.ncells;
+  const size_t gbytes = geo.Q * N * geo.word, lbytes = geo.Q * N * geo.real, vbytes = geo.D * N * geo.real;
+  if (overlap(lam_out, lbytes, g, gbytes) || overlap(lam_out, lbytes, force, vbytes) ||
+      overlap(lam_out, lbytes, dL_drho, N * geo.real) || overlap(lam_out, lbytes, dL_du, vbytes) ||
+      overlap(lam_out, lbytes, dforce, vbytes))
+    return fail(LBM_EALIAS, "lam_out overlaps another argument");
+  if (overlap(dforce, vbytes, g, gbytes) || overlap(dforce, vbytes, force, vbytes) ||
+      overlap(dforce, vbytes, dL_drho, N * geo.real) || overlap(dforce, vbytes, dL_du, vbytes))
+    return fail(LBM_EALIAS, "dforce overlaps another argument");
+  const hipError_t e = lbm::launch_moments_adjoint(grid->lattice, grid->storage, g, force, dL_drho, dL_du, lam_out,
+                                                   dforce, geo.args, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments_adjoint launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,31 @@
+// Internal interface between the C ABI layer (api.hip) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kNred = 8;              // reduction results of lbm_moments
+constexpr int kMaxReduceBlocks = 1024;  // fixed reduction grid (bitwise-reproducible sums)
+
+// Grid geometry passed by value to every cell-parallel kernel.
+struct GridArgs {
+  uint32_t nx, ny, nz;
+  uint32_t block_x;  // cells of one row handled by a 256-thread block: 64, 128 or 256
+  uint64_t ncells;   // nx * ny * nz (< 2^31)
+};
+
+hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, const GridArgs& g,
+                       double omega, hipStream_t s);
+hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s);
+hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
+                       hipStream_t s);
+hipError_t launch_moments(int lattice, int storage, const void* f, const void* force, void* rho, void* u,
+                          double* partials, int nblocks, double* red, const GridArgs& g, hipStream_t s);
+hipError_t launch_adjoint(int lattice, int storage, const void* gt, const void* lam_next, void* lam_out,
+                          const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s);
+hipError_t launch_moments_adjoint(int lattice, int storage, const void* f, const void* force, const void* drho,
+                                  const void* du, void* lam_out, void* dforce, const GridArgs& g, hipStream_t s);
+
+}  // namespace lbm

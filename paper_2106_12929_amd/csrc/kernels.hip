@@ -1,0 +1,607 @@
+// HIP kernels (gfx950) of the lattice-Boltzmann stream-and-collide step.
+//
+// Paper: Bedrunka et al., arXiv:2106.12929, Sec. 2.1, Eqs. 1-4 (stream, BGK collide,
+// second-order equilibrium, moments); Sec. 3.2 (differentiating the solver).
+//
+// Data layout: SoA populations, word (i, n) at i*N + n with n = (z*ny + y)*nx + x.
+// Launch shape: one thread per cell, 256 threads per block covering `bx` consecutive
+// cells of a row (bx = 64, 128 or 256) and 256/bx consecutive rows; rows are (y, z)
+// pairs.  A block therefore reads and writes whole row segments of every direction:
+// each population row is a contiguous run shifted by c_x in x, so loads are coalesced
+// and stores aligned.  The step is HBM-bound (about 1.5 flop per byte moved for
+// D3Q27 FP32), so there is no MFMA and no LDS staging: L1/L2 absorb the +-1-element
+// misalignment of the shifted loads.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "lattice.h"
+
+namespace lbm {
+
+// Index helper: offsets of the 3 source columns / rows / planes of a cell.
+// src[k] is the coordinate of x - c for c = k - 1, wrapped periodically.
+struct Neighbours {
+  uint32_t x[3];
+  uint32_t row[3];    // (y - c_y) * nx
+  uint32_t plane[3];  // (z - c_z) * nx * ny
+  uint32_t self;      // linear index of the cell
+};
+
+__device__ __forceinline__ uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
+
+__device__ __forceinline__ Neighbours neighbours(uint32_t x, uint32_t y, uint32_t z, const GridArgs& g) {
+  Neighbours nb;
+  // c = -1 reads x + 1, c = 0 reads x, c = +1 reads x - 1
+  nb.x[0] = wrap_inc(x, g.nx);
+  nb.x[1] = x;
+  nb.x[2] = wrap_dec(x, g.nx);
+  nb.row[0] = wrap_inc(y, g.ny) * g.nx;
+  nb.row[1] = y * g.nx;
+  nb.row[2] = wrap_dec(y, g.ny) * g.nx;
+  const uint32_t plane = g.nx * g.ny;
+  nb.plane[0] = wrap_inc(z, g.nz) * plane;
+  nb.plane[1] = z * plane;
+  nb.plane[2] = wrap_dec(z, g.nz) * plane;
+  nb.self = nb.plane[1] + nb.row[1] + x;
+  return nb;
+}
+
+template <typename LT>
+__device__ __forceinline__ uint32_t src_index(const Neighbours& nb, int i) {
+  return nb.plane[LT::cz(i) + 1] + nb.row[LT::cy(i) + 1] + nb.x[LT::cx(i) + 1];
+}
+
+// Thread -> cell mapping shared by all cell-parallel kernels.  Returns false for the
+// threads of the ragged tail.
+__device__ __forceinline__ bool cell_of_thread(const GridArgs& g, uint32_t& x, uint32_t& y, uint32_t& z) {
+  const uint32_t bx = g.block_x;
+  const uint32_t rows_per_block = 256u / bx;
+  const uint32_t tx = threadIdx.x % bx;
+  const uint32_t ty = threadIdx.x / bx;
+  const uint32_t blocks_x = (g.nx + bx - 1) / bx;
+  const uint32_t bxi = blockIdx.x % blocks_x;
+  const uint32_t byi = blockIdx.x / blocks_x;
+  x = bxi * bx + tx;
+  const uint32_t r = byi * rows_per_block + ty;
+  if (x >= g.nx || r >= g.ny * g.nz) return false;
+  y = r % g.ny;
+  z = r / g.ny;
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_stream(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// ---------------------------------------------------------------------------------
+// Fused pull stream + BGK collide (+ Guo force).  Eq. 1-4.
+// ---------------------------------------------------------------------------------
+template <int L, int S, bool FORCED>
+__global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::word* __restrict__ fin,
+                                                   typename Storage<S>::word* __restrict__ fout,
+                                                   const typename Storage<S>::real* __restrict__ force,
+                                                   GridArgs g, typename Storage<S>::real omega) {
+  using LT = Lattice<L>;
+  using ST = Storage<S>;
+  using real = typename ST::real;
+  using CO = Coef<L, real>;
+  constexpr int Q = LT::Q;
+  uint32_t x, y, z;
+  if (!cell_of_thread(g, x, y, z)) return;
+  const Neighbours nb = neighbours(x, y, z, g);
+  const size_t N = g.ncells;
+
+  // Gather (pull streaming, Eq. 1): h_i(x) = g_i(x - c_i), as deviations from w_i.
+  real d[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(fin[i * N + src_index<LT>(nb, i)], CO::W(i));
+
+  // Moments (Eq. 4) in deviation form: rho = 1 + sum d, rho u = sum c d (+ F/2).
+  real drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += d[i];
+    if (LT::cx(i) > 0) jx += d[i];
+    if (LT::cx(i) < 0) jx -= d[i];
+    if (LT::cy(i) > 0) jy += d[i];
+    if (LT::cy(i) < 0) jy -= d[i];
+    if (LT::cz(i) > 0) jz += d[i];
+    if (LT::cz(i) < 0) jz -= d[i];
+  }
+  real Fx = 0, Fy = 0, Fz = 0;
+  if constexpr (FORCED) {
+    Fx = force[nb.self];
+    Fy = force[N + nb.self];
+    if constexpr (LT::D == 3) Fz = force[2 * N + nb.self];
+    jx += real(0.5) * Fx;
+    jy += real(0.5) * Fy;
+    jz += real(0.5) * Fz;
+  }
+  const real rho = real(1) + drho;
+  const real inv_rho = real(1) / rho;
+  const real ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+  const real usq = real(1.5) * (ux * ux + uy * uy + uz * uz);
+  const real uF = ux * Fx + uy * Fy + uz * Fz;
+  const real guo = real(1) - real(0.5) * omega;
+
+  // Equilibrium (Eq. 3) as a deviation, BGK relaxation (Eq. 2), Guo source, store.
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    constexpr real zero = 0;
+    real cu = zero;
+    if (LT::cx(i) > 0) cu += ux;
+    if (LT::cx(i) < 0) cu -= ux;
+    if (LT::cy(i) > 0) cu += uy;
+    if (LT::cy(i) < 0) cu -= uy;
+    if (LT::cz(i) > 0) cu += uz;
+    if (LT::cz(i) < 0) cu -= uz;
+    const real deq = CO::W(i) * drho + rho * (CO::A(i) * cu + CO::B(i) * cu * cu - CO::W(i) * usq);
+    real dn = d[i] + omega * (deq - d[i]);
+    if constexpr (FORCED) {
+      real cF = zero;
+      if (LT::cx(i) > 0) cF += Fx;
+      if (LT::cx(i) < 0) cF -= Fx;
+      if (LT::cy(i) > 0) cF += Fy;
+      if (LT::cy(i) < 0) cF -= Fy;
+      if (LT::cz(i) > 0) cF += Fz;
+      if (LT::cz(i) < 0) cF -= Fz;
+      dn += guo * (CO::A(i) * cF - real(3) * CO::W(i) * uF + real(2) * CO::B(i) * cu * cF);
+    }
+    store_stream(&fout[i * N + nb.self], ST::from_dev(dn, CO::W(i)));
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Streaming only: raw word permutation (bit-exact for every storage kind).
+// ---------------------------------------------------------------------------------
+template <int L, typename W>
+__global__ __launch_bounds__(256) void stream_kernel(const W* __restrict__ fin, W* __restrict__ fout, GridArgs g) {
+  using LT = Lattice<L>;
+  uint32_t x, y, z;
+  if (!cell_of_thread(g, x, y, z)) return;
+  const Neighbours nb = neighbours(x, y, z, g);
+  const size_t N = g.ncells;
+#pragma unroll
+  for (int i = 0; i < LT::Q; ++i) fout[i * N + nb.self] = fin[i * N + src_index<LT>(nb, i)];
+}
+
+// ---------------------------------------------------------------------------------
+// Equilibrium initialisation (Eq. 3) in FP64, one rounding to storage.
+// ---------------------------------------------------------------------------------
+template <int L, int S>
+__global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ rho_in, const double* __restrict__ u,
+                                                   typename Storage<S>::word* __restrict__ fout, GridArgs g) {
+  using LT = Lattice<L>;
+  using ST = Storage<S>;
+  uint32_t x, y, z;
+  if (!cell_of_thread(g, x, y, z)) return;
+  const size_t N = g.ncells;
+  const uint32_t n = (z * g.ny + y) * g.nx + x;
+  const double rho = rho_in ? rho_in[n] : 1.0;
+  const double ux = u[n], uy = u[N + n], uz = LT::D == 3 ? u[2 * N + n] : 0.0;
+  const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int i = 0; i < LT::Q; ++i) {
+    const double cu = LT::cx(i) * ux + LT::cy(i) * uy + LT::cz(i) * uz;
+    const double dev = LT::w(i) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - usq));
+    // unshifted storage keeps f = W_i + dev with the base the kernels subtract again
+    fout[i * N + n] = ST::from_f64_dev(dev, static_cast<double>(Coef<L, typename ST::real>::W(i)));
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Moments (Eq. 4) and FP64 reductions.  Grid-stride over cells with a fixed grid, so
+// that every reduction is summed in the same order on every call.
+// ---------------------------------------------------------------------------------
+template <typename real>
+struct CellMoments {
+  real drho, rho, u[3];
+};
+
+template <int L, int S>
+__device__ __forceinline__ CellMoments<typename Storage<S>::real> cell_moments(
+    const typename Storage<S>::word* __restrict__ f, const typename Storage<S>::real* __restrict__ force, size_t N,
+    size_t n) {
+  using LT = Lattice<L>;
+  using ST = Storage<S>;
+  using real = typename ST::real;
+  real drho = 0, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < LT::Q; ++i) {
+    const real d = ST::to_dev(f[i * N + n], Coef<L, real>::W(i));
+    drho += d;
+    j[0] += real(LT::cx(i)) * d;
+    j[1] += real(LT::cy(i)) * d;
+    j[2] += real(LT::cz(i)) * d;
+  }
+  if (force) {
+#pragma unroll
+    for (int a = 0; a < LT::D; ++a) j[a] -= real(0.5) * force[a * N + n];
+  }
+  CellMoments<real> m;
+  m.drho = drho;
+  m.rho = real(1) + drho;
+  const real inv = real(1) / m.rho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) m.u[a] = j[a] * inv;
+  return m;
+}
+
+template <int L, int S>
+__global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>::word* __restrict__ f,
+                                                      const typename Storage<S>::real* __restrict__ force,
+                                                      typename Storage<S>::real* __restrict__ rho_out,
+                                                      typename Storage<S>::real* __restrict__ u_out,
+                                                      double* __restrict__ partials, size_t N) {
+  using LT = Lattice<L>;
+  // acc: [0] sum drho, [1..3] sum rho u, [4] 1/2 sum |u|^2, [5] non-finite, [6] max|u|, [7] min rho
+  double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 1.0e300};
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+    const auto m = cell_moments<L, S>(f, force, N, n);
+    if (rho_out) rho_out[n] = m.rho;
+    if (u_out) {
+#pragma unroll
+      for (int a = 0; a < LT::D; ++a) u_out[a * N + n] = m.u[a];
+    }
+    if (partials) {
+      const double rho = m.rho;
+      const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
+      const double usq = ux * ux + uy * uy + uz * uz;
+      const bool finite = isfinite(rho) && isfinite(usq);
+      if (finite) {
+        acc[0] += (double)m.drho;
+        acc[1] += rho * ux;
+        acc[2] += rho * uy;
+        acc[3] += rho * uz;
+        acc[4] += 0.5 * usq;
+        acc[6] = fmax(acc[6], sqrt(usq));
+        acc[7] = fmin(acc[7], rho);
+      } else {
+        acc[5] += 1.0;
+      }
+    }
+  }
+  if (!partials) return;
+  __shared__ double sh[kNred][256];
+#pragma unroll
+  for (int k = 0; k < kNred; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < kNred; ++k) {
+        const double a = sh[k][threadIdx.x], b = sh[k][threadIdx.x + s];
+        sh[k][threadIdx.x] = k == 6 ? fmax(a, b) : k == 7 ? fmin(a, b) : a + b;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kNred) partials[blockIdx.x * kNred + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// One block folds the per-block partials in a fixed order; adds N to turn sum(drho)
+// into the mass.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials, int nblocks,
+                                                              double* __restrict__ red, double ncells) {
+  __shared__ double sh[kNred][256];
+  double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 1.0e300};
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+    for (int k = 0; k < kNred; ++k) {
+      const double v = partials[b * kNred + k];
+      acc[k] = k == 6 ? fmax(acc[k], v) : k == 7 ? fmin(acc[k], v) : acc[k] + v;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kNred; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < kNred; ++k) {
+        const double a = sh[k][threadIdx.x], b = sh[k][threadIdx.x + s];
+        sh[k][threadIdx.x] = k == 6 ? fmax(a, b) : k == 7 ? fmin(a, b) : a + b;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    red[0] = ncells + sh[0][0];
+    for (int k = 1; k < kNred; ++k) red[k] = sh[k][0];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Adjoint of one step.  The forward collision, with h = S g_t gathered, rho = 1 + drho,
+// u = (sum c h + F/2)/rho and deq_i = W_i drho + rho (A_i c_i.u + B_i (c_i.u)^2 -
+// W_i 3/2 |u|^2), is g'_i = (1 - omega) h_i + omega deq_i + G_i with the Guo source
+// G_i = (1 - omega/2)(A_i c_i.F - 3 W_i u.F + 2 B_i (c_i.u)(c_i.F)).  With lam' =
+// lam_next(x) and the weighted moments
+//   mW = sum W_i lam'_i,  mA_a = sum A_i c_ia lam'_i,  mB_ab = sum B_i c_ia c_ib lam'_i
+// its transpose is
+//   P   = omega (mW + u.mA + u.mB.u - 3/2 |u|^2 mW)                    (via drho)
+//   V_a = omega rho (mA_a + 2 (mB u)_a - 3 u_a mW)
+//         + (1 - omega/2)(2 (mB F)_a - 3 F_a mW)                        (via u)
+//   mu_j = (1 - omega) lam'_j + P + sum_a V_a (c_ja - u_a) / rho
+//   dF_a = (1 - omega/2)(mA_a - 3 u_a mW + 2 (mB u)_a) + V_a / (2 rho)
+// and lam_t,j(x - c_j) = mu_j(x): the transpose of the pull gather is a scatter to the
+// same addresses, each written exactly once (no atomics).
+// ---------------------------------------------------------------------------------
+template <int L, int S, bool FORCED>
+__global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>::word* __restrict__ gt,
+                                                      const typename Storage<S>::real* __restrict__ lam_next,
+                                                      typename Storage<S>::real* __restrict__ lam_out,
+                                                      const typename Storage<S>::real* __restrict__ force,
+                                                      typename Storage<S>::real* __restrict__ dforce, GridArgs g,
+                                                      typename Storage<S>::real omega) {
+  using LT = Lattice<L>;
+  using ST = Storage<S>;
+  using real = typename ST::real;
+  using CO = Coef<L, real>;
+  constexpr int Q = LT::Q;
+  uint32_t x, y, z;
+  if (!cell_of_thread(g, x, y, z)) return;
+  const Neighbours nb = neighbours(x, y, z, g);
+  const size_t N = g.ncells;
+
+  real drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const real d = ST::to_dev(gt[i * N + src_index<LT>(nb, i)], CO::W(i));
+    drho += d;
+    jx += real(LT::cx(i)) * d;
+    jy += real(LT::cy(i)) * d;
+    jz += real(LT::cz(i)) * d;
+  }
+  real Fx = 0, Fy = 0, Fz = 0;
+  if constexpr (FORCED) {
+    Fx = force[nb.self];
+    Fy = force[N + nb.self];
+    if constexpr (LT::D == 3) Fz = force[2 * N + nb.self];
+    jx += real(0.5) * Fx;
+    jy += real(0.5) * Fy;
+    jz += real(0.5) * Fz;
+  }
+  const real rho = real(1) + drho;
+  const real inv_rho = real(1) / rho;
+  const real ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+
+  real lam[Q];
+  real mW = 0, mAx = 0, mAy = 0, mAz = 0, bxx = 0, byy = 0, bzz = 0, bxy = 0, bxz = 0, byz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    lam[i] = lam_next[i * N + nb.self];
+    const real l = lam[i];
+    const real cx = LT::cx(i), cy = LT::cy(i), cz = LT::cz(i);
+    const real al = CO::A(i) * l, bl = CO::B(i) * l;
+    mW += CO::W(i) * l;
+    mAx += cx * al;
+    mAy += cy * al;
+    mAz += cz * al;
+    bxx += cx * cx * bl;
+    byy += cy * cy * bl;
+    bzz += cz * cz * bl;
+    bxy += cx * cy * bl;
+    bxz += cx * cz * bl;
+    byz += cy * cz * bl;
+  }
+  const real mBux = bxx * ux + bxy * uy + bxz * uz;
+  const real mBuy = bxy * ux + byy * uy + byz * uz;
+  const real mBuz = bxz * ux + byz * uy + bzz * uz;
+  const real usq15 = real(1.5) * (ux * ux + uy * uy + uz * uz);
+  const real P = omega * (mW + ux * mAx + uy * mAy + uz * mAz + ux * mBux + uy * mBuy + uz * mBuz - usq15 * mW);
+  const real orho = omega * rho;
+  real Vx = orho * (mAx + real(2) * mBux - real(3) * ux * mW);
+  real Vy = orho * (mAy + real(2) * mBuy - real(3) * uy * mW);
+  real Vz = orho * (mAz + real(2) * mBuz - real(3) * uz * mW);
+  const real guo = real(1) - real(0.5) * omega;
+  if constexpr (FORCED) {
+    const real mBFx = bxx * Fx + bxy * Fy + bxz * Fz;
+    const real mBFy = bxy * Fx + byy * Fy + byz * Fz;
+    const real mBFz = bxz * Fx + byz * Fy + bzz * Fz;
+    Vx += guo * (real(2) * mBFx - real(3) * Fx * mW);
+    Vy += guo * (real(2) * mBFy - real(3) * Fy * mW);
+    Vz += guo * (real(2) * mBFz - real(3) * Fz * mW);
+  }
+  const real vx = Vx * inv_rho, vy = Vy * inv_rho, vz = Vz * inv_rho;
+  const real base = P - (vx * ux + vy * uy + vz * uz);
+  const real keep = real(1) - omega;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    real mu = keep * lam[j] + base;
+    if (LT::cx(j) > 0) mu += vx;
+    if (LT::cx(j) < 0) mu -= vx;
+    if (LT::cy(j) > 0) mu += vy;
+    if (LT::cy(j) < 0) mu -= vy;
+    if (LT::cz(j) > 0) mu += vz;
+    if (LT::cz(j) < 0) mu -= vz;
+    lam_out[j * N + src_index<LT>(nb, j)] = mu;
+  }
+  if constexpr (FORCED) {
+    if (dforce) {
+      const real half_inv = real(0.5) * inv_rho;
+      dforce[nb.self] += guo * (mAx - real(3) * ux * mW + real(2) * mBux) + Vx * half_inv;
+      dforce[N + nb.self] += guo * (mAy - real(3) * uy * mW + real(2) * mBuy) + Vy * half_inv;
+      if constexpr (LT::D == 3)
+        dforce[2 * N + nb.self] += guo * (mAz - real(3) * uz * mW + real(2) * mBuz) + Vz * half_inv;
+    }
+  }
+}
+
+// Adjoint of the moments map (rho, u) = (sum g, (sum c g - F/2)/rho).
+template <int L, int S>
+__global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Storage<S>::word* __restrict__ f,
+                                                              const typename Storage<S>::real* __restrict__ force,
+                                                              const typename Storage<S>::real* __restrict__ drho_in,
+                                                              const typename Storage<S>::real* __restrict__ du_in,
+                                                              typename Storage<S>::real* __restrict__ lam_out,
+                                                              typename Storage<S>::real* __restrict__ dforce,
+                                                              size_t N) {
+  using LT = Lattice<L>;
+  using real = typename Storage<S>::real;
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const auto m = cell_moments<L, S>(f, force, N, n);
+  const real inv = real(1) / m.rho;
+  const real dr = drho_in ? drho_in[n] : real(0);
+  real du[3] = {0, 0, 0};
+  if (du_in) {
+#pragma unroll
+    for (int a = 0; a < LT::D; ++a) du[a] = du_in[a * N + n];
+  }
+  const real bx = du[0] * inv, by = du[1] * inv, bz = du[2] * inv;
+  const real base = dr - (bx * m.u[0] + by * m.u[1] + bz * m.u[2]);
+#pragma unroll
+  for (int j = 0; j < LT::Q; ++j) {
+    real v = base;
+    if (LT::cx(j) > 0) v += bx;
+    if (LT::cx(j) < 0) v -= bx;
+    if (LT::cy(j) > 0) v += by;
+    if (LT::cy(j) < 0) v -= by;
+    if (LT::cz(j) > 0) v += bz;
+    if (LT::cz(j) < 0) v -= bz;
+    lam_out[j * N + n] = v;
+  }
+  if (dforce) {
+#pragma unroll
+    for (int a = 0; a < LT::D; ++a) dforce[a * N + n] -= real(0.5) * du[a] * inv;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Host-side launchers (template dispatch over lattice x storage x forced).
+// ---------------------------------------------------------------------------------
+static dim3 cell_grid(const GridArgs& g) {
+  const uint32_t blocks_x = (g.nx + g.block_x - 1) / g.block_x;
+  const uint64_t rows = (uint64_t)g.ny * g.nz;
+  const uint32_t rows_per_block = 256u / g.block_x;
+  return dim3((unsigned)(blocks_x * ((rows + rows_per_block - 1) / rows_per_block)));
+}
+
+template <int L, int S>
+static hipError_t launch_step_ls(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
+                                 hipStream_t s) {
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using R = typename ST::real;
+  if (force)
+    step_kernel<L, S, true><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, (R)omega);
+  else
+    step_kernel<L, S, false><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, nullptr, g, (R)omega);
+  return hipGetLastError();
+}
+
+template <int L, int S>
+static hipError_t launch_adjoint_ls(const void* gt, const void* lam_next, void* lam_out, const void* force,
+                                    void* dforce, const GridArgs& g, double omega, hipStream_t s) {
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using R = typename ST::real;
+  if (force)
+    adjoint_kernel<L, S, true><<<cell_grid(g), 256, 0, s>>>((const W*)gt, (const R*)lam_next, (R*)lam_out,
+                                                             (const R*)force, (R*)dforce, g, (R)omega);
+  else
+    adjoint_kernel<L, S, false><<<cell_grid(g), 256, 0, s>>>((const W*)gt, (const R*)lam_next, (R*)lam_out,
+                                                              nullptr, nullptr, g, (R)omega);
+  return hipGetLastError();
+}
+
+template <int L, int S>
+static hipError_t launch_init_ls(const double* rho, const double* u, void* fout, const GridArgs& g, hipStream_t s) {
+  using W = typename Storage<S>::word;
+  init_kernel<L, S><<<cell_grid(g), 256, 0, s>>>(rho, u, (W*)fout, g);
+  return hipGetLastError();
+}
+
+template <int L, int S>
+static hipError_t launch_moments_ls(const void* f, const void* force, void* rho, void* u, double* partials,
+                                    int nblocks, double* red, const GridArgs& g, hipStream_t s) {
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using R = typename ST::real;
+  moments_kernel<L, S><<<nblocks, 256, 0, s>>>((const W*)f, (const R*)force, (R*)rho, (R*)u, partials, g.ncells);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !red) return e;
+  reduce_partials_kernel<<<1, 256, 0, s>>>(partials, nblocks, red, (double)g.ncells);
+  return hipGetLastError();
+}
+
+template <int L, int S>
+static hipError_t launch_moments_adjoint_ls(const void* f, const void* force, const void* drho, const void* du,
+                                            void* lam_out, void* dforce, const GridArgs& g, hipStream_t s) {
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using R = typename ST::real;
+  const unsigned blocks = (unsigned)((g.ncells + 255) / 256);
+  moments_adjoint_kernel<L, S><<<blocks, 256, 0, s>>>((const W*)f, (const R*)force, (const R*)drho, (const R*)du,
+                                                       (R*)lam_out, (R*)dforce, g.ncells);
+  return hipGetLastError();
+}
+
+#define LBM_DISPATCH(LAUNCH, lattice, storage, ...)                                        \
+  do {                                                                                     \
+    if ((lattice) == kD2Q9) {                                                              \
+      switch (storage) {                                                                   \
+        case kF64: return LAUNCH<kD2Q9, kF64>(__VA_ARGS__);                                \
+        case kF32: return LAUNCH<kD2Q9, kF32>(__VA_ARGS__);                                \
+        case kF32S: return LAUNCH<kD2Q9, kF32S>(__VA_ARGS__);                              \
+        case kF16S: return LAUNCH<kD2Q9, kF16S>(__VA_ARGS__);                              \
+        case kBF16S: return LAUNCH<kD2Q9, kBF16S>(__VA_ARGS__);                            \
+      }                                                                                    \
+    } else {                                                                               \
+      switch (storage) {                                                                   \
+        case kF64: return LAUNCH<kD3Q27, kF64>(__VA_ARGS__);                               \
+        case kF32: return LAUNCH<kD3Q27, kF32>(__VA_ARGS__);                               \
+        case kF32S: return LAUNCH<kD3Q27, kF32S>(__VA_ARGS__);                             \
+        case kF16S: return LAUNCH<kD3Q27, kF16S>(__VA_ARGS__);                             \
+        case kBF16S: return LAUNCH<kD3Q27, kBF16S>(__VA_ARGS__);                           \
+      }                                                                                    \
+    }                                                                                      \
+    return hipErrorInvalidValue;                                                           \
+  } while (0)
+
+hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, const GridArgs& g,
+                       double omega, hipStream_t s) {
+  LBM_DISPATCH(launch_step_ls, lattice, storage, fin, fout, force, g, omega, s);
+}
+
+hipError_t launch_adjoint(int lattice, int storage, const void* gt, const void* lam_next, void* lam_out,
+                          const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s) {
+  LBM_DISPATCH(launch_adjoint_ls, lattice, storage, gt, lam_next, lam_out, force, dforce, g, omega, s);
+}
+
+hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
+                       hipStream_t s) {
+  LBM_DISPATCH(launch_init_ls, lattice, storage, rho, u, fout, g, s);
+}
+
+hipError_t launch_moments(int lattice, int storage, const void* f, const void* force, void* rho, void* u,
+                          double* partials, int nblocks, double* red, const GridArgs& g, hipStream_t s) {
+  LBM_DISPATCH(launch_moments_ls, lattice, storage, f, force, rho, u, partials, nblocks, red, g, s);
+}
+
+hipError_t launch_moments_adjoint(int lattice, int storage, const void* f, const void* force, const void* drho,
+                                  const void* du, void* lam_out, void* dforce, const GridArgs& g, hipStream_t s) {
+  LBM_DISPATCH(launch_moments_adjoint_ls, lattice, storage, f, force, drho, du, lam_out, dforce, g, s);
+}
+
+template <int L>
+static hipError_t launch_stream_l(int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s) {
+  switch (word_bytes) {
+    case 2: stream_kernel<L, uint16_t><<<cell_grid(g), 256, 0, s>>>((const uint16_t*)fin, (uint16_t*)fout, g); break;
+    case 4: stream_kernel<L, uint32_t><<<cell_grid(g), 256, 0, s>>>((const uint32_t*)fin, (uint32_t*)fout, g); break;
+    case 8: stream_kernel<L, uint64_t><<<cell_grid(g), 256, 0, s>>>((const uint64_t*)fin, (uint64_t*)fout, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s) {
+  return lattice == kD2Q9 ? launch_stream_l<kD2Q9>(word_bytes, fin, fout, g, s)
+                          : launch_stream_l<kD3Q27>(word_bytes, fin, fout, g, s);
+}
+
+}  // namespace lbm

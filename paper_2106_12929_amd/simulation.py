@@ -1,0 +1,63 @@
+"""A small simulation driver over the C ABI (the Simulation.step(num_steps) usage of
+the paper's Listing 1): owns the two population buffers of the ping-pong scheme and
+tracks which one holds the current state."""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+class Simulation:
+    """Populations of one grid on one GPU.
+
+    grid: binding.Grid.  tau: BGK relaxation time.  force: optional [D, *spatial]
+    real-typed GPU tensor, constant in time.
+    """
+
+    def __init__(self, grid: B.Grid, tau: float, force: torch.Tensor | None = None, device="cuda"):
+        self.grid = grid
+        self.tau = float(tau)
+        self.force = force
+        self.device = torch.device(device)
+        self.bufs = [grid.empty_populations(self.device), grid.empty_populations(self.device)]
+        self.cur = 0
+        self.steps_done = 0
+        self._red = torch.zeros(B.NRED, dtype=torch.float64, device=self.device)
+        self._ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device=self.device)
+
+    @property
+    def f(self) -> torch.Tensor:
+        """The current state g(t) (storage words)."""
+        return self.bufs[self.cur]
+
+    def init_equilibrium(self, u: torch.Tensor, rho: torch.Tensor | None = None) -> None:
+        """g(0) = f^eq(rho, u) from FP64 fields (moved to the GPU if needed)."""
+        u = u.to(self.device, torch.float64).contiguous()
+        rho = None if rho is None else rho.to(self.device, torch.float64).contiguous()
+        B.lbm_init_equilibrium(self.grid, rho, u, self.bufs[self.cur])
+        self.steps_done = 0
+
+    def load(self, f: torch.Tensor) -> None:
+        """Set the state from stored words of the right dtype and shape."""
+        self.bufs[self.cur].copy_(f.to(self.device))
+
+    def step(self, n_steps: int = 1) -> None:
+        src, dst = self.bufs[self.cur], self.bufs[1 - self.cur]
+        where = B.lbm_step(self.grid, src, dst, self.tau, self.force, n_steps)
+        self.cur = (1 - self.cur) if where == 0 else self.cur
+        self.steps_done += n_steps
+
+    def moments(self):
+        """(rho [*spatial], u [D, *spatial]) of the current state, real dtype."""
+        rho = self.grid.empty_real(0, self.device)
+        u = self.grid.empty_real(self.grid.D, self.device)
+        B.lbm_moments(self.grid, self.f, self.force, rho, u)
+        return rho, u
+
+    def reductions(self) -> dict:
+        """FP64 mass, momentum, kinetic energy, non-finite count, max speed, min density
+        (copies 8 doubles to the host, which waits for the stream)."""
+        B.lbm_moments(self.grid, self.f, self.force, None, None, self._red, self._ws)
+        vals = self._red.cpu().tolist()
+        return dict(zip(B.RED_NAMES, vals))

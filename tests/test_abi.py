@@ -1,0 +1,134 @@
+"""CPU tests of the C ABI boundary: the library loads, exports every entry point the
+header declares, publishes the oracle's lattice tables, and rejects invalid
+arguments on the host before any HIP call (so no GPU is needed here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from oracle import lbm as olbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2106_12929_amd import binding
+
+    return binding
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for need in ("lbm_init_equilibrium", "lbm_step", "lbm_moments", "lbm_adjoint_step",
+                 "lbm_moments_adjoint", "lbm_stream_only", "lbm_lattice_info", "lbm_strerror"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\sT\s+(\w+)", out.stdout))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    for n in _declared():
+        assert hasattr(B._lib, n)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+def test_lattice_info_matches_oracle_tables(B, name):
+    D, Q, c, w = B.lbm_lattice_info(name)
+    st = olbm.stencil(name)
+    assert (D, Q) == (st.D, st.Q)
+    assert [tuple(r) for r in st.c.tolist()] == c
+    assert st.w.tolist() == w
+
+
+def _grid(B, lattice="D3Q27", storage="f32", nx=8, ny=8, nz=8):
+    return B._CGrid(B.LATTICES.get(lattice, lattice) if isinstance(lattice, str) else lattice,
+                    B.STORAGES.get(storage, storage) if isinstance(storage, str) else storage, nx, ny, nz)
+
+
+P1 = ctypes.c_void_p(0x10000)        # aligned fake device addresses: validation
+P2 = ctypes.c_void_p(0x4000000000)   # fails before any of them is dereferenced
+P3 = ctypes.c_void_p(0x8000000000)
+MIS = ctypes.c_void_p(0x10004)
+
+
+def _step(B, g, a, b, tau=0.6, force=None, n=1):
+    return B._lib.lbm_step(ctypes.byref(g), a, b, tau, force, n, None)
+
+
+def test_step_validation(B):
+    lib = B._lib
+    g = _grid(B)
+    assert _step(B, g, P1, P2, tau=0.5) == -1           # tau <= 1/2
+    assert _step(B, g, P1, P2, tau=float("nan")) == -1
+    assert _step(B, g, P1, P2, tau=float("inf")) == -1
+    assert _step(B, g, P1, P2, n=0) == -1                # n_steps < 1
+    assert _step(B, g, None, P2) == -2
+    assert _step(B, g, P1, None) == -2
+    assert _step(B, g, MIS, P2) == -3
+    assert _step(B, g, P1, P1) == -4                     # f_in == f_out
+    assert _step(B, g, P1, ctypes.c_void_p(0x10000 + 16)) == -4  # overlapping ranges
+    assert _step(B, g, P1, P2, force=P1) == -4           # force overlaps f_in
+    assert b"overlap" in lib.lbm_last_error()
+    assert lib.lbm_step(None, P1, P2, 0.6, None, 1, None) == -2
+
+
+@pytest.mark.parametrize("dims,code", [((0, 4, 4), -1), ((4, -1, 4), -1), ((1 << 31, 1, 1), -6),
+                                       ((1 << 16, 1 << 16, 1), -6)])
+def test_grid_validation(B, dims, code):
+    g = _grid(B, nx=dims[0], ny=dims[1], nz=dims[2])
+    assert _step(B, g, P1, P2) == code
+
+
+def test_lattice_storage_validation(B):
+    assert _step(B, _grid(B, lattice=5), P1, P2) == -1
+    assert _step(B, _grid(B, storage=9), P1, P2) == -1
+    assert _step(B, _grid(B, lattice="D2Q9", nz=2), P1, P2) == -1  # D2Q9 needs nz == 1
+
+
+def test_other_entry_points_validate(B):
+    lib = B._lib
+    g = _grid(B)
+    gp = ctypes.byref(g)
+    assert lib.lbm_init_equilibrium(gp, None, None, P1, None) == -2       # u required
+    assert lib.lbm_init_equilibrium(gp, None, P1, P1, None) == -4         # f_out overlaps u
+    assert lib.lbm_stream_only(gp, P1, P1, None) == -4
+    assert lib.lbm_moments(gp, None, None, None, None, None, None, 0, None) == -2
+    red = ctypes.c_void_p(0x40000000)
+    assert lib.lbm_moments(gp, P1, None, None, None, red, None, 0, None) == -2    # workspace needed
+    need = ctypes.c_size_t()
+    assert lib.lbm_moments_workspace_size(gp, ctypes.byref(need)) == 0
+    assert need.value == 8 * 8 * ((8 ** 3 + 255) // 256)
+    assert lib.lbm_moments(gp, P1, None, None, None, red, P2, need.value - 1, None) == -1
+    assert lib.lbm_moments(gp, P1, None, P1, None, None, None, 0, None) == -4    # rho_out overlaps g
+    assert lib.lbm_adjoint_step(gp, P1, P2, P2, 0.6, None, None, None) == -4     # lam_out == lam_next
+    assert lib.lbm_adjoint_step(gp, P1, P2, P3, 0.6, None, ctypes.c_void_p(0xC000000000), None) == -5
+    assert lib.lbm_adjoint_step(gp, P1, P2, P3, 0.4, None, None, None) == -1
+    assert lib.lbm_moments_adjoint(gp, P1, None, None, None, P1, None, None) == -4
+    assert lib.lbm_moments_adjoint(gp, P1, None, None, None, None, None, None) == -2
+
+
+def test_strerror(B):
+    for code in range(-7, 1):
+        assert B._lib.lbm_strerror(code)
+    assert B._lib.lbm_strerror(-99) == b"unknown status"
+
+
+def test_binding_rejects_host_tensors(B):
+    import torch
+
+    grid = B.Grid("D3Q27", "f32", 4, 4, 4)
+    a = torch.zeros(grid.population_shape(), dtype=torch.float32)
+    with pytest.raises(ValueError):
+        B.lbm_step(grid, a, a.clone(), 0.6)

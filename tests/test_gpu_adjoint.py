@@ -1,0 +1,222 @@
+"""GPU parity of the hand-written adjoint (lbm_adjoint_step, lbm_moments_adjoint and
+the checkpointed autograd rollout) against the oracle's autograd gradient and
+finite differences of the GPU FP64 forward path."""
+import pytest
+import torch
+
+import synthetic
+from oracle import adjoint as oadj
+from oracle import lbm as olbm
+from oracle import spectrum as ospec
+from oracle import storage as ost
+
+from _helpers import binding, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("D2Q9", (37, 9, 1)), ("D3Q27", (17, 13, 11)), ("D3Q27", (130, 5, 3))]
+
+
+def _spatial(lat, shape):
+    nx, ny, nz = shape
+    return (ny, nx) if lat == "D2Q9" else (nz, ny, nx)
+
+
+def _state(st, spatial, seed):
+    rho, u = synthetic.random_fields(spatial, st.D, seed, drho=0.03, umax=0.06)
+    return olbm.equilibrium(rho, u, st) * (1 + synthetic.random_normal((st.Q,) + spatial, seed + 1, 0.02))
+
+
+@pytest.mark.parametrize("lat,shape", CASES)
+@pytest.mark.parametrize("kind", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("forced", [False, True])
+def test_adjoint_step_vs_oracle_autograd(lat, shape, kind, forced):
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    spatial = _spatial(lat, shape)
+    grid = B.Grid(lat, kind, *shape)
+    tau = 0.56
+    say(f"adjoint {lat} {kind} {shape} forced={forced}")
+    s = ost.quantize(_state(st, spatial, 61), st, kind)
+    g64 = ost.dequantize(s, st, kind)
+    F = synthetic.random_normal((st.D,) + spatial, 62, 1e-4).to(grid.real_dtype) if forced else None
+    lam = synthetic.random_normal((st.Q,) + spatial, 63).to(grid.real_dtype)
+    lam_out = torch.empty_like(lam, device="cuda")
+    dF = torch.zeros_like(F, device="cuda") if forced else None
+    if forced:
+        dF += 0.25  # accumulation: the kernel adds to what is there
+    B.lbm_adjoint_step(grid, s.cuda(), lam.cuda(), lam_out, tau, None if F is None else F.cuda(), dF)
+    ref, ref_dF = oadj.step_vjp(g64, lam.double(), tau, st, None if F is None else F.double())
+    tol = 1e-13 if kind == "f64" else 2e-6
+    err = float((lam_out.cpu().double() - ref).abs().max() / ref.abs().max())
+    say(f"  lambda rel err {err:.2e}")
+    assert err < tol
+    if forced:
+        errF = float(((dF.cpu().double() - 0.25) - ref_dF).abs().max() / ref_dF.abs().max())
+        say(f"  dF rel err {errF:.2e}")
+        assert errF < (1e-12 if kind == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("lat,shape", CASES[:2])
+@pytest.mark.parametrize("forced", [False, True])
+def test_adjoint_transposition_fd(lat, shape, forced):
+    """<lam', J dg> by a central finite difference of the GPU FP64 forward step
+    against <J^T lam', dg> from the GPU adjoint."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    spatial = _spatial(lat, shape)
+    grid = B.Grid(lat, "f64", *shape)
+    tau = 0.56
+    g = _state(st, spatial, 71).cuda()
+    F = synthetic.random_normal((st.D,) + spatial, 72, 1e-4).cuda() if forced else None
+    lam = synthetic.random_normal((st.Q,) + spatial, 73).cuda()
+    dg = synthetic.random_normal((st.Q,) + spatial, 74, 1e-3).cuda()
+    eps = 1e-4
+
+    def fwd(x, FF=F):
+        out = torch.empty_like(x)
+        B.lbm_step(grid, x.contiguous(), out, tau, FF, 1)
+        return out
+
+    jvp = (fwd(g + eps * dg) - fwd(g - eps * dg)) / (2 * eps)
+    lam_out = torch.empty_like(lam)
+    dF = torch.zeros_like(F) if forced else None
+    B.lbm_adjoint_step(grid, g, lam, lam_out, tau, F, dF)
+    lhs, rhs = float((lam * jvp).sum()), float((lam_out * dg).sum())
+    say(f"transposition {lat} forced={forced}: {lhs:.12e} vs {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+    if forced:
+        dFdir = synthetic.random_normal((st.D,) + spatial, 75, 1e-4).cuda()
+        jvpF = (fwd(g, F + eps * dFdir) - fwd(g, F - eps * dFdir)) / (2 * eps)
+        lhs, rhs = float((lam * jvpF).sum()), float((dF * dFdir).sum())
+        assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+
+
+@pytest.mark.parametrize("lat,shape", CASES)
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+@pytest.mark.parametrize("forced", [False, True])
+def test_moments_adjoint_vs_oracle(lat, shape, kind, forced):
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    spatial = _spatial(lat, shape)
+    grid = B.Grid(lat, kind, *shape)
+    s = ost.quantize(_state(st, spatial, 81), st, kind)
+    F = synthetic.random_normal((st.D,) + spatial, 82, 1e-4).to(grid.real_dtype) if forced else None
+    a = synthetic.random_normal(spatial, 83).to(grid.real_dtype)
+    b = synthetic.random_normal((st.D,) + spatial, 84).to(grid.real_dtype)
+    lam = torch.empty((st.Q,) + spatial, dtype=grid.real_dtype, device="cuda")
+    dF = torch.zeros_like(F, device="cuda") if forced else None
+    B.lbm_moments_adjoint(grid, s.cuda(), None if F is None else F.cuda(), a.cuda(), b.cuda(), lam, dF)
+    ref, ref_dF = oadj.moments_vjp(ost.dequantize(s, st, kind), st, None if F is None else F.double(),
+                                   a.double(), b.double())
+    tol = 1e-13 if kind == "f64" else 2e-6
+    assert float((lam.cpu().double() - ref).abs().max() / ref.abs().max()) < tol
+    if forced:
+        assert float((dF.cpu().double() - ref_dF).abs().max() / ref_dF.abs().max()) < tol
+    # NULL cotangents mean zero
+    B.lbm_moments_adjoint(grid, s.cuda(), None if F is None else F.cuda(), None, None, lam, None)
+    assert float(lam.abs().max()) == 0.0
+
+
+def _spectral_loss_fn(n, k_hi=3):
+    K = torch.arange(n, dtype=torch.float64).clamp(min=1)
+    target = 1e-4 * K ** (-5.0 / 3.0)
+    return target, k_hi
+
+
+def test_rollout_gradient_vs_oracle_autograd():
+    """Whole differentiated rollout (8^3, 12 steps, checkpoint every 5) through the
+    autograd wrapper and the GPU spectral loss head, against the oracle's autograd
+    through its own steps and spectrum, in FP64."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd import autograd as AG
+    from paper_2106_12929_amd import spectrum as gspec
+
+    st = olbm.stencil("D3Q27")
+    n, tau, T = 8, 0.6, 12
+    u0 = synthetic.isotropic_turbulence(n, 2.0, 0.03, seed=3)
+    g0 = olbm.equilibrium(torch.ones(n, n, n, dtype=torch.float64), u0, st)
+    F = synthetic.random_normal((3, n, n, n), 91, 1e-4)
+    target, k_hi = _spectral_loss_fn(n)
+
+    def oracle_loss(rho, u):
+        return ospec.log_spectrum_loss(ospec.energy_spectrum(u), target, 1, k_hi, 1e-14)
+
+    L_ref, dg_ref, dF_ref = oadj.rollout_grad(g0, F, tau, st, T, oracle_loss)
+
+    grid = B.Grid("D3Q27", "f64", n, n, n)
+    g0d = g0.cuda().requires_grad_(True)
+    Fd = F.cuda().requires_grad_(True)
+    gT = AG.rollout(grid, g0d, Fd, tau, T, checkpoint_every=5)
+    rho, u = AG.moments(grid, gT, Fd)
+    L = gspec.log_spectrum_loss(gspec.energy_spectrum(u), target.cuda(), 1, k_hi, 1e-14)
+    L.backward()
+    say(f"rollout loss gpu {float(L):.12e} oracle {float(L_ref):.12e}")
+    assert abs(float(L) - float(L_ref)) <= 1e-10 * abs(float(L_ref))
+    eF = float((Fd.grad.cpu() - dF_ref).abs().max() / dF_ref.abs().max())
+    eg = float((g0d.grad.cpu() - dg_ref).abs().max() / dg_ref.abs().max())
+    say(f"  dF rel err {eF:.2e}, dg0 rel err {eg:.2e}")
+    assert eF < 1e-10 and eg < 1e-10
+
+
+def test_rollout_gradient_fd_32cube():
+    """FD check of dL/dF along a random direction: 32^3 FP64, 100 steps (the forced
+    workload's reduced copy), checkpoint every 10."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd import autograd as AG
+    from paper_2106_12929_amd import spectrum as gspec
+
+    n, tau, T = 32, 0.51, 100
+    grid = B.Grid("D3Q27", "f64", n, n, n)
+    u0 = synthetic.isotropic_turbulence(n, 4.0, 0.05, seed=0).cuda()
+    g0 = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u0, g0)
+    E0 = gspec.energy_spectrum(u0)
+    K = torch.arange(E0.numel(), dtype=torch.float64, device="cuda").clamp(min=1)
+    target = K ** (-5.0 / 3.0)
+    target = target * E0[2:17].sum() / target[2:17].sum()
+    cut = 1e-12 * float(E0.sum())
+
+    def loss_of(F, grad=False):
+        gT = AG.rollout(grid, g0, F, tau, T, checkpoint_every=10)
+        _, u = AG.moments(grid, gT, F)
+        return gspec.log_spectrum_loss(gspec.energy_spectrum(u), target, 2, 16, cut)
+
+    F = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda", requires_grad=True)
+    L = loss_of(F)
+    L.backward()
+    d = synthetic.random_normal((3, n, n, n), 92, 1.0).cuda()
+    eps = 1e-8
+    with torch.no_grad():
+        Lp = float(loss_of(F + eps * d))
+        Lm = float(loss_of(F - eps * d))
+    fd = (Lp - Lm) / (2 * eps)
+    an = float((F.grad * d).sum())
+    say(f"FD {fd:.10e} adjoint {an:.10e}")
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_checkpoint_invariance_bitwise():
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd import autograd as AG
+
+    n, tau, T = 24, 0.51, 40
+    grid = B.Grid("D3Q27", "f32", n, n, n)
+    u0 = synthetic.isotropic_turbulence(n, 4.0, 0.05, seed=1).cuda()
+    g0 = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u0, g0)
+    grads = []
+    for K in (1, 7, 40, 100):
+        F = torch.zeros((3, n, n, n), dtype=torch.float32, device="cuda", requires_grad=True)
+        gT = AG.rollout(grid, g0, F, tau, T, checkpoint_every=K)
+        _, u = AG.moments(grid, gT, F)
+        (0.5 * (u.double() ** 2).sum()).backward()
+        grads.append(F.grad.clone())
+    for g in grads[1:]:
+        assert torch.equal(g, grads[0])
