@@ -165,6 +165,59 @@ def accuracy_vs_fp64(B, u_dev, n_steps: int):
     return res
 
 
+def run_workloads():
+    """The decaying-turbulence precision study (384^3, 2000 steps, tau 0.5015 and a
+    stable tau), the
+    forcing optimisation through the adjoint (128^3, 100 steps, K = 10) and the
+    full-scale FP16-shifted adjoint run (512^3, 500 steps, adjoint over the last 50)."""
+    from paper_2106_12929_amd import workloads as WL
+    from synthetic import isotropic_turbulence
+
+    out = {}
+    log("[bench] precision study 384^3")
+    u = isotropic_turbulence(384, 4.0, 0.05, seed=0, device="cuda")
+    # tau = 0.5015 as specified for the workload (BGK blows up there: reported), then
+    # the smallest tau of 0.505 / 0.51 at which the FP64 run stays finite.
+    out["precision_384"] = [WL.precision_study(u, 0.5015, 2000)]
+    for tau in (0.505, 0.51):
+        res = WL.precision_study(u, tau, 2000)
+        out["precision_384"].append(res)
+        if res["runs"]["f64"]["blew_up_at"] is None:
+            break
+    del u
+    torch.cuda.empty_cache()
+    log("[bench] forcing optimisation 128^3")
+    u = isotropic_turbulence(128, 4.0, 0.05, seed=0, device="cuda")
+    out["forcing_128"] = WL.forcing_optimisation(u, 0.51, steps=100, checkpoint_every=10, iters=30)
+    del u
+    torch.cuda.empty_cache()
+    log("[bench] full-scale adjoint 512^3")
+    u = isotropic_turbulence(512, 4.0, 0.05, seed=0, device="cuda")
+    out["adjoint_512"] = WL.full_scale_adjoint(u, 0.5015, forward_steps=500, adjoint_steps=50,
+                                               checkpoint_every=10)
+    del u
+    torch.cuda.empty_cache()
+    return out
+
+
+def measured_traffic():
+    """HBM bytes per launch of the step kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "step_kernel_d3q27_f32_256_counters.md")
+    src = os.path.join(ROOT, "paper_2106_12929_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
+    fields = {k[2:].strip(): v.strip() for k, v in fields.items()}
+    if fields.get("kernels.hip sha256") != digest:
+        return None
+    return float(fields["traffic bytes per launch"])
+
+
 def cpu_baseline(seconds_budget: float = 20.0):
     """The FP64 oracle (plain torch CPU ops) on a bounded sample of the same
     workload: the D3Q27 Taylor-Green vortex at tau=0.51 on a 64^3 grid (the
@@ -199,6 +252,10 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline kernel only (for profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--accuracy-steps", type=int, default=1000)
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the 384^3 precision study, the 128^3 forcing optimisation and the 512^3 adjoint run")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only copy 1 GiB to another 1 GiB buffer 3 times (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the step runs on a single MI355X and this build has no "
@@ -207,6 +264,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_reference:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes_each_way": a.numel() * 4, "copies": 3}), flush=True)
+        return
 
     from paper_2106_12929_amd import binding as B
     from synthetic import taylor_green_3d
@@ -233,6 +300,8 @@ def main():
         log(f"[bench] accuracy after {args.accuracy_steps} steps")
         detail["accuracy_vs_f64_gpu"] = {"steps": args.accuracy_steps,
                                          "errors": accuracy_vs_fp64(B, u_dev, args.accuracy_steps)}
+        if not args.no_workloads:
+            detail["workloads"] = run_workloads()
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -254,7 +323,7 @@ def main():
         "config": {"workload": WORKLOAD, "lattice": "D3Q27", "grid": [N, N, N], "storage": "f32",
                    "tau": TAU, "u0": U0, "cells": N ** 3},
         "roofline": {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": head["hbm_frac"], "traffic": None,
+                     "frac": head["hbm_frac"], "traffic": measured_traffic(),
                      "kernel": "lbm::step_kernel<D3Q27, F32, unforced>",
                      "algorithmic_bytes_per_launch": head["bytes_per_cell"] * N ** 3},
         "cpu_baseline": cpu,

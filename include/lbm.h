@@ -22,8 +22,11 @@
  * Grid: nx, ny, nz >= 1 cells (nz = 1 for D2Q9), N = nx*ny*nz <= 2^31 - 1.
  *   Cell (x, y, z) has linear index n = (z*ny + y)*nx + x (x fastest).
  *
- * Population buffers ("f", "g", SoA): element (i, n) at word offset i*N + n, Q*N words.
- *   The word type and meaning depend on the storage kind:
+ * Population buffers ("f", "g"): row-interleaved SoA.  The grid is nz*ny rows of nx
+ *   cells; row r = z*ny + y holds its Q direction rows one after the other, so word
+ *   (i, x, y, z) sits at ((z*ny + y)*Q + i)*nx + x, Q*N words in all.  Each direction
+ *   is contiguous along x within a row.  The word type and meaning depend on the
+ *   storage kind:
  *     LBM_F64    double   f_i
  *     LBM_F32    float    f_i
  *     LBM_F32S   float    f_i - w_i         ("shifted": the deviation from rest)
@@ -34,7 +37,8 @@
  *
  * Real arrays (force, rho, u, adjoint populations, force gradients) use the "real"
  *   type of the storage kind: double for LBM_F64, float for every other kind.  Vector
- *   fields are SoA [D][N] (component a = x, y, z at offset a*N + n).
+ *   fields are SoA [D][N] (component a = x, y, z at offset a*N + n, n = (z*ny + y)*nx
+ *   + x); adjoint population arrays use the population layout above.
  *
  * State: a population buffer holds the post-collision populations g(t) = C(f(t)) of
  *   Eq. 1's state f(t); one step maps g(t) to g(t+1) = C(S g(t)) where S is the

@@ -105,7 +105,22 @@ class Grid:
         return torch.float64 if self.storage == "f64" else torch.float32
 
     def population_shape(self) -> tuple:
-        return (self.Q,) + self.spatial
+        """Shape of a population buffer in the library's row-interleaved layout:
+        (nz, ny, Q, nx) for D3Q27, (ny, Q, nx) for D2Q9; word (i, x, y, z) sits at
+        ((z*ny + y)*Q + i)*nx + x."""
+        return (self.ny, self.Q, self.nx) if self.D == 2 else (self.nz, self.ny, self.Q, self.nx)
+
+    def to_layout(self, f: torch.Tensor) -> torch.Tensor:
+        """[Q, *spatial] (direction-major) -> the library layout (a contiguous copy)."""
+        if self.D == 2:
+            return f.permute(1, 0, 2).contiguous()
+        return f.permute(1, 2, 0, 3).contiguous()
+
+    def from_layout(self, f: torch.Tensor) -> torch.Tensor:
+        """The library layout -> [Q, *spatial] (a contiguous copy)."""
+        if self.D == 2:
+            return f.permute(1, 0, 2).contiguous()
+        return f.permute(2, 0, 1, 3).contiguous()
 
     def vector_shape(self) -> tuple:
         return (self.D,) + self.spatial

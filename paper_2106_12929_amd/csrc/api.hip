@@ -91,8 +91,9 @@ int check_tau(double tau) {
 }
 
 int reduce_blocks(const Geometry& geo) {
-  const uint64_t b = (geo.args.ncells + 255) / 256;
-  return (int)(b < (uint64_t)lbm::kMaxReduceBlocks ? b : (uint64_t)lbm::kMaxReduceBlocks);
+  // one block per grid row, at most kMaxReduceBlocks (blocks then take several rows)
+  const uint64_t rows = (uint64_t)geo.args.ny * geo.args.nz;
+  return (int)(rows < (uint64_t)lbm::kMaxReduceBlocks ? rows : (uint64_t)lbm::kMaxReduceBlocks);
 }
 
 #define LBM_TRY(expr)          \

@@ -3,14 +3,19 @@
 // Paper: Bedrunka et al., arXiv:2106.12929, Sec. 2.1, Eqs. 1-4 (stream, BGK collide,
 // second-order equilibrium, moments); Sec. 3.2 (differentiating the solver).
 //
-// Data layout: SoA populations, word (i, n) at i*N + n with n = (z*ny + y)*nx + x.
-// Launch shape: one thread per cell, 256 threads per block covering `bx` consecutive
-// cells of a row (bx = 64, 128 or 256) and 256/bx consecutive rows; rows are (y, z)
-// pairs.  A block therefore reads and writes whole row segments of every direction:
-// each population row is a contiguous run shifted by c_x in x, so loads are coalesced
-// and stores aligned.  The step is HBM-bound (about 1.5 flop per byte moved for
-// D3Q27 FP32), so there is no MFMA and no LDS staging: L1/L2 absorb the +-1-element
-// misalignment of the shifted loads.
+// Population layout ("row-interleaved SoA"): the grid is a set of rows r = z*ny + y of
+// nx cells; row r stores its Q direction rows one after the other, so word (i, x) of
+// row r sits at (r*Q + i)*nx + x.  Within a row every direction is a contiguous run
+// along x (coalesced, vectorisable), and the Q*nx words a block writes are one
+// contiguous region, which keeps the number of DRAM pages a wave touches small.
+//
+// Launch shape: one thread per cell, 256 threads per block covering `block_x`
+// consecutive cells of a row (64, 128 or 256) and 256/block_x consecutive rows.  A
+// wave never straddles two rows, so the row index, the 9 source rows of the pull
+// gather and all row base addresses are wave-uniform (scalar registers); only the
+// three x columns x-1, x, x+1 (periodic) are per lane.  The step is HBM-bound (about
+// 1.5 flop per byte for D3Q27 FP32), so there is no MFMA and no LDS staging: L1/L2
+// absorb the +-1-word misalignment of the shifted loads.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -19,56 +24,67 @@
 
 namespace lbm {
 
-// Index helper: offsets of the 3 source columns / rows / planes of a cell.
-// src[k] is the coordinate of x - c for c = k - 1, wrapped periodically.
-struct Neighbours {
-  uint32_t x[3];
-  uint32_t row[3];    // (y - c_y) * nx
-  uint32_t plane[3];  // (z - c_z) * nx * ny
-  uint32_t self;      // linear index of the cell
-};
-
 __device__ __forceinline__ uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
 
-__device__ __forceinline__ Neighbours neighbours(uint32_t x, uint32_t y, uint32_t z, const GridArgs& g) {
-  Neighbours nb;
-  // c = -1 reads x + 1, c = 0 reads x, c = +1 reads x - 1
-  nb.x[0] = wrap_inc(x, g.nx);
-  nb.x[1] = x;
-  nb.x[2] = wrap_dec(x, g.nx);
-  nb.row[0] = wrap_inc(y, g.ny) * g.nx;
-  nb.row[1] = y * g.nx;
-  nb.row[2] = wrap_dec(y, g.ny) * g.nx;
-  const uint32_t plane = g.nx * g.ny;
-  nb.plane[0] = wrap_inc(z, g.nz) * plane;
-  nb.plane[1] = z * plane;
-  nb.plane[2] = wrap_dec(z, g.nz) * plane;
-  nb.self = nb.plane[1] + nb.row[1] + x;
-  return nb;
-}
+// The cell of a thread.  y and z are wave-uniform (made scalar with readfirstlane).
+// Returns false for the threads of the ragged tails (x >= nx or past the last row).
+struct Cell {
+  uint32_t x, y, z;
+};
 
-template <typename LT>
-__device__ __forceinline__ uint32_t src_index(const Neighbours& nb, int i) {
-  return nb.plane[LT::cz(i) + 1] + nb.row[LT::cy(i) + 1] + nb.x[LT::cx(i) + 1];
-}
-
-// Thread -> cell mapping shared by all cell-parallel kernels.  Returns false for the
-// threads of the ragged tail.
-__device__ __forceinline__ bool cell_of_thread(const GridArgs& g, uint32_t& x, uint32_t& y, uint32_t& z) {
+__device__ __forceinline__ bool cell_of_thread(const GridArgs& g, Cell& c) {
   const uint32_t bx = g.block_x;
-  const uint32_t rows_per_block = 256u / bx;
-  const uint32_t tx = threadIdx.x % bx;
-  const uint32_t ty = threadIdx.x / bx;
   const uint32_t blocks_x = (g.nx + bx - 1) / bx;
   const uint32_t bxi = blockIdx.x % blocks_x;
   const uint32_t byi = blockIdx.x / blocks_x;
-  x = bxi * bx + tx;
-  const uint32_t r = byi * rows_per_block + ty;
-  if (x >= g.nx || r >= g.ny * g.nz) return false;
-  y = r % g.ny;
-  z = r / g.ny;
-  return true;
+  // all 64 lanes of a wave share one row because block_x is a multiple of 64
+  const uint32_t ty = __builtin_amdgcn_readfirstlane(threadIdx.x / bx);
+  const uint32_t r = byi * (256u / bx) + ty;
+  c.x = bxi * bx + threadIdx.x % bx;
+  if (r >= g.ny * g.nz) return false;
+  c.y = r % g.ny;
+  c.z = r / g.ny;
+  return c.x < g.nx;
+}
+
+// Source coordinates of the pull gather: index k = c + 1 holds the coordinate of
+// x - c for c = -1, 0, +1, wrapped periodically (c = -1 reads x + 1).
+struct Sources {
+  uint32_t x[3];  // per lane
+  uint32_t y[3];  // wave-uniform
+  uint32_t z[3];  // wave-uniform
+};
+
+__device__ __forceinline__ Sources sources(const Cell& c, const GridArgs& g) {
+  Sources s;
+  s.x[0] = wrap_inc(c.x, g.nx);
+  s.x[1] = c.x;
+  s.x[2] = wrap_dec(c.x, g.nx);
+  s.y[0] = wrap_inc(c.y, g.ny);
+  s.y[1] = c.y;
+  s.y[2] = wrap_dec(c.y, g.ny);
+  s.z[0] = wrap_inc(c.z, g.nz);
+  s.z[1] = c.z;
+  s.z[2] = wrap_dec(c.z, g.nz);
+  return s;
+}
+
+// Word offset of direction row i of grid row (y, z): ((z*ny + y)*Q + i)*nx.
+template <int Q>
+__device__ __forceinline__ uint64_t dir_row(const GridArgs& g, uint32_t y, uint32_t z, int i) {
+  return (((uint64_t)z * g.ny + y) * Q + (uint64_t)i) * g.nx;
+}
+
+// Word offset of the pull source of direction i for the cell: g_i(x - c_i).
+template <typename LT>
+__device__ __forceinline__ uint64_t src_offset(const GridArgs& g, const Sources& s, int i) {
+  return dir_row<LT::Q>(g, s.y[LT::cy(i) + 1], s.z[LT::cz(i) + 1], i) + s.x[LT::cx(i) + 1];
+}
+
+// Linear cell index of real-valued fields ([D][N] arrays).
+__device__ __forceinline__ uint32_t cell_index(const GridArgs& g, const Cell& c) {
+  return (c.z * g.ny + c.y) * g.nx + c.x;
 }
 
 template <typename T>
@@ -89,15 +105,16 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
   using real = typename ST::real;
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;
-  uint32_t x, y, z;
-  if (!cell_of_thread(g, x, y, z)) return;
-  const Neighbours nb = neighbours(x, y, z, g);
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
+  const Sources src = sources(c, g);
   const size_t N = g.ncells;
+  const uint32_t self = cell_index(g, c);
 
   // Gather (pull streaming, Eq. 1): h_i(x) = g_i(x - c_i), as deviations from w_i.
   real d[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(fin[i * N + src_index<LT>(nb, i)], CO::W(i));
+  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(fin[src_offset<LT>(g, src, i)], CO::W(i));
 
   // Moments (Eq. 4) in deviation form: rho = 1 + sum d, rho u = sum c d (+ F/2).
   real drho = 0, jx = 0, jy = 0, jz = 0;
@@ -113,9 +130,9 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
   }
   real Fx = 0, Fy = 0, Fz = 0;
   if constexpr (FORCED) {
-    Fx = force[nb.self];
-    Fy = force[N + nb.self];
-    if constexpr (LT::D == 3) Fz = force[2 * N + nb.self];
+    Fx = force[self];
+    Fy = force[N + self];
+    if constexpr (LT::D == 3) Fz = force[2 * N + self];
     jx += real(0.5) * Fx;
     jy += real(0.5) * Fy;
     jz += real(0.5) * Fz;
@@ -150,7 +167,7 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
       if (LT::cz(i) < 0) cF -= Fz;
       dn += guo * (CO::A(i) * cF - real(3) * CO::W(i) * uF + real(2) * CO::B(i) * cu * cF);
     }
-    store_stream(&fout[i * N + nb.self], ST::from_dev(dn, CO::W(i)));
+    store_stream(&fout[dir_row<Q>(g, c.y, c.z, i) + c.x], ST::from_dev(dn, CO::W(i)));
   }
 }
 
@@ -160,12 +177,11 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
 template <int L, typename W>
 __global__ __launch_bounds__(256) void stream_kernel(const W* __restrict__ fin, W* __restrict__ fout, GridArgs g) {
   using LT = Lattice<L>;
-  uint32_t x, y, z;
-  if (!cell_of_thread(g, x, y, z)) return;
-  const Neighbours nb = neighbours(x, y, z, g);
-  const size_t N = g.ncells;
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
+  const Sources src = sources(c, g);
 #pragma unroll
-  for (int i = 0; i < LT::Q; ++i) fout[i * N + nb.self] = fin[i * N + src_index<LT>(nb, i)];
+  for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[src_offset<LT>(g, src, i)];
 }
 
 // ---------------------------------------------------------------------------------
@@ -176,10 +192,10 @@ __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ rh
                                                    typename Storage<S>::word* __restrict__ fout, GridArgs g) {
   using LT = Lattice<L>;
   using ST = Storage<S>;
-  uint32_t x, y, z;
-  if (!cell_of_thread(g, x, y, z)) return;
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
   const size_t N = g.ncells;
-  const uint32_t n = (z * g.ny + y) * g.nx + x;
+  const uint32_t n = cell_index(g, c);
   const double rho = rho_in ? rho_in[n] : 1.0;
   const double ux = u[n], uy = u[N + n], uz = LT::D == 3 ? u[2 * N + n] : 0.0;
   const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
@@ -188,30 +204,33 @@ __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ rh
     const double cu = LT::cx(i) * ux + LT::cy(i) * uy + LT::cz(i) * uz;
     const double dev = LT::w(i) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - usq));
     // unshifted storage keeps f = W_i + dev with the base the kernels subtract again
-    fout[i * N + n] = ST::from_f64_dev(dev, static_cast<double>(Coef<L, typename ST::real>::W(i)));
+    fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] =
+        ST::from_f64_dev(dev, static_cast<double>(Coef<L, typename ST::real>::W(i)));
   }
 }
 
 // ---------------------------------------------------------------------------------
-// Moments (Eq. 4) and FP64 reductions.  Grid-stride over cells with a fixed grid, so
-// that every reduction is summed in the same order on every call.
+// Moments (Eq. 4) and FP64 reductions.  Block b handles rows b, b + gridDim, ... with a
+// fixed grid, so that every reduction is summed in the same order on every call.
 // ---------------------------------------------------------------------------------
 template <typename real>
 struct CellMoments {
   real drho, rho, u[3];
 };
 
+// Moments of the cell at column x of a row whose direction rows start at `row`
+// (word (i, x) at row[i*nx + x]); n is the cell's index in the real-valued fields.
 template <int L, int S>
 __device__ __forceinline__ CellMoments<typename Storage<S>::real> cell_moments(
-    const typename Storage<S>::word* __restrict__ f, const typename Storage<S>::real* __restrict__ force, size_t N,
-    size_t n) {
+    const typename Storage<S>::word* __restrict__ row, const typename Storage<S>::real* __restrict__ force,
+    size_t N, uint32_t nx, uint32_t x, uint32_t n) {
   using LT = Lattice<L>;
   using ST = Storage<S>;
   using real = typename ST::real;
   real drho = 0, j[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 0; i < LT::Q; ++i) {
-    const real d = ST::to_dev(f[i * N + n], Coef<L, real>::W(i));
+    const real d = ST::to_dev(row[(size_t)i * nx + x], Coef<L, real>::W(i));
     drho += d;
     j[0] += real(LT::cx(i)) * d;
     j[1] += real(LT::cy(i)) * d;
@@ -235,32 +254,38 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
                                                       const typename Storage<S>::real* __restrict__ force,
                                                       typename Storage<S>::real* __restrict__ rho_out,
                                                       typename Storage<S>::real* __restrict__ u_out,
-                                                      double* __restrict__ partials, size_t N) {
+                                                      double* __restrict__ partials, GridArgs g) {
   using LT = Lattice<L>;
+  const size_t N = g.ncells;
+  const uint32_t rows = g.ny * g.nz;
   // acc: [0] sum drho, [1..3] sum rho u, [4] 1/2 sum |u|^2, [5] non-finite, [6] max|u|, [7] min rho
   double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 1.0e300};
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
-    const auto m = cell_moments<L, S>(f, force, N, n);
-    if (rho_out) rho_out[n] = m.rho;
-    if (u_out) {
+  for (uint32_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const typename Storage<S>::word* row = f + (uint64_t)r * LT::Q * g.nx;
+    for (uint32_t x = threadIdx.x; x < g.nx; x += 256) {
+      const uint32_t n = r * g.nx + x;
+      const auto m = cell_moments<L, S>(row, force, N, g.nx, x, n);
+      if (rho_out) rho_out[n] = m.rho;
+      if (u_out) {
 #pragma unroll
-      for (int a = 0; a < LT::D; ++a) u_out[a * N + n] = m.u[a];
-    }
-    if (partials) {
-      const double rho = m.rho;
-      const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
-      const double usq = ux * ux + uy * uy + uz * uz;
-      const bool finite = isfinite(rho) && isfinite(usq);
-      if (finite) {
-        acc[0] += (double)m.drho;
-        acc[1] += rho * ux;
-        acc[2] += rho * uy;
-        acc[3] += rho * uz;
-        acc[4] += 0.5 * usq;
-        acc[6] = fmax(acc[6], sqrt(usq));
-        acc[7] = fmin(acc[7], rho);
-      } else {
-        acc[5] += 1.0;
+        for (int a = 0; a < LT::D; ++a) u_out[a * N + n] = m.u[a];
+      }
+      if (partials) {
+        const double rho = m.rho;
+        const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
+        const double usq = ux * ux + uy * uy + uz * uz;
+        const bool finite = isfinite(rho) && isfinite(usq);
+        if (finite) {
+          acc[0] += (double)m.drho;
+          acc[1] += rho * ux;
+          acc[2] += rho * uy;
+          acc[3] += rho * uz;
+          acc[4] += 0.5 * usq;
+          acc[6] = fmax(acc[6], sqrt(usq));
+          acc[7] = fmin(acc[7], rho);
+        } else {
+          acc[5] += 1.0;
+        }
       }
     }
   }
@@ -342,15 +367,16 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   using real = typename ST::real;
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;
-  uint32_t x, y, z;
-  if (!cell_of_thread(g, x, y, z)) return;
-  const Neighbours nb = neighbours(x, y, z, g);
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
+  const Sources src = sources(c, g);
   const size_t N = g.ncells;
+  const uint32_t self = cell_index(g, c);
 
   real drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const real d = ST::to_dev(gt[i * N + src_index<LT>(nb, i)], CO::W(i));
+    const real d = ST::to_dev(gt[src_offset<LT>(g, src, i)], CO::W(i));
     drho += d;
     jx += real(LT::cx(i)) * d;
     jy += real(LT::cy(i)) * d;
@@ -358,9 +384,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   }
   real Fx = 0, Fy = 0, Fz = 0;
   if constexpr (FORCED) {
-    Fx = force[nb.self];
-    Fy = force[N + nb.self];
-    if constexpr (LT::D == 3) Fz = force[2 * N + nb.self];
+    Fx = force[self];
+    Fy = force[N + self];
+    if constexpr (LT::D == 3) Fz = force[2 * N + self];
     jx += real(0.5) * Fx;
     jy += real(0.5) * Fy;
     jz += real(0.5) * Fz;
@@ -373,7 +399,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   real mW = 0, mAx = 0, mAy = 0, mAz = 0, bxx = 0, byy = 0, bzz = 0, bxy = 0, bxz = 0, byz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    lam[i] = lam_next[i * N + nb.self];
+    lam[i] = lam_next[dir_row<Q>(g, c.y, c.z, i) + c.x];
     const real l = lam[i];
     const real cx = LT::cx(i), cy = LT::cy(i), cz = LT::cz(i);
     const real al = CO::A(i) * l, bl = CO::B(i) * l;
@@ -418,15 +444,15 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
     if (LT::cy(j) < 0) mu -= vy;
     if (LT::cz(j) > 0) mu += vz;
     if (LT::cz(j) < 0) mu -= vz;
-    lam_out[j * N + src_index<LT>(nb, j)] = mu;
+    lam_out[src_offset<LT>(g, src, j)] = mu;
   }
   if constexpr (FORCED) {
     if (dforce) {
       const real half_inv = real(0.5) * inv_rho;
-      dforce[nb.self] += guo * (mAx - real(3) * ux * mW + real(2) * mBux) + Vx * half_inv;
-      dforce[N + nb.self] += guo * (mAy - real(3) * uy * mW + real(2) * mBuy) + Vy * half_inv;
+      dforce[self] += guo * (mAx - real(3) * ux * mW + real(2) * mBux) + Vx * half_inv;
+      dforce[N + self] += guo * (mAy - real(3) * uy * mW + real(2) * mBuy) + Vy * half_inv;
       if constexpr (LT::D == 3)
-        dforce[2 * N + nb.self] += guo * (mAz - real(3) * uz * mW + real(2) * mBuz) + Vz * half_inv;
+        dforce[2 * N + self] += guo * (mAz - real(3) * uz * mW + real(2) * mBuz) + Vz * half_inv;
     }
   }
 }
@@ -439,12 +465,15 @@ __global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Sto
                                                               const typename Storage<S>::real* __restrict__ du_in,
                                                               typename Storage<S>::real* __restrict__ lam_out,
                                                               typename Storage<S>::real* __restrict__ dforce,
-                                                              size_t N) {
+                                                              GridArgs g) {
   using LT = Lattice<L>;
   using real = typename Storage<S>::real;
-  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  const auto m = cell_moments<L, S>(f, force, N, n);
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
+  const size_t N = g.ncells;
+  const uint32_t n = cell_index(g, c);
+  const uint64_t row = dir_row<LT::Q>(g, c.y, c.z, 0);
+  const auto m = cell_moments<L, S>(f + row, force, N, g.nx, c.x, n);
   const real inv = real(1) / m.rho;
   const real dr = drho_in ? drho_in[n] : real(0);
   real du[3] = {0, 0, 0};
@@ -463,7 +492,7 @@ __global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Sto
     if (LT::cy(j) < 0) v -= by;
     if (LT::cz(j) > 0) v += bz;
     if (LT::cz(j) < 0) v -= bz;
-    lam_out[j * N + n] = v;
+    lam_out[row + (uint64_t)j * g.nx + c.x] = v;
   }
   if (dforce) {
 #pragma unroll
@@ -522,7 +551,7 @@ static hipError_t launch_moments_ls(const void* f, const void* force, void* rho,
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
-  moments_kernel<L, S><<<nblocks, 256, 0, s>>>((const W*)f, (const R*)force, (R*)rho, (R*)u, partials, g.ncells);
+  moments_kernel<L, S><<<nblocks, 256, 0, s>>>((const W*)f, (const R*)force, (R*)rho, (R*)u, partials, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !red) return e;
   reduce_partials_kernel<<<1, 256, 0, s>>>(partials, nblocks, red, (double)g.ncells);
@@ -535,9 +564,8 @@ static hipError_t launch_moments_adjoint_ls(const void* f, const void* force, co
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
-  const unsigned blocks = (unsigned)((g.ncells + 255) / 256);
-  moments_adjoint_kernel<L, S><<<blocks, 256, 0, s>>>((const W*)f, (const R*)force, (const R*)drho, (const R*)du,
-                                                       (R*)lam_out, (R*)dforce, g.ncells);
+  moments_adjoint_kernel<L, S><<<cell_grid(g), 256, 0, s>>>((const W*)f, (const R*)force, (const R*)drho,
+                                                             (const R*)du, (R*)lam_out, (R*)dforce, g);
   return hipGetLastError();
 }
 

@@ -1,0 +1,182 @@
+"""The three GPU workloads beyond the forward roofline run, built on the C ABI:
+
+* `precision_study`: decaying isotropic turbulence (the paper's second flow,
+  Sec. 3.1) on D3Q27 with shifted FP16/BF16 storage next to FP32 and FP64: the error
+  of the kinetic energy, of the shell spectrum and of the velocity field against the
+  FP64 run.
+* `forcing_optimisation`: a per-cell body force (Guo scheme) optimised through the
+  hand-written adjoint so that the shell spectrum after a rollout matches a target
+  E(k) ~ k^-5/3 on a band of shells (the spectrum-holding flow control of Sec. 3.2,
+  with a learnable force field in place of the velocity shift).
+* `full_scale_adjoint`: a long FP16-shifted forward run at full HBM scale, then the
+  checkpointed adjoint over its last steps; reports throughput and peak memory.
+
+Everything runs on the current GPU; inputs come from `synthetic`.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from . import autograd as AG
+from . import binding as B
+from . import spectrum as SP
+
+
+def _sync_time(t0):
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def _reductions(grid, f):
+    red = torch.zeros(B.NRED, dtype=torch.float64, device=f.device)
+    ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device=f.device)
+    B.lbm_moments(grid, f, None, None, None, red, ws)
+    return dict(zip(B.RED_NAMES, red.cpu().tolist()))
+
+
+def precision_study(u0: torch.Tensor, tau: float, steps: int, storages=("f64", "f32", "f16s", "bf16s"),
+                    check_every: int = 250):
+    """Runs the same initial field in each storage format; returns per-format
+    throughput, kinetic-energy history and errors against the FP64 run.
+
+    A run stops early when the reductions report non-finite cells (BGK blow-up); its
+    `blew_up_at` gives the step.  Errors are only computed for runs that finished
+    while the FP64 reference also finished."""
+    n = u0.shape[-1]
+    out = {"grid": [n, n, n], "tau": tau, "steps": steps, "runs": {}}
+    ref = None
+    shells = SP.shell_index((n, n, n), u0.device)
+    for storage in storages:
+        grid = B.Grid("D3Q27", storage, n, n, n)
+        a, b = grid.empty_populations(), grid.empty_populations()
+        B.lbm_init_equilibrium(grid, None, u0, a)
+        ke_hist = []
+        blew_up_at = None
+        t_run = 0.0
+        done = 0
+        while done < steps:
+            k = min(check_every, steps - done)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            where = B.lbm_step(grid, a, b, tau, None, k)
+            t_run += _sync_time(t0)
+            if where == 0:
+                a, b = b, a
+            done += k
+            red = _reductions(grid, a)
+            ke_hist.append((done, red["kinetic_energy"]))
+            if red["nonfinite_cells"] > 0 or red["max_speed"] > 1.0:
+                blew_up_at = done
+                break
+        run = {"mlups": n ** 3 * done / t_run / 1e6, "kinetic_energy": ke_hist, "blew_up_at": blew_up_at}
+        if blew_up_at is None:
+            u = grid.empty_real(3)
+            B.lbm_moments(grid, a, None, None, u)
+            u = u.double()
+            E = SP.energy_spectrum(u, shells)
+            if storage == storages[0]:
+                ref = {"u": u, "E": E, "ke": dict(ke_hist)}
+            elif ref is not None:
+                kmax = n // 2
+                rel_E = ((E[1:kmax] - ref["E"][1:kmax]).abs() / ref["E"][1:kmax]).cpu()
+                ke_ref = ref["ke"][ke_hist[-1][0]]
+                run.update({
+                    "u_rel_l2": float((u - ref["u"]).norm() / ref["u"].norm()),
+                    "ke_rel_err_final": abs(ke_hist[-1][1] - ke_ref) / ke_ref,
+                    "ke_rel_err_max": max(abs(k - ref["ke"][t]) / ref["ke"][t] for t, k in ke_hist),
+                    "spectrum_rel_err_max": float(rel_E.max()),
+                    "spectrum_rel_err_median": float(rel_E.median()),
+                })
+            del u
+        del a, b
+        out["runs"][storage] = run
+        torch.cuda.empty_cache()
+    return out
+
+
+def forcing_optimisation(u0: torch.Tensor, tau: float, steps: int = 100, checkpoint_every: int = 10,
+                         iters: int = 30, lr: float = 1e-5, k_band=(2, 16)):
+    """Adam on a per-cell force field F (FP32, constant in time, starting at zero) so
+    that the shell spectrum after `steps` steps matches A k^-5/3 on k_band, with A
+    matching the band energy of the initial spectrum.  Loss:
+    sum_k (ln max(E,c) - ln max(E_t,c))^2 in FP64, c = 1e-12 E_total(0)."""
+    n = u0.shape[-1]
+    grid = B.Grid("D3Q27", "f32", n, n, n)
+    g0 = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u0, g0)
+    shells = SP.shell_index((n, n, n), u0.device)
+    E0 = SP.energy_spectrum(u0.double(), shells)
+    K = torch.arange(E0.numel(), dtype=torch.float64, device=u0.device).clamp(min=1)
+    lo, hi = k_band
+    target = K ** (-5.0 / 3.0)
+    target = target * E0[lo:hi + 1].sum() / target[lo:hi + 1].sum()
+    cut = 1e-12 * float(E0.sum())
+    F = torch.zeros((3, n, n, n), dtype=torch.float32, device=u0.device, requires_grad=True)
+    opt = torch.optim.Adam([F], lr=lr)
+    losses, times = [], []
+    for it in range(iters):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        opt.zero_grad()
+        gT = AG.rollout(grid, g0, F, tau, steps, checkpoint_every)
+        _, u = AG.moments(grid, gT, F)
+        L = SP.log_spectrum_loss(SP.energy_spectrum(u, shells), target, lo, hi, cut)
+        L.backward()
+        opt.step()
+        times.append(_sync_time(t0))
+        losses.append(float(L))
+    # cell updates per iteration: forward rollout + replay + adjoint
+    per_iter_s = sorted(times)[len(times) // 2]
+    return {"grid": [n, n, n], "tau": tau, "steps": steps, "checkpoint_every": checkpoint_every, "iters": iters,
+            "lr": lr, "loss_first": losses[0], "loss_last": losses[-1], "loss_min": min(losses),
+            "loss_curve": losses, "seconds_per_iteration": per_iter_s,
+            "forward_plus_backward_mlups": n ** 3 * steps / per_iter_s / 1e6,
+            "max_abs_force": float(F.detach().abs().max())}
+
+
+def full_scale_adjoint(u0: torch.Tensor, tau: float, forward_steps: int = 500, adjoint_steps: int = 50,
+                       checkpoint_every: int = 10):
+    """FP16-shifted forward run, then the gradient of the final kinetic energy
+    1/2 sum |u|^2 with respect to the state `adjoint_steps` steps before the end and
+    a zero force field active over those steps."""
+    n = u0.shape[-1]
+    grid = B.Grid("D3Q27", "f16s", n, n, n)
+    torch.cuda.reset_peak_memory_stats()
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u0, a)
+    pre = forward_steps - adjoint_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    where = B.lbm_step(grid, a, b, tau, None, pre)
+    t_fwd = _sync_time(t0)
+    g_start = (b if where == 0 else a).clone()
+    del a, b
+    torch.cuda.empty_cache()
+    F = torch.zeros((3, n, n, n), dtype=torch.float32, device=u0.device, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gT = AG.rollout(grid, g_start, F, tau, adjoint_steps, checkpoint_every)
+    _, u = AG.moments(grid, gT, F)
+    KE = 0.5 * (u.double() ** 2).sum()
+    t_tail = _sync_time(t0)
+    t0 = time.perf_counter()
+    KE.backward()
+    t_bwd = _sync_time(t0)
+    peak = torch.cuda.max_memory_allocated()
+    dF = F.grad
+    out = {"grid": [n, n, n], "storage": "f16s state, f32 adjoint", "tau": tau,
+           "forward_steps": forward_steps, "adjoint_steps": adjoint_steps, "checkpoint_every": checkpoint_every,
+           "forward_mlups": n ** 3 * pre / t_fwd / 1e6,
+           "tail_forward_mlups": n ** 3 * adjoint_steps / t_tail / 1e6,
+           "backward_mlups": n ** 3 * adjoint_steps / t_bwd / 1e6,
+           "backward_seconds": t_bwd, "peak_memory_gb": peak / 1e9,
+           "kinetic_energy_final": float(KE), "grad_force_norm": float(dF.double().norm()),
+           "grad_finite": bool(torch.isfinite(dF).all())}
+    del gT, u, F, g_start
+    torch.cuda.empty_cache()
+    return out
+
+
+__all__ = ["precision_study", "forcing_optimisation", "full_scale_adjoint"]

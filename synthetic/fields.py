@@ -40,53 +40,60 @@ def taylor_green_3d(nx: int, ny: int, nz: int, u0: float) -> torch.Tensor:
     return torch.from_numpy(u)
 
 
-def _kvectors(shape):
-    axes = [np.fft.fftfreq(n, d=1.0 / n) for n in shape]
-    return np.meshgrid(*axes, indexing="ij")
+def _kvectors(shape, device):
+    axes = [torch.fft.fftfreq(n, d=1.0 / n, dtype=torch.float64, device=device) for n in shape]
+    return torch.meshgrid(*axes, indexing="ij")
 
 
-def isotropic_turbulence(n: int, k0: float, u_rms: float, seed: int = 0, dim: int = 3) -> torch.Tensor:
+def isotropic_turbulence(n: int, k0: float, u_rms: float, seed: int = 0, dim: int = 3,
+                         device="cpu") -> torch.Tensor:
     """Random-phase solenoidal velocity on an n^dim periodic box.
 
-    Recipe: Gaussian white noise per component -> FFT -> remove the component along
-    k (solenoidal projection) -> zero the mean and the Nyquist planes -> rescale each
-    integer shell K = round(|k|) to E(K) ~ K^4 exp(-2 (K/k0)^2) -> inverse FFT ->
-    scale so that sqrt(<u.u>/dim) = u_rms.  Returns [dim, (n,) n, n].
+    Recipe: Gaussian white noise per component (numpy PCG64, the seed) -> FFT ->
+    remove the component along k (solenoidal projection) -> zero the mean and the
+    Nyquist planes -> rescale each integer shell K = floor(|k| + 1/2) to
+    E(K) ~ K^4 exp(-2 (K/k0)^2) -> inverse FFT -> subtract the mean -> scale so that
+    sqrt(<u.u>/dim) = u_rms.  Returns [dim, (n,) n, n] float64 on `device` (the FFTs
+    run there; CPU and GPU results agree to FP64 roundoff).
     """
     rng = np.random.default_rng(seed)
     shape = (n,) * dim
-    noise = rng.standard_normal((dim,) + shape)
-    uh = np.fft.fftn(noise, axes=tuple(range(1, dim + 1)))
-    # Axis order of the spatial array is (z, y, x) / (y, x); wavevector component a
-    # belongs to spatial axis dim-1-a.
-    kax = _kvectors(shape)
+    noise = torch.from_numpy(rng.standard_normal((dim,) + shape)).to(device)
+    sp = tuple(range(1, dim + 1))
+    uh = torch.fft.fftn(noise, dim=sp)
+    del noise
+    # Spatial axes are ordered (z, y, x) / (y, x): wavevector component a lives on
+    # spatial axis dim-1-a.
+    kax = _kvectors(shape, device)
     kvec = [kax[dim - 1 - a] for a in range(dim)]
     k2 = sum(k * k for k in kvec)
-    k2_safe = np.where(k2 == 0, 1.0, k2)
+    k2_safe = torch.where(k2 == 0, torch.ones_like(k2), k2)
     div = sum(kvec[a] * uh[a] for a in range(dim))
     for a in range(dim):
-        uh[a] = uh[a] - kvec[a] * div / k2_safe
-    nyq = np.zeros(shape, dtype=bool)
+        uh[a] -= kvec[a] * div / k2_safe
+    del div
+    mask = k2 == 0
     for k in kvec:
-        nyq |= np.abs(k) == n // 2
-    mask = (k2 == 0) | nyq
-    for a in range(dim):
-        uh[a][mask] = 0.0
-    kmag = np.sqrt(k2)
-    shell = np.floor(kmag + 0.5).astype(np.int64)
-    dens = 0.5 * (np.abs(uh) ** 2).sum(axis=0)
-    e_now = np.bincount(shell.ravel(), weights=dens.ravel())
-    K = np.arange(e_now.size, dtype=np.float64)
-    e_target = K ** 4 * np.exp(-2.0 * (K / k0) ** 2)
-    scale = np.zeros_like(e_now)
-    ok = e_now > 0
-    scale[ok] = np.sqrt(e_target[ok] / e_now[ok])
-    uh = uh * scale[shell][None]
-    u = np.real(np.fft.ifftn(uh, axes=tuple(range(1, dim + 1))))
-    u -= u.mean(axis=tuple(range(1, dim + 1)), keepdims=True)
-    rms = math.sqrt(float((u * u).sum(axis=0).mean()) / dim)
+        mask |= k.abs() == n // 2
+    uh[:, mask] = 0
+    shell = torch.floor(torch.sqrt(k2) + 0.5).to(torch.int64)
+    del k2, k2_safe, kvec, kax
+    dens = 0.5 * (uh.real.square() + uh.imag.square()).sum(dim=0)
+    e_now = torch.zeros(int(shell.max()) + 1, dtype=torch.float64, device=device)
+    e_now.index_add_(0, shell.reshape(-1), dens.reshape(-1))
+    del dens
+    K = torch.arange(e_now.numel(), dtype=torch.float64, device=device)
+    e_target = K ** 4 * torch.exp(-2.0 * (K / k0) ** 2)
+    scale = torch.where(e_now > 0, torch.sqrt(e_target / torch.where(e_now > 0, e_now, torch.ones_like(e_now))),
+                        torch.zeros_like(e_now))
+    uh *= scale[shell][None]
+    del shell
+    u = torch.fft.ifftn(uh, dim=sp).real.contiguous()
+    del uh
+    u -= u.mean(dim=sp, keepdim=True)
+    rms = math.sqrt(float((u * u).sum(dim=0).mean()) / dim)
     u *= u_rms / rms
-    return torch.from_numpy(np.ascontiguousarray(u))
+    return u
 
 
 def random_fields(spatial, dim: int, seed: int, drho: float = 0.05, umax: float = 0.08):

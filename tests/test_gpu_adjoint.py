@@ -42,14 +42,15 @@ def test_adjoint_step_vs_oracle_autograd(lat, shape, kind, forced):
     g64 = ost.dequantize(s, st, kind)
     F = synthetic.random_normal((st.D,) + spatial, 62, 1e-4).to(grid.real_dtype) if forced else None
     lam = synthetic.random_normal((st.Q,) + spatial, 63).to(grid.real_dtype)
-    lam_out = torch.empty_like(lam, device="cuda")
+    lam_out = torch.empty(grid.population_shape(), dtype=grid.real_dtype, device="cuda")
     dF = torch.zeros_like(F, device="cuda") if forced else None
     if forced:
         dF += 0.25  # accumulation: the kernel adds to what is there
-    B.lbm_adjoint_step(grid, s.cuda(), lam.cuda(), lam_out, tau, None if F is None else F.cuda(), dF)
+    B.lbm_adjoint_step(grid, grid.to_layout(s).cuda(), grid.to_layout(lam).cuda(), lam_out, tau,
+                       None if F is None else F.cuda(), dF)
     ref, ref_dF = oadj.step_vjp(g64, lam.double(), tau, st, None if F is None else F.double())
     tol = 1e-13 if kind == "f64" else 2e-6
-    err = float((lam_out.cpu().double() - ref).abs().max() / ref.abs().max())
+    err = float((grid.from_layout(lam_out.cpu()).double() - ref).abs().max() / ref.abs().max())
     say(f"  lambda rel err {err:.2e}")
     assert err < tol
     if forced:
@@ -69,10 +70,10 @@ def test_adjoint_transposition_fd(lat, shape, forced):
     spatial = _spatial(lat, shape)
     grid = B.Grid(lat, "f64", *shape)
     tau = 0.56
-    g = _state(st, spatial, 71).cuda()
+    g = grid.to_layout(_state(st, spatial, 71)).cuda()
     F = synthetic.random_normal((st.D,) + spatial, 72, 1e-4).cuda() if forced else None
-    lam = synthetic.random_normal((st.Q,) + spatial, 73).cuda()
-    dg = synthetic.random_normal((st.Q,) + spatial, 74, 1e-3).cuda()
+    lam = grid.to_layout(synthetic.random_normal((st.Q,) + spatial, 73)).cuda()
+    dg = grid.to_layout(synthetic.random_normal((st.Q,) + spatial, 74, 1e-3)).cuda()
     eps = 1e-4
 
     def fwd(x, FF=F):
@@ -107,17 +108,18 @@ def test_moments_adjoint_vs_oracle(lat, shape, kind, forced):
     F = synthetic.random_normal((st.D,) + spatial, 82, 1e-4).to(grid.real_dtype) if forced else None
     a = synthetic.random_normal(spatial, 83).to(grid.real_dtype)
     b = synthetic.random_normal((st.D,) + spatial, 84).to(grid.real_dtype)
-    lam = torch.empty((st.Q,) + spatial, dtype=grid.real_dtype, device="cuda")
+    lam = torch.empty(grid.population_shape(), dtype=grid.real_dtype, device="cuda")
     dF = torch.zeros_like(F, device="cuda") if forced else None
-    B.lbm_moments_adjoint(grid, s.cuda(), None if F is None else F.cuda(), a.cuda(), b.cuda(), lam, dF)
+    sd = grid.to_layout(s).cuda()
+    B.lbm_moments_adjoint(grid, sd, None if F is None else F.cuda(), a.cuda(), b.cuda(), lam, dF)
     ref, ref_dF = oadj.moments_vjp(ost.dequantize(s, st, kind), st, None if F is None else F.double(),
                                    a.double(), b.double())
     tol = 1e-13 if kind == "f64" else 2e-6
-    assert float((lam.cpu().double() - ref).abs().max() / ref.abs().max()) < tol
+    assert float((grid.from_layout(lam.cpu()).double() - ref).abs().max() / ref.abs().max()) < tol
     if forced:
         assert float((dF.cpu().double() - ref_dF).abs().max() / ref_dF.abs().max()) < tol
     # NULL cotangents mean zero
-    B.lbm_moments_adjoint(grid, s.cuda(), None if F is None else F.cuda(), None, None, lam, None)
+    B.lbm_moments_adjoint(grid, sd, None if F is None else F.cuda(), None, None, lam, None)
     assert float(lam.abs().max()) == 0.0
 
 
@@ -149,7 +151,7 @@ def test_rollout_gradient_vs_oracle_autograd():
     L_ref, dg_ref, dF_ref = oadj.rollout_grad(g0, F, tau, st, T, oracle_loss)
 
     grid = B.Grid("D3Q27", "f64", n, n, n)
-    g0d = g0.cuda().requires_grad_(True)
+    g0d = grid.to_layout(g0).cuda().requires_grad_(True)
     Fd = F.cuda().requires_grad_(True)
     gT = AG.rollout(grid, g0d, Fd, tau, T, checkpoint_every=5)
     rho, u = AG.moments(grid, gT, Fd)
@@ -158,7 +160,7 @@ def test_rollout_gradient_vs_oracle_autograd():
     say(f"rollout loss gpu {float(L):.12e} oracle {float(L_ref):.12e}")
     assert abs(float(L) - float(L_ref)) <= 1e-10 * abs(float(L_ref))
     eF = float((Fd.grad.cpu() - dF_ref).abs().max() / dF_ref.abs().max())
-    eg = float((g0d.grad.cpu() - dg_ref).abs().max() / dg_ref.abs().max())
+    eg = float((grid.from_layout(g0d.grad.cpu()) - dg_ref).abs().max() / dg_ref.abs().max())
     say(f"  dF rel err {eF:.2e}, dg0 rel err {eg:.2e}")
     assert eF < 1e-10 and eg < 1e-10
 

@@ -45,10 +45,14 @@ def _force(grid, spatial, seed):
     return synthetic.random_normal((grid.D,) + spatial, seed, 1e-4).to(grid.real_dtype)
 
 
-def _tolerance_ok(kind, st, got, ref):
+def _tolerance_ok(kind, st, got, ref, tau=0.57):
     """Elementwise bound of the GPU step against the oracle's emulated step.
 
-    f64: FP64 roundoff of the deviation-form arithmetic.  f32: 3 ulps of the result.
+    f64: FP64 roundoff of the deviation-form arithmetic.
+    f32: 3 ulps of the result, plus omega * 1.5 ulp(w_i): the kernels read an
+      unshifted word as W_i + d with binary32 base weights W_i that lie within 1.5 ulp
+      of w_i (chosen for exact conservation sums), and the relaxation carries that
+      base offset through with factor omega.
     f32s: 1 ulp of the stored deviation plus FP32 roundoff of terms of size w_i.
     f16s/bf16s: 1 ulp of the storage format (the FP32 arithmetic may land on the
     other side of a rounding boundary than exact arithmetic).
@@ -60,7 +64,7 @@ def _tolerance_ok(kind, st, got, ref):
     if kind == "f64":
         bound = 1e-15 * torch.ones_like(r)
     elif kind == "f32":
-        bound = 3 * ost.ulp(r, kind)
+        bound = 3 * ost.ulp(r, kind) + (1.0 / tau) * 1.5 * ost.ulp(w.expand_as(r), kind)
     else:
         dev_r = ost.quantize(r, st, kind).double()
         dev_g = got.cpu().double()
@@ -81,10 +85,10 @@ def test_stream_only_bit_exact(lat, shape, kind):
     spatial = _spatial(lat, shape)
     say(f"stream_only {lat} {kind} {shape}")
     s = _state(st, spatial, 3, kind)
-    out = torch.empty_like(s, device="cuda")
-    B.lbm_stream_only(grid, s.cuda(), out)
+    out = grid.empty_populations()
+    B.lbm_stream_only(grid, grid.to_layout(s).cuda(), out)
     ref = ost.stream_stored(s, st)
-    assert torch.equal(bits(out.cpu()), bits(ref))
+    assert torch.equal(bits(grid.from_layout(out.cpu())), bits(ref))
 
 
 @pytest.mark.parametrize("lat,shape", CASES)
@@ -99,11 +103,11 @@ def test_init_equilibrium(lat, shape, kind):
     rho, u = synthetic.random_fields(spatial, st.D, 5, drho=0.05, umax=0.08)
     out = grid.empty_populations()
     B.lbm_init_equilibrium(grid, rho.cuda(), u.cuda(), out)
-    _check_init(out.cpu(), ost.quantize(olbm.equilibrium(rho, u, st), st, kind), st, kind)
+    _check_init(grid.from_layout(out.cpu()), ost.quantize(olbm.equilibrium(rho, u, st), st, kind), st, kind)
     # rho = None means rho = 1
     B.lbm_init_equilibrium(grid, None, u.cuda(), out)
     ones = torch.ones(spatial, dtype=torch.float64)
-    _check_init(out.cpu(), ost.quantize(olbm.equilibrium(ones, u, st), st, kind), st, kind)
+    _check_init(grid.from_layout(out.cpu()), ost.quantize(olbm.equilibrium(ones, u, st), st, kind), st, kind)
 
 
 def _check_init(got, ref, st, kind):
@@ -135,11 +139,11 @@ def test_one_step_parity(lat, shape, kind, forced):
     say(f"step {lat} {kind} {shape} forced={forced}")
     s = _state(st, spatial, 11, kind)
     F = _force(grid, spatial, 12) if forced else None
-    out = torch.empty_like(s, device="cuda")
-    rc = B.lbm_step(grid, s.cuda(), out, tau, None if F is None else F.cuda(), 1)
+    out = grid.empty_populations()
+    rc = B.lbm_step(grid, grid.to_layout(s).cuda(), out, tau, None if F is None else F.cuda(), 1)
     assert rc == 0
     ref = ost.step_emulated(s, tau, st, kind, None if F is None else F.double())
-    excess, ratio, same = _tolerance_ok(kind, st, out, ref)
+    excess, ratio, same = _tolerance_ok(kind, st, grid.from_layout(out.cpu()), ref, tau)
     say(f"  max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
     assert excess <= 0, ratio
 
@@ -150,7 +154,7 @@ def test_rest_state_bit_exact(kind):
     B = binding()
     grid = B.Grid("D3Q27", kind, 19, 6, 5)
     say(f"rest {kind}")
-    u = torch.zeros((3, 5, 6, 19), dtype=torch.float64, device="cuda")
+    u = torch.zeros((3, 5, 6, 19), dtype=torch.float64, device="cuda")  # [D, nz, ny, nx]
     a = grid.empty_populations()
     b = grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, u, a)
@@ -168,13 +172,13 @@ def test_ping_pong_return_value():
     st = olbm.stencil("D2Q9")
     grid = B.Grid("D2Q9", "f64", 11, 9)
     s = _state(st, (9, 11), 21, "f64")
-    a, b = s.cuda(), torch.empty_like(s, device="cuda")
+    a, b = grid.to_layout(s).cuda(), grid.empty_populations()
     assert B.lbm_step(grid, a, b, 0.8, None, 2) == 1
     ref = olbm.run(s, 0.8, st, 2)
-    assert float((a.cpu() - ref).abs().max()) < 1e-15
+    assert float((grid.from_layout(a.cpu()) - ref).abs().max()) < 1e-15
     assert B.lbm_step(grid, a, b, 0.8, None, 3) == 0
     ref = olbm.run(ref, 0.8, st, 3)
-    assert float((b.cpu() - ref).abs().max()) < 1e-15
+    assert float((grid.from_layout(b.cpu()) - ref).abs().max()) < 1e-15
 
 
 @pytest.mark.parametrize("lat,shape", CASES)
@@ -193,7 +197,7 @@ def test_moments_parity(lat, shape, kind, forced):
     u = grid.empty_real(grid.D)
     red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
     ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
-    B.lbm_moments(grid, s.cuda(), None if F is None else F.cuda(), rho, u, red, ws)
+    B.lbm_moments(grid, grid.to_layout(s).cuda(), None if F is None else F.cuda(), rho, u, red, ws)
     r_ref, u_ref = olbm.state_moments(ost.dequantize(s, st, kind), st, None if F is None else F.double())
     tol = 1e-14 if kind == "f64" else 2e-6
     assert float((rho.cpu().double() - r_ref).abs().max()) < tol
@@ -222,7 +226,7 @@ def test_nonfinite_cells_are_counted():
     s[0, 2, 6, 19] = float("inf")
     red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
     ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
-    B.lbm_moments(grid, s.cuda(), None, None, None, red, ws)
+    B.lbm_moments(grid, grid.to_layout(s).cuda(), None, None, None, red, ws)
     assert float(red[5].cpu()) == 2.0
 
 
@@ -333,11 +337,11 @@ def test_full_size_sampled(kind, n):
     cells = torch.randint(0, n, (4096, 3), generator=gen)
     corners = torch.tensor([[x, y, z] for x in (0, n - 1) for y in (0, n - 1) for z in (0, n - 1)])
     cells = torch.cat([cells, corners])
-    g_in = b.cpu()
+    g_in = b.cpu().permute(2, 0, 1, 3)  # a [Q, z, y, x] view of the row-interleaved words
     ref = ost.step_at_cells_emulated(g_in, tau, st, kind, cells)
     del g_in
     out = a.cpu()
-    got = out[:, cells[:, 2], cells[:, 1], cells[:, 0]]
-    excess, ratio, same = _tolerance_ok(kind, st, got, ost.quantize(ref, st, kind))
+    got = out[cells[:, 2], cells[:, 1], :, cells[:, 0]].T
+    excess, ratio, same = _tolerance_ok(kind, st, got, ost.quantize(ref, st, kind), tau)
     say(f"  max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
     assert excess <= 0, ratio
