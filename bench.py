@@ -193,7 +193,9 @@ def run_workloads():
     torch.cuda.empty_cache()
     log("[bench] full-scale adjoint 512^3")
     u = isotropic_turbulence(512, 4.0, 0.05, seed=0, device="cuda")
-    out["adjoint_512"] = WL.full_scale_adjoint(u, 0.5015, forward_steps=500, adjoint_steps=50,
+    # tau = 0.505: at the workload's nominal 0.5015 BGK diverges before step 500 (the
+    # precision study above records where), leaving nothing finite to differentiate.
+    out["adjoint_512"] = WL.full_scale_adjoint(u, 0.505, forward_steps=500, adjoint_steps=50,
                                                checkpoint_every=10)
     del u
     torch.cuda.empty_cache()
@@ -202,19 +204,21 @@ def run_workloads():
 
 def measured_traffic():
     """HBM bytes per launch of the step kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source (else None)."""
+    summary, if it was taken on the current kernel sources (else None)."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "step_kernel_d3q27_f32_256_counters.md")
-    src = os.path.join(ROOT, "paper_2106_12929_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
-    text = open(path).read()
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
-    fields = {k[2:].strip(): v.strip() for k, v in fields.items()}
-    if fields.get("kernels.hip sha256") != digest:
-        return None
+    fields = {}
+    for line in open(path).read().splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip()
+    for name in ("kernels.hip", "lattice.h", "coeffs.h"):
+        src = os.path.join(ROOT, "paper_2106_12929_amd", "csrc", name)
+        if fields.get(f"{name} sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
     return float(fields["traffic bytes per launch"])
 
 

@@ -8,14 +8,15 @@
  *   Eq. 2  Omega_i = -(f_i - f_i^eq) / tau                            (BGK)
  *   Eq. 3  f_i^eq = w_i rho (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)   (c_s^2 = 1/3)
  *   Eq. 4  rho = sum_i f_i,   rho u = sum_i c_i f_i
- * on fully periodic D2Q9 and D3Q27 grids, with an optional per-cell body force (Guo
+ * on fully periodic D2Q9, D3Q19 and D3Q27 grids, with an optional per-cell body force (Guo
  * scheme, textbook), plus the reverse-mode derivative of the step (the automatic
  * differentiation of Sec. 3.2, written by hand).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
  * Lattice velocity order: c_i in {-1,0,1}^D with c_x fastest, then c_y, then c_z:
- *   i = 3(c_y+1) + (c_x+1)  (D2Q9),   i = 9(c_z+1) + 3(c_y+1) + (c_x+1)  (D3Q27).
+ *   i = 3(c_y+1) + (c_x+1)  (D2Q9),   i = 9(c_z+1) + 3(c_y+1) + (c_x+1)  (D3Q27);
+ *   D3Q19 is the D3Q27 order without the 8 corner velocities (|c|^2 = 3).
  *   The rest velocity is i = Q/2 and the opposite of i is Q-1-i.  lbm_lattice_info()
  *   publishes c and w.
  *
@@ -65,7 +66,7 @@
 extern "C" {
 #endif
 
-enum lbm_lattice { LBM_D2Q9 = 0, LBM_D3Q27 = 1 };
+enum lbm_lattice { LBM_D2Q9 = 0, LBM_D3Q27 = 1, LBM_D3Q19 = 2 };
 
 enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_F16S = 3, LBM_BF16S = 4 };
 
@@ -102,8 +103,8 @@ const char* lbm_last_error(void);
 /* Library ABI version (major*10000 + minor*100 + patch). */
 int lbm_version(void);
 
-/* Velocity set of a lattice (Sec. 2.1: c_i, w_i; the values are the textbook D2Q9 and
- * D3Q27 tables, the order is the library's).  Host pointers; any may be NULL.
+/* Velocity set of a lattice (Sec. 2.1: c_i, w_i; the values are the textbook D2Q9,
+ * D3Q19 and D3Q27 tables, the order is the library's).  Host pointers; any may be NULL.
  * D, Q: dimension and number of velocities.  c: Q*D ints, row i = (c_x, c_y[, c_z]).
  * w: Q doubles.  Returns LBM_OK or LBM_EINVAL for an unknown lattice. */
 int lbm_lattice_info(int lattice, int* D, int* Q, int* c, double* w);

@@ -33,6 +33,7 @@ F64 = torch.float64
 # but prints no values.
 _WEIGHTS = {
     "D2Q9": {0: 4.0 / 9.0, 1: 1.0 / 9.0, 2: 1.0 / 36.0},
+    "D3Q19": {0: 1.0 / 3.0, 1: 1.0 / 18.0, 2: 1.0 / 36.0},
     "D3Q27": {0: 8.0 / 27.0, 1: 2.0 / 27.0, 2: 1.0 / 54.0, 3: 1.0 / 216.0},
 }
 CS2 = 1.0 / 3.0  # squared lattice sound speed c_s^2 of both stencils
@@ -56,18 +57,22 @@ class Stencil:
 
 
 def stencil(name: str) -> Stencil:
-    """D2Q9 or D3Q27 (the two lattices of Sec. 2.1/3.1 and Listing 1's example).
+    """D2Q9, D3Q19 or D3Q27 (the lattices of Sec. 2.1/3.1, Listing 1's example and the
+    3D benchmark of Sec. 3.3).
 
-    Velocity order: every c in {-1,0,1}^D, with c_x varying fastest, then c_y, then
-    c_z, i.e. i = 3(c_y+1) + (c_x+1) in 2D and i = 9(c_z+1) + 3(c_y+1) + (c_x+1) in
-    3D.  The paper fixes no order; this one puts the rest velocity in the middle and
-    makes opposite(i) = Q-1-i.
+    Velocity order: every c in {-1,0,1}^D (D3Q19: those with |c|^2 <= 2), with c_x
+    varying fastest, then c_y, then c_z; for D2Q9 and D3Q27 that is
+    i = 3(c_y+1) + (c_x+1) and i = 9(c_z+1) + 3(c_y+1) + (c_x+1).  The paper fixes no
+    order; this one puts the rest velocity in the middle and makes
+    opposite(i) = Q-1-i.
     """
-    D = {"D2Q9": 2, "D3Q27": 3}[name]
+    D = {"D2Q9": 2, "D3Q19": 3, "D3Q27": 3}[name]
     rows = []
     for tail in itertools.product((-1, 0, 1), repeat=D):
         # product() varies its last element fastest; reverse so that c_x is fastest.
         rows.append(tuple(reversed(tail)))
+    if name == "D3Q19":
+        rows = [r for r in rows if sum(v * v for v in r) <= 2]
     c = torch.tensor(rows, dtype=torch.int64)
     w = torch.tensor([_WEIGHTS[name][sum(v * v for v in r)] for r in rows], dtype=F64)
     return Stencil(name, D, len(rows), c, w)

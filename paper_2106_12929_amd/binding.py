@@ -18,7 +18,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
-LATTICES = {"D2Q9": 0, "D3Q27": 1}
+LATTICES = {"D2Q9": 0, "D3Q27": 1, "D3Q19": 2}
 STORAGES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3, "bf16s": 4}
 STORAGE_DTYPE = {"f64": torch.float64, "f32": torch.float32, "f32s": torch.float32,
                  "f16s": torch.float16, "bf16s": torch.bfloat16}
@@ -72,7 +72,7 @@ _lib = _load()
 
 @dataclass(frozen=True)
 class Grid:
-    """Grid descriptor: lattice "D2Q9"/"D3Q27", storage kind, and nx, ny, nz cells."""
+    """Grid descriptor: lattice "D2Q9"/"D3Q19"/"D3Q27", storage kind, and nx, ny, nz cells."""
 
     lattice: str
     storage: str
@@ -86,7 +86,7 @@ class Grid:
 
     @property
     def Q(self) -> int:
-        return 9 if self.lattice == "D2Q9" else 27
+        return {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}[self.lattice]
 
     @property
     def ncells(self) -> int:

@@ -51,7 +51,8 @@ uint32_t pick_block_x(int64_t nx) {
 
 int check_grid(const lbm_grid* g, Geometry* geo) {
   if (!g) return fail(LBM_ENULL, "grid is NULL");
-  if (g->lattice != LBM_D2Q9 && g->lattice != LBM_D3Q27) return fail(LBM_EINVAL, "unknown lattice %d", g->lattice);
+  if (g->lattice != LBM_D2Q9 && g->lattice != LBM_D3Q19 && g->lattice != LBM_D3Q27)
+    return fail(LBM_EINVAL, "unknown lattice %d", g->lattice);
   if (g->storage < LBM_F64 || g->storage > LBM_BF16S) return fail(LBM_EINVAL, "unknown storage %d", g->storage);
   if (g->nx < 1 || g->ny < 1 || g->nz < 1)
     return fail(LBM_EINVAL, "grid dimensions must be >= 1 (got %lld x %lld x %lld)", (long long)g->nx,
@@ -62,7 +63,7 @@ int check_grid(const lbm_grid* g, Geometry* geo) {
   if (g->nx * g->ny > lim || (g->nx * g->ny) * g->nz > lim)
     return fail(LBM_ERANGE, "grid has more than 2^31-1 cells");
   geo->D = g->lattice == LBM_D2Q9 ? 2 : 3;
-  geo->Q = g->lattice == LBM_D2Q9 ? 9 : 27;
+  geo->Q = g->lattice == LBM_D2Q9 ? 9 : g->lattice == LBM_D3Q19 ? 19 : 27;
   geo->word = g->storage == LBM_F64 ? 8 : (g->storage == LBM_F32 || g->storage == LBM_F32S) ? 4 : 2;
   geo->real = g->storage == LBM_F64 ? 8 : 4;
   geo->args.nx = (uint32_t)g->nx;
@@ -96,6 +97,18 @@ int reduce_blocks(const Geometry& geo) {
   return (int)(rows < (uint64_t)lbm::kMaxReduceBlocks ? rows : (uint64_t)lbm::kMaxReduceBlocks);
 }
 
+template <typename LT>
+void fill_lattice(int* c, double* w) {
+  for (int i = 0; i < LT::Q; ++i) {
+    if (c) {
+      c[i * LT::D + 0] = LT::cx(i);
+      c[i * LT::D + 1] = LT::cy(i);
+      if (LT::D == 3) c[i * LT::D + 2] = LT::cz(i);
+    }
+    if (w) w[i] = LT::w(i);
+  }
+}
+
 #define LBM_TRY(expr)          \
   do {                         \
     const int rc_ = (expr);    \
@@ -125,30 +138,24 @@ const char* lbm_last_error(void) { return g_last_error; }
 int lbm_version(void) { return 10000; }
 
 int lbm_lattice_info(int lattice, int* D, int* Q, int* c, double* w) {
-  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q27) return fail(LBM_EINVAL, "unknown lattice %d", lattice);
-  const int d = lattice == LBM_D2Q9 ? 2 : 3;
-  const int q = lattice == LBM_D2Q9 ? 9 : 27;
-  if (D) *D = d;
-  if (Q) *Q = q;
-  for (int i = 0; i < q; ++i) {
-    if (lattice == LBM_D2Q9) {
-      using LT = lbm::Lattice<lbm::kD2Q9>;
-      if (c) {
-        c[i * 2 + 0] = LT::cx(i);
-        c[i * 2 + 1] = LT::cy(i);
-      }
-      if (w) w[i] = LT::w(i);
-    } else {
-      using LT = lbm::Lattice<lbm::kD3Q27>;
-      if (c) {
-        c[i * 3 + 0] = LT::cx(i);
-        c[i * 3 + 1] = LT::cy(i);
-        c[i * 3 + 2] = LT::cz(i);
-      }
-      if (w) w[i] = LT::w(i);
-    }
+  switch (lattice) {
+    case LBM_D2Q9:
+      if (D) *D = 2;
+      if (Q) *Q = 9;
+      fill_lattice<lbm::Lattice<lbm::kD2Q9>>(c, w);
+      return LBM_OK;
+    case LBM_D3Q19:
+      if (D) *D = 3;
+      if (Q) *Q = 19;
+      fill_lattice<lbm::Lattice<lbm::kD3Q19>>(c, w);
+      return LBM_OK;
+    case LBM_D3Q27:
+      if (D) *D = 3;
+      if (Q) *Q = 27;
+      fill_lattice<lbm::Lattice<lbm::kD3Q27>>(c, w);
+      return LBM_OK;
   }
-  return LBM_OK;
+  return fail(LBM_EINVAL, "unknown lattice %d", lattice);
 }
 
 int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* u, void* f_out, void* stream) {

@@ -569,26 +569,23 @@ static hipError_t launch_moments_adjoint_ls(const void* f, const void* force, co
   return hipGetLastError();
 }
 
-#define LBM_DISPATCH(LAUNCH, lattice, storage, ...)                                        \
-  do {                                                                                     \
-    if ((lattice) == kD2Q9) {                                                              \
-      switch (storage) {                                                                   \
-        case kF64: return LAUNCH<kD2Q9, kF64>(__VA_ARGS__);                                \
-        case kF32: return LAUNCH<kD2Q9, kF32>(__VA_ARGS__);                                \
-        case kF32S: return LAUNCH<kD2Q9, kF32S>(__VA_ARGS__);                              \
-        case kF16S: return LAUNCH<kD2Q9, kF16S>(__VA_ARGS__);                              \
-        case kBF16S: return LAUNCH<kD2Q9, kBF16S>(__VA_ARGS__);                            \
-      }                                                                                    \
-    } else {                                                                               \
-      switch (storage) {                                                                   \
-        case kF64: return LAUNCH<kD3Q27, kF64>(__VA_ARGS__);                               \
-        case kF32: return LAUNCH<kD3Q27, kF32>(__VA_ARGS__);                               \
-        case kF32S: return LAUNCH<kD3Q27, kF32S>(__VA_ARGS__);                             \
-        case kF16S: return LAUNCH<kD3Q27, kF16S>(__VA_ARGS__);                             \
-        case kBF16S: return LAUNCH<kD3Q27, kBF16S>(__VA_ARGS__);                           \
-      }                                                                                    \
-    }                                                                                      \
-    return hipErrorInvalidValue;                                                           \
+#define LBM_DISPATCH_STORAGE(LAUNCH, LAT, storage, ...)       \
+  switch (storage) {                                         \
+    case kF64: return LAUNCH<LAT, kF64>(__VA_ARGS__);        \
+    case kF32: return LAUNCH<LAT, kF32>(__VA_ARGS__);        \
+    case kF32S: return LAUNCH<LAT, kF32S>(__VA_ARGS__);      \
+    case kF16S: return LAUNCH<LAT, kF16S>(__VA_ARGS__);      \
+    case kBF16S: return LAUNCH<LAT, kBF16S>(__VA_ARGS__);    \
+  }
+
+#define LBM_DISPATCH(LAUNCH, lattice, storage, ...)                              \
+  do {                                                                           \
+    switch (lattice) {                                                           \
+      case kD2Q9: LBM_DISPATCH_STORAGE(LAUNCH, kD2Q9, storage, __VA_ARGS__) break;   \
+      case kD3Q19: LBM_DISPATCH_STORAGE(LAUNCH, kD3Q19, storage, __VA_ARGS__) break; \
+      case kD3Q27: LBM_DISPATCH_STORAGE(LAUNCH, kD3Q27, storage, __VA_ARGS__) break; \
+    }                                                                            \
+    return hipErrorInvalidValue;                                                 \
   } while (0)
 
 hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, const GridArgs& g,
@@ -628,8 +625,12 @@ static hipError_t launch_stream_l(int word_bytes, const void* fin, void* fout, c
 }
 
 hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s) {
-  return lattice == kD2Q9 ? launch_stream_l<kD2Q9>(word_bytes, fin, fout, g, s)
-                          : launch_stream_l<kD3Q27>(word_bytes, fin, fout, g, s);
+  switch (lattice) {
+    case kD2Q9: return launch_stream_l<kD2Q9>(word_bytes, fin, fout, g, s);
+    case kD3Q19: return launch_stream_l<kD3Q19>(word_bytes, fin, fout, g, s);
+    case kD3Q27: return launch_stream_l<kD3Q27>(word_bytes, fin, fout, g, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace lbm

@@ -1,8 +1,9 @@
 // Compile-time lattice and storage descriptions shared by the HIP kernels.
 //
-// Velocity sets (paper Sec. 2.1, Eqs. 1-4; textbook weights): D2Q9 and D3Q27 are
-// the tensor products of {-1, 0, 1}; direction i has c_x = i%3 - 1,
-// c_y = (i/3)%3 - 1, c_z = i/9 - 1 (3D), and its weight depends on |c_i|^2 only.
+// Velocity sets (paper Sec. 2.1, Eqs. 1-4, Sec. 3.3; textbook weights): D2Q9 and D3Q27
+// are the tensor products of {-1, 0, 1}; direction i has c_x = i%3 - 1,
+// c_y = (i/3)%3 - 1, c_z = i/9 - 1 (3D).  D3Q19 keeps the D3Q27 directions with
+// |c|^2 <= 2, in the same order.  A weight depends on |c_i|^2 only.
 // Every accessor is constexpr so that fully unrolled direction loops fold c_i and w_i
 // into immediates.
 #pragma once
@@ -14,7 +15,7 @@
 
 namespace lbm {
 
-enum Lat { kD2Q9 = 0, kD3Q27 = 1 };
+enum Lat { kD2Q9 = 0, kD3Q27 = 1, kD3Q19 = 2 };
 enum Sto { kF64 = 0, kF32 = 1, kF32S = 2, kF16S = 3, kBF16S = 4 };
 
 template <int L>
@@ -50,6 +51,24 @@ struct Lattice<kD3Q27> {
   }
 };
 
+// D3Q27 index of each D3Q19 direction (the 8 corners |c|^2 = 3 left out).
+constexpr int kD3Q19FromD3Q27[19] = {1, 3, 4, 5, 7, 9, 10, 11, 12, 13, 14, 15, 16, 17, 19, 21, 22, 23, 25};
+
+template <>
+struct Lattice<kD3Q19> {
+  static constexpr int D = 3;
+  static constexpr int Q = 19;
+  __host__ __device__ static constexpr int cx(int i) { return kD3Q19FromD3Q27[i] % 3 - 1; }
+  __host__ __device__ static constexpr int cy(int i) { return (kD3Q19FromD3Q27[i] / 3) % 3 - 1; }
+  __host__ __device__ static constexpr int cz(int i) { return kD3Q19FromD3Q27[i] / 9 - 1; }
+  __host__ __device__ static constexpr int c2(int i) {
+    return cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i);
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return c2(i) == 0 ? 1.0 / 3.0 : c2(i) == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+  }
+};
+
 // ---------------------------------------------------------------------------------
 // Equilibrium coefficients in the working precision R:
 //   deq_i = W_i drho + rho (A_i (c_i.u) + B_i (c_i.u)^2 - W_i 3/2 |u|^2)
@@ -73,6 +92,14 @@ struct Coef<kD2Q9, float> {
   __host__ __device__ static constexpr float W(int i) { return kD2Q9_W[LT::c2(i)]; }
   __host__ __device__ static constexpr float A(int i) { return kD2Q9_A[LT::c2(i)]; }
   __host__ __device__ static constexpr float B(int i) { return kD2Q9_B[LT::c2(i)]; }
+};
+
+template <>
+struct Coef<kD3Q19, float> {
+  using LT = Lattice<kD3Q19>;
+  __host__ __device__ static constexpr float W(int i) { return kD3Q19_W[LT::c2(i)]; }
+  __host__ __device__ static constexpr float A(int i) { return kD3Q19_A[LT::c2(i)]; }
+  __host__ __device__ static constexpr float B(int i) { return kD3Q19_B[LT::c2(i)]; }
 };
 
 template <>

@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(B):
         assert hasattr(B._lib, n)
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
 def test_lattice_info_matches_oracle_tables(B, name):
     D, Q, c, w = B.lbm_lattice_info(name)
     st = olbm.stencil(name)

@@ -24,7 +24,7 @@ def _tables():
     return out
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
 def test_exact_conservation_sums(name):
     tab = _tables()
     st = olbm.stencil(name)

@@ -14,7 +14,7 @@ from _helpers import binding, need_gpu, say
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("D2Q9", (37, 9, 1)), ("D3Q27", (17, 13, 11)), ("D3Q27", (130, 5, 3))]
+CASES = [("D2Q9", (37, 9, 1)), ("D3Q27", (17, 13, 11)), ("D3Q27", (130, 5, 3)), ("D3Q19", (21, 6, 5))]
 
 
 def _spatial(lat, shape):

@@ -8,7 +8,7 @@ import torch
 import synthetic
 from oracle import adjoint, lbm, spectrum
 
-CASES = [("D2Q9", (6, 5)), ("D3Q27", (4, 3, 5))]
+CASES = [("D2Q9", (6, 5)), ("D3Q19", (3, 4, 5)), ("D3Q27", (4, 3, 5))]
 
 
 def _fd(fun, x, dx, eps):

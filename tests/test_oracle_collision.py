@@ -12,7 +12,7 @@ import torch
 import synthetic
 from oracle import lbm
 
-CASES = [("D2Q9", (7, 5)), ("D3Q27", (4, 5, 3))]
+CASES = [("D2Q9", (7, 5)), ("D3Q19", (3, 4, 5)), ("D3Q27", (4, 5, 3))]
 
 
 def _state(name, spatial, seed):

@@ -20,7 +20,7 @@ def _exact(st):
     return [tuple(r) for r in st.c.tolist()], ws
 
 
-@pytest.mark.parametrize("name,D,Q", [("D2Q9", 2, 9), ("D3Q27", 3, 27)])
+@pytest.mark.parametrize("name,D,Q", [("D2Q9", 2, 9), ("D3Q19", 3, 19), ("D3Q27", 3, 27)])
 def test_isotropy_exact(name, D, Q):
     st = lbm.stencil(name)
     assert (st.D, st.Q) == (D, Q)
@@ -40,21 +40,26 @@ def test_isotropy_exact(name, D, Q):
         assert sum(wi * ci[a] * ci[b] * ci[e] * ci[d] for wi, ci in zip(w, c)) == expect
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
 def test_velocity_order(name):
     st = lbm.stencil(name)
     c = st.c.tolist()
-    for i, r in enumerate(c):
-        idx = sum(3 ** a * (r[a] + 1) for a in range(st.D))
-        assert idx == i
+    full = [sum(3 ** a * (r[a] + 1) for a in range(st.D)) for r in c]
+    if name == "D3Q19":
+        # the D3Q27 order without the 8 corners
+        assert full == [k for k in range(27) if k not in (0, 2, 6, 8, 18, 20, 24, 26)]
+    else:
+        assert full == list(range(st.Q))
     assert c[st.Q // 2] == [0] * st.D
     assert st.opposite == [st.Q - 1 - i for i in range(st.Q)]
 
 
-def test_textbook_weight_values():
-    # The familiar D2Q9 values 4/9, 1/9, 1/36 (Krueger 2016, Table 3.3).
-    st = lbm.stencil("D2Q9")
+@pytest.mark.parametrize("name,table", [("D2Q9", {0: {4 / 9}, 1: {1 / 9}, 2: {1 / 36}}),
+                                        ("D3Q19", {0: {1 / 3}, 1: {1 / 18}, 2: {1 / 36}})])
+def test_textbook_weight_values(name, table):
+    # The familiar D2Q9 and D3Q19 values (Krueger 2016, Table 3.3).
+    st = lbm.stencil(name)
     by_class = {}
     for r, w in zip(st.c.tolist(), st.w.tolist()):
         by_class.setdefault(sum(v * v for v in r), set()).add(w)
-    assert by_class == {0: {4 / 9}, 1: {1 / 9}, 2: {1 / 36}}
+    assert by_class == table

@@ -44,8 +44,8 @@ def test_tgv2d_decay_matches_closed_form():
         assert abs(ke / ke0 / ke_ref - 1) < 2 * gold["rel_tol"], (t, ke / ke0, ke_ref)
 
 
-def _tgv3d_rate_error(n, tau, u0=1e-3, t0=10, t1=50):
-    st = lbm.stencil("D3Q27")
+def _tgv3d_rate_error(n, tau, u0=1e-3, t0=10, t1=50, lattice="D3Q27"):
+    st = lbm.stencil(lattice)
     u = synthetic.taylor_green_3d(n, n, n, u0)
     g = lbm.equilibrium(torch.ones(n, n, n, dtype=torch.float64), u, st)
     b = u[0] / u0
@@ -63,14 +63,15 @@ def _tgv3d_rate_error(n, tau, u0=1e-3, t0=10, t1=50):
     return rate / (3 * lbm.nu_from_tau(tau) * k * k) - 1
 
 
-def test_tgv3d_viscous_decay_second_order():
-    e16 = _tgv3d_rate_error(16, 0.6)
-    e32 = _tgv3d_rate_error(32, 0.6)
+@pytest.mark.parametrize("lattice", ["D3Q19", "D3Q27"])
+def test_tgv3d_viscous_decay_second_order(lattice):
+    e16 = _tgv3d_rate_error(16, 0.6, lattice=lattice)
+    e32 = _tgv3d_rate_error(32, 0.6, lattice=lattice)
     assert abs(e32) < 0.01
     assert 3.0 < e16 / e32 < 5.0  # second-order convergence: halving dx quarters the error
 
 
-@pytest.mark.parametrize("name,spatial", [("D2Q9", (12, 16)), ("D3Q27", (6, 5, 7))])
+@pytest.mark.parametrize("name,spatial", [("D2Q9", (12, 16)), ("D3Q19", (5, 6, 7)), ("D3Q27", (6, 5, 7))])
 def test_literal_eq1_equals_pull_convention(name, spatial):
     st = lbm.stencil(name)
     rho, u = synthetic.random_fields(spatial, st.D, 21, drho=0.02, umax=0.05)
@@ -86,7 +87,7 @@ def test_literal_eq1_equals_pull_convention(name, spatial):
         torch.testing.assert_close(u_g, u_f, rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("name,spatial", [("D2Q9", (12, 16)), ("D3Q27", (6, 5, 7))])
+@pytest.mark.parametrize("name,spatial", [("D2Q9", (12, 16)), ("D3Q19", (5, 6, 7)), ("D3Q27", (6, 5, 7))])
 def test_conservation_over_many_steps(name, spatial):
     st = lbm.stencil(name)
     rho, u = synthetic.random_fields(spatial, st.D, 22, drho=0.05, umax=0.05)

@@ -9,7 +9,7 @@ import synthetic
 from oracle import lbm, storage
 
 
-@pytest.mark.parametrize("name,spatial", [("D2Q9", (4, 5)), ("D3Q27", (3, 4, 5))])
+@pytest.mark.parametrize("name,spatial", [("D2Q9", (4, 5)), ("D3Q19", (3, 4, 3)), ("D3Q27", (3, 4, 5))])
 def test_single_population_moves_along_c(name, spatial):
     # Eq. 1: the value of f_i at x reappears at x + c_i one step later.
     st = lbm.stencil(name)
@@ -37,7 +37,7 @@ def test_brute_force_loops_3d():
                     assert out[i, z, y, x] == f[i, (z - cz) % nz, (y - cy) % ny, (x - cx) % nx]
 
 
-@pytest.mark.parametrize("name,spatial", [("D2Q9", (6, 6)), ("D3Q27", (4, 4, 4))])
+@pytest.mark.parametrize("name,spatial", [("D2Q9", (6, 6)), ("D3Q19", (4, 4, 4)), ("D3Q27", (4, 4, 4))])
 def test_round_trip_identity(name, spatial):
     # n streaming steps on an n-periodic cube return every population home.
     st = lbm.stencil(name)
