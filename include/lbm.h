@@ -131,10 +131,23 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
 int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force,
              int n_steps, void* stream);
 
+/* lbm_step with the flow-control forcing of Sec. 3.2 instead of a body force: the
+ * equilibrium is evaluated at a locally shifted velocity, f^eq(rho, u + du), with
+ * u = sum_i c_i f_i / rho (Eq. 4) and du a per-cell shift (D*N reals, required).
+ * The collision then adds rho du / tau of momentum per cell and step.  Same ping-pong,
+ * return value and argument rules as lbm_step. */
+int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* du,
+                     int n_steps, void* stream);
+
 /* Streaming only: f_out_i(x) = f_in_i(x - c_i), periodic (Eq. 1's shift), copying the
  * raw storage words (a permutation: bit-exact for every storage kind).  Buffers must not
  * overlap. */
 int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* stream);
+
+/* Plain device-to-device copy of `bytes` (a multiple of 16) with one 16-byte word per
+ * thread and streaming stores: the practical HBM bandwidth reference that the step
+ * kernel's GB/s are compared with (no part of the method).  Buffers must not overlap. */
+int lbm_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Bytes of device workspace lbm_moments needs when it computes reductions. */
 int lbm_moments_workspace_size(const lbm_grid* grid, size_t* bytes);

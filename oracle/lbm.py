@@ -154,6 +154,16 @@ def bgk_collide(f: torch.Tensor, tau: float, st: Stencil, force: torch.Tensor | 
     return out
 
 
+def bgk_collide_shifted(f: torch.Tensor, tau: float, st: Stencil, du: torch.Tensor) -> torch.Tensor:
+    """BGK collision with the flow-control forcing of Sec. 3.2: the equilibrium is
+    expanded around the locally shifted velocity u + du, with u from Eq. 4:
+        f_i - (f_i - f_i^eq(rho, u + du)) / tau.
+    """
+    rho = density(f)
+    u = momentum(f, st) / rho
+    return f - (f - equilibrium(rho, u + du, st)) / tau
+
+
 def stream(f: torch.Tensor, st: Stencil) -> torch.Tensor:
     """Streaming (Eq. 1): the population moving with c_i travels from x to x + c_i,
     on a periodic grid.  out_i(x + c_i) = f_i(x), i.e. out_i(x) = f_i(x - c_i).
@@ -174,6 +184,11 @@ def step(g: torch.Tensor, tau: float, st: Stencil, force: torch.Tensor | None = 
     `step_literal` for Eq. 1 as printed and the test that ties the two together.
     """
     return bgk_collide(stream(g, st), tau, st, force)
+
+
+def step_shifted(g: torch.Tensor, tau: float, st: Stencil, du: torch.Tensor) -> torch.Tensor:
+    """Pull-convention step with the shifted-velocity equilibrium: C_du(S g)."""
+    return bgk_collide_shifted(stream(g, st), tau, st, du)
 
 
 def step_literal(f: torch.Tensor, tau: float, st: Stencil, force: torch.Tensor | None = None) -> torch.Tensor:

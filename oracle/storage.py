@@ -54,9 +54,12 @@ def dequantize(s: torch.Tensor, st: lbm.Stencil, kind: str) -> torch.Tensor:
 
 
 def step_emulated(s: torch.Tensor, tau: float, st: lbm.Stencil, kind: str,
-                  force: torch.Tensor | None = None) -> torch.Tensor:
-    """One pull step on stored populations: dequantise, exact FP64 step, quantise."""
-    return quantize(lbm.step(dequantize(s, st, kind), tau, st, force), st, kind)
+                  force: torch.Tensor | None = None, du: torch.Tensor | None = None) -> torch.Tensor:
+    """One pull step on stored populations: dequantise, exact FP64 step, quantise.
+    With `du` the step uses the shifted-velocity equilibrium instead of a force."""
+    f = dequantize(s, st, kind)
+    out = lbm.step_shifted(f, tau, st, du) if du is not None else lbm.step(f, tau, st, force)
+    return quantize(out, st, kind)
 
 
 def step_at_cells_emulated(s: torch.Tensor, tau: float, st: lbm.Stencil, kind: str, cells: torch.Tensor,

@@ -7,8 +7,10 @@ library's adjoint kernels instead:
   LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every) -> g_T
       forward: n_steps lbm_step calls, keeping a copy of the state every K steps;
       backward: for each K-step segment, last to first, replay the segment from
-      its checkpoint (keeping its K states), then run K lbm_adjoint_step calls
-      backwards; the force gradient accumulates in place in the kernels.
+      its checkpoint (keeping its K states), then run K adjoint steps backwards in
+      the collision-local form (lbm_adjoint_step_local, aligned stores only) and
+      finish with one lbm_adjoint_unstream; the force gradient accumulates in
+      place in the kernels.
       Memory: ceil(n/K) checkpoints + K segment states + 2 adjoint buffers.
       Forward and adjoint kernels are deterministic (no atomics), so the gradient
       is bitwise independent of K.
@@ -55,11 +57,16 @@ class LBMRollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, lam_T):
         grid, tau, n, K, F = ctx.grid, ctx.tau, ctx.n, ctx.K, ctx.force
-        lam = lam_T.detach().to(grid.real_dtype).contiguous().clone()
-        lam_out = torch.empty_like(lam)
+        # Adjoint in collision-local form: chi_t = J_C(h_t)^T lam_{t+1} with
+        # lam_{t+1} = S^T chi_{t+1}; every kernel store is aligned, and
+        # lam_0 = S^T chi_0 at the end (bitwise what the scatter form gives).
+        cur = lam_T.detach().to(grid.real_dtype).contiguous()
+        bufs = [torch.empty_like(cur), torch.empty_like(cur)]
+        is_chi = False
         dF = torch.zeros_like(F) if ctx.force_needs_grad else None
         n_seg = len(ctx.ckpts)
         states = [torch.empty_like(ctx.ckpts[0]) for _ in range(min(K, n))]
+        k = 0
         for seg in reversed(range(n_seg)):
             t0 = seg * K
             t1 = min(t0 + K, n)
@@ -67,10 +74,13 @@ class LBMRollout(torch.autograd.Function):
             for t in range(t0 + 1, t1):
                 B.lbm_step(grid, states[t - 1 - t0], states[t - t0], tau, F, 1)
             for t in reversed(range(t0, t1)):
-                B.lbm_adjoint_step(grid, states[t - t0], lam, lam_out, tau, F, dF)
-                lam, lam_out = lam_out, lam
+                out = bufs[k & 1]
+                B.lbm_adjoint_step_local(grid, states[t - t0], cur, is_chi, out, tau, F, dF)
+                cur, is_chi, k = out, True, k + 1
             ctx.ckpts[seg] = None  # release the checkpoint once its segment is done
-        return lam, dF, None, None, None, None
+        lam0 = bufs[k & 1]
+        B.lbm_adjoint_unstream(grid, cur, lam0)
+        return lam0, dF, None, None, None, None
 
 
 class LBMMoments(torch.autograd.Function):

@@ -54,11 +54,15 @@ def _load() -> ctypes.CDLL:
                                    ctypes.POINTER(dbl)]),
         "lbm_init_equilibrium": (i32, [gp, vp, vp, vp, vp]),
         "lbm_step": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
+        "lbm_step_shifted": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
         "lbm_stream_only": (i32, [gp, vp, vp, vp]),
         "lbm_moments_workspace_size": (i32, [gp, ctypes.POINTER(sz)]),
         "lbm_moments": (i32, [gp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lbm_adjoint_step": (i32, [gp, vp, vp, vp, dbl, vp, vp, vp]),
         "lbm_moments_adjoint": (i32, [gp, vp, vp, vp, vp, vp, vp, vp]),
+        "lbm_adjoint_step_local": (i32, [gp, vp, vp, i32, vp, dbl, vp, vp, vp]),
+        "lbm_adjoint_unstream": (i32, [gp, vp, vp, vp]),
+        "lbm_copy": (i32, [vp, vp, sz, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -208,12 +212,34 @@ def lbm_step(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: float,
     return _check(_lib.lbm_step(ctypes.byref(g), a, b, float(tau), F, int(n_steps), _stream(stream)), "lbm_step")
 
 
+def lbm_step_shifted(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: float, du: torch.Tensor,
+                     n_steps: int = 1, stream=None) -> int:
+    """n_steps steps with f^eq(rho, u + du); returns 0 (result in f_out) or 1 (in f_in)."""
+    N = grid.ncells
+    g = grid.c_struct()
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    d = _dev_ptr(du, "du", grid.real_dtype, grid.D * N)
+    return _check(_lib.lbm_step_shifted(ctypes.byref(g), a, b, float(tau), d, int(n_steps), _stream(stream)),
+                  "lbm_step_shifted")
+
+
 def lbm_stream_only(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, stream=None) -> None:
     N = grid.ncells
     g = grid.c_struct()
     a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
     b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
     _check(_lib.lbm_stream_only(ctypes.byref(g), a, b, _stream(stream)), "lbm_stream_only")
+
+
+def lbm_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """dst <- src byte for byte (same number of bytes, a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same size in bytes")
+    a = _dev_ptr(src, "src", src.dtype, src.numel())
+    b = _dev_ptr(dst, "dst", dst.dtype, dst.numel())
+    _check(_lib.lbm_copy(a, b, ctypes.c_size_t(nbytes), _stream(stream)), "lbm_copy")
 
 
 def lbm_moments_workspace_size(grid: Grid) -> int:
@@ -260,6 +286,31 @@ def lbm_adjoint_step(grid: Grid, g_t: torch.Tensor, lam_next: torch.Tensor, lam_
     F = _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False)
     dF = _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False)
     _check(_lib.lbm_adjoint_step(ctypes.byref(g), *args, float(tau), F, dF, _stream(stream)), "lbm_adjoint_step")
+
+
+def lbm_adjoint_step_local(grid: Grid, g_t: torch.Tensor, adj_next: torch.Tensor, adj_is_chi: bool,
+                           chi_out: torch.Tensor, tau: float, force: torch.Tensor | None = None,
+                           dforce: torch.Tensor | None = None, stream=None) -> None:
+    """chi_out <- J_C^T lam_{t+1} with lam_{t+1} = adj_next or S^T adj_next (adj_is_chi);
+    dforce += (dC/dF)^T lam_{t+1}."""
+    N = grid.ncells
+    g = grid.c_struct()
+    args = (_dev_ptr(g_t, "g_t", grid.word_dtype, grid.Q * N),
+            _dev_ptr(adj_next, "adj_next", grid.real_dtype, grid.Q * N))
+    out = _dev_ptr(chi_out, "chi_out", grid.real_dtype, grid.Q * N)
+    F = _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False)
+    dF = _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False)
+    _check(_lib.lbm_adjoint_step_local(ctypes.byref(g), *args, 1 if adj_is_chi else 0, out, float(tau), F, dF,
+                                       _stream(stream)), "lbm_adjoint_step_local")
+
+
+def lbm_adjoint_unstream(grid: Grid, chi: torch.Tensor, lam_out: torch.Tensor, stream=None) -> None:
+    """lam_out <- S^T chi."""
+    N = grid.ncells
+    g = grid.c_struct()
+    a = _dev_ptr(chi, "chi", grid.real_dtype, grid.Q * N)
+    b = _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.Q * N)
+    _check(_lib.lbm_adjoint_unstream(ctypes.byref(g), a, b, _stream(stream)), "lbm_adjoint_unstream")
 
 
 def lbm_moments_adjoint(grid: Grid, f: torch.Tensor, force: torch.Tensor | None,

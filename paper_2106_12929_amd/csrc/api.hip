@@ -172,28 +172,46 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init_equilibrium launch");
 }
 
-int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force, int n_steps,
-             void* stream) {
+}  // extern "C"
+
+namespace {
+
+int step_common(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* field, int force_mode,
+                int n_steps, void* stream, const char* name) {
   Geometry geo;
   LBM_TRY(check_grid(grid, &geo));
   LBM_TRY(check_tau(tau));
   if (n_steps < 1) return fail(LBM_EINVAL, "n_steps must be >= 1 (got %d)", n_steps);
   LBM_TRY(check_ptr(f_in, "f_in", true));
   LBM_TRY(check_ptr(f_out, "f_out", true));
-  LBM_TRY(check_ptr(force, "force", false));
+  LBM_TRY(check_ptr(field, force_mode == lbm::kShiftForce ? "du" : "force", force_mode == lbm::kShiftForce));
   const size_t N = geo.args.ncells;
-  const size_t fbytes = geo.Q * N * geo.word;
+  const size_t fbytes = geo.Q * N * geo.word, vbytes = geo.D * N * geo.real;
   if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
-  if (overlap(force, geo.D * N * geo.real, f_in, fbytes) || overlap(force, geo.D * N * geo.real, f_out, fbytes))
-    return fail(LBM_EALIAS, "force overlaps a population buffer");
+  if (overlap(field, vbytes, f_in, fbytes) || overlap(field, vbytes, f_out, fbytes))
+    return fail(LBM_EALIAS, "the per-cell field overlaps a population buffer");
   const double omega = 1.0 / tau;
   void* bufs[2] = {f_in, f_out};
   for (int k = 0; k < n_steps; ++k) {
-    const hipError_t e = lbm::launch_step(grid->lattice, grid->storage, bufs[k & 1], bufs[(k + 1) & 1], force,
-                                          geo.args, omega, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "lbm_step launch");
+    const hipError_t e = lbm::launch_step(grid->lattice, grid->storage, bufs[k & 1], bufs[(k + 1) & 1], field,
+                                          field ? force_mode : lbm::kNoForce, geo.args, omega, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, name);
   }
   return (n_steps & 1) ? 0 : 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force, int n_steps,
+             void* stream) {
+  return step_common(grid, f_in, f_out, tau, force, lbm::kGuoForce, n_steps, stream, "lbm_step launch");
+}
+
+int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* du, int n_steps,
+                     void* stream) {
+  return step_common(grid, f_in, f_out, tau, du, lbm::kShiftForce, n_steps, stream, "lbm_step_shifted launch");
 }
 
 int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* stream) {
@@ -205,6 +223,16 @@ int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* s
   if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
   const hipError_t e = lbm::launch_stream(grid->lattice, (int)geo.word, f_in, f_out, geo.args, (hipStream_t)stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_stream_only launch");
+}
+
+int lbm_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  LBM_TRY(check_ptr(src, "src", true));
+  LBM_TRY(check_ptr(dst, "dst", true));
+  if (bytes % 16 != 0) return fail(LBM_EINVAL, "bytes must be a multiple of 16 (got %zu)", bytes);
+  if (bytes / 16 > (size_t)0xFFFFFFFF * 256) return fail(LBM_ERANGE, "copy too large");
+  if (overlap(src, bytes, dst, bytes)) return fail(LBM_EALIAS, "src and dst overlap");
+  const hipError_t e = lbm::launch_copy16(src, dst, bytes / 16, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_copy launch");
 }
 
 int lbm_moments_workspace_size(const lbm_grid* grid, size_t* bytes) {
@@ -250,28 +278,62 @@ int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rh
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments launch");
 }
 
-int lbm_adjoint_step(const lbm_grid* grid, const void* g_t, const void* lam_next, void* lam_out, double tau,
-                     const void* force, void* dforce, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Shared validation of the three adjoint-step forms; `in_gathered` says whether adj_next
+// is read at shifted addresses (all forms read g_t shifted).
+int adjoint_common(const lbm_grid* grid, const void* g_t, const void* adj_next, void* adj_out, double tau,
+                   const void* force, void* dforce, int mode, void* stream, const char* name) {
   Geometry geo;
   LBM_TRY(check_grid(grid, &geo));
   LBM_TRY(check_tau(tau));
   LBM_TRY(check_ptr(g_t, "g_t", true));
-  LBM_TRY(check_ptr(lam_next, "lam_next", true));
-  LBM_TRY(check_ptr(lam_out, "lam_out", true));
+  LBM_TRY(check_ptr(adj_next, "adjoint input", true));
+  LBM_TRY(check_ptr(adj_out, "adjoint output", true));
   LBM_TRY(check_ptr(force, "force", false));
   LBM_TRY(check_ptr(dforce, "dforce", false));
   if (dforce && !force) return fail(LBM_EUNSUP, "dforce needs the force the step used");
   const size_t N = geo.args.ncells;
   const size_t gbytes = geo.Q * N * geo.word, lbytes = geo.Q * N * geo.real, fbytes = geo.D * N * geo.real;
-  if (overlap(lam_out, lbytes, g_t, gbytes) || overlap(lam_out, lbytes, lam_next, lbytes) ||
-      overlap(lam_out, lbytes, force, fbytes) || overlap(lam_out, lbytes, dforce, fbytes))
-    return fail(LBM_EALIAS, "lam_out overlaps another argument");
-  if (overlap(dforce, fbytes, g_t, gbytes) || overlap(dforce, fbytes, lam_next, lbytes) ||
+  if (overlap(adj_out, lbytes, g_t, gbytes) || overlap(adj_out, lbytes, adj_next, lbytes) ||
+      overlap(adj_out, lbytes, force, fbytes) || overlap(adj_out, lbytes, dforce, fbytes))
+    return fail(LBM_EALIAS, "the adjoint output overlaps another argument");
+  if (overlap(dforce, fbytes, g_t, gbytes) || overlap(dforce, fbytes, adj_next, lbytes) ||
       overlap(dforce, fbytes, force, fbytes))
     return fail(LBM_EALIAS, "dforce overlaps another argument");
-  const hipError_t e = lbm::launch_adjoint(grid->lattice, grid->storage, g_t, lam_next, lam_out, force, dforce,
+  const hipError_t e = lbm::launch_adjoint(grid->lattice, grid->storage, mode, g_t, adj_next, adj_out, force, dforce,
                                            geo.args, 1.0 / tau, (hipStream_t)stream);
-  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step launch");
+  return e == hipSuccess ? LBM_OK : hip_fail(e, name);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_adjoint_step(const lbm_grid* grid, const void* g_t, const void* lam_next, void* lam_out, double tau,
+                     const void* force, void* dforce, void* stream) {
+  return adjoint_common(grid, g_t, lam_next, lam_out, tau, force, dforce, lbm::kAdjScatter, stream,
+                        "lbm_adjoint_step launch");
+}
+
+int lbm_adjoint_step_local(const lbm_grid* grid, const void* g_t, const void* adj_next, int adj_is_chi,
+                           void* chi_out, double tau, const void* force, void* dforce, void* stream) {
+  if (adj_is_chi != 0 && adj_is_chi != 1) return fail(LBM_EINVAL, "adj_is_chi must be 0 or 1 (got %d)", adj_is_chi);
+  return adjoint_common(grid, g_t, adj_next, chi_out, tau, force, dforce,
+                        adj_is_chi ? lbm::kAdjLocalChi : lbm::kAdjLocalLam, stream, "lbm_adjoint_step_local launch");
+}
+
+int lbm_adjoint_unstream(const lbm_grid* grid, const void* chi, void* lam_out, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_ptr(chi, "chi", true));
+  LBM_TRY(check_ptr(lam_out, "lam_out", true));
+  const size_t lbytes = geo.Q * geo.args.ncells * geo.real;
+  if (overlap(chi, lbytes, lam_out, lbytes)) return fail(LBM_EALIAS, "chi and lam_out overlap");
+  const hipError_t e = lbm::launch_unstream(grid->lattice, (int)geo.real, chi, lam_out, geo.args, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_unstream launch");
 }
 
 int lbm_moments_adjoint(const lbm_grid* grid, const void* g, const void* force, const void* dL_drho,

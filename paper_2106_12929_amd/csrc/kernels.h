@@ -7,6 +7,8 @@
 namespace lbm {
 
 constexpr int kNred = 8;              // reduction results of lbm_moments
+enum AdjointMode { kAdjScatter = 0, kAdjLocalLam = 1, kAdjLocalChi = 2 };
+enum ForceMode { kNoForce = 0, kGuoForce = 1, kShiftForce = 2 };
 constexpr int kMaxReduceBlocks = 1024;  // fixed reduction grid (bitwise-reproducible sums)
 
 // Grid geometry passed by value to every cell-parallel kernel.
@@ -16,15 +18,18 @@ struct GridArgs {
   uint64_t ncells;   // nx * ny * nz (< 2^31)
 };
 
-hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, const GridArgs& g,
-                       double omega, hipStream_t s);
+hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
+                       const GridArgs& g, double omega, hipStream_t s);
 hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s);
 hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
                        hipStream_t s);
 hipError_t launch_moments(int lattice, int storage, const void* f, const void* force, void* rho, void* u,
                           double* partials, int nblocks, double* red, const GridArgs& g, hipStream_t s);
-hipError_t launch_adjoint(int lattice, int storage, const void* gt, const void* lam_next, void* lam_out,
+hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, const void* lam_next, void* lam_out,
                           const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s);
+hipError_t launch_unstream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g,
+                           hipStream_t s);
+hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s);
 hipError_t launch_moments_adjoint(int lattice, int storage, const void* f, const void* force, const void* drho,
                                   const void* du, void* lam_out, void* dforce, const GridArgs& g, hipStream_t s);
 

@@ -82,6 +82,12 @@ __device__ __forceinline__ uint64_t src_offset(const GridArgs& g, const Sources&
   return dir_row<LT::Q>(g, s.y[LT::cy(i) + 1], s.z[LT::cz(i) + 1], i) + s.x[LT::cx(i) + 1];
 }
 
+// Word offset of direction i at x + c_i: the transpose of the pull gather (S^T).
+template <typename LT>
+__device__ __forceinline__ uint64_t rev_offset(const GridArgs& g, const Sources& s, int i) {
+  return dir_row<LT::Q>(g, s.y[1 - LT::cy(i)], s.z[1 - LT::cz(i)], i) + s.x[1 - LT::cx(i)];
+}
+
 // Linear cell index of real-valued fields ([D][N] arrays).
 __device__ __forceinline__ uint32_t cell_index(const GridArgs& g, const Cell& c) {
   return (c.z * g.ny + c.y) * g.nx + c.x;
@@ -93,9 +99,13 @@ __device__ __forceinline__ void store_stream(T* p, T v) {
 }
 
 // ---------------------------------------------------------------------------------
-// Fused pull stream + BGK collide (+ Guo force).  Eq. 1-4.
+// Fused pull stream + BGK collide.  Eq. 1-4.  FM selects the per-cell field `force`:
+//   kNoForce     none
+//   kGuoForce    body force F (Guo: u = (sum c h + F/2)/rho in f^eq, plus the source)
+//   kShiftForce  velocity shift du: f^eq(rho, u + du) with u = sum c h / rho (the
+//                flow-control forcing of Sec. 3.2)
 // ---------------------------------------------------------------------------------
-template <int L, int S, bool FORCED>
+template <int L, int S, int FM>
 __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::word* __restrict__ fin,
                                                    typename Storage<S>::word* __restrict__ fout,
                                                    const typename Storage<S>::real* __restrict__ force,
@@ -128,18 +138,26 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
     if (LT::cz(i) > 0) jz += d[i];
     if (LT::cz(i) < 0) jz -= d[i];
   }
+  constexpr bool FORCED = FM == kGuoForce;
   real Fx = 0, Fy = 0, Fz = 0;
-  if constexpr (FORCED) {
+  if constexpr (FM != kNoForce) {
     Fx = force[self];
     Fy = force[N + self];
     if constexpr (LT::D == 3) Fz = force[2 * N + self];
+  }
+  if constexpr (FORCED) {
     jx += real(0.5) * Fx;
     jy += real(0.5) * Fy;
     jz += real(0.5) * Fz;
   }
   const real rho = real(1) + drho;
   const real inv_rho = real(1) / rho;
-  const real ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+  real ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+  if constexpr (FM == kShiftForce) {
+    ux += Fx;
+    uy += Fy;
+    uz += Fz;
+  }
   const real usq = real(1.5) * (ux * ux + uy * uy + uz * uz);
   const real uF = ux * Fx + uy * Fy + uz * Fz;
   const real guo = real(1) - real(0.5) * omega;
@@ -182,6 +200,17 @@ __global__ __launch_bounds__(256) void stream_kernel(const W* __restrict__ fin, 
   const Sources src = sources(c, g);
 #pragma unroll
   for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[src_offset<LT>(g, src, i)];
+}
+
+// The transpose of streaming, on real words: out_i(x) = in_i(x + c_i).
+template <int L, typename W>
+__global__ __launch_bounds__(256) void unstream_kernel(const W* __restrict__ fin, W* __restrict__ fout, GridArgs g) {
+  using LT = Lattice<L>;
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
+  const Sources src = sources(c, g);
+#pragma unroll
+  for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[rev_offset<LT>(g, src, i)];
 }
 
 // ---------------------------------------------------------------------------------
@@ -354,8 +383,15 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
 //   dF_a = (1 - omega/2)(mA_a - 3 u_a mW + 2 (mB u)_a) + V_a / (2 rho)
 // and lam_t,j(x - c_j) = mu_j(x): the transpose of the pull gather is a scatter to the
 // same addresses, each written exactly once (no atomics).
+//
+// MODE selects where lam' comes from and where mu goes:
+//   kAdjScatter:    lam' = lam_next(x) (aligned);  lam_t,j(x - c_j) = mu_j (scattered)
+//   kAdjLocalLam:   lam' = lam_next(x) (aligned);  chi_t(x) = mu (aligned)
+//   kAdjLocalChi:   lam'_i = chi_next_i(x + c_i)  (gathered: lam_{t+1} = S^T chi_{t+1});
+//                   chi_t(x) = mu (aligned)
+// In the local ("chi") form every store is aligned; lam_t = S^T chi_t.
 // ---------------------------------------------------------------------------------
-template <int L, int S, bool FORCED>
+template <int L, int S, bool FORCED, int MODE>
 __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>::word* __restrict__ gt,
                                                       const typename Storage<S>::real* __restrict__ lam_next,
                                                       typename Storage<S>::real* __restrict__ lam_out,
@@ -399,7 +435,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   real mW = 0, mAx = 0, mAy = 0, mAz = 0, bxx = 0, byy = 0, bzz = 0, bxy = 0, bxz = 0, byz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    lam[i] = lam_next[dir_row<Q>(g, c.y, c.z, i) + c.x];
+    lam[i] = MODE == kAdjLocalChi ? lam_next[rev_offset<LT>(g, src, i)] : lam_next[dir_row<Q>(g, c.y, c.z, i) + c.x];
     const real l = lam[i];
     const real cx = LT::cx(i), cy = LT::cy(i), cz = LT::cz(i);
     const real al = CO::A(i) * l, bl = CO::B(i) * l;
@@ -444,7 +480,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
     if (LT::cy(j) < 0) mu -= vy;
     if (LT::cz(j) > 0) mu += vz;
     if (LT::cz(j) < 0) mu -= vz;
-    lam_out[src_offset<LT>(g, src, j)] = mu;
+    lam_out[MODE == kAdjScatter ? src_offset<LT>(g, src, j) : dir_row<Q>(g, c.y, c.z, j) + c.x] = mu;
   }
   if constexpr (FORCED) {
     if (dforce) {
@@ -511,31 +547,46 @@ static dim3 cell_grid(const GridArgs& g) {
 }
 
 template <int L, int S>
-static hipError_t launch_step_ls(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
-                                 hipStream_t s) {
+static hipError_t launch_step_ls(const void* fin, void* fout, const void* force, int force_mode, const GridArgs& g,
+                                 double omega, hipStream_t s) {
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using R = typename ST::real;
+  if (!force || force_mode == kNoForce)
+    step_kernel<L, S, kNoForce><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, nullptr, g, (R)omega);
+  else if (force_mode == kGuoForce)
+    step_kernel<L, S, kGuoForce><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, (R)omega);
+  else if (force_mode == kShiftForce)
+    step_kernel<L, S, kShiftForce><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, (R)omega);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int L, int S, int MODE>
+static hipError_t launch_adjoint_lsm(const void* gt, const void* lam_next, void* lam_out, const void* force,
+                                     void* dforce, const GridArgs& g, double omega, hipStream_t s) {
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
   if (force)
-    step_kernel<L, S, true><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, (R)omega);
+    adjoint_kernel<L, S, true, MODE><<<cell_grid(g), 256, 0, s>>>((const W*)gt, (const R*)lam_next, (R*)lam_out,
+                                                                   (const R*)force, (R*)dforce, g, (R)omega);
   else
-    step_kernel<L, S, false><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, nullptr, g, (R)omega);
+    adjoint_kernel<L, S, false, MODE><<<cell_grid(g), 256, 0, s>>>((const W*)gt, (const R*)lam_next, (R*)lam_out,
+                                                                    nullptr, nullptr, g, (R)omega);
   return hipGetLastError();
 }
 
 template <int L, int S>
-static hipError_t launch_adjoint_ls(const void* gt, const void* lam_next, void* lam_out, const void* force,
+static hipError_t launch_adjoint_ls(int mode, const void* gt, const void* lam_next, void* lam_out, const void* force,
                                     void* dforce, const GridArgs& g, double omega, hipStream_t s) {
-  using ST = Storage<S>;
-  using W = typename ST::word;
-  using R = typename ST::real;
-  if (force)
-    adjoint_kernel<L, S, true><<<cell_grid(g), 256, 0, s>>>((const W*)gt, (const R*)lam_next, (R*)lam_out,
-                                                             (const R*)force, (R*)dforce, g, (R)omega);
-  else
-    adjoint_kernel<L, S, false><<<cell_grid(g), 256, 0, s>>>((const W*)gt, (const R*)lam_next, (R*)lam_out,
-                                                              nullptr, nullptr, g, (R)omega);
-  return hipGetLastError();
+  switch (mode) {
+    case kAdjScatter: return launch_adjoint_lsm<L, S, kAdjScatter>(gt, lam_next, lam_out, force, dforce, g, omega, s);
+    case kAdjLocalLam: return launch_adjoint_lsm<L, S, kAdjLocalLam>(gt, lam_next, lam_out, force, dforce, g, omega, s);
+    case kAdjLocalChi: return launch_adjoint_lsm<L, S, kAdjLocalChi>(gt, lam_next, lam_out, force, dforce, g, omega, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int L, int S>
@@ -588,14 +639,14 @@ static hipError_t launch_moments_adjoint_ls(const void* f, const void* force, co
     return hipErrorInvalidValue;                                                 \
   } while (0)
 
-hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, const GridArgs& g,
-                       double omega, hipStream_t s) {
-  LBM_DISPATCH(launch_step_ls, lattice, storage, fin, fout, force, g, omega, s);
+hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
+                       const GridArgs& g, double omega, hipStream_t s) {
+  LBM_DISPATCH(launch_step_ls, lattice, storage, fin, fout, force, force_mode, g, omega, s);
 }
 
-hipError_t launch_adjoint(int lattice, int storage, const void* gt, const void* lam_next, void* lam_out,
+hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, const void* lam_next, void* lam_out,
                           const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s) {
-  LBM_DISPATCH(launch_adjoint_ls, lattice, storage, gt, lam_next, lam_out, force, dforce, g, omega, s);
+  LBM_DISPATCH(launch_adjoint_ls, lattice, storage, mode, gt, lam_next, lam_out, force, dforce, g, omega, s);
 }
 
 hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
@@ -629,6 +680,41 @@ hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fou
     case kD2Q9: return launch_stream_l<kD2Q9>(word_bytes, fin, fout, g, s);
     case kD3Q19: return launch_stream_l<kD3Q19>(word_bytes, fin, fout, g, s);
     case kD3Q27: return launch_stream_l<kD3Q27>(word_bytes, fin, fout, g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Plain streaming copy (16-byte words, one per thread): the practical HBM bandwidth
+// reference the step kernel is compared with.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void copy16_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(src[i], &dst[i]);
+}
+
+hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s) {
+  if (n16 == 0) return hipSuccess;
+  copy16_kernel<<<(unsigned)((n16 + 255) / 256), 256, 0, s>>>((const u32x4*)src, (u32x4*)dst, n16);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_unstream_l(int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s) {
+  switch (word_bytes) {
+    case 4: unstream_kernel<L, uint32_t><<<cell_grid(g), 256, 0, s>>>((const uint32_t*)fin, (uint32_t*)fout, g); break;
+    case 8: unstream_kernel<L, uint64_t><<<cell_grid(g), 256, 0, s>>>((const uint64_t*)fin, (uint64_t*)fout, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_unstream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g,
+                           hipStream_t s) {
+  switch (lattice) {
+    case kD2Q9: return launch_unstream_l<kD2Q9>(word_bytes, fin, fout, g, s);
+    case kD3Q19: return launch_unstream_l<kD3Q19>(word_bytes, fin, fout, g, s);
+    case kD3Q27: return launch_unstream_l<kD3Q27>(word_bytes, fin, fout, g, s);
   }
   return hipErrorInvalidValue;
 }

@@ -6,30 +6,46 @@ Sec. 3.2 without formulas; this is the standard reading): u_hat = FFT(u)/N over
 the periodic box, E(K) = sum of 1/2 |u_hat(k)|^2 over integer wavevectors with
 K - 1/2 <= |k| < K + 1/2; the loss sums (ln max(E, c) - ln max(E_target, c))^2 over
 a band of shells.  Sums are taken in FP64.
+
+The shell sums are segmented reductions over the wavevectors sorted by shell (a
+permutation computed once per grid): no atomics, so the result is deterministic and
+does not serialise on the few shell bins the way a scatter-add does.
 """
 from __future__ import annotations
 
 import math
+from dataclasses import dataclass
 
 import torch
 
 
-def shell_index(spatial, device) -> torch.Tensor:
+@dataclass(frozen=True)
+class Shells:
+    """Wavevectors of a periodic grid grouped by shell K = floor(|k| + 1/2)."""
+
+    spatial: tuple
+    order: torch.Tensor    # flat wavevector indices sorted by shell
+    lengths: torch.Tensor  # wavevectors per shell, K = 0 .. K_max
+
+
+def shell_index(spatial, device) -> Shells:
     ks = [torch.fft.fftfreq(n, d=1.0 / n, device=device, dtype=torch.float64) for n in spatial]
     grids = torch.meshgrid(*ks, indexing="ij")
     kmag = torch.sqrt(sum(g * g for g in grids))
-    return torch.floor(kmag + 0.5).to(torch.int64)
+    shell = torch.floor(kmag + 0.5).to(torch.int64).reshape(-1)
+    order = torch.argsort(shell, stable=True)
+    lengths = torch.bincount(shell)
+    return Shells(tuple(spatial), order, lengths)
 
 
-def energy_spectrum(u: torch.Tensor, shells: torch.Tensor | None = None) -> torch.Tensor:
+def energy_spectrum(u: torch.Tensor, shells: Shells | None = None) -> torch.Tensor:
     """E(K), K = 0..K_max, of u[a, *spatial] (promoted to FP64)."""
     spatial = tuple(u.shape[1:])
     if shells is None:
         shells = shell_index(spatial, u.device)
     uh = torch.fft.fftn(u.to(torch.float64), dim=tuple(range(1, u.dim()))) / math.prod(spatial)
     dens = 0.5 * (uh.real.square() + uh.imag.square()).sum(dim=0)
-    E = torch.zeros(int(shells.max()) + 1, dtype=torch.float64, device=u.device)
-    return E.index_add(0, shells.reshape(-1), dens.reshape(-1))
+    return torch.segment_reduce(dens.reshape(-1)[shells.order], "sum", lengths=shells.lengths, unsafe=True)
 
 
 def log_spectrum_loss(E: torch.Tensor, E_target: torch.Tensor, k_lo: int, k_hi: int, cutoff: float) -> torch.Tensor:

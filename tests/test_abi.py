@@ -119,6 +119,36 @@ def test_other_entry_points_validate(B):
     assert lib.lbm_moments_adjoint(gp, P1, None, None, None, None, None, None) == -2
 
 
+def test_shifted_step_validation(B):
+    lib = B._lib
+    g = _grid(B)
+    gp = ctypes.byref(g)
+    assert lib.lbm_step_shifted(gp, P1, P2, 0.6, None, 1, None) == -2   # du is required
+    assert lib.lbm_step_shifted(gp, P1, P2, 0.6, P1, 1, None) == -4     # du overlaps f_in
+    assert lib.lbm_step_shifted(gp, P1, P2, 0.5, P3, 1, None) == -1
+    assert lib.lbm_step_shifted(gp, P1, P2, 0.6, P3, 0, None) == -1
+
+
+def test_local_adjoint_validation(B):
+    lib = B._lib
+    g = _grid(B)
+    gp = ctypes.byref(g)
+    assert lib.lbm_adjoint_step_local(gp, P1, P2, 2, P3, 0.6, None, None, None) == -1   # adj_is_chi not 0/1
+    assert lib.lbm_adjoint_step_local(gp, P1, P2, 1, P2, 0.6, None, None, None) == -4   # output == input
+    assert lib.lbm_adjoint_step_local(gp, P1, P2, 0, None, 0.6, None, None, None) == -2
+    assert lib.lbm_adjoint_step_local(gp, P1, P2, 0, P3, 0.5, None, None, None) == -1
+    assert lib.lbm_adjoint_unstream(gp, P1, P1, None) == -4
+    assert lib.lbm_adjoint_unstream(gp, None, P1, None) == -2
+
+
+def test_copy_validation(B):
+    lib = B._lib
+    assert lib.lbm_copy(P1, P2, 17, None) == -1      # not a multiple of 16
+    assert lib.lbm_copy(P1, ctypes.c_void_p(0x10000 + 32), 64, None) == -4
+    assert lib.lbm_copy(None, P2, 16, None) == -2
+    assert lib.lbm_copy(MIS, P2, 16, None) == -3
+
+
 def test_strerror(B):
     for code in range(-7, 1):
         assert B._lib.lbm_strerror(code)

@@ -222,3 +222,41 @@ def test_checkpoint_invariance_bitwise():
         grads.append(F.grad.clone())
     for g in grads[1:]:
         assert torch.equal(g, grads[0])
+
+
+@pytest.mark.parametrize("lat,shape", CASES)
+@pytest.mark.parametrize("kind", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("forced", [False, True])
+def test_local_form_chain_matches_scatter_form_bitwise(lat, shape, kind, forced):
+    """Five adjoint steps in the collision-local form followed by one unstream give
+    the same words as five scatter-form steps (the same arithmetic, stored at other
+    addresses), and the same force gradient."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    spatial = _spatial(lat, shape)
+    grid = B.Grid(lat, kind, *shape)
+    tau = 0.53
+    say(f"local-form chain {lat} {kind} {shape} forced={forced}")
+    states = [grid.to_layout(ost.quantize(_state(st, spatial, 100 + k), st, kind)).cuda() for k in range(5)]
+    F = synthetic.random_normal((st.D,) + spatial, 120, 1e-4).to(grid.real_dtype).cuda() if forced else None
+    lamT = grid.to_layout(synthetic.random_normal((st.Q,) + spatial, 121).to(grid.real_dtype)).cuda()
+    # scatter form
+    lam = lamT.clone()
+    out = torch.empty_like(lam)
+    dF1 = torch.zeros_like(F) if forced else None
+    for t in reversed(range(5)):
+        B.lbm_adjoint_step(grid, states[t], lam, out, tau, F, dF1)
+        lam, out = out, lam
+    # local form
+    bufs = [torch.empty_like(lamT), torch.empty_like(lamT)]
+    cur, is_chi = lamT.clone(), False
+    dF2 = torch.zeros_like(F) if forced else None
+    for k, t in enumerate(reversed(range(5))):
+        B.lbm_adjoint_step_local(grid, states[t], cur, is_chi, bufs[k & 1], tau, F, dF2)
+        cur, is_chi = bufs[k & 1], True
+    lam2 = torch.empty_like(lamT)
+    B.lbm_adjoint_unstream(grid, cur, lam2)
+    assert torch.equal(lam, lam2)
+    if forced:
+        assert torch.equal(dF1, dF2)

@@ -168,6 +168,28 @@ def test_one_step_parity(lat, shape, kind, forced):
     assert excess <= 0, ratio
 
 
+@pytest.mark.parametrize("lat,shape", CASES)
+@pytest.mark.parametrize("kind", KINDS)
+def test_shifted_step_parity(lat, shape, kind):
+    """lbm_step_shifted (equilibrium at u + du, the flow-control forcing) against the
+    oracle's shifted step."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    grid = _grid(B, lat, kind, shape)
+    spatial = _spatial(lat, shape)
+    tau = 0.57
+    say(f"shifted step {lat} {kind} {shape}")
+    s = _state(st, spatial, 14, kind)
+    du = synthetic.random_normal((grid.D,) + spatial, 15, 1e-3).to(grid.real_dtype)
+    out = grid.empty_populations()
+    assert B.lbm_step_shifted(grid, grid.to_layout(s).cuda(), out, tau, du.cuda(), 1) == 0
+    ref = ost.step_emulated(s, tau, st, kind, du=du.double())
+    excess, ratio, same = _tolerance_ok(kind, st, grid.from_layout(out.cpu()), ref, tau)
+    say(f"  max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
+    assert excess <= 0, ratio
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_rest_state_bit_exact(kind):
     need_gpu()

@@ -1,5 +1,6 @@
-"""Pins of the oracle's Guo-forced step (textbook; used by the forced adjoint
-workloads).
+"""Pins of the oracle's forced steps: the Guo body force (textbook; used by the
+forced adjoint workloads) and the shifted-velocity equilibrium of the paper's flow
+control (Sec. 3.2).
 
 * Uniform body force: the physical momentum grows by exactly sum_x F per step.
 * Kolmogorov flow F_x = F0 sin(k y): the steady state u_x = F0 sin(k y)/(rho nu k^2)
@@ -65,3 +66,21 @@ def test_forced_state_moments_match_literal_eq1():
         torch.testing.assert_close(u_g, lbm.velocity(f, st, F), rtol=0, atol=1e-15)
         f = lbm.step_literal(f, tau, st, F)
         g = lbm.step(g, tau, st, F)
+
+
+def test_shifted_equilibrium_momentum_gain():
+    # f^eq(rho, u + du) has first moment rho (u + du) (Eq. 3's moments), so one
+    # collision adds exactly rho du / tau of momentum and keeps the mass; du = 0 is
+    # the plain BGK collision.
+    for name, spatial in (("D2Q9", (6, 7)), ("D3Q19", (3, 4, 5)), ("D3Q27", (4, 3, 5))):
+        st = lbm.stencil(name)
+        rho, u = synthetic.random_fields(spatial, st.D, 34, drho=0.03, umax=0.05)
+        f = lbm.equilibrium(rho, u, st) * (1 + synthetic.random_normal((st.Q,) + spatial, 35, 0.02))
+        du = synthetic.random_normal((st.D,) + spatial, 36, 1e-3)
+        tau = 0.58
+        out = lbm.bgk_collide_shifted(f, tau, st, du)
+        torch.testing.assert_close(lbm.density(out), lbm.density(f), rtol=1e-14, atol=0)
+        gain = lbm.momentum(out, st) - lbm.momentum(f, st)
+        torch.testing.assert_close(gain, lbm.density(f) * du / tau, rtol=0, atol=4e-16)  # FP64 roundoff
+        zero = torch.zeros_like(du)
+        torch.testing.assert_close(lbm.step_shifted(f, tau, st, zero), lbm.step(f, tau, st), rtol=0, atol=1e-16)
