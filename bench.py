@@ -204,7 +204,9 @@ def run_workloads():
     torch.cuda.empty_cache()
     log("[bench] flow control 128^2 (D2Q9)")
     u = isotropic_turbulence(128, 4.0, 0.04, seed=0, dim=2, device="cuda")
-    out["flow_control_128_2d"] = WL.flow_control_2d(u, 0.5018, 4000)
+    # the paper's kappa = 5e-5 belongs to its own spectrum normalisation; with this
+    # library's (u_hat = FFT/N) a larger kappa is needed for the same hold: sweep.
+    out["flow_control_128_2d"] = [WL.flow_control_2d(u, 0.5018, 4000, kappa=k) for k in (5e-5, 5e-4, 5e-3)]
     del u
     log("[bench] full-scale adjoint 512^3")
     u = isotropic_turbulence(512, 4.0, 0.05, seed=0, device="cuda")
@@ -215,7 +217,7 @@ def run_workloads():
     for tau in (0.505, 0.51, 0.52):
         res = WL.full_scale_adjoint(u, tau, forward_steps=500, adjoint_steps=50, checkpoint_every=10)
         if "diverged_before_step" in res:
-            res["f64_check"] = WL.precision_study(u, tau, 450, storages=("f64",), check_every=50)["runs"]["f64"]
+            res["f64_check"] = WL.precision_study(u, tau, 500, storages=("f64",), check_every=50)["runs"]["f64"]
         out["adjoint_512"].append(res)
         if "diverged_before_step" not in res:
             break

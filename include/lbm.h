@@ -139,6 +139,20 @@ int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const vo
 int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* du,
                      int n_steps, void* stream);
 
+/* D2Q9 steps with the multiple-relaxation-time collision of Sec. 3.1 (Eq. 5),
+ * Omega(f) = -M^{-1} S^{-1} (M f - m^eq), m^eq = M f^eq, in the Dellar moment basis
+ * m = (rho, rho u, rho v, Pi_xx, Pi_xy, Pi_yy, N, J_x, J_y).
+ * tau_moments: host array of 9 relaxation times S = diag(tau_0 .. tau_8); tau_0..2
+ *   (conserved moments) are ignored, tau_3..8 must be finite and > 1/2.  The shear
+ *   times tau_3..5 set nu = (tau - 1/2)/3; all nine equal give BGK.
+ * tau_ghost: NULL, or 3*N reals giving per-cell tau_6, tau_7, tau_8 (N, J_x, J_y) in
+ *   place of the uniform ones (the outputs of the paper's neural collision model);
+ *   every value must be > 1/2 (not checked on the device).
+ * Same ping-pong, return value and buffer rules as lbm_step.  LBM_EUNSUP for lattices
+ * other than D2Q9. */
+int lbm_step_mrt(const lbm_grid* grid, void* f_in, void* f_out, const double* tau_moments,
+                 const void* tau_ghost, int n_steps, void* stream);
+
 /* Streaming only: f_out_i(x) = f_in_i(x - c_i), periodic (Eq. 1's shift), copying the
  * raw storage words (a permutation: bit-exact for every storage kind).  Buffers must not
  * overlap. */

@@ -256,3 +256,47 @@ def step_at_cells(g: torch.Tensor, tau: float, st: Stencil, cells: torch.Tensor,
     h = gather_at_cells(g, st, cells)
     F = None if force is None else force_at_cells(force, st, cells)
     return bgk_collide(h, tau, st, F)
+
+
+# --------------------------------------------------------------------------------------
+# Multiple-relaxation-time collision (Sec. 3.1, Eq. 5), D2Q9, Dellar moment basis
+# --------------------------------------------------------------------------------------
+
+def dellar_matrix(st: Stencil) -> torch.Tensor:
+    """Moment matrix M of the D2Q9 basis m = M f = (rho, rho u, rho v, Pi_xx, Pi_xy,
+    Pi_yy, N, J_x, J_y) (Sec. 3.1, following Dellar 2003).
+
+    Rows: 1, c_x, c_y, c_x^2, c_x c_y, c_y^2, g, g c_x, g c_y with the non-hydrodynamic
+    weight g = (3 c_x^2 - 1)(3 c_y^2 - 1), i.e. g = 1, -2, 4 on the rest, axis and
+    diagonal velocities (Dellar's N and J moments).
+    """
+    if st.name != "D2Q9":
+        raise ValueError("the Dellar basis is defined for D2Q9")
+    cx = st.c[:, 0].to(F64)
+    cy = st.c[:, 1].to(F64)
+    g = (3.0 * cx * cx - 1.0) * (3.0 * cy * cy - 1.0)
+    return torch.stack([torch.ones_like(cx), cx, cy, cx * cx, cx * cy, cy * cy, g, g * cx, g * cy])
+
+
+def mrt_collide(f: torch.Tensor, taus, st: Stencil) -> torch.Tensor:
+    """Eq. 5: f + Omega with Omega = -M^{-1} S^{-1} (M f - m^eq), m^eq = M f^eq(rho, u),
+    S = diag(tau_0 .. tau_8).
+
+    taus: 9 relaxation times (numbers or tensors broadcastable to the spatial shape;
+    per-cell values for tau_6..8 model the neural collision's outputs).  The conserved
+    moments (0..2) have m = m^eq, so their tau has no effect.
+    """
+    M = dellar_matrix(st)
+    Minv = torch.linalg.inv(M)
+    rho = density(f)
+    u = momentum(f, st) / rho
+    feq = equilibrium(rho, u, st)
+    m = torch.einsum("kq,q...->k...", M, f)
+    meq = torch.einsum("kq,q...->k...", M, feq)
+    rel = torch.stack([(m[k] - meq[k]) / taus[k] for k in range(st.Q)])
+    return f - torch.einsum("qk,k...->q...", Minv, rel)
+
+
+def step_mrt(g: torch.Tensor, taus, st: Stencil) -> torch.Tensor:
+    """Pull-convention step with the MRT collision: C_MRT(S g)."""
+    return mrt_collide(stream(g, st), taus, st)

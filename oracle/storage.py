@@ -54,11 +54,18 @@ def dequantize(s: torch.Tensor, st: lbm.Stencil, kind: str) -> torch.Tensor:
 
 
 def step_emulated(s: torch.Tensor, tau: float, st: lbm.Stencil, kind: str,
-                  force: torch.Tensor | None = None, du: torch.Tensor | None = None) -> torch.Tensor:
+                  force: torch.Tensor | None = None, du: torch.Tensor | None = None,
+                  mrt_taus=None) -> torch.Tensor:
     """One pull step on stored populations: dequantise, exact FP64 step, quantise.
-    With `du` the step uses the shifted-velocity equilibrium instead of a force."""
+    With `du` the step uses the shifted-velocity equilibrium instead of a force; with
+    `mrt_taus` (9 relaxation times) the MRT collision of Eq. 5."""
     f = dequantize(s, st, kind)
-    out = lbm.step_shifted(f, tau, st, du) if du is not None else lbm.step(f, tau, st, force)
+    if mrt_taus is not None:
+        out = lbm.step_mrt(f, mrt_taus, st)
+    elif du is not None:
+        out = lbm.step_shifted(f, tau, st, du)
+    else:
+        out = lbm.step(f, tau, st, force)
     return quantize(out, st, kind)
 
 

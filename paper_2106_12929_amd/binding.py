@@ -55,6 +55,7 @@ def _load() -> ctypes.CDLL:
         "lbm_init_equilibrium": (i32, [gp, vp, vp, vp, vp]),
         "lbm_step": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
         "lbm_step_shifted": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
+        "lbm_step_mrt": (i32, [gp, vp, vp, ctypes.POINTER(dbl), vp, i32, vp]),
         "lbm_stream_only": (i32, [gp, vp, vp, vp]),
         "lbm_moments_workspace_size": (i32, [gp, ctypes.POINTER(sz)]),
         "lbm_moments": (i32, [gp, vp, vp, vp, vp, vp, vp, sz, vp]),
@@ -222,6 +223,19 @@ def lbm_step_shifted(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: f
     d = _dev_ptr(du, "du", grid.real_dtype, grid.D * N)
     return _check(_lib.lbm_step_shifted(ctypes.byref(g), a, b, float(tau), d, int(n_steps), _stream(stream)),
                   "lbm_step_shifted")
+
+
+def lbm_step_mrt(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, taus, tau_ghost: torch.Tensor | None = None,
+                 n_steps: int = 1, stream=None) -> int:
+    """D2Q9 MRT steps (Dellar basis); taus: 9 relaxation times; tau_ghost: optional
+    [3, ny, nx] per-cell tau_6..8.  Returns 0 (result in f_out) or 1 (in f_in)."""
+    N = grid.ncells
+    g = grid.c_struct()
+    t = (ctypes.c_double * 9)(*[float(v) for v in taus])
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    tg = _dev_ptr(tau_ghost, "tau_ghost", grid.real_dtype, 3 * N, required=False)
+    return _check(_lib.lbm_step_mrt(ctypes.byref(g), a, b, t, tg, int(n_steps), _stream(stream)), "lbm_step_mrt")
 
 
 def lbm_stream_only(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, stream=None) -> None:

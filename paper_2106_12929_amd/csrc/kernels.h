@@ -29,6 +29,9 @@ hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, co
                           const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s);
 hipError_t launch_unstream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g,
                            hipStream_t s);
+// scales[k] = 1 / (tau_{k+3} |R_{k+3}|^2), k = 0..5 (see mrt_step_kernel)
+hipError_t launch_mrt(int storage, const void* fin, void* fout, const void* tau_ghost, const GridArgs& g,
+                      const double* scales, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s);
 hipError_t launch_moments_adjoint(int lattice, int storage, const void* f, const void* force, const void* drho,
                                   const void* du, void* lam_out, void* dforce, const GridArgs& g, hipStream_t s);

@@ -190,6 +190,90 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
 }
 
 // ---------------------------------------------------------------------------------
+// D2Q9 multiple-relaxation-time step (Sec. 3.1, Eq. 5) in the Dellar basis.
+//
+// The basis {1, c_x, c_y, c_x^2, c_x c_y, c_y^2, g, g c_x, g c_y}, g = (3c_x^2-1)(3c_y^2-1),
+// spans the same moment subspaces as the w-orthogonal set
+//   R = {1, c_x, c_y, 3c_x^2-1, c_x c_y, 3c_y^2-1, g, g c_x, g c_y}
+// (the second-order rows differ from Dellar's only by multiples of the conserved rho),
+// so Eq. 5's operator -M^{-1} S^{-1} (M f - m^eq) acting on f - f^eq (zero conserved
+// part) is  f'_i = h_i - w_i sum_{k=3..8} R_k(c_i) n_k / (tau_k |R_k|^2),
+// n_k = sum_i R_k(c_i) (h_i - f^eq_i),  |R_k|^2 = sum_i w_i R_k(c_i)^2 = 2, 1/9, 2, 4,
+// 8/3, 8/3.  scale[k-3] = 1/(tau_k |R_k|^2) for uniform times; a per-cell field
+// tau_ghost[3][N] replaces tau_6..8 (the neural collision's outputs).
+// ---------------------------------------------------------------------------------
+struct MrtScales {
+  double s[6];
+};
+
+template <int S, bool CELL_GHOST>
+__global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>::word* __restrict__ fin,
+                                                       typename Storage<S>::word* __restrict__ fout,
+                                                       const typename Storage<S>::real* __restrict__ tau_ghost,
+                                                       GridArgs g, MrtScales sc) {
+  using LT = Lattice<kD2Q9>;
+  using ST = Storage<S>;
+  using real = typename ST::real;
+  using CO = Coef<kD2Q9, real>;
+  constexpr int Q = 9;
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
+  const Sources src = sources(c, g);
+  const size_t N = g.ncells;
+
+  real d[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(fin[src_offset<LT>(g, src, i)], CO::W(i));
+  real drho = 0, jx = 0, jy = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += d[i];
+    jx += real(LT::cx(i)) * d[i];
+    jy += real(LT::cy(i)) * d[i];
+  }
+  const real rho = real(1) + drho;
+  const real inv_rho = real(1) / rho;
+  const real ux = jx * inv_rho, uy = jy * inv_rho;
+  const real usq = real(1.5) * (ux * ux + uy * uy);
+
+  // non-equilibrium part and its six non-conserved moments
+  real ne[Q];
+  real nxx = 0, nxy = 0, nyy = 0, nN = 0, nJx = 0, nJy = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const real cu = real(LT::cx(i)) * ux + real(LT::cy(i)) * uy;
+    const real deq = CO::W(i) * drho + rho * (CO::A(i) * cu + CO::B(i) * cu * cu - CO::W(i) * usq);
+    ne[i] = d[i] - deq;
+    const int cx = LT::cx(i), cy = LT::cy(i);
+    const real gi = real((3 * cx * cx - 1) * (3 * cy * cy - 1));
+    nxx += real(3 * cx * cx - 1) * ne[i];
+    nxy += real(cx * cy) * ne[i];
+    nyy += real(3 * cy * cy - 1) * ne[i];
+    nN += gi * ne[i];
+    nJx += gi * real(cx) * ne[i];
+    nJy += gi * real(cy) * ne[i];
+  }
+  real s6 = real(sc.s[3]), s7 = real(sc.s[4]), s8 = real(sc.s[5]);
+  if constexpr (CELL_GHOST) {
+    const uint32_t n = cell_index(g, c);
+    s6 = real(1) / (real(4) * tau_ghost[n]);
+    s7 = real(3) / (real(8) * tau_ghost[N + n]);
+    s8 = real(3) / (real(8) * tau_ghost[2 * N + n]);
+  }
+  const real axx = nxx * real(sc.s[0]), axy = nxy * real(sc.s[1]), ayy = nyy * real(sc.s[2]);
+  const real aN = nN * s6, aJx = nJx * s7, aJy = nJy * s8;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = LT::cx(i), cy = LT::cy(i);
+    const real gi = real((3 * cx * cx - 1) * (3 * cy * cy - 1));
+    const real corr = real(3 * cx * cx - 1) * axx + real(cx * cy) * axy + real(3 * cy * cy - 1) * ayy +
+                      gi * (aN + real(cx) * aJx + real(cy) * aJy);
+    const real dn = d[i] - CO::W(i) * corr;
+    store_stream(&fout[dir_row<Q>(g, c.y, c.z, i) + c.x], ST::from_dev(dn, CO::W(i)));
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // Streaming only: raw word permutation (bit-exact for every storage kind).
 // ---------------------------------------------------------------------------------
 template <int L, typename W>
@@ -561,6 +645,33 @@ static hipError_t launch_step_ls(const void* fin, void* fout, const void* force,
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_mrt_s(const void* fin, void* fout, const void* tau_ghost, const GridArgs& g,
+                               const double* scales, hipStream_t s) {
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using R = typename ST::real;
+  MrtScales sc;
+  for (int k = 0; k < 6; ++k) sc.s[k] = scales[k];
+  if (tau_ghost)
+    mrt_step_kernel<S, true><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, (const R*)tau_ghost, g, sc);
+  else
+    mrt_step_kernel<S, false><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, nullptr, g, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_mrt(int storage, const void* fin, void* fout, const void* tau_ghost, const GridArgs& g,
+                      const double* scales, hipStream_t s) {
+  switch (storage) {
+    case kF64: return launch_mrt_s<kF64>(fin, fout, tau_ghost, g, scales, s);
+    case kF32: return launch_mrt_s<kF32>(fin, fout, tau_ghost, g, scales, s);
+    case kF32S: return launch_mrt_s<kF32S>(fin, fout, tau_ghost, g, scales, s);
+    case kF16S: return launch_mrt_s<kF16S>(fin, fout, tau_ghost, g, scales, s);
+    case kBF16S: return launch_mrt_s<kBF16S>(fin, fout, tau_ghost, g, scales, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int L, int S, int MODE>

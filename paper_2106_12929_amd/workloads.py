@@ -175,6 +175,12 @@ def full_scale_adjoint(u0: torch.Tensor, tau: float, forward_steps: int = 500, a
     t_bwd = _sync_time(t0)
     peak = torch.cuda.max_memory_allocated()
     dF = F.grad
+    if not bool(torch.isfinite(KE)):
+        del gT, u, F, g_start
+        torch.cuda.empty_cache()
+        return {"grid": [n, n, n], "tau": tau, "forward_steps": forward_steps,
+                "diverged_before_step": forward_steps, "finite_at_step": pre,
+                "max_speed_at_step_%d" % pre: red["max_speed"], "forward_mlups": n ** 3 * pre / t_fwd / 1e6}
     out = {"grid": [n, n, n], "storage": "f16s state, f32 adjoint", "tau": tau,
            "forward_steps": forward_steps, "adjoint_steps": adjoint_steps, "checkpoint_every": checkpoint_every,
            "forward_mlups": n ** 3 * pre / t_fwd / 1e6,

@@ -129,6 +129,20 @@ def test_shifted_step_validation(B):
     assert lib.lbm_step_shifted(gp, P1, P2, 0.6, P3, 0, None) == -1
 
 
+def test_mrt_validation(B):
+    lib = B._lib
+    taus = (ctypes.c_double * 9)(1, 1, 1, 0.6, 0.6, 0.6, 1, 1, 1)
+    bad = (ctypes.c_double * 9)(1, 1, 1, 0.6, 0.5, 0.6, 1, 1, 1)
+    g3 = _grid(B)                                      # D3Q27
+    g2 = _grid(B, lattice="D2Q9", nz=1)
+    assert lib.lbm_step_mrt(ctypes.byref(g3), P1, P2, taus, None, 1, None) == -5
+    assert lib.lbm_step_mrt(ctypes.byref(g2), P1, P2, None, None, 1, None) == -2
+    assert lib.lbm_step_mrt(ctypes.byref(g2), P1, P2, bad, None, 1, None) == -1
+    assert lib.lbm_step_mrt(ctypes.byref(g2), P1, P1, taus, None, 1, None) == -4
+    assert lib.lbm_step_mrt(ctypes.byref(g2), P1, P2, taus, P1, 1, None) == -4
+    assert lib.lbm_step_mrt(ctypes.byref(g2), P1, P2, taus, None, 0, None) == -1
+
+
 def test_local_adjoint_validation(B):
     lib = B._lib
     g = _grid(B)

@@ -190,6 +190,61 @@ def test_shifted_step_parity(lat, shape, kind):
     assert excess <= 0, ratio
 
 
+MRT_TAUS = [1.0, 1.0, 1.0, 0.57, 0.57, 0.57, 0.9, 1.3, 1.2]
+
+
+@pytest.mark.parametrize("shape", SHAPES["D2Q9"])
+@pytest.mark.parametrize("kind", KINDS)
+def test_mrt_step_parity(shape, kind):
+    """lbm_step_mrt (D2Q9, Dellar basis, Eq. 5) against the oracle's MRT step."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D2Q9")
+    grid = _grid(B, "D2Q9", kind, shape)
+    spatial = _spatial("D2Q9", shape)
+    say(f"mrt step {kind} {shape}")
+    s = _state(st, spatial, 16, kind)
+    out = grid.empty_populations()
+    assert B.lbm_step_mrt(grid, grid.to_layout(s).cuda(), out, MRT_TAUS, None, 1) == 0
+    ref = ost.step_emulated(s, 0.57, st, kind, mrt_taus=MRT_TAUS)
+    excess, ratio, same = _tolerance_ok(kind, st, grid.from_layout(out.cpu()), ref, 0.57)
+    say(f"  max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
+    assert excess <= 0, ratio
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_mrt_per_cell_ghost_times(kind):
+    """Per-cell tau_6..8 (the neural collision's outputs) against the oracle with the
+    same fields."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D2Q9")
+    shape = (37, 11, 1)
+    grid = _grid(B, "D2Q9", kind, shape)
+    spatial = _spatial("D2Q9", shape)
+    s = _state(st, spatial, 17, kind)
+    ghost = (0.55 + torch.rand((3,) + spatial, generator=torch.Generator().manual_seed(5), dtype=torch.float64))
+    ghost = ghost.to(grid.real_dtype)
+    taus = MRT_TAUS[:6] + [ghost[0].double(), ghost[1].double(), ghost[2].double()]
+    out = grid.empty_populations()
+    B.lbm_step_mrt(grid, grid.to_layout(s).cuda(), out, MRT_TAUS, ghost.cuda(), 1)
+    ref = ost.step_emulated(s, 0.57, st, kind, mrt_taus=taus)
+    excess, ratio, same = _tolerance_ok(kind, st, grid.from_layout(out.cpu()), ref, 0.57)
+    assert excess <= 0, ratio
+
+
+def test_mrt_equal_times_match_bgk_kernel():
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D2Q9")
+    grid = B.Grid("D2Q9", "f64", 40, 23)
+    s = grid.to_layout(_state(st, (23, 40), 18, "f64")).cuda()
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_step_mrt(grid, s, a, [0.61] * 9, None, 1)
+    B.lbm_step(grid, s, b, 0.61, None, 1)
+    assert float((a - b).abs().max()) < 1e-15
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_rest_state_bit_exact(kind):
     need_gpu()

@@ -113,3 +113,49 @@ def test_forced_collision_momentum_gain(name, spatial):
     out = lbm.bgk_collide(f, 0.6, st, F)
     torch.testing.assert_close(lbm.density(out), lbm.density(f), rtol=1e-14, atol=0)
     torch.testing.assert_close(lbm.momentum(out, st), lbm.momentum(f, st) + F, rtol=0, atol=1e-15)
+
+
+def test_dellar_basis_structure():
+    # The non-hydrodynamic weight g is (up to a factor) the fourth-order Hermite
+    # polynomial (c_x^2 - 1/3)(c_y^2 - 1/3): w-orthogonal to 1, c, cc, and g on the
+    # rest/axis/diagonal velocities is 1, -2, 4 (Dellar 2003).
+    st = lbm.stencil("D2Q9")
+    M = lbm.dellar_matrix(st)
+    assert torch.linalg.matrix_rank(M) == 9
+    cls = (st.c ** 2).sum(1)
+    g = M[6]
+    assert torch.equal(g[cls == 0], torch.tensor([1.0], dtype=torch.float64))
+    assert bool((g[cls == 1] == -2).all()) and bool((g[cls == 2] == 4).all())
+    # the three non-hydrodynamic rows are w-orthogonal to the six hydrodynamic ones and
+    # to each other
+    for k in range(6):
+        for j in (6, 7, 8):
+            assert abs(float((st.w * M[k] * M[j]).sum())) < 1e-15
+    for j, l in ((6, 7), (6, 8), (7, 8)):
+        assert abs(float((st.w * M[j] * M[l]).sum())) < 1e-15
+
+
+def test_mrt_equal_times_is_bgk():
+    st = lbm.stencil("D2Q9")
+    spatial = (6, 7)
+    rho, u = synthetic.random_fields(spatial, 2, 91, drho=0.03, umax=0.06)
+    f = lbm.equilibrium(rho, u, st) * (1 + synthetic.random_normal((9,) + spatial, 92, 0.02))
+    for tau in (0.53, 0.8, 1.4):
+        torch.testing.assert_close(lbm.mrt_collide(f, [tau] * 9, st), lbm.bgk_collide(f, tau, st),
+                                   rtol=0, atol=2e-15)  # roundoff of the moment-space round trip
+
+
+def test_mrt_conserves_and_relaxes_each_moment():
+    st = lbm.stencil("D2Q9")
+    spatial = (5, 4)
+    rho, u = synthetic.random_fields(spatial, 2, 93, drho=0.03, umax=0.06)
+    f = lbm.equilibrium(rho, u, st) * (1 + synthetic.random_normal((9,) + spatial, 94, 0.02))
+    taus = [1.0, 1.0, 1.0, 0.6, 0.6, 0.6, 0.9, 1.3, 1.3]
+    out = lbm.mrt_collide(f, taus, st)
+    torch.testing.assert_close(lbm.density(out), lbm.density(f), rtol=1e-14, atol=0)
+    torch.testing.assert_close(lbm.momentum(out, st), lbm.momentum(f, st), rtol=0, atol=1e-15)
+    # the stress relaxes at rate 1/tau_3..5 like BGK with tau = 0.6: the second
+    # moment of out equals BGK's
+    cf = st.c.to(torch.float64)
+    m2 = lambda x: torch.einsum("qa,qb,q...->ab...", cf, cf, x)
+    torch.testing.assert_close(m2(out), m2(lbm.bgk_collide(f, 0.6, st)), rtol=0, atol=1e-15)

@@ -118,3 +118,18 @@ def test_centre_of_mass_moves_by_momentum():
         r1 = lbm.density(g)
         assert abs(float(((r1 - r0) * x).sum() - J[0])) < 1e-10  # roundoff of 1024 cells x 31
         assert abs(float(((r1 - r0) * y).sum() - J[1])) < 1e-10
+
+
+def test_mrt_tgv2d_decay_follows_shear_relaxation_time():
+    # With the MRT collision (Eq. 5) the shear viscosity comes from tau_3..5 alone
+    # (Sec. 3.1: tau_n = nu/c_s^2 + 1/2); different ghost-moment times must leave the
+    # Taylor-Green decay at the closed form of that viscosity.
+    gold = json.load(open(GOLDEN))
+    st = lbm.stencil("D2Q9")
+    n, u0, tau = gold["n"], gold["u0"], gold["tau"]
+    taus = [1.0, 1.0, 1.0, tau, tau, tau, 1.1, 1.3, 1.3]
+    g = lbm.equilibrium(torch.ones(n, n, dtype=torch.float64), synthetic.taylor_green_2d(n, n, u0), st)
+    for _ in range(gold["t"][-1]):
+        g = lbm.step_mrt(g, taus, st)
+    amp, _ = _tgv2d_amplitude(g, st, n, u0)
+    assert abs(amp / gold["amplitude"][-1] - 1) < gold["rel_tol"]
