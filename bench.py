@@ -176,6 +176,32 @@ def accuracy_vs_fp64(B, u_dev, n_steps: int):
     return res
 
 
+def run_tgv2d_small(B, steps: int = 1000, reps: int = 5):
+    """The 64x64 D2Q9 FP64 Taylor-Green run (tau 0.6): 4096 cells, so every step is a
+    few microseconds of kernel and the launch rate decides.  Timed as lbm_step with
+    n_steps = 1000 (one C-side launch loop) and as a captured HIP graph replay."""
+    from synthetic import taylor_green_2d
+
+    grid = B.Grid("D2Q9", "f64", 64, 64)
+    a, b = grid.empty_populations(), grid.empty_populations()
+    u = taylor_green_2d(64, 64, 0.05).cuda()
+    B.lbm_init_equilibrium(grid, None, u, a)
+    ms_loop = time_launches(lambda: B.lbm_step(grid, a, b, 0.6, None, steps), reps, 1)
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        B.lbm_step(grid, a, b, 0.6, None, 2)  # warm-up on the capture stream
+        with torch.cuda.graph(graph, stream=s):
+            B.lbm_step(grid, a, b, 0.6, None, steps)
+    torch.cuda.current_stream().wait_stream(s)
+    ms_graph = time_launches(graph.replay, reps, 1)
+    cells = 64 * 64
+    return {"grid": [64, 64], "steps_per_call": steps,
+            "launch_loop_mlups": cells * steps / (ms_loop * 1e-3) / 1e6, "launch_loop_us_per_step": 1e3 * ms_loop / steps,
+            "graph_mlups": cells * steps / (ms_graph * 1e-3) / 1e6, "graph_us_per_step": 1e3 * ms_graph / steps}
+
+
 def run_workloads():
     """The decaying-turbulence precision study (384^3, 2000 steps, tau 0.5015 and a
     stable tau), the
@@ -200,6 +226,8 @@ def run_workloads():
     log("[bench] forcing optimisation 128^3")
     u = isotropic_turbulence(128, 4.0, 0.05, seed=0, device="cuda")
     out["forcing_128"] = WL.forcing_optimisation(u, 0.51, steps=100, checkpoint_every=10, iters=30)
+    log("[bench] gradient precision 128^3")
+    out["gradient_precision_128"] = WL.gradient_precision(u, 0.51, steps=100, checkpoint_every=10)
     del u
     torch.cuda.empty_cache()
     log("[bench] flow control 128^2 (D2Q9)")
@@ -327,6 +355,8 @@ def main():
                                           for s in ("f32", "f16s")}
         log("[bench] moments")
         detail["moments_f32"] = run_moments(B, 20, 3, u_dev)
+        log("[bench] 64x64 D2Q9 launch-bound run")
+        detail["tgv2d_64_f64"] = run_tgv2d_small(B)
         log("[bench] copy")
         detail["device_copy"] = run_copy(B, 20, 3)
         head["frac_of_copy"] = head["hbm_gbs"] / detail["device_copy"]["gbs"]

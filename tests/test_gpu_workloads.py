@@ -1,0 +1,114 @@
+"""GPU checks of the workloads built on the C ABI: captured HIP-graph replays of the
+step, the flow-control restraint, and the adjoint-driven forcing optimisation."""
+import pytest
+import torch
+
+import synthetic
+from oracle import lbm as olbm
+
+from _helpers import binding, bits, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_graph_replay_matches_eager():
+    """A captured 10-step lbm_step replayed three times, with eager work and
+    synchronisations in between, reproduces the eager result every time."""
+    need_gpu()
+    B = binding()
+    grid = B.Grid("D3Q27", "f32", 40, 12, 9)
+    u = synthetic.random_fields((9, 12, 40), 3, 7, umax=0.05)[1].cuda()
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u, a)
+    start = a.clone()
+    # eager reference: 10, 20 and 30 steps
+    refs = []
+    x, y = start.clone(), grid.empty_populations()
+    for _ in range(3):
+        B.lbm_step(grid, x, y, 0.55, None, 10)  # even: result back in x
+        refs.append(x.clone())
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            B.lbm_step(grid, a, b, 0.55, None, 10)
+    torch.cuda.current_stream().wait_stream(s)
+    a.copy_(start)
+    for k in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = (a.float().sum() + 1).item()  # eager work between replays
+        assert torch.equal(bits(a), bits(refs[k])), k
+
+
+def test_flow_control_restrains_the_spectrum():
+    need_gpu()
+    binding()
+    from paper_2106_12929_amd import workloads as WL
+
+    u = synthetic.isotropic_turbulence(64, 4.0, 0.04, seed=1, dim=2, device="cuda")
+    out = WL.flow_control_2d(u, 0.51, 400, kappa=5e-3, record_every=100)
+    R_free = out["free"]["history"][-1][1]
+    R_ctrl = out["restrained"]["history"][-1][1]
+    say(f"flow control 64^2: R free {R_free:.3f}, restrained {R_ctrl:.3f}")
+    assert R_ctrl < 0.25 * R_free
+
+
+def test_forcing_optimisation_lowers_the_loss():
+    need_gpu()
+    binding()
+    from paper_2106_12929_amd import workloads as WL
+
+    u = synthetic.isotropic_turbulence(32, 4.0, 0.05, seed=0, device="cuda")
+    out = WL.forcing_optimisation(u, 0.51, steps=20, checkpoint_every=5, iters=6, lr=1e-5, k_band=(2, 8))
+    say(f"forcing 32^3: loss {out['loss_first']:.4f} -> {out['loss_last']:.4f}")
+    assert out["loss_last"] < out["loss_first"]
+    assert out["loss_min"] < 0.95 * out["loss_first"]
+
+
+def test_simulation_driver_and_copy():
+    """The ping-pong driver (Listing 1's Simulation.step usage) against the oracle,
+    and the reference copy."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd.simulation import Simulation
+    from oracle import storage as ost
+
+    st = olbm.stencil("D2Q9")
+    grid = B.Grid("D2Q9", "f64", 24, 20)
+    u = synthetic.taylor_green_2d(24, 20, 0.04)
+    sim = Simulation(grid, 0.7)
+    sim.init_equilibrium(u)
+    sim.step(3)
+    sim.step(4)
+    assert sim.steps_done == 7
+    ref = olbm.run(olbm.equilibrium(torch.ones(20, 24, dtype=torch.float64), u, st), 0.7, st, 7)
+    assert float((grid.from_layout(sim.f.cpu()) - ref).abs().max()) < 1e-15
+    rho, uu = sim.moments()
+    r_ref, u_ref = olbm.state_moments(ref, st)
+    assert float((uu.cpu() - u_ref).abs().max()) < 1e-15
+    red = sim.reductions()
+    assert abs(red["mass"] - float(r_ref.sum())) < 1e-10
+    assert red["nonfinite_cells"] == 0.0
+    x = torch.randn(1 << 20, device="cuda")
+    y = torch.empty_like(x)
+    B.lbm_copy(x, y)
+    assert torch.equal(x, y)
+
+
+def test_gradient_precision_fp32_matches_fp64():
+    """The FP32 adjoint's force gradient points where the FP64 one does (48^3, 50
+    steps): cosine >= 0.999."""
+    need_gpu()
+    binding()
+    from paper_2106_12929_amd import workloads as WL
+
+    u = synthetic.isotropic_turbulence(48, 4.0, 0.05, seed=2, device="cuda")
+    out = WL.gradient_precision(u, 0.51, steps=50, checkpoint_every=10, storages=("f64", "f32", "f16s"),
+                                k_band=(2, 12))
+    c32 = out["runs"]["f32"]["cosine_vs_f64"]
+    c16 = out["runs"]["f16s"]["cosine_vs_f64"]
+    say(f"gradient cosine vs f64: f32 {c32:.8f}, f16s {c16:.6f}")
+    assert c32 >= 0.999
+    assert c16 >= 0.9
