@@ -425,6 +425,70 @@ def test_tgv3d_d3q19_vs_oracle():
     assert errs["f16s"] <= 1e-2
 
 
+DEGENERATE = [("D3Q27", (1, 1, 1)), ("D3Q27", (1, 5, 3)), ("D3Q27", (7, 1, 1)), ("D3Q27", (3, 1, 4)),
+              ("D3Q19", (2, 1, 1)), ("D2Q9", (1, 1, 1)), ("D2Q9", (64, 1, 1)), ("D2Q9", (1, 70, 1))]
+
+
+@pytest.mark.parametrize("lat,shape", DEGENERATE)
+@pytest.mark.parametrize("kind", ["f64", "f32", "f16s"])
+def test_degenerate_grids(lat, shape, kind):
+    """Grids one cell thick in some direction (a population streams back onto its own
+    cell there), including a single cell: stream-only bit-exact and one step within
+    the usual bound."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    grid = _grid(B, lat, kind, shape)
+    spatial = _spatial(lat, shape)
+    say(f"degenerate {lat} {kind} {shape}")
+    s = _state(st, spatial, 19, kind)
+    out = grid.empty_populations()
+    B.lbm_stream_only(grid, grid.to_layout(s).cuda(), out)
+    assert torch.equal(bits(grid.from_layout(out.cpu())), bits(ost.stream_stored(s, st)))
+    B.lbm_step(grid, grid.to_layout(s).cuda(), out, 0.57, None, 1)
+    ref = ost.step_emulated(s, 0.57, st, kind)
+    excess, ratio, same = _tolerance_ok(kind, st, grid.from_layout(out.cpu()), ref, 0.57)
+    assert excess <= 0, ratio
+
+
+def test_tau_one_writes_the_equilibrium():
+    """tau = 1 (omega = 1): one step replaces the streamed populations by their
+    equilibrium, i.e. lbm_init_equilibrium of the streamed moments."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D3Q27")
+    grid = B.Grid("D3Q27", "f64", 19, 7, 6)
+    s = _state(st, (6, 7, 19), 20, "f64")
+    out = grid.empty_populations()
+    B.lbm_step(grid, grid.to_layout(s).cuda(), out, 1.0, None, 1)
+    h = olbm.stream(s, st)
+    feq = olbm.equilibrium(olbm.density(h), olbm.momentum(h, st) / olbm.density(h), st)
+    assert float((grid.from_layout(out.cpu()) - feq).abs().max()) < 1e-15
+
+
+def test_large_2d_grid_sampled():
+    """A 8192 x 8192 D2Q9 FP32 grid (67M cells, 2.4 GB per buffer): one step from a
+    Taylor-Green start plus 2 steps, compared at sampled cells."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D2Q9")
+    n = 8192
+    grid = B.Grid("D2Q9", "f32", n, n)
+    say("large 2D 8192^2 f32")
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, synthetic.taylor_green_2d(n, n, 0.05).cuda(), a)
+    B.lbm_step(grid, a, b, 0.6, None, 2)  # result in a
+    B.lbm_step(grid, a, b, 0.6, None, 1)  # result in b
+    gen = torch.Generator().manual_seed(8)
+    cells = torch.cat([torch.randint(0, n, (2048, 2), generator=gen),
+                       torch.tensor([[0, 0], [n - 1, 0], [0, n - 1], [n - 1, n - 1]])])
+    g_in = a.cpu().permute(1, 0, 2)  # [Q, y, x] view
+    ref = ost.step_at_cells_emulated(g_in, 0.6, st, "f32", cells)
+    got = b.cpu()[cells[:, 1], :, cells[:, 0]].T
+    excess, ratio, same = _tolerance_ok("f32", st, got, ost.quantize(ref, st, "f32"), 0.6)
+    assert excess <= 0, ratio
+
+
 @pytest.mark.parametrize("kind,n", [("f32", 256), ("f64", 256), ("f16s", 256), ("bf16s", 256), ("f16s", 512)])
 def test_full_size_sampled(kind, n):
     """Full-size grids in the benchmark's launch shape: one step compared with the
