@@ -84,6 +84,86 @@ def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = 
     return out
 
 
+def run_d2q9(B, steps: int, warmup: int, n: int = 8192):
+    """D2Q9 throughput on an n x n periodic grid (Taylor-Green start): the BGK step for
+    several storage kinds, and the MRT step (Eq. 5) with uniform relaxation times and
+    with per-cell ghost-moment times (3 more values read per cell)."""
+    from synthetic import taylor_green_2d
+    u = taylor_green_2d(n, n, 0.05).cuda()
+    taus = [1, 1, 1, 0.6, 0.6, 0.6, 0.9, 0.8, 0.7]
+    out = {}
+    for storage, kinds in (("f32", ("bgk", "mrt", "mrt_cell")), ("f16s", ("bgk", "mrt", "mrt_cell")),
+                           ("f64", ("bgk", "mrt"))):
+        grid = B.Grid("D2Q9", storage, n, n)
+        bufs = [grid.empty_populations(), grid.empty_populations()]
+        B.lbm_init_equilibrium(grid, None, u, bufs[0])
+        tg = None
+        for kind in kinds:
+            if kind == "mrt_cell":
+                tg = torch.empty((3, n, n), dtype=grid.real_dtype, device="cuda").uniform_(0.55, 1.2)
+            cur = [0]
+
+            def one():
+                a, b = bufs[cur[0]], bufs[1 - cur[0]]
+                if kind == "bgk":
+                    B.lbm_step(grid, a, b, 0.6, None, 1)
+                else:
+                    B.lbm_step_mrt(grid, a, b, taus, tg if kind == "mrt_cell" else None, 1)
+                cur[0] ^= 1
+
+            ms = time_launches(one, steps, warmup)
+            bpc = B.bytes_per_cell_step(grid) + (3 * tg.element_size() if kind == "mrt_cell" else 0)
+            gbs = bpc * grid.ncells / (ms * 1e-3) / 1e9
+            out[f"{kind}_{storage}"] = {"ms_per_step": ms, "mlups": grid.ncells / (ms * 1e-3) / 1e6,
+                                        "bytes_per_cell": bpc, "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+        del bufs, tg
+        torch.cuda.empty_cache()
+    out["grid"] = [n, n]
+    return out
+
+
+def run_shard(B, steps: int, warmup: int, nx: int = 512, ny: int = 512, nz: int = 64, storage: str = "f16s"):
+    """One device's share of a z-slab decomposition of a 512^2 x (64 P) grid: the slab
+    step with ghost planes, its halo exchange (here each slab is its own periodic
+    neighbour, so the copies stay on the device), and the periodic step of the same
+    shape for comparison."""
+    from paper_2106_12929_amd.slabs import SlabSet
+    from synthetic import taylor_green_3d
+    grid = B.Grid("D3Q27", storage, nx, ny, nz)
+    f = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, taylor_green_3d(nx, ny, nz, U0).cuda(), f)
+    S = SlabSet(grid, 1)
+    S.scatter(f)
+    bufs = [f, grid.empty_populations()]
+    cur = [0]
+
+    def periodic():
+        B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, None, 1)
+        cur[0] ^= 1
+
+    out = {"shape": [nx, ny, nz], "storage": storage}
+    bpc = B.bytes_per_cell_step(grid)
+    n_face = 9
+    halo_bytes = 2 * n_face * nx * ny * torch.tensor([], dtype=grid.word_dtype).element_size()
+    for name, fn in (("periodic_step", periodic),
+                     ("slab_step_sequential", lambda: S.step(TAU, overlap=False)),
+                     ("slab_step_overlapped", lambda: S.step(TAU, overlap=True)),
+                     ("halo_exchange_only", lambda: S.exchange())):
+        ms = time_launches(fn, steps, warmup)
+        row = {"ms": ms}
+        if name != "halo_exchange_only":
+            row["mlups"] = grid.ncells / (ms * 1e-3) / 1e6
+            row["hbm_gbs"] = bpc * grid.ncells / (ms * 1e-3) / 1e9
+        else:
+            row["bytes_each_way"] = halo_bytes  # read and written, both faces
+            row["gbs"] = 2 * halo_bytes / (ms * 1e-3) / 1e9
+        out[name] = row
+    out["halo_bytes_per_face"] = halo_bytes // 2
+    del bufs, f, S
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_adjoint(B, storage: str, steps: int, warmup: int, u_dev, local: bool = True):
     """Adjoint-step kernel throughput: the collision-local form the rollout uses
     (gathered reads, aligned writes) or the scatter form of lbm_adjoint_step."""
@@ -349,6 +429,10 @@ def main():
         # D3Q19, the lattice of the paper's 3D benchmark (Taylor-Green vortex, Sec. 3.3)
         detail["forward_d3q19"] = {s: run_forward(B, s, args.steps, args.warmup, u_dev, "D3Q19")
                                    for s in ("f32", "f64", "f16s")}
+        log("[bench] D2Q9 8192^2 BGK and MRT")
+        detail["d2q9_8192"] = run_d2q9(B, args.steps, args.warmup)
+        log("[bench] z-slab shard 512x512x64 f16s")
+        detail["shard_512x512x64_f16s"] = run_shard(B, args.steps, args.warmup)
         log("[bench] adjoint")
         detail["adjoint"] = {s: run_adjoint(B, s, max(20, args.steps // 4), 5, u_dev) for s in ("f32", "f16s")}
         detail["adjoint_scatter_form"] = {s: run_adjoint(B, s, max(20, args.steps // 4), 5, u_dev, local=False)

@@ -90,6 +90,9 @@ typedef struct lbm_grid {
   int64_t nx, ny, nz;
 } lbm_grid;
 
+/* Faces of a z-slab (lbm_slab_halo_copy). */
+enum lbm_face { LBM_FACE_LOW = 0, LBM_FACE_HIGH = 1 };
+
 /* Number of reduction results written by lbm_moments (see there). */
 #define LBM_NRED 8
 
@@ -152,6 +155,42 @@ int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, 
  * other than D2Q9. */
 int lbm_step_mrt(const lbm_grid* grid, void* f_in, void* f_out, const double* tau_moments,
                  const void* tau_ghost, int n_steps, void* stream);
+
+/* One step (Eqs. 1-4, as lbm_step) on a z-slab: one shard of a grid that is periodic
+ * in x and y and split into slabs of consecutive planes along z, each slab stepping
+ * on its own device with ghost planes for the populations that cross its faces.
+ * slab: D3Q19 or D3Q27 (LBM_EUNSUP otherwise); nx, ny as the whole grid, nz = the
+ *   slab's own planes.
+ * f_in, f_out: slab buffers of (nz + 2) planes in the population layout, i.e. the
+ *   layout of a grid of nz + 2 planes: buffer plane 0 is the ghost plane below the
+ *   slab, planes 1..nz hold slab planes 0..nz-1, plane nz + 1 is the ghost plane
+ *   above.  The pull gather of slab plane 0 reads the directions with c_z = +1 from
+ *   the lower ghost plane, that of plane nz-1 the directions with c_z = -1 from the
+ *   upper one (filled by lbm_slab_halo_copy); no other ghost words are read, and
+ *   nothing wraps in z.
+ * z_begin, z_end: the slab planes [z_begin, z_end) to compute, 0 <= z_begin < z_end
+ *   <= nz; only those planes of f_out are written.  Splitting a step into the inner
+ *   planes [1, nz-1), which need no ghost data, and the two boundary planes lets the
+ *   halo exchange of the previous step overlap the inner work.
+ * tau, force: as in lbm_step; force holds D*nx*ny*nz reals for the slab's own cells.
+ * f_in and f_out must not overlap; force must not overlap either.  Returns LBM_OK. */
+int lbm_step_slab(const lbm_grid* slab, const void* f_in, void* f_out, double tau,
+                  const void* force, int64_t z_begin, int64_t z_end, void* stream);
+
+/* Halo exchange of the slab step: copies the populations that leave a slab through one
+ * face into the ghost plane of the neighbouring slab on that side (Eq. 1's streaming
+ * across the cut).
+ *   LBM_FACE_LOW:  directions with c_z = -1 of src's lowest plane (buffer plane 1)
+ *                  into dst's upper ghost plane (buffer plane nz_dst + 1);
+ *   LBM_FACE_HIGH: directions with c_z = +1 of src's highest plane (buffer plane
+ *                  nz_src) into dst's lower ghost plane (buffer plane 0).
+ * Those directions are consecutive in the velocity order (9 of 27, 5 of 19), so each
+ * grid row moves one contiguous run of n_dir*nx words.  The two slabs must agree in
+ * lattice, storage, nx and ny (nz may differ); src and dst may be the same buffer (one
+ * slab that is its own periodic neighbour) but the source plane must not overlap the
+ * destination ghost plane. */
+int lbm_slab_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid* dst_slab,
+                       void* dst, int face, void* stream);
 
 /* Streaming only: f_out_i(x) = f_in_i(x - c_i), periodic (Eq. 1's shift), copying the
  * raw storage words (a permutation: bit-exact for every storage kind).  Buffers must not

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LATTICES = {"D2Q9": 0, "D3Q27": 1, "D3Q19": 2}
 STORAGES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3, "bf16s": 4}
+FACES = {"low": 0, "high": 1}
 STORAGE_DTYPE = {"f64": torch.float64, "f32": torch.float32, "f32s": torch.float32,
                  "f16s": torch.float16, "bf16s": torch.bfloat16}
 NRED = 8
@@ -64,6 +65,8 @@ def _load() -> ctypes.CDLL:
         "lbm_adjoint_step_local": (i32, [gp, vp, vp, i32, vp, dbl, vp, vp, vp]),
         "lbm_adjoint_unstream": (i32, [gp, vp, vp, vp]),
         "lbm_copy": (i32, [vp, vp, sz, vp]),
+        "lbm_step_slab": (i32, [gp, vp, vp, dbl, vp, ctypes.c_int64, ctypes.c_int64, vp]),
+        "lbm_slab_halo_copy": (i32, [gp, vp, gp, vp, i32, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -139,6 +142,16 @@ class Grid:
 
     def empty_populations(self, device="cuda") -> torch.Tensor:
         return torch.empty(self.population_shape(), dtype=self.word_dtype, device=device)
+
+    def slab_population_shape(self) -> tuple:
+        """Shape of a z-slab buffer (lbm_step_slab): the population layout of nz + 2
+        planes, buffer plane 0 and nz + 1 being the ghost planes."""
+        if self.D != 3:
+            raise ValueError("z-slabs need a 3D lattice")
+        return (self.nz + 2, self.ny, self.Q, self.nx)
+
+    def empty_slab_populations(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.slab_population_shape(), dtype=self.word_dtype, device=device)
 
     def empty_real(self, components: int, device="cuda") -> torch.Tensor:
         shape = self.spatial if components == 0 else (components,) + self.spatial
@@ -236,6 +249,33 @@ def lbm_step_mrt(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, taus, tau_
     b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
     tg = _dev_ptr(tau_ghost, "tau_ghost", grid.real_dtype, 3 * N, required=False)
     return _check(_lib.lbm_step_mrt(ctypes.byref(g), a, b, t, tg, int(n_steps), _stream(stream)), "lbm_step_mrt")
+
+
+def lbm_step_slab(slab: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: float,
+                  force: torch.Tensor | None = None, z_begin: int = 0, z_end: int | None = None,
+                  stream=None) -> None:
+    """One step of slab planes [z_begin, z_end) (default: all) of a z-slab; f_in and
+    f_out are slab buffers (nz + 2 planes), force holds the slab's own D*N reals."""
+    N = slab.ncells
+    words = slab.Q * slab.nx * slab.ny * (slab.nz + 2)
+    g = slab.c_struct()
+    a = _dev_ptr(f_in, "f_in", slab.word_dtype, words)
+    b = _dev_ptr(f_out, "f_out", slab.word_dtype, words)
+    F = _dev_ptr(force, "force", slab.real_dtype, slab.D * N, required=False)
+    z1 = slab.nz if z_end is None else int(z_end)
+    _check(_lib.lbm_step_slab(ctypes.byref(g), a, b, float(tau), F, int(z_begin), z1, _stream(stream)),
+           "lbm_step_slab")
+
+
+def lbm_slab_halo_copy(src_slab: Grid, src: torch.Tensor, dst_slab: Grid, dst: torch.Tensor, face: str,
+                       stream=None) -> None:
+    """Copies the populations leaving src through `face` ("low" or "high") into the
+    matching ghost plane of dst, the neighbouring slab on that side."""
+    gs, gd = src_slab.c_struct(), dst_slab.c_struct()
+    a = _dev_ptr(src, "src", src_slab.word_dtype, src_slab.Q * src_slab.nx * src_slab.ny * (src_slab.nz + 2))
+    b = _dev_ptr(dst, "dst", dst_slab.word_dtype, dst_slab.Q * dst_slab.nx * dst_slab.ny * (dst_slab.nz + 2))
+    _check(_lib.lbm_slab_halo_copy(ctypes.byref(gs), a, ctypes.byref(gd), b, FACES[face], _stream(stream)),
+           "lbm_slab_halo_copy")
 
 
 def lbm_stream_only(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, stream=None) -> None:

@@ -71,6 +71,9 @@ int check_grid(const lbm_grid* g, Geometry* geo) {
   geo->args.nz = (uint32_t)g->nz;
   geo->args.ncells = (uint64_t)(g->nx * g->ny * g->nz);
   geo->args.block_x = pick_block_x(g->nx);
+  geo->args.z0 = 0;
+  geo->args.nzl = (uint32_t)g->nz;
+  geo->args.ghost = 0;
   return LBM_OK;
 }
 
@@ -107,6 +110,26 @@ void fill_lattice(int* c, double* w) {
     }
     if (w) w[i] = LT::w(i);
   }
+}
+
+// The directions crossing a z face: those with c_z == cz, which are consecutive in the
+// lattice order (c_z varies slowest); returns the first index and the count.
+template <typename LT>
+void face_dirs_of(int cz, int* i0, int* n) {
+  *i0 = -1;
+  *n = 0;
+  for (int i = 0; i < LT::Q; ++i)
+    if (LT::cz(i) == cz) {
+      if (*i0 < 0) *i0 = i;
+      ++*n;
+    }
+}
+
+void face_dirs(int lattice, int cz, int* i0, int* n) {
+  if (lattice == LBM_D3Q19)
+    face_dirs_of<lbm::Lattice<lbm::kD3Q19>>(cz, i0, n);
+  else
+    face_dirs_of<lbm::Lattice<lbm::kD3Q27>>(cz, i0, n);
 }
 
 #define LBM_TRY(expr)          \
@@ -241,6 +264,59 @@ int lbm_step_mrt(const lbm_grid* grid, void* f_in, void* f_out, const double* ta
     if (e != hipSuccess) return hip_fail(e, "lbm_step_mrt launch");
   }
   return (n_steps & 1) ? 0 : 1;
+}
+
+int lbm_step_slab(const lbm_grid* slab, const void* f_in, void* f_out, double tau, const void* force,
+                  int64_t z_begin, int64_t z_end, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(slab, &geo));
+  if (geo.D != 3) return fail(LBM_EUNSUP, "lbm_step_slab needs a 3D lattice (z-slabs)");
+  LBM_TRY(check_tau(tau));
+  if (z_begin < 0 || z_end > slab->nz || z_begin >= z_end)
+    return fail(LBM_EINVAL, "plane range [%lld, %lld) is empty or outside [0, %lld)", (long long)z_begin,
+                (long long)z_end, (long long)slab->nz);
+  LBM_TRY(check_ptr(f_in, "f_in", true));
+  LBM_TRY(check_ptr(f_out, "f_out", true));
+  LBM_TRY(check_ptr(force, "force", false));
+  const size_t plane = (size_t)geo.Q * geo.args.nx * geo.args.ny * geo.word;
+  const size_t fbytes = plane * (size_t)(slab->nz + 2), vbytes = geo.D * geo.args.ncells * geo.real;
+  if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
+  if (overlap(force, vbytes, f_in, fbytes) || overlap(force, vbytes, f_out, fbytes))
+    return fail(LBM_EALIAS, "force overlaps a population buffer");
+  geo.args.z0 = (uint32_t)z_begin;
+  geo.args.nzl = (uint32_t)(z_end - z_begin);
+  geo.args.ghost = 1;
+  const hipError_t e = lbm::launch_step(slab->lattice, slab->storage, f_in, f_out, force,
+                                        force ? lbm::kGuoForce : lbm::kNoForce, geo.args, 1.0 / tau,
+                                        (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_slab launch");
+}
+
+int lbm_slab_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid* dst_slab, void* dst, int face,
+                       void* stream) {
+  Geometry gs, gd;
+  LBM_TRY(check_grid(src_slab, &gs));
+  LBM_TRY(check_grid(dst_slab, &gd));
+  if (gs.D != 3) return fail(LBM_EUNSUP, "lbm_slab_halo_copy needs a 3D lattice (z-slabs)");
+  if (src_slab->lattice != dst_slab->lattice || src_slab->storage != dst_slab->storage ||
+      src_slab->nx != dst_slab->nx || src_slab->ny != dst_slab->ny)
+    return fail(LBM_EINVAL, "source and destination slabs differ in lattice, storage, nx or ny");
+  if (face != LBM_FACE_LOW && face != LBM_FACE_HIGH) return fail(LBM_EINVAL, "face must be 0 or 1 (got %d)", face);
+  LBM_TRY(check_ptr(src, "src", true));
+  LBM_TRY(check_ptr(dst, "dst", true));
+  // LOW: src's lowest interior plane (buffer plane 1), directions with c_z = -1, into dst's
+  // upper ghost plane (nz + 1).  HIGH: src's highest interior plane (nz), c_z = +1, into
+  // dst's lower ghost plane (0).
+  const uint64_t src_plane = face == LBM_FACE_LOW ? 1 : (uint64_t)src_slab->nz;
+  const uint64_t dst_plane = face == LBM_FACE_LOW ? (uint64_t)dst_slab->nz + 1 : 0;
+  int i0 = 0, n = 0;
+  face_dirs(src_slab->lattice, face == LBM_FACE_LOW ? -1 : 1, &i0, &n);
+  const size_t plane = (size_t)gs.Q * gs.args.nx * gs.args.ny * gs.word;
+  if (overlap((const char*)src + src_plane * plane, plane, (const char*)dst + dst_plane * plane, plane))
+    return fail(LBM_EALIAS, "the source plane overlaps the destination ghost plane");
+  const hipError_t e = lbm::launch_halo_copy(gs.Q, (int)gs.word, src, src_plane, dst, dst_plane, i0, n, gs.args.nx,
+                                             gs.args.ny, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_slab_halo_copy launch");
 }
 
 int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* stream) {

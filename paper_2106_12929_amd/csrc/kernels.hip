@@ -42,9 +42,9 @@ __device__ __forceinline__ bool cell_of_thread(const GridArgs& g, Cell& c) {
   const uint32_t ty = __builtin_amdgcn_readfirstlane(threadIdx.x / bx);
   const uint32_t r = byi * (256u / bx) + ty;
   c.x = bxi * bx + threadIdx.x % bx;
-  if (r >= g.ny * g.nz) return false;
+  if (r >= g.ny * g.nzl) return false;
   c.y = r % g.ny;
-  c.z = r / g.ny;
+  c.z = g.z0 + r / g.ny;
   return c.x < g.nx;
 }
 
@@ -64,9 +64,15 @@ __device__ __forceinline__ Sources sources(const Cell& c, const GridArgs& g) {
   s.y[0] = wrap_inc(c.y, g.ny);
   s.y[1] = c.y;
   s.y[2] = wrap_dec(c.y, g.ny);
-  s.z[0] = wrap_inc(c.z, g.nz);
-  s.z[1] = c.z;
-  s.z[2] = wrap_dec(c.z, g.nz);
+  if (g.ghost) {  // z-slab: neighbours in z are buffer planes c.z + 2 and c.z (ghost planes at the ends)
+    s.z[0] = c.z + 2;
+    s.z[1] = c.z + 1;
+    s.z[2] = c.z;
+  } else {
+    s.z[0] = wrap_inc(c.z, g.nz);
+    s.z[1] = c.z;
+    s.z[2] = wrap_dec(c.z, g.nz);
+  }
   return s;
 }
 
@@ -185,7 +191,7 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
       if (LT::cz(i) < 0) cF -= Fz;
       dn += guo * (CO::A(i) * cF - real(3) * CO::W(i) * uF + real(2) * CO::B(i) * cu * cF);
     }
-    store_stream(&fout[dir_row<Q>(g, c.y, c.z, i) + c.x], ST::from_dev(dn, CO::W(i)));
+    store_stream(&fout[dir_row<Q>(g, c.y, c.z + g.ghost, i) + c.x], ST::from_dev(dn, CO::W(i)));
   }
 }
 
@@ -625,7 +631,7 @@ __global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Sto
 // ---------------------------------------------------------------------------------
 static dim3 cell_grid(const GridArgs& g) {
   const uint32_t blocks_x = (g.nx + g.block_x - 1) / g.block_x;
-  const uint64_t rows = (uint64_t)g.ny * g.nz;
+  const uint64_t rows = (uint64_t)g.ny * g.nzl;
   const uint32_t rows_per_block = 256u / g.block_x;
   return dim3((unsigned)(blocks_x * ((rows + rows_per_block - 1) / rows_per_block)));
 }
@@ -807,6 +813,37 @@ __global__ __launch_bounds__(256) void copy16_kernel(const u32x4* __restrict__ s
 hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s) {
   if (n16 == 0) return hipSuccess;
   copy16_kernel<<<(unsigned)((n16 + 255) / 256), 256, 0, s>>>((const u32x4*)src, (u32x4*)dst, n16);
+  return hipGetLastError();
+}
+
+// z-slab halo exchange: direction rows [i0, i0 + n_dir) of each grid row of one plane,
+// a contiguous chunk of n_dir * nx words per row at a pitch of Q * nx words.
+template <typename W>
+__global__ __launch_bounds__(256) void halo_copy_kernel(const W* __restrict__ src, W* __restrict__ dst,
+                                                        uint64_t src_base, uint64_t dst_base, uint64_t pitch,
+                                                        uint64_t chunk, uint32_t ny) {
+  const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= chunk) return;
+  for (uint32_t y = blockIdx.y; y < ny; y += gridDim.y) dst[dst_base + y * pitch + k] = src[src_base + y * pitch + k];
+}
+
+hipError_t launch_halo_copy(int Q, int word_bytes, const void* src, uint64_t src_plane, void* dst, uint64_t dst_plane,
+                            int i0, int n_dir, uint32_t nx, uint32_t ny, hipStream_t s) {
+  const uint64_t pitch = (uint64_t)Q * nx, chunk = (uint64_t)n_dir * nx;
+  const uint64_t sb = (src_plane * ny * Q + (uint64_t)i0) * nx, db = (dst_plane * ny * Q + (uint64_t)i0) * nx;
+  const dim3 grid((unsigned)((chunk + 255) / 256), ny < 4096u ? ny : 4096u);
+  switch (word_bytes) {
+    case 2:
+      halo_copy_kernel<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)src, (uint16_t*)dst, sb, db, pitch, chunk, ny);
+      break;
+    case 4:
+      halo_copy_kernel<uint32_t><<<grid, 256, 0, s>>>((const uint32_t*)src, (uint32_t*)dst, sb, db, pitch, chunk, ny);
+      break;
+    case 8:
+      halo_copy_kernel<uint64_t><<<grid, 256, 0, s>>>((const uint64_t*)src, (uint64_t*)dst, sb, db, pitch, chunk, ny);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

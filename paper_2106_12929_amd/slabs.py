@@ -1,0 +1,115 @@
+"""z-slab domain decomposition of a periodic 3D grid: the shape the step takes when a
+grid is split over several devices.
+
+A grid periodic in x, y and z is cut into P slabs of consecutive z planes.  Each slab
+keeps its planes in a buffer with one ghost plane below and one above
+(`lbm_step_slab`), and one step of the whole grid becomes, for every slab:
+
+  1. halo exchange (`lbm_slab_halo_copy`): the populations with c_z = +1 of the
+     slab's top plane go to the lower ghost plane of the slab above it, those with
+     c_z = -1 of its bottom plane to the upper ghost plane of the slab below (Eq. 1's
+     streaming across the cut; P = 1 exchanges with itself);
+  2. the step of the inner planes [1, nz-1), which reads no ghost data and so can run
+     while the exchange is in flight;
+  3. the step of the two boundary planes once the exchange has landed.
+
+`SlabSet` runs the P slabs on one device, each with its own buffers, with the
+exchange on a second stream when `overlap` is set.  The result is bitwise the
+periodic `lbm_step` of the whole grid: every cell runs the same kernel arithmetic on
+the same words.  On several devices each slab would live on its own device and the
+exchange would cross xGMI; the buffers, the kernels and the order of operations are
+the ones used here.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+def split_planes(nz: int, parts: int) -> list[int]:
+    """nz planes split into `parts` slabs as evenly as possible (larger slabs first)."""
+    if not 1 <= parts <= nz:
+        raise ValueError(f"cannot split {nz} planes into {parts} slabs")
+    q, r = divmod(nz, parts)
+    return [q + 1] * r + [q] * (parts - r)
+
+
+class SlabSet:
+    def __init__(self, grid: B.Grid, planes, device="cuda"):
+        if grid.D != 3:
+            raise ValueError("z-slabs need a 3D lattice")
+        planes = split_planes(grid.nz, planes) if isinstance(planes, int) else [int(p) for p in planes]
+        if sum(planes) != grid.nz or min(planes) < 1:
+            raise ValueError(f"slab plane counts {planes} do not partition nz = {grid.nz}")
+        self.grid = grid
+        self.planes = planes
+        self.z0 = [sum(planes[:p]) for p in range(len(planes))]
+        self.slabs = [B.Grid(grid.lattice, grid.storage, grid.nx, grid.ny, n) for n in planes]
+        self.bufs = [[s.empty_slab_populations(device), s.empty_slab_populations(device)] for s in self.slabs]
+        self.cur = 0
+        self._halo_stream = None
+
+    @property
+    def P(self) -> int:
+        return len(self.slabs)
+
+    def interior(self, p: int, which: int | None = None) -> torch.Tensor:
+        """View of slab p's own planes (buffer planes 1..nz) in the current buffer."""
+        b = self.bufs[p][self.cur if which is None else which]
+        return b[1:self.planes[p] + 1]
+
+    def scatter(self, f: torch.Tensor) -> None:
+        """Loads a whole-grid population buffer (population layout) into the slabs."""
+        for p in range(self.P):
+            self.interior(p).copy_(f[self.z0[p]:self.z0[p] + self.planes[p]])
+
+    def gather(self) -> torch.Tensor:
+        """The whole-grid population buffer assembled from the slabs."""
+        return torch.cat([self.interior(p) for p in range(self.P)], dim=0)
+
+    def split_field(self, v: torch.Tensor | None):
+        """A whole-grid [D, nz, ny, nx] real field cut into the slabs' own cells."""
+        if v is None:
+            return [None] * self.P
+        return [v[:, self.z0[p]:self.z0[p] + self.planes[p]].contiguous() for p in range(self.P)]
+
+    def exchange(self, stream=None) -> None:
+        """Fills every slab's ghost planes of the current buffer from its neighbours."""
+        c = self.cur
+        for p in range(self.P):
+            up, down = (p + 1) % self.P, (p - 1) % self.P
+            B.lbm_slab_halo_copy(self.slabs[p], self.bufs[p][c], self.slabs[up], self.bufs[up][c], "high", stream)
+            B.lbm_slab_halo_copy(self.slabs[p], self.bufs[p][c], self.slabs[down], self.bufs[down][c], "low", stream)
+
+    def _launch(self, p: int, tau: float, force, z_begin: int, z_end: int) -> None:
+        if z_begin < z_end:
+            B.lbm_step_slab(self.slabs[p], self.bufs[p][self.cur], self.bufs[p][1 - self.cur], tau, force,
+                            z_begin, z_end)
+
+    def step(self, tau: float, forces=None, overlap: bool = False) -> None:
+        """One step of the whole grid: exchange, inner planes, boundary planes.  With
+        `overlap` the exchange runs on a second stream concurrently with the inner
+        planes; the boundary planes wait for it."""
+        forces = forces if forces is not None else [None] * self.P
+        main = torch.cuda.current_stream()
+        if overlap:
+            if self._halo_stream is None:
+                self._halo_stream = torch.cuda.Stream()
+            hs = self._halo_stream
+            hs.wait_stream(main)  # the previous step has written the planes being sent
+            with torch.cuda.stream(hs):
+                self.exchange(hs)
+            for p in range(self.P):
+                self._launch(p, tau, forces[p], 1, self.planes[p] - 1)
+            main.wait_stream(hs)
+        else:
+            self.exchange()
+            for p in range(self.P):
+                self._launch(p, tau, forces[p], 1, self.planes[p] - 1)
+        for p in range(self.P):
+            n = self.planes[p]
+            self._launch(p, tau, forces[p], 0, 1)
+            if n > 1:
+                self._launch(p, tau, forces[p], n - 1, n)
+        self.cur = 1 - self.cur

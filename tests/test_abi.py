@@ -163,6 +163,47 @@ def test_copy_validation(B):
     assert lib.lbm_copy(MIS, P2, 16, None) == -3
 
 
+def test_slab_step_validation(B):
+    lib = B._lib
+    g = _grid(B)  # 8 x 8 x 8 D3Q27 f32: slab buffers of 10 planes
+
+    def step(grid, a=P1, b=P2, tau=0.6, force=None, z0=0, z1=8):
+        return lib.lbm_step_slab(ctypes.byref(grid), a, b, tau, force, z0, z1, None)
+
+    assert step(_grid(B, "D2Q9", nz=1), z1=1) == -5     # z-slabs need a 3D lattice
+    for z0, z1 in ((0, 0), (-1, 4), (0, 9), (5, 3)):
+        assert step(g, z0=z0, z1=z1) == -1              # empty or out-of-range plane range
+    assert step(g, tau=0.5) == -1
+    assert step(g, a=None) == -2
+    assert step(g, b=None) == -2
+    assert step(g, a=MIS) == -3
+    assert step(g, a=P1, b=P1) == -4
+    plane = 27 * 8 * 8 * 4
+    # f_out starts inside the last ghost plane of f_in: the buffers overlap
+    assert step(g, a=P1, b=ctypes.c_void_p(0x10000 + 9 * plane)) == -4
+    assert step(g, force=ctypes.c_void_p(0x10000 + 16)) == -4
+
+
+def test_slab_halo_validation(B):
+    lib = B._lib
+    g = _grid(B)
+
+    def halo(src_grid=g, src=P1, dst_grid=g, dst=P2, face=0):
+        return lib.lbm_slab_halo_copy(ctypes.byref(src_grid), src, ctypes.byref(dst_grid), dst, face, None)
+
+    assert halo(src_grid=_grid(B, "D2Q9", nz=1), dst_grid=_grid(B, "D2Q9", nz=1)) == -5
+    assert halo(dst_grid=_grid(B, nx=9)) == -1          # slabs must agree in nx, ny
+    assert halo(dst_grid=_grid(B, storage="f16s")) == -1
+    assert halo(dst_grid=_grid(B, "D3Q19")) == -1
+    assert halo(face=2) == -1
+    assert halo(src=None) == -2
+    assert halo(dst=MIS) == -3
+    plane = 27 * 8 * 8 * 4
+    # LOW reads src plane 1 and writes dst plane nz + 1 = 9: a dst 8 planes below src
+    # puts that ghost plane on top of the source plane
+    assert halo(dst=ctypes.c_void_p(0x10000 - 8 * plane), face=0) == -4
+
+
 def test_strerror(B):
     for code in range(-7, 1):
         assert B._lib.lbm_strerror(code)
