@@ -817,9 +817,10 @@ hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s) 
 }
 
 // z-slab halo exchange: direction rows [i0, i0 + n_dir) of each grid row of one plane,
-// a contiguous chunk of n_dir * nx words per row at a pitch of Q * nx words.
-template <typename W>
-__global__ __launch_bounds__(256) void halo_copy_kernel(const W* __restrict__ src, W* __restrict__ dst,
+// a contiguous chunk of n_dir * nx words per row at a pitch of Q * nx words.  T is the
+// word type, or a 16-byte vector when nx words fill whole 16-byte units.
+template <typename T>
+__global__ __launch_bounds__(256) void halo_copy_kernel(const T* __restrict__ src, T* __restrict__ dst,
                                                         uint64_t src_base, uint64_t dst_base, uint64_t pitch,
                                                         uint64_t chunk, uint32_t ny) {
   const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
@@ -827,21 +828,26 @@ __global__ __launch_bounds__(256) void halo_copy_kernel(const W* __restrict__ sr
   for (uint32_t y = blockIdx.y; y < ny; y += gridDim.y) dst[dst_base + y * pitch + k] = src[src_base + y * pitch + k];
 }
 
+template <typename T>
+static void launch_halo_t(const void* src, void* dst, uint64_t sb, uint64_t db, uint64_t pitch, uint64_t chunk,
+                          uint32_t ny, hipStream_t s) {
+  const dim3 grid((unsigned)((chunk + 255) / 256), ny < 4096u ? ny : 4096u);
+  halo_copy_kernel<T><<<grid, 256, 0, s>>>((const T*)src, (T*)dst, sb, db, pitch, chunk, ny);
+}
+
 hipError_t launch_halo_copy(int Q, int word_bytes, const void* src, uint64_t src_plane, void* dst, uint64_t dst_plane,
                             int i0, int n_dir, uint32_t nx, uint32_t ny, hipStream_t s) {
   const uint64_t pitch = (uint64_t)Q * nx, chunk = (uint64_t)n_dir * nx;
   const uint64_t sb = (src_plane * ny * Q + (uint64_t)i0) * nx, db = (dst_plane * ny * Q + (uint64_t)i0) * nx;
-  const dim3 grid((unsigned)((chunk + 255) / 256), ny < 4096u ? ny : 4096u);
+  if (((uint64_t)nx * word_bytes) % 16 == 0) {  // every offset is a whole number of 16-byte units
+    const uint64_t u = 16 / word_bytes;
+    launch_halo_t<u32x4>(src, dst, sb / u, db / u, pitch / u, chunk / u, ny, s);
+    return hipGetLastError();
+  }
   switch (word_bytes) {
-    case 2:
-      halo_copy_kernel<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)src, (uint16_t*)dst, sb, db, pitch, chunk, ny);
-      break;
-    case 4:
-      halo_copy_kernel<uint32_t><<<grid, 256, 0, s>>>((const uint32_t*)src, (uint32_t*)dst, sb, db, pitch, chunk, ny);
-      break;
-    case 8:
-      halo_copy_kernel<uint64_t><<<grid, 256, 0, s>>>((const uint64_t*)src, (uint64_t*)dst, sb, db, pitch, chunk, ny);
-      break;
+    case 2: launch_halo_t<uint16_t>(src, dst, sb, db, pitch, chunk, ny, s); break;
+    case 4: launch_halo_t<uint32_t>(src, dst, sb, db, pitch, chunk, ny, s); break;
+    case 8: launch_halo_t<uint64_t>(src, dst, sb, db, pitch, chunk, ny, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -58,6 +58,28 @@ def test_slabs_match_periodic_step(parts, lat, kind, forced):
     assert torch.equal(bits(S.gather()), bits(ref))
 
 
+@pytest.mark.parametrize("kind", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("parts", [[9], [5, 4], [3, 3, 3]], ids=lambda p: "x".join(map(str, p)))
+def test_slabs_match_periodic_step_vector_halo(kind, parts):
+    """nx = 64: rows are whole 16-byte units, so the exchange copies 16-byte vectors."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd.slabs import SlabSet
+
+    st = olbm.stencil("D3Q27")
+    spatial = (9, 5, 64)
+    grid = B.Grid("D3Q27", kind, 64, 5, 9)
+    say(f"slabs vector halo {kind} parts={parts}")
+    g0 = grid.to_layout(_state(st, spatial, 41, kind)).cuda()
+    ref = _periodic(B, grid, g0, 0.6, None, 3)
+    S = SlabSet(grid, parts)
+    S.scatter(g0)
+    for t in range(3):
+        S.step(0.6, overlap=True)
+    torch.cuda.synchronize()
+    assert torch.equal(bits(S.gather()), bits(ref))
+
+
 def test_slab_plane_ranges_compose():
     """Any split of a slab's planes into launches gives the same step as one launch
     over all of them, and planes outside the range are left untouched."""
