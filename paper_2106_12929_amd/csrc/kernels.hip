@@ -14,102 +14,23 @@
 // wave never straddles two rows, so the row index, the 9 source rows of the pull
 // gather and all row base addresses are wave-uniform (scalar registers); only the
 // three x columns x-1, x, x+1 (periodic) are per lane.  The step is HBM-bound (about
-// 1.5 flop per byte for D3Q27 FP32), so there is no MFMA and no LDS staging: L1/L2
-// absorb the +-1-word misalignment of the shifted loads.
+// 1.5 flop per byte for D3Q27 FP32), so there is no MFMA.  This file's step_kernel
+// moves one storage word per lane and access (L1/L2 absorb the +-1-word misalignment
+// of the shifted loads); step_lds.hip holds the variant that stages rows through LDS
+// with 16-byte accesses, used for 2- and 4-byte words when the rows split evenly into
+// block segments.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device.h"
 #include "kernels.h"
 #include "lattice.h"
 
 namespace lbm {
 
-__device__ __forceinline__ uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
-__device__ __forceinline__ uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
-
-// The cell of a thread.  y and z are wave-uniform (made scalar with readfirstlane).
-// Returns false for the threads of the ragged tails (x >= nx or past the last row).
-struct Cell {
-  uint32_t x, y, z;
-};
-
-__device__ __forceinline__ bool cell_of_thread(const GridArgs& g, Cell& c) {
-  const uint32_t bx = g.block_x;
-  const uint32_t blocks_x = (g.nx + bx - 1) / bx;
-  const uint32_t bxi = blockIdx.x % blocks_x;
-  const uint32_t byi = blockIdx.x / blocks_x;
-  // all 64 lanes of a wave share one row because block_x is a multiple of 64
-  const uint32_t ty = __builtin_amdgcn_readfirstlane(threadIdx.x / bx);
-  const uint32_t r = byi * (256u / bx) + ty;
-  c.x = bxi * bx + threadIdx.x % bx;
-  if (r >= g.ny * g.nzl) return false;
-  c.y = r % g.ny;
-  c.z = g.z0 + r / g.ny;
-  return c.x < g.nx;
-}
-
-// Source coordinates of the pull gather: index k = c + 1 holds the coordinate of
-// x - c for c = -1, 0, +1, wrapped periodically (c = -1 reads x + 1).
-struct Sources {
-  uint32_t x[3];  // per lane
-  uint32_t y[3];  // wave-uniform
-  uint32_t z[3];  // wave-uniform
-};
-
-__device__ __forceinline__ Sources sources(const Cell& c, const GridArgs& g) {
-  Sources s;
-  s.x[0] = wrap_inc(c.x, g.nx);
-  s.x[1] = c.x;
-  s.x[2] = wrap_dec(c.x, g.nx);
-  s.y[0] = wrap_inc(c.y, g.ny);
-  s.y[1] = c.y;
-  s.y[2] = wrap_dec(c.y, g.ny);
-  if (g.ghost) {  // z-slab: neighbours in z are buffer planes c.z + 2 and c.z (ghost planes at the ends)
-    s.z[0] = c.z + 2;
-    s.z[1] = c.z + 1;
-    s.z[2] = c.z;
-  } else {
-    s.z[0] = wrap_inc(c.z, g.nz);
-    s.z[1] = c.z;
-    s.z[2] = wrap_dec(c.z, g.nz);
-  }
-  return s;
-}
-
-// Word offset of direction row i of grid row (y, z): ((z*ny + y)*Q + i)*nx.
-template <int Q>
-__device__ __forceinline__ uint64_t dir_row(const GridArgs& g, uint32_t y, uint32_t z, int i) {
-  return (((uint64_t)z * g.ny + y) * Q + (uint64_t)i) * g.nx;
-}
-
-// Word offset of the pull source of direction i for the cell: g_i(x - c_i).
-template <typename LT>
-__device__ __forceinline__ uint64_t src_offset(const GridArgs& g, const Sources& s, int i) {
-  return dir_row<LT::Q>(g, s.y[LT::cy(i) + 1], s.z[LT::cz(i) + 1], i) + s.x[LT::cx(i) + 1];
-}
-
-// Word offset of direction i at x + c_i: the transpose of the pull gather (S^T).
-template <typename LT>
-__device__ __forceinline__ uint64_t rev_offset(const GridArgs& g, const Sources& s, int i) {
-  return dir_row<LT::Q>(g, s.y[1 - LT::cy(i)], s.z[1 - LT::cz(i)], i) + s.x[1 - LT::cx(i)];
-}
-
-// Linear cell index of real-valued fields ([D][N] arrays).
-__device__ __forceinline__ uint32_t cell_index(const GridArgs& g, const Cell& c) {
-  return (c.z * g.ny + c.y) * g.nx + c.x;
-}
-
-template <typename T>
-__device__ __forceinline__ void store_stream(T* p, T v) {
-  __builtin_nontemporal_store(v, p);
-}
-
 // ---------------------------------------------------------------------------------
-// Fused pull stream + BGK collide.  Eq. 1-4.  FM selects the per-cell field `force`:
-//   kNoForce     none
-//   kGuoForce    body force F (Guo: u = (sum c h + F/2)/rho in f^eq, plus the source)
-//   kShiftForce  velocity shift du: f^eq(rho, u + du) with u = sum c h / rho (the
-//                flow-control forcing of Sec. 3.2)
+// Fused pull stream + BGK collide (Eqs. 1-4), one word per lane and access.  FM selects
+// the per-cell field `force` (see bgk_collide).
 // ---------------------------------------------------------------------------------
 template <int L, int S, int FM>
 __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::word* __restrict__ fin,
@@ -132,67 +53,16 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(fin[src_offset<LT>(g, src, i)], CO::W(i));
 
-  // Moments (Eq. 4) in deviation form: rho = 1 + sum d, rho u = sum c d (+ F/2).
-  real drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    drho += d[i];
-    if (LT::cx(i) > 0) jx += d[i];
-    if (LT::cx(i) < 0) jx -= d[i];
-    if (LT::cy(i) > 0) jy += d[i];
-    if (LT::cy(i) < 0) jy -= d[i];
-    if (LT::cz(i) > 0) jz += d[i];
-    if (LT::cz(i) < 0) jz -= d[i];
-  }
-  constexpr bool FORCED = FM == kGuoForce;
   real Fx = 0, Fy = 0, Fz = 0;
   if constexpr (FM != kNoForce) {
     Fx = force[self];
     Fy = force[N + self];
     if constexpr (LT::D == 3) Fz = force[2 * N + self];
   }
-  if constexpr (FORCED) {
-    jx += real(0.5) * Fx;
-    jy += real(0.5) * Fy;
-    jz += real(0.5) * Fz;
-  }
-  const real rho = real(1) + drho;
-  const real inv_rho = real(1) / rho;
-  real ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
-  if constexpr (FM == kShiftForce) {
-    ux += Fx;
-    uy += Fy;
-    uz += Fz;
-  }
-  const real usq = real(1.5) * (ux * ux + uy * uy + uz * uz);
-  const real uF = ux * Fx + uy * Fy + uz * Fz;
-  const real guo = real(1) - real(0.5) * omega;
-
-  // Equilibrium (Eq. 3) as a deviation, BGK relaxation (Eq. 2), Guo source, store.
+  bgk_collide<L, real, FM>(d, Fx, Fy, Fz, omega);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    constexpr real zero = 0;
-    real cu = zero;
-    if (LT::cx(i) > 0) cu += ux;
-    if (LT::cx(i) < 0) cu -= ux;
-    if (LT::cy(i) > 0) cu += uy;
-    if (LT::cy(i) < 0) cu -= uy;
-    if (LT::cz(i) > 0) cu += uz;
-    if (LT::cz(i) < 0) cu -= uz;
-    const real deq = CO::W(i) * drho + rho * (CO::A(i) * cu + CO::B(i) * cu * cu - CO::W(i) * usq);
-    real dn = d[i] + omega * (deq - d[i]);
-    if constexpr (FORCED) {
-      real cF = zero;
-      if (LT::cx(i) > 0) cF += Fx;
-      if (LT::cx(i) < 0) cF -= Fx;
-      if (LT::cy(i) > 0) cF += Fy;
-      if (LT::cy(i) < 0) cF -= Fy;
-      if (LT::cz(i) > 0) cF += Fz;
-      if (LT::cz(i) < 0) cF -= Fz;
-      dn += guo * (CO::A(i) * cF - real(3) * CO::W(i) * uF + real(2) * CO::B(i) * cu * cF);
-    }
-    store_stream(&fout[dir_row<Q>(g, c.y, c.z + g.ghost, i) + c.x], ST::from_dev(dn, CO::W(i)));
-  }
+  for (int i = 0; i < Q; ++i)
+    store_stream(&fout[dir_row<Q>(g, c.y, c.z + g.ghost, i) + c.x], ST::from_dev(d[i], CO::W(i)));
 }
 
 // ---------------------------------------------------------------------------------
@@ -758,6 +628,8 @@ static hipError_t launch_moments_adjoint_ls(const void* f, const void* force, co
 
 hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
                        const GridArgs& g, double omega, hipStream_t s) {
+  if (step_lds_eligible(storage, g))
+    return launch_step_lds(lattice, storage, fin, fout, force, force_mode, g, omega, s);
   LBM_DISPATCH(launch_step_ls, lattice, storage, fin, fout, force, force_mode, g, omega, s);
 }
 
@@ -803,7 +675,6 @@ hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fou
 
 // Plain streaming copy (16-byte words, one per thread): the practical HBM bandwidth
 // reference the step kernel is compared with.
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void copy16_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
