@@ -75,7 +75,9 @@ def _tolerance_ok(kind, st, got, ref, tau=0.57):
       base offset through with factor omega.
     f32s: 1 ulp of the stored deviation plus FP32 roundoff of terms of size w_i.
     f16s/bf16s: 1 ulp of the storage format (the FP32 arithmetic may land on the
-    other side of a rounding boundary than exact arithmetic).
+    other side of a rounding boundary than exact arithmetic), plus the same FP32
+    roundoff floor: where the deviation itself is tiny, one bfloat16 ulp is smaller
+    than the absolute error of FP32 arithmetic on terms of size w_i.
     """
     g = ost.dequantize(got.cpu(), st, kind)
     r = ost.dequantize(ref, st, kind)
@@ -89,7 +91,7 @@ def _tolerance_ok(kind, st, got, ref, tau=0.57):
         dev_r = ost.quantize(r, st, kind).double()
         dev_g = got.cpu().double()
         u = torch.maximum(ost.ulp(dev_r, kind), ost.ulp(dev_g, kind))
-        bound = u + (8 * 2.0 ** -24 * w if kind == "f32s" else 0.0)
+        bound = u + 8 * 2.0 ** -24 * w
     excess = diff - bound
     same = float((bits(got.cpu()) == bits(ost.quantize(r, st, kind))).double().mean())
     return float(excess.max()), float((diff / bound.clamp(min=1e-300)).max()), same
