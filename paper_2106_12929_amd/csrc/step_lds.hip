@@ -113,9 +113,14 @@ __global__ __launch_bounds__(256) void step_lds_kernel(const typename Storage<S>
   const uint32_t lx = threadIdx.x % BX;
   const uint32_t r = row0 + ty;
   const bool live = r < rows;
-  real d[Q];
+  // The words to store are formed right after the collision, in the same basic block as
+  // its last arithmetic, so the compiler rounds to the storage format exactly as in
+  // step_kernel (for 16-bit words it fuses the last FMA with the conversion) and both
+  // kernels give identical bits.
+  W out[Q];
   if (live) {
     const uint32_t base = ty * Q * P * V + V + lx;
+    real d[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(sw[base + (uint32_t)i * P * V - LT::cx(i)], CO::W(i));
     real Fx = 0, Fy = 0, Fz = 0;
@@ -128,12 +133,14 @@ __global__ __launch_bounds__(256) void step_lds_kernel(const typename Storage<S>
       if constexpr (LT::D == 3) Fz = force[2 * N + self];
     }
     bgk_collide<L, real, FM>(d, Fx, Fy, Fz, omega);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i] = ST::from_dev(d[i], CO::W(i));
   }
   __syncthreads();
   if (live) {
     const uint32_t base = ty * Q * P * V + V + lx;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) sw[base + (uint32_t)i * P * V] = ST::from_dev(d[i], CO::W(i));
+    for (int i = 0; i < Q; ++i) sw[base + (uint32_t)i * P * V] = out[i];
   }
   __syncthreads();
 
