@@ -23,11 +23,6 @@ struct GridArgs {
 
 hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
                        const GridArgs& g, double omega, hipStream_t s);
-// LDS-staged step (step_lds.hip): eligible for 2- and 4-byte words when nx is a multiple
-// of block_x; launch_step uses it whenever it is.
-bool step_lds_eligible(int storage, const GridArgs& g);
-hipError_t launch_step_lds(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
-                           const GridArgs& g, double omega, hipStream_t s);
 hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s);
 hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
                        hipStream_t s);

@@ -14,11 +14,11 @@
 // wave never straddles two rows, so the row index, the 9 source rows of the pull
 // gather and all row base addresses are wave-uniform (scalar registers); only the
 // three x columns x-1, x, x+1 (periodic) are per lane.  The step is HBM-bound (about
-// 1.5 flop per byte for D3Q27 FP32), so there is no MFMA.  This file's step_kernel
-// moves one storage word per lane and access (L1/L2 absorb the +-1-word misalignment
-// of the shifted loads); step_lds.hip holds the variant that stages rows through LDS
-// with 16-byte accesses, used for 2- and 4-byte words when the rows split evenly into
-// block segments.
+// 1.5 flop per byte for D3Q27 FP32), so there is no MFMA; each lane moves one storage
+// word per access and keeps its cell's Q populations in registers (L1/L2 absorb the
+// +-1-word misalignment of the shifted loads).  Staging rows through LDS with 16-byte
+// accesses speeds up a bare gather-copy but slows the full step: the LDS a block needs
+// caps occupancy below what the register-resident form reaches.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -628,8 +628,6 @@ static hipError_t launch_moments_adjoint_ls(const void* f, const void* force, co
 
 hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
                        const GridArgs& g, double omega, hipStream_t s) {
-  if (step_lds_eligible(storage, g))
-    return launch_step_lds(lattice, storage, fin, fout, force, force_mode, g, omega, s);
   LBM_DISPATCH(launch_step_ls, lattice, storage, fin, fout, force, force_mode, g, omega, s);
 }
 

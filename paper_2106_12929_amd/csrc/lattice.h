@@ -115,11 +115,6 @@ struct Coef<kD3Q27, float> {
 // ---------------------------------------------------------------------------------
 
 __device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
-  // The empty asm pins x as a finished FP32 value: the compiler may otherwise fuse the
-  // FMA that produced it with this conversion (v_fma_mixlo_f16, one rounding instead of
-  // FP32-then-FP16), and whether it does depends on the surrounding code, so two kernels
-  // with the same arithmetic could store different bits.
-  __asm__ volatile("" : "+v"(x));
   _Float16 h = static_cast<_Float16>(x);  // v_cvt_f16_f32: RNE in the default mode
   return __builtin_bit_cast(uint16_t, h);
 }

@@ -491,6 +491,40 @@ def test_large_2d_grid_sampled():
     assert excess <= 0, ratio
 
 
+# nx a multiple of the block's row segment (64, 128 or 256 cells) with row counts that
+# leave the last block of 4 or 2 rows partly empty
+ALIGNED = [("D3Q27", (64, 7, 5)), ("D3Q27", (128, 5, 3)), ("D3Q27", (256, 3, 2)), ("D3Q27", (384, 3, 2)),
+           ("D3Q27", (192, 3, 3)), ("D3Q19", (64, 5, 3)), ("D3Q19", (256, 3, 3)), ("D2Q9", (64, 13, 1)),
+           ("D2Q9", (256, 5, 1)), ("D2Q9", (384, 7, 1))]
+
+
+@pytest.mark.parametrize("lat,shape", ALIGNED)
+@pytest.mark.parametrize("kind", ["f32", "f32s", "f16s", "bf16s"])
+@pytest.mark.parametrize("mode", ["none", "guo", "shift"])
+def test_aligned_shapes_step_parity(lat, shape, kind, mode):
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    grid = B.Grid(lat, kind, *shape)
+    spatial = _spatial(lat, shape)
+    tau = 0.57
+    say(f"aligned step {lat} {kind} {shape} {mode}")
+    s = _state(st, spatial, 21, kind)
+    out = grid.empty_populations()
+    g_in = grid.to_layout(s).cuda()
+    if mode == "shift":
+        du = synthetic.random_normal((grid.D,) + spatial, 23, 1e-3).to(grid.real_dtype)
+        assert B.lbm_step_shifted(grid, g_in, out, tau, du.cuda(), 1) == 0
+        ref = ost.step_emulated(s, tau, st, kind, du=du.double())
+    else:
+        F = _force(grid, spatial, 22) if mode == "guo" else None
+        assert B.lbm_step(grid, g_in, out, tau, None if F is None else F.cuda(), 1) == 0
+        ref = ost.step_emulated(s, tau, st, kind, None if F is None else F.double())
+    excess, ratio, same = _tolerance_ok(kind, st, grid.from_layout(out.cpu()), ref, tau)
+    say(f"  max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
+    assert excess <= 0, ratio
+
+
 @pytest.mark.parametrize("kind,n", [("f32", 256), ("f64", 256), ("f16s", 256), ("bf16s", 256), ("f16s", 512)])
 def test_full_size_sampled(kind, n):
     """Full-size grids in the benchmark's launch shape: one step compared with the
