@@ -19,6 +19,7 @@ from __future__ import annotations
 import torch
 
 from . import lbm
+from . import neural as nn_oracle
 
 KINDS = ("f64", "f32", "f32s", "f16s", "bf16s")
 _DTYPE = {"f64": torch.float64, "f32": torch.float32, "f32s": torch.float32,
@@ -55,12 +56,16 @@ def dequantize(s: torch.Tensor, st: lbm.Stencil, kind: str) -> torch.Tensor:
 
 def step_emulated(s: torch.Tensor, tau: float, st: lbm.Stencil, kind: str,
                   force: torch.Tensor | None = None, du: torch.Tensor | None = None,
-                  mrt_taus=None) -> torch.Tensor:
+                  mrt_taus=None, neural=None) -> torch.Tensor:
     """One pull step on stored populations: dequantise, exact FP64 step, quantise.
     With `du` the step uses the shifted-velocity equilibrium instead of a force; with
-    `mrt_taus` (9 relaxation times) the MRT collision of Eq. 5."""
+    `mrt_taus` (9 relaxation times) the MRT collision of Eq. 5; with
+    `neural` = (params, activation) the neural collision of Sec. 3.1 with shear time
+    `tau`."""
     f = dequantize(s, st, kind)
-    if mrt_taus is not None:
+    if neural is not None:
+        out = nn_oracle.step(f, tau, neural[0], neural[1], st)
+    elif mrt_taus is not None:
         out = lbm.step_mrt(f, mrt_taus, st)
     elif du is not None:
         out = lbm.step_shifted(f, tau, st, du)
