@@ -86,13 +86,20 @@ def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = 
 
 def run_d2q9(B, steps: int, warmup: int, n: int = 8192):
     """D2Q9 throughput on an n x n periodic grid (Taylor-Green start): the BGK step for
-    several storage kinds, and the MRT step (Eq. 5) with uniform relaxation times and
-    with per-cell ghost-moment times (3 more values read per cell)."""
+    several storage kinds, the MRT step (Eq. 5) with uniform relaxation times and with
+    per-cell ghost-moment times (3 more values read per cell), and the neural collision
+    (MRT with ghost times from a 6-53-3 network per cell, Sec. 3.1)."""
     from synthetic import taylor_green_2d
     u = taylor_green_2d(n, n, 0.05).cuda()
     taus = [1, 1, 1, 0.6, 0.6, 0.6, 0.9, 0.8, 0.7]
     out = {}
-    for storage, kinds in (("f32", ("bgk", "mrt", "mrt_cell")), ("f16s", ("bgk", "mrt", "mrt_cell")),
+    gen = torch.Generator().manual_seed(5)
+    # a random 6-53-3 network (first layer scaled to inputs of ~1e-3)
+    params = torch.cat([torch.randn(318, generator=gen, dtype=torch.float64) * 1e3,
+                        torch.randn(53, generator=gen, dtype=torch.float64) * 0.5,
+                        torch.randn(159, generator=gen, dtype=torch.float64) * 0.2])
+    for storage, kinds in (("f32", ("bgk", "mrt", "mrt_cell", "neural_relu", "neural_tanh")),
+                           ("f16s", ("bgk", "mrt", "mrt_cell", "neural_relu", "neural_tanh")),
                            ("f64", ("bgk", "mrt"))):
         grid = B.Grid("D2Q9", storage, n, n)
         bufs = [grid.empty_populations(), grid.empty_populations()]
@@ -103,10 +110,14 @@ def run_d2q9(B, steps: int, warmup: int, n: int = 8192):
                 tg = torch.empty((3, n, n), dtype=grid.real_dtype, device="cuda").uniform_(0.55, 1.2)
             cur = [0]
 
+            p_dev = params.to(grid.real_dtype).cuda()
+
             def one():
                 a, b = bufs[cur[0]], bufs[1 - cur[0]]
                 if kind == "bgk":
                     B.lbm_step(grid, a, b, 0.6, None, 1)
+                elif kind.startswith("neural"):
+                    B.lbm_step_neural(grid, a, b, 0.6, p_dev, kind.split("_")[1], 1)
                 else:
                     B.lbm_step_mrt(grid, a, b, taus, tg if kind == "mrt_cell" else None, 1)
                 cur[0] ^= 1

@@ -192,6 +192,32 @@ int lbm_step_slab(const lbm_grid* slab, const void* f_in, void* f_out, double ta
 int lbm_slab_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid* dst_slab,
                        void* dst, int face, void* stream);
 
+/* Activation of the neural collision's hidden layer (lbm_step_neural). */
+enum lbm_activation { LBM_ACT_RELU = 0, LBM_ACT_TANH = 1 };
+
+/* Number of parameters of the neural collision's network. */
+#define LBM_NEURAL_PARAMS 530
+
+/* D2Q9 steps with the neural collision model of Sec. 3.1: the MRT collision of Eq. 5
+ * (as lbm_step_mrt) with tau_0..2 = 1, tau_3..5 = tau_shear, and tau_6, tau_7, tau_8
+ * given per cell and step by a shallow network, tau_n = exp(t_n) + 1/2.
+ * The paper fixes one hidden layer, 530 parameters, local moments as inputs and the
+ * exp(.) + 1/2 output map; the library reads it as
+ *   inputs  x = (Pi_xx, Pi_xy, Pi_yy, N, J_x, J_y) of the non-equilibrium part h - f^eq
+ *           of the streamed populations (Dellar's rows c_x^2, c_x c_y, c_y^2, g, g c_x,
+ *           g c_y, g = (3c_x^2-1)(3c_y^2-1));
+ *   hidden  a_j = act(b1_j + sum_k W1_jk x_k), j = 0..52;
+ *   output  t_n = sum_j W2_nj a_j, n = 0..2 (tau_6, tau_7, tau_8), no output bias;
+ * 6*53 + 53 + 3*53 = 530 parameters.
+ * params: LBM_NEURAL_PARAMS reals (device) in the order W1 [53][6] row-major, b1 [53],
+ *   W2 [3][53] row-major; arithmetic in the storage kind's real type.
+ * activation: LBM_ACT_RELU or LBM_ACT_TANH.
+ * tau_shear > 1/2 sets nu = (tau_shear - 1/2)/3.  Same ping-pong, return value and
+ * buffer rules as lbm_step; params must not overlap the population buffers.  LBM_EUNSUP
+ * for lattices other than D2Q9. */
+int lbm_step_neural(const lbm_grid* grid, void* f_in, void* f_out, double tau_shear,
+                    const void* params, int activation, int n_steps, void* stream);
+
 /* Streaming only: f_out_i(x) = f_in_i(x - c_i), periodic (Eq. 1's shift), copying the
  * raw storage words (a permutation: bit-exact for every storage kind).  Buffers must not
  * overlap. */

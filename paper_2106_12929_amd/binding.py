@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LATTICES = {"D2Q9": 0, "D3Q27": 1, "D3Q19": 2}
 STORAGES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3, "bf16s": 4}
 FACES = {"low": 0, "high": 1}
+ACTIVATIONS = {"relu": 0, "tanh": 1}
+NEURAL_PARAMS = 530
 STORAGE_DTYPE = {"f64": torch.float64, "f32": torch.float32, "f32s": torch.float32,
                  "f16s": torch.float16, "bf16s": torch.bfloat16}
 NRED = 8
@@ -57,6 +59,7 @@ def _load() -> ctypes.CDLL:
         "lbm_step": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
         "lbm_step_shifted": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
         "lbm_step_mrt": (i32, [gp, vp, vp, ctypes.POINTER(dbl), vp, i32, vp]),
+        "lbm_step_neural": (i32, [gp, vp, vp, dbl, vp, i32, i32, vp]),
         "lbm_stream_only": (i32, [gp, vp, vp, vp]),
         "lbm_moments_workspace_size": (i32, [gp, ctypes.POINTER(sz)]),
         "lbm_moments": (i32, [gp, vp, vp, vp, vp, vp, vp, sz, vp]),
@@ -249,6 +252,20 @@ def lbm_step_mrt(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, taus, tau_
     b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
     tg = _dev_ptr(tau_ghost, "tau_ghost", grid.real_dtype, 3 * N, required=False)
     return _check(_lib.lbm_step_mrt(ctypes.byref(g), a, b, t, tg, int(n_steps), _stream(stream)), "lbm_step_mrt")
+
+
+def lbm_step_neural(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau_shear: float,
+                    params: torch.Tensor, activation: str = "relu", n_steps: int = 1, stream=None) -> int:
+    """D2Q9 steps with the neural collision (MRT with network-given tau_6..8);
+    params: 530 reals (W1 [53][6], b1 [53], W2 [3][53]).  Returns 0 (result in f_out)
+    or 1 (in f_in)."""
+    N = grid.ncells
+    g = grid.c_struct()
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    p = _dev_ptr(params, "params", grid.real_dtype, NEURAL_PARAMS)
+    return _check(_lib.lbm_step_neural(ctypes.byref(g), a, b, float(tau_shear), p, ACTIVATIONS[activation],
+                                       int(n_steps), _stream(stream)), "lbm_step_neural")
 
 
 def lbm_step_slab(slab: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: float,

@@ -237,33 +237,65 @@ int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, 
   return step_common(grid, f_in, f_out, tau, du, lbm::kShiftForce, n_steps, stream, "lbm_step_shifted launch");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Shared validation and launch loop of the MRT entry points.
+int mrt_common(const lbm_grid* grid, void* f_in, void* f_out, const double* taus, const void* ghost,
+               size_t ghost_bytes, int ghost_mode, int n_steps, void* stream, const char* name) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  if (grid->lattice != LBM_D2Q9) return fail(LBM_EUNSUP, "%s supports D2Q9 only", name);
+  if (n_steps < 1) return fail(LBM_EINVAL, "n_steps must be >= 1 (got %d)", n_steps);
+  LBM_TRY(check_ptr(f_in, "f_in", true));
+  LBM_TRY(check_ptr(f_out, "f_out", true));
+  const size_t N = geo.args.ncells;
+  const size_t fbytes = geo.Q * N * geo.word;
+  if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
+  if (overlap(ghost, ghost_bytes, f_in, fbytes) || overlap(ghost, ghost_bytes, f_out, fbytes))
+    return fail(LBM_EALIAS, "the ghost-time source overlaps a population buffer");
+  // |R_k|^2 of the w-orthogonal moment rows 3..8 (see mrt_step_kernel)
+  const double norm2[6] = {2.0, 1.0 / 9.0, 2.0, 4.0, 8.0 / 3.0, 8.0 / 3.0};
+  double scales[6];
+  for (int k = 0; k < 6; ++k) scales[k] = 1.0 / (taus[k + 3] * norm2[k]);
+  void* bufs[2] = {f_in, f_out};
+  for (int k = 0; k < n_steps; ++k) {
+    const hipError_t e = lbm::launch_mrt(grid->storage, bufs[k & 1], bufs[(k + 1) & 1], ghost, ghost_mode, geo.args,
+                                         scales, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, name);
+  }
+  return (n_steps & 1) ? 0 : 1;
+}
+
+}  // namespace
+
+extern "C" {
+
 int lbm_step_mrt(const lbm_grid* grid, void* f_in, void* f_out, const double* tau_moments, const void* tau_ghost,
                  int n_steps, void* stream) {
   Geometry geo;
   LBM_TRY(check_grid(grid, &geo));
-  if (grid->lattice != LBM_D2Q9) return fail(LBM_EUNSUP, "lbm_step_mrt supports D2Q9 only");
   if (!tau_moments) return fail(LBM_ENULL, "tau_moments is NULL");
   for (int k = 3; k < 9; ++k) LBM_TRY(check_tau(tau_moments[k]));
-  if (n_steps < 1) return fail(LBM_EINVAL, "n_steps must be >= 1 (got %d)", n_steps);
-  LBM_TRY(check_ptr(f_in, "f_in", true));
-  LBM_TRY(check_ptr(f_out, "f_out", true));
   LBM_TRY(check_ptr(tau_ghost, "tau_ghost", false));
-  const size_t N = geo.args.ncells;
-  const size_t fbytes = geo.Q * N * geo.word, tbytes = 3 * N * geo.real;
-  if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
-  if (overlap(tau_ghost, tbytes, f_in, fbytes) || overlap(tau_ghost, tbytes, f_out, fbytes))
-    return fail(LBM_EALIAS, "tau_ghost overlaps a population buffer");
-  // |R_k|^2 of the w-orthogonal moment rows 3..8 (see mrt_step_kernel)
-  const double norm2[6] = {2.0, 1.0 / 9.0, 2.0, 4.0, 8.0 / 3.0, 8.0 / 3.0};
-  double scales[6];
-  for (int k = 0; k < 6; ++k) scales[k] = 1.0 / (tau_moments[k + 3] * norm2[k]);
-  void* bufs[2] = {f_in, f_out};
-  for (int k = 0; k < n_steps; ++k) {
-    const hipError_t e = lbm::launch_mrt(grid->storage, bufs[k & 1], bufs[(k + 1) & 1], tau_ghost, geo.args, scales,
-                                         (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "lbm_step_mrt launch");
-  }
-  return (n_steps & 1) ? 0 : 1;
+  return mrt_common(grid, f_in, f_out, tau_moments, tau_ghost, 3 * geo.args.ncells * geo.real,
+                    tau_ghost ? lbm::kGhostField : lbm::kGhostUniform, n_steps, stream, "lbm_step_mrt");
+}
+
+int lbm_step_neural(const lbm_grid* grid, void* f_in, void* f_out, double tau_shear, const void* params,
+                    int activation, int n_steps, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_tau(tau_shear));
+  if (activation != LBM_ACT_RELU && activation != LBM_ACT_TANH)
+    return fail(LBM_EINVAL, "activation must be LBM_ACT_RELU or LBM_ACT_TANH (got %d)", activation);
+  LBM_TRY(check_ptr(params, "params", true));
+  // tau_6..8 come from the network; these uniform values are not used
+  const double taus[9] = {1, 1, 1, tau_shear, tau_shear, tau_shear, 1, 1, 1};
+  return mrt_common(grid, f_in, f_out, taus, params, (size_t)lbm::kNeuralParams * geo.real,
+                    activation == LBM_ACT_RELU ? lbm::kGhostRelu : lbm::kGhostTanh, n_steps, stream,
+                    "lbm_step_neural");
 }
 
 int lbm_step_slab(const lbm_grid* slab, const void* f_in, void* f_out, double tau, const void* force,

@@ -32,8 +32,13 @@ hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, co
                           const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s);
 hipError_t launch_unstream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g,
                            hipStream_t s);
-// scales[k] = 1 / (tau_{k+3} |R_{k+3}|^2), k = 0..5 (see mrt_step_kernel)
-hipError_t launch_mrt(int storage, const void* fin, void* fout, const void* tau_ghost, const GridArgs& g,
+// Source of the MRT ghost times tau_6..8 (see mrt_step_kernel).
+enum GhostMode { kGhostUniform = 0, kGhostField = 1, kGhostRelu = 2, kGhostTanh = 3 };
+constexpr int kNeuralHidden = 53;                            // hidden units of the neural collision
+constexpr int kNeuralParams = 6 * kNeuralHidden + kNeuralHidden + 3 * kNeuralHidden;  // 530
+// scales[k] = 1 / (tau_{k+3} |R_{k+3}|^2), k = 0..5 (see mrt_step_kernel); ghost: the
+// per-cell times (kGhostField) or the network parameters (kGhostRelu, kGhostTanh).
+hipError_t launch_mrt(int storage, const void* fin, void* fout, const void* ghost, int ghost_mode, const GridArgs& g,
                       const double* scales, hipStream_t s);
 // Copies n_dir consecutive direction rows of every grid row of plane `src_plane` of
 // src into plane `dst_plane` of dst (planes in buffer coordinates), starting at

@@ -75,17 +75,46 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
 // so Eq. 5's operator -M^{-1} S^{-1} (M f - m^eq) acting on f - f^eq (zero conserved
 // part) is  f'_i = h_i - w_i sum_{k=3..8} R_k(c_i) n_k / (tau_k |R_k|^2),
 // n_k = sum_i R_k(c_i) (h_i - f^eq_i),  |R_k|^2 = sum_i w_i R_k(c_i)^2 = 2, 1/9, 2, 4,
-// 8/3, 8/3.  scale[k-3] = 1/(tau_k |R_k|^2) for uniform times; a per-cell field
-// tau_ghost[3][N] replaces tau_6..8 (the neural collision's outputs).
+// 8/3, 8/3.  scale[k-3] = 1/(tau_k |R_k|^2) for uniform times.  GM selects where the
+// ghost times tau_6..8 come from:
+//   kGhostUniform  the uniform scales
+//   kGhostField    a per-cell field ghost[3][N]
+//   kGhostRelu,    the neural collision of Sec. 3.1: per cell, a network with inputs
+//   kGhostTanh     x = (Pi_xx, Pi_xy, Pi_yy, N, J_x, J_y) of h - f^eq, i.e.
+//                  (n_3/3, n_4, n_5/3, n_6, n_7, n_8), 53 hidden units
+//                  a_j = act(b1_j + sum_k W1_jk x_k) and outputs t_n = sum_j W2_nj a_j,
+//                  tau_{6+n} = exp(t_n) + 1/2.  ghost = the 530 parameters, W1 [53][6],
+//                  b1 [53], W2 [3][53]; every lane reads the same addresses, so they
+//                  come in through scalar loads.
 // ---------------------------------------------------------------------------------
 struct MrtScales {
   double s[6];
 };
 
-template <int S, bool CELL_GHOST>
+template <typename real>
+__device__ __forceinline__ real act_tanh(real z) {
+  return tanh(z);
+}
+// FP32: tanh z = 1 - 2/(e^{2z} + 1) with the hardware exponential; absolute error about
+// 1e-7 (relative error grows only where tanh z itself is below that), saturating
+// cleanly to +-1 where e^{2z} overflows or underflows.
+template <>
+__device__ __forceinline__ float act_tanh<float>(float z) {
+  return 1.0f - 2.0f / (__expf(2.0f * z) + 1.0f);
+}
+template <typename real>
+__device__ __forceinline__ real exp_real(real z) {
+  return exp(z);
+}
+template <>
+__device__ __forceinline__ float exp_real<float>(float z) {
+  return expf(z);
+}
+
+template <int S, int GM>
 __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>::word* __restrict__ fin,
                                                        typename Storage<S>::word* __restrict__ fout,
-                                                       const typename Storage<S>::real* __restrict__ tau_ghost,
+                                                       const typename Storage<S>::real* __restrict__ ghost,
                                                        GridArgs g, MrtScales sc) {
   using LT = Lattice<kD2Q9>;
   using ST = Storage<S>;
@@ -130,11 +159,30 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
     nJy += gi * real(cy) * ne[i];
   }
   real s6 = real(sc.s[3]), s7 = real(sc.s[4]), s8 = real(sc.s[5]);
-  if constexpr (CELL_GHOST) {
+  if constexpr (GM == kGhostField) {
     const uint32_t n = cell_index(g, c);
-    s6 = real(1) / (real(4) * tau_ghost[n]);
-    s7 = real(3) / (real(8) * tau_ghost[N + n]);
-    s8 = real(3) / (real(8) * tau_ghost[2 * N + n]);
+    s6 = real(1) / (real(4) * ghost[n]);
+    s7 = real(3) / (real(8) * ghost[N + n]);
+    s8 = real(3) / (real(8) * ghost[2 * N + n]);
+  } else if constexpr (GM == kGhostRelu || GM == kGhostTanh) {
+    const real x[6] = {nxx * real(1.0 / 3.0), nxy, nyy * real(1.0 / 3.0), nN, nJx, nJy};
+    const real* __restrict__ W1 = ghost;
+    const real* __restrict__ b1 = ghost + kNeuralHidden * 6;
+    const real* __restrict__ W2 = b1 + kNeuralHidden;
+    real t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+    for (int j = 0; j < kNeuralHidden; ++j) {
+      real z = b1[j];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) z += W1[6 * j + k] * x[k];
+      const real a = GM == kGhostRelu ? (z > real(0) ? z : real(0)) : act_tanh<real>(z);
+      t0 += W2[j] * a;
+      t1 += W2[kNeuralHidden + j] * a;
+      t2 += W2[2 * kNeuralHidden + j] * a;
+    }
+    s6 = real(1) / (real(4) * (exp_real<real>(t0) + real(0.5)));
+    s7 = real(3) / (real(8) * (exp_real<real>(t1) + real(0.5)));
+    s8 = real(3) / (real(8) * (exp_real<real>(t2) + real(0.5)));
   }
   const real axx = nxx * real(sc.s[0]), axy = nxy * real(sc.s[1]), ayy = nyy * real(sc.s[2]);
   const real aN = nN * s6, aJx = nJx * s7, aJy = nJy * s8;
@@ -524,28 +572,34 @@ static hipError_t launch_step_ls(const void* fin, void* fout, const void* force,
 }
 
 template <int S>
-static hipError_t launch_mrt_s(const void* fin, void* fout, const void* tau_ghost, const GridArgs& g,
+static hipError_t launch_mrt_s(const void* fin, void* fout, const void* ghost, int ghost_mode, const GridArgs& g,
                                const double* scales, hipStream_t s) {
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
   MrtScales sc;
   for (int k = 0; k < 6; ++k) sc.s[k] = scales[k];
-  if (tau_ghost)
-    mrt_step_kernel<S, true><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, (const R*)tau_ghost, g, sc);
-  else
-    mrt_step_kernel<S, false><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, nullptr, g, sc);
+  const W* a = (const W*)fin;
+  W* b = (W*)fout;
+  const R* gh = (const R*)ghost;
+  switch (ghost_mode) {
+    case kGhostUniform: mrt_step_kernel<S, kGhostUniform><<<cell_grid(g), 256, 0, s>>>(a, b, nullptr, g, sc); break;
+    case kGhostField: mrt_step_kernel<S, kGhostField><<<cell_grid(g), 256, 0, s>>>(a, b, gh, g, sc); break;
+    case kGhostRelu: mrt_step_kernel<S, kGhostRelu><<<cell_grid(g), 256, 0, s>>>(a, b, gh, g, sc); break;
+    case kGhostTanh: mrt_step_kernel<S, kGhostTanh><<<cell_grid(g), 256, 0, s>>>(a, b, gh, g, sc); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_mrt(int storage, const void* fin, void* fout, const void* tau_ghost, const GridArgs& g,
+hipError_t launch_mrt(int storage, const void* fin, void* fout, const void* ghost, int ghost_mode, const GridArgs& g,
                       const double* scales, hipStream_t s) {
   switch (storage) {
-    case kF64: return launch_mrt_s<kF64>(fin, fout, tau_ghost, g, scales, s);
-    case kF32: return launch_mrt_s<kF32>(fin, fout, tau_ghost, g, scales, s);
-    case kF32S: return launch_mrt_s<kF32S>(fin, fout, tau_ghost, g, scales, s);
-    case kF16S: return launch_mrt_s<kF16S>(fin, fout, tau_ghost, g, scales, s);
-    case kBF16S: return launch_mrt_s<kBF16S>(fin, fout, tau_ghost, g, scales, s);
+    case kF64: return launch_mrt_s<kF64>(fin, fout, ghost, ghost_mode, g, scales, s);
+    case kF32: return launch_mrt_s<kF32>(fin, fout, ghost, ghost_mode, g, scales, s);
+    case kF32S: return launch_mrt_s<kF32S>(fin, fout, ghost, ghost_mode, g, scales, s);
+    case kF16S: return launch_mrt_s<kF16S>(fin, fout, ghost, ghost_mode, g, scales, s);
+    case kBF16S: return launch_mrt_s<kBF16S>(fin, fout, ghost, ghost_mode, g, scales, s);
   }
   return hipErrorInvalidValue;
 }

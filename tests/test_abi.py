@@ -163,6 +163,23 @@ def test_copy_validation(B):
     assert lib.lbm_copy(MIS, P2, 16, None) == -3
 
 
+def test_neural_step_validation(B):
+    lib = B._lib
+    g2 = _grid(B, "D2Q9", nz=1)
+
+    def neural(grid=g2, a=P1, b=P2, tau=0.6, params=P3, act=0, n=1):
+        return lib.lbm_step_neural(ctypes.byref(grid), a, b, tau, params, act, n, None)
+
+    assert neural(grid=_grid(B)) == -5                  # D2Q9 only
+    assert neural(tau=0.5) == -1
+    assert neural(act=2) == -1
+    assert neural(n=0) == -1
+    assert neural(params=None) == -2
+    assert neural(params=MIS) == -3
+    assert neural(a=P1, b=P1) == -4
+    assert neural(params=ctypes.c_void_p(0x10000 + 64)) == -4   # params inside f_in
+
+
 def test_slab_step_validation(B):
     lib = B._lib
     g = _grid(B)  # 8 x 8 x 8 D3Q27 f32: slab buffers of 10 planes

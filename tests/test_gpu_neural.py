@@ -1,0 +1,106 @@
+"""GPU checks of lbm_step_neural (the neural collision of Sec. 3.1: MRT with ghost
+relaxation times from a 6-53-3 network evaluated per cell): one-step parity with the
+oracle for every storage kind and both activations, the zero network against the
+MRT kernel with ghost times 3/2, and a stable multi-step run."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import lbm as olbm
+from oracle import neural as onn
+from oracle import storage as ost
+
+from _helpers import binding, bits, need_gpu, say
+from test_gpu_forward import KINDS, _state, _tolerance_ok
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(13, 17), (300, 7), (64, 13)]
+
+
+def _params(st, s, kind, seed, w2_scale=0.3):
+    """Random network whose first layer is scaled to the spread of the inputs, so that
+    the pre-activations are of order one (the inputs themselves are ~1e-3)."""
+    x = onn.inputs(olbm.stream(ost.dequantize(s, st, kind), st), st).reshape(6, -1)
+    spread = x.std(dim=1).numpy() + 1e-30
+    g = np.random.default_rng(seed)
+    W1 = g.normal(0, 1, (onn.N_HIDDEN, onn.N_IN)) / spread
+    b1 = g.normal(0, 0.5, onn.N_HIDDEN)
+    W2 = g.normal(0, w2_scale, (onn.N_OUT, onn.N_HIDDEN))
+    return torch.from_numpy(np.concatenate([W1.ravel(), b1, W2.ravel()]))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("activation", ["relu", "tanh"])
+def test_neural_step_parity(shape, kind, activation):
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D2Q9")
+    nx, ny = shape
+    grid = B.Grid("D2Q9", kind, nx, ny)
+    say(f"neural step {kind} {shape} {activation}")
+    s = _state(st, (ny, nx), 51, kind)
+    p = _params(st, s, kind, 52).to(grid.real_dtype)
+    out = grid.empty_populations()
+    assert B.lbm_step_neural(grid, grid.to_layout(s).cuda(), out, 0.57, p.cuda(), activation, 1) == 0
+    ref = ost.step_emulated(s, 0.57, st, kind, neural=(p.double(), activation))
+    excess, ratio, same = _tolerance_ok(kind, st, grid.from_layout(out.cpu()), ref, 0.57)
+    say(f"  max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
+    assert excess <= 0, ratio
+    # the network moves the ghost times away from any uniform value
+    taus = onn.ghost_taus(olbm.stream(ost.dequantize(s, st, kind), st), p.double(), activation, st)
+    assert float(taus.std()) > 0.05
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_zero_network_equals_mrt_with_ghost_times_three_halves(kind):
+    """All parameters zero: t = 0, tau_6..8 = 3/2; bitwise the uniform MRT step."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D2Q9")
+    grid = B.Grid("D2Q9", kind, 70, 9)
+    s = grid.to_layout(_state(st, (9, 70), 53, kind)).cuda()
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_step_neural(grid, s, a, 0.6, torch.zeros(530, dtype=grid.real_dtype, device="cuda"), "relu", 1)
+    B.lbm_step_mrt(grid, s, b, [1, 1, 1, 0.6, 0.6, 0.6, 1.5, 1.5, 1.5], None, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(bits(a), bits(b))
+
+
+def _reductions(B, grid, f):
+    red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
+    ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
+    B.lbm_moments(grid, f, None, None, None, red, ws)
+    return dict(zip(B.RED_NAMES, red.cpu().tolist()))
+
+
+@pytest.mark.parametrize("activation", ["relu", "tanh"])
+def test_neural_run_stays_finite_and_conserves_mass(activation):
+    """1000 steps of a 128^2 doubly periodic shear layer (FP32) under a random network:
+    finite, mass conserved to FP32 roundoff."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D2Q9")
+    n = 128
+    grid = B.Grid("D2Q9", "f32", n, n)
+    say(f"neural run {activation}")
+    y = (torch.arange(n, dtype=torch.float64) + 0.5) / n
+    x = (torch.arange(n, dtype=torch.float64) + 0.5) / n
+    Y, X = torch.meshgrid(y, x, indexing="ij")
+    u0 = 0.05
+    ux = torch.where(Y <= 0.5, u0 * torch.tanh(80 * (Y - 0.25)), u0 * torch.tanh(80 * (0.75 - Y)))
+    uy = 0.05 * u0 * torch.sin(2 * torch.pi * (X + 0.25))
+    u = torch.stack([ux, uy]).contiguous()
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u.cuda(), a)
+    g = np.random.default_rng(54)
+    W1 = g.normal(0, 1e3, (53, 6))
+    p = torch.from_numpy(np.concatenate([W1.ravel(), g.normal(0, 0.5, 53), g.normal(0, 0.2, 159)])).float().cuda()
+    m0 = _reductions(B, grid, a)["mass"]
+    where = B.lbm_step_neural(grid, a, b, 0.5 + 3 * u0 * n / 5000, p, activation, 1000)
+    red = _reductions(B, grid, b if where == 0 else a)
+    assert red["nonfinite_cells"] == 0
+    assert abs(red["mass"] - m0) / m0 < 1e-5
+    assert red["max_speed"] < 0.2
