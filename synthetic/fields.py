@@ -40,6 +40,30 @@ def taylor_green_3d(nx: int, ny: int, nz: int, u0: float) -> torch.Tensor:
     return torch.from_numpy(u)
 
 
+def taylor_green_2d_on(device, nx: int, ny: int, u0: float) -> torch.Tensor:
+    """taylor_green_2d built directly on `device` by broadcasting (for grids too large
+    to stage in host memory); the same field up to the last ulp of sin/cos."""
+    x = torch.arange(nx, device=device, dtype=torch.float64) * (2 * math.pi / nx)
+    y = torch.arange(ny, device=device, dtype=torch.float64) * (2 * math.pi / ny)
+    u = torch.empty((2, ny, nx), device=device, dtype=torch.float64)
+    u[0] = (u0 * torch.sin(x))[None, :] * torch.cos(y)[:, None]
+    u[1] = (-u0 * torch.cos(x))[None, :] * torch.sin(y)[:, None]
+    return u
+
+
+def taylor_green_3d_on(device, nx: int, ny: int, nz: int, u0: float) -> torch.Tensor:
+    """taylor_green_3d built directly on `device` by broadcasting (for grids too large
+    to stage in host memory); the same field up to the last ulp of sin/cos."""
+    x = torch.arange(nx, device=device, dtype=torch.float64) * (2 * math.pi / nx)
+    y = torch.arange(ny, device=device, dtype=torch.float64) * (2 * math.pi / ny)
+    z = torch.arange(nz, device=device, dtype=torch.float64) * (2 * math.pi / nz)
+    u = torch.empty((3, nz, ny, nx), device=device, dtype=torch.float64)
+    u[0] = ((u0 * torch.sin(x))[None, :] * torch.cos(y)[:, None])[None] * torch.cos(z)[:, None, None]
+    u[1] = ((-u0 * torch.cos(x))[None, :] * torch.sin(y)[:, None])[None] * torch.cos(z)[:, None, None]
+    u[2] = 0.0
+    return u
+
+
 def _kvectors(shape, device):
     axes = [torch.fft.fftfreq(n, d=1.0 / n, dtype=torch.float64, device=device) for n in shape]
     return torch.meshgrid(*axes, indexing="ij")
