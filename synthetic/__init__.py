@@ -8,5 +8,7 @@ from .fields import (  # noqa: F401
     random_fields,
     random_normal,
     taylor_green_2d,
+    taylor_green_2d_on,
     taylor_green_3d,
+    taylor_green_3d_on,
 )
