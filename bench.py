@@ -175,6 +175,30 @@ def run_shard(B, steps: int, warmup: int, nx: int = 512, ny: int = 512, nz: int 
     return out
 
 
+def run_pitch(B, steps: int, warmup: int):
+    """Rows whose length is not a multiple of 64 words, stored dense and padded to a
+    256-byte row pitch (lbm_grid.pitch): the padding restores full bandwidth."""
+    out = {}
+    for lat, shape in (("D3Q27", (255, 256, 256)), ("D2Q9", (8191, 8192, 1))):
+        for layout in ("dense", "padded"):
+            grid = B.Grid(lat, "f32", *shape) if layout == "dense" else B.Grid.padded(lat, "f32", *shape)
+            bufs = [grid.empty_populations().zero_(), grid.empty_populations().zero_()]
+            cur = [0]
+
+            def one():
+                B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], 0.6, None, 1)
+                cur[0] ^= 1
+
+            ms = time_launches(one, steps, warmup)
+            bpc = B.bytes_per_cell_step(grid)
+            out[f"{lat}_{'x'.join(map(str, shape))}_{layout}"] = {
+                "pitch": grid.row_pitch, "ms_per_step": ms, "mlups": grid.ncells / (ms * 1e-3) / 1e6,
+                "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9}
+            del bufs
+            torch.cuda.empty_cache()
+    return out
+
+
 def run_adjoint(B, storage: str, steps: int, warmup: int, u_dev, local: bool = True):
     """Adjoint-step kernel throughput: the collision-local form the rollout uses
     (gathered reads, aligned writes) or the scatter form of lbm_adjoint_step."""
@@ -442,6 +466,8 @@ def main():
                                    for s in ("f32", "f64", "f16s")}
         log("[bench] D2Q9 8192^2 BGK and MRT")
         detail["d2q9_8192"] = run_d2q9(B, args.steps, args.warmup)
+        log("[bench] unaligned rows, dense and padded")
+        detail["row_pitch"] = run_pitch(B, max(20, args.steps // 4), 3)
         log("[bench] z-slab shard 512x512x64 f16s")
         detail["shard_512x512x64_f16s"] = run_shard(B, args.steps, args.warmup)
         log("[bench] adjoint")

@@ -25,8 +25,9 @@
  *
  * Population buffers ("f", "g"): row-interleaved SoA.  The grid is nz*ny rows of nx
  *   cells; row r = z*ny + y holds its Q direction rows one after the other, so word
- *   (i, x, y, z) sits at ((z*ny + y)*Q + i)*nx + x, Q*N words in all.  Each direction
- *   is contiguous along x within a row.  The word type and meaning depend on the
+ *   (i, x, y, z) sits at ((z*ny + y)*Q + i)*nx + x, Q*N words in all (with a row pitch,
+ *   see lbm_grid, nx is replaced by the pitch in both).  Each direction is contiguous
+ *   along x within a row.  The word type and meaning depend on the
  *   storage kind:
  *     LBM_F64    double   f_i
  *     LBM_F32    float    f_i
@@ -73,8 +74,8 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_F16S = 3, LBM_BF1
 enum lbm_status {
   LBM_OK = 0,
   LBM_EINVAL = -1, /* bad scalar argument: tau <= 1/2 or not finite, n_steps < 1,
-                      dims < 1, nz != 1 for D2Q9, unknown lattice or storage,
-                      workspace too small */
+                      dims < 1, nz != 1 for D2Q9, 0 < pitch < nx, unknown lattice or
+                      storage, workspace too small */
   LBM_ENULL = -2,  /* a required pointer is NULL */
   LBM_EALIGN = -3, /* a pointer is not 16-byte aligned */
   LBM_EALIAS = -4, /* an output buffer overlaps an input buffer it must not overlap */
@@ -83,11 +84,19 @@ enum lbm_status {
   LBM_EHIP = -7    /* a HIP runtime call failed; lbm_last_error() has the text */
 };
 
-/* Grid descriptor.  lattice: enum lbm_lattice; storage: enum lbm_storage. */
+/* Grid descriptor.  lattice: enum lbm_lattice; storage: enum lbm_storage.
+ * pitch: words between consecutive direction rows of a population buffer, 0 (= nx, no
+ *   padding) or >= nx.  Population buffers (and adjoint population arrays) then hold
+ *   Q*pitch*ny*nz words, word (i, x, y, z) at ((z*ny + y)*Q + i)*pitch + x; the step,
+ *   moments and adjoint kernels never read or write the pitch - nx pad words of a
+ *   direction row (lbm_slab_halo_copy moves them along with the face rows).  Rows whose byte length
+ *   is a multiple of 256 (pitch a multiple of 64 for 4-byte words) keep the step at full
+ *   bandwidth for any nx.  Real fields (rho, u, force) stay dense. */
 typedef struct lbm_grid {
   int32_t lattice;
   int32_t storage;
   int64_t nx, ny, nz;
+  int64_t pitch;
 } lbm_grid;
 
 /* Faces of a z-slab (lbm_slab_halo_copy). */

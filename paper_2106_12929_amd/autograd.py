@@ -61,7 +61,9 @@ class LBMRollout(torch.autograd.Function):
         # lam_{t+1} = S^T chi_{t+1}; every kernel store is aligned, and
         # lam_0 = S^T chi_0 at the end (bitwise what the scatter form gives).
         cur = lam_T.detach().to(grid.real_dtype).contiguous()
-        bufs = [torch.empty_like(cur), torch.empty_like(cur)]
+        # zero-filled: the kernels never write the pad words of a pitched layout, whose
+        # gradient is zero
+        bufs = [torch.zeros_like(cur), torch.zeros_like(cur)]
         is_chi = False
         dF = torch.zeros_like(F) if ctx.force_needs_grad else None
         n_seg = len(ctx.ckpts)
@@ -100,7 +102,7 @@ class LBMMoments(torch.autograd.Function):
     def backward(ctx, drho, du):
         (g,) = ctx.saved_tensors
         grid, F = ctx.grid, ctx.force
-        lam = torch.empty(grid.population_shape(), dtype=grid.real_dtype, device=g.device)
+        lam = torch.zeros(grid.population_shape(), dtype=grid.real_dtype, device=g.device)
         dF = torch.zeros_like(F) if ctx.force_needs_grad else None
         B.lbm_moments_adjoint(grid, g, F, _real(grid, drho), _real(grid, du), lam, dF)
         return lam, dF, None

@@ -40,7 +40,8 @@ class LbmError(RuntimeError):
 
 class _CGrid(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32),
-                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("pitch", ctypes.c_int64)]
 
 
 def _load() -> ctypes.CDLL:
@@ -83,13 +84,31 @@ _lib = _load()
 
 @dataclass(frozen=True)
 class Grid:
-    """Grid descriptor: lattice "D2Q9"/"D3Q19"/"D3Q27", storage kind, and nx, ny, nz cells."""
+    """Grid descriptor: lattice "D2Q9"/"D3Q19"/"D3Q27", storage kind, nx, ny, nz cells,
+    and the words between direction rows of population buffers (pitch; None = nx)."""
 
     lattice: str
     storage: str
     nx: int
     ny: int
     nz: int = 1
+    pitch: int | None = None
+
+    @staticmethod
+    def padded(lattice: str, storage: str, nx: int, ny: int, nz: int = 1) -> "Grid":
+        """A grid whose direction rows are padded to a multiple of 256 bytes (full
+        bandwidth for any nx)."""
+        per = 256 // torch.tensor([], dtype=STORAGE_DTYPE[storage]).element_size()
+        return Grid(lattice, storage, nx, ny, nz, -(-nx // per) * per)
+
+    @property
+    def row_pitch(self) -> int:
+        return self.nx if self.pitch is None else self.pitch
+
+    @property
+    def pop_size(self) -> int:
+        """Entries of a population buffer (and of an adjoint population array)."""
+        return self.Q * self.row_pitch * self.ny * self.nz
 
     @property
     def D(self) -> int:
@@ -117,18 +136,24 @@ class Grid:
 
     def population_shape(self) -> tuple:
         """Shape of a population buffer in the library's row-interleaved layout:
-        (nz, ny, Q, nx) for D3Q27, (ny, Q, nx) for D2Q9; word (i, x, y, z) sits at
-        ((z*ny + y)*Q + i)*nx + x."""
-        return (self.ny, self.Q, self.nx) if self.D == 2 else (self.nz, self.ny, self.Q, self.nx)
+        (nz, ny, Q, pitch) for 3D lattices, (ny, Q, pitch) for D2Q9; word (i, x, y, z)
+        sits at ((z*ny + y)*Q + i)*pitch + x (pitch = nx unless padded)."""
+        p = self.row_pitch
+        return (self.ny, self.Q, p) if self.D == 2 else (self.nz, self.ny, self.Q, p)
 
     def to_layout(self, f: torch.Tensor) -> torch.Tensor:
-        """[Q, *spatial] (direction-major) -> the library layout (a contiguous copy)."""
-        if self.D == 2:
-            return f.permute(1, 0, 2).contiguous()
-        return f.permute(1, 2, 0, 3).contiguous()
+        """[Q, *spatial] (direction-major) -> the library layout (a contiguous copy;
+        pad words are zero)."""
+        g = f.permute(1, 0, 2) if self.D == 2 else f.permute(1, 2, 0, 3)
+        if self.row_pitch == self.nx:
+            return g.contiguous()
+        out = torch.zeros(g.shape[:-1] + (self.row_pitch,), dtype=f.dtype, device=f.device)
+        out[..., :self.nx] = g
+        return out
 
     def from_layout(self, f: torch.Tensor) -> torch.Tensor:
-        """The library layout -> [Q, *spatial] (a contiguous copy)."""
+        """The library layout -> [Q, *spatial] (a contiguous copy; pad words dropped)."""
+        f = f[..., :self.nx]
         if self.D == 2:
             return f.permute(1, 0, 2).contiguous()
         return f.permute(2, 0, 1, 3).contiguous()
@@ -141,7 +166,8 @@ class Grid:
             raise ValueError(f"unknown lattice {self.lattice!r}")
         if self.storage not in STORAGES:
             raise ValueError(f"unknown storage {self.storage!r}")
-        return _CGrid(LATTICES[self.lattice], STORAGES[self.storage], self.nx, self.ny, self.nz)
+        return _CGrid(LATTICES[self.lattice], STORAGES[self.storage], self.nx, self.ny, self.nz,
+                      0 if self.pitch is None else self.pitch)
 
     def empty_populations(self, device="cuda") -> torch.Tensor:
         return torch.empty(self.population_shape(), dtype=self.word_dtype, device=device)
@@ -151,7 +177,7 @@ class Grid:
         planes, buffer plane 0 and nz + 1 being the ghost planes."""
         if self.D != 3:
             raise ValueError("z-slabs need a 3D lattice")
-        return (self.nz + 2, self.ny, self.Q, self.nx)
+        return (self.nz + 2, self.ny, self.Q, self.row_pitch)
 
     def empty_slab_populations(self, device="cuda") -> torch.Tensor:
         return torch.empty(self.slab_population_shape(), dtype=self.word_dtype, device=device)
@@ -214,7 +240,7 @@ def lbm_init_equilibrium(grid: Grid, rho: torch.Tensor | None, u: torch.Tensor, 
     g = grid.c_struct()
     args = (_dev_ptr(rho, "rho", torch.float64, N, required=False),
             _dev_ptr(u, "u", torch.float64, grid.D * N),
-            _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N))
+            _dev_ptr(f_out, "f_out", grid.word_dtype, grid.pop_size))
     _check(_lib.lbm_init_equilibrium(ctypes.byref(g), *args, _stream(stream)), "lbm_init_equilibrium")
 
 
@@ -223,8 +249,8 @@ def lbm_step(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: float,
     """n_steps ping-pong steps; returns 0 if the result is in f_out, 1 if in f_in."""
     N = grid.ncells
     g = grid.c_struct()
-    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
-    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.pop_size)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.pop_size)
     F = _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False)
     return _check(_lib.lbm_step(ctypes.byref(g), a, b, float(tau), F, int(n_steps), _stream(stream)), "lbm_step")
 
@@ -234,8 +260,8 @@ def lbm_step_shifted(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: f
     """n_steps steps with f^eq(rho, u + du); returns 0 (result in f_out) or 1 (in f_in)."""
     N = grid.ncells
     g = grid.c_struct()
-    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
-    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.pop_size)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.pop_size)
     d = _dev_ptr(du, "du", grid.real_dtype, grid.D * N)
     return _check(_lib.lbm_step_shifted(ctypes.byref(g), a, b, float(tau), d, int(n_steps), _stream(stream)),
                   "lbm_step_shifted")
@@ -248,8 +274,8 @@ def lbm_step_mrt(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, taus, tau_
     N = grid.ncells
     g = grid.c_struct()
     t = (ctypes.c_double * 9)(*[float(v) for v in taus])
-    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
-    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.pop_size)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.pop_size)
     tg = _dev_ptr(tau_ghost, "tau_ghost", grid.real_dtype, 3 * N, required=False)
     return _check(_lib.lbm_step_mrt(ctypes.byref(g), a, b, t, tg, int(n_steps), _stream(stream)), "lbm_step_mrt")
 
@@ -261,8 +287,8 @@ def lbm_step_neural(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau_she
     or 1 (in f_in)."""
     N = grid.ncells
     g = grid.c_struct()
-    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
-    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.pop_size)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.pop_size)
     p = _dev_ptr(params, "params", grid.real_dtype, NEURAL_PARAMS)
     return _check(_lib.lbm_step_neural(ctypes.byref(g), a, b, float(tau_shear), p, ACTIVATIONS[activation],
                                        int(n_steps), _stream(stream)), "lbm_step_neural")
@@ -274,7 +300,7 @@ def lbm_step_slab(slab: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: floa
     """One step of slab planes [z_begin, z_end) (default: all) of a z-slab; f_in and
     f_out are slab buffers (nz + 2 planes), force holds the slab's own D*N reals."""
     N = slab.ncells
-    words = slab.Q * slab.nx * slab.ny * (slab.nz + 2)
+    words = slab.Q * slab.row_pitch * slab.ny * (slab.nz + 2)
     g = slab.c_struct()
     a = _dev_ptr(f_in, "f_in", slab.word_dtype, words)
     b = _dev_ptr(f_out, "f_out", slab.word_dtype, words)
@@ -289,8 +315,8 @@ def lbm_slab_halo_copy(src_slab: Grid, src: torch.Tensor, dst_slab: Grid, dst: t
     """Copies the populations leaving src through `face` ("low" or "high") into the
     matching ghost plane of dst, the neighbouring slab on that side."""
     gs, gd = src_slab.c_struct(), dst_slab.c_struct()
-    a = _dev_ptr(src, "src", src_slab.word_dtype, src_slab.Q * src_slab.nx * src_slab.ny * (src_slab.nz + 2))
-    b = _dev_ptr(dst, "dst", dst_slab.word_dtype, dst_slab.Q * dst_slab.nx * dst_slab.ny * (dst_slab.nz + 2))
+    a = _dev_ptr(src, "src", src_slab.word_dtype, src_slab.Q * src_slab.row_pitch * src_slab.ny * (src_slab.nz + 2))
+    b = _dev_ptr(dst, "dst", dst_slab.word_dtype, dst_slab.Q * dst_slab.row_pitch * dst_slab.ny * (dst_slab.nz + 2))
     _check(_lib.lbm_slab_halo_copy(ctypes.byref(gs), a, ctypes.byref(gd), b, FACES[face], _stream(stream)),
            "lbm_slab_halo_copy")
 
@@ -298,8 +324,8 @@ def lbm_slab_halo_copy(src_slab: Grid, src: torch.Tensor, dst_slab: Grid, dst: t
 def lbm_stream_only(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, stream=None) -> None:
     N = grid.ncells
     g = grid.c_struct()
-    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.Q * N)
-    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.Q * N)
+    a = _dev_ptr(f_in, "f_in", grid.word_dtype, grid.pop_size)
+    b = _dev_ptr(f_out, "f_out", grid.word_dtype, grid.pop_size)
     _check(_lib.lbm_stream_only(ctypes.byref(g), a, b, _stream(stream)), "lbm_stream_only")
 
 
@@ -337,7 +363,7 @@ def lbm_moments(grid: Grid, f: torch.Tensor, force: torch.Tensor | None = None,
             raise ValueError(f"workspace must be a uint8 GPU tensor of >= {need} bytes")
         ws_ptr = _dev_ptr(workspace, "workspace", torch.uint8, workspace.numel())
         ws_bytes = workspace.numel()
-    args = (_dev_ptr(f, "f", grid.word_dtype, grid.Q * N),
+    args = (_dev_ptr(f, "f", grid.word_dtype, grid.pop_size),
             _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False),
             _dev_ptr(rho_out, "rho_out", grid.real_dtype, N, required=False),
             _dev_ptr(u_out, "u_out", grid.real_dtype, grid.D * N, required=False),
@@ -351,9 +377,9 @@ def lbm_adjoint_step(grid: Grid, g_t: torch.Tensor, lam_next: torch.Tensor, lam_
     """lam_out <- (dg'/dg_t)^T lam_next; dforce += (dg'/dF)^T lam_next."""
     N = grid.ncells
     g = grid.c_struct()
-    args = (_dev_ptr(g_t, "g_t", grid.word_dtype, grid.Q * N),
-            _dev_ptr(lam_next, "lam_next", grid.real_dtype, grid.Q * N),
-            _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.Q * N))
+    args = (_dev_ptr(g_t, "g_t", grid.word_dtype, grid.pop_size),
+            _dev_ptr(lam_next, "lam_next", grid.real_dtype, grid.pop_size),
+            _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.pop_size))
     F = _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False)
     dF = _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False)
     _check(_lib.lbm_adjoint_step(ctypes.byref(g), *args, float(tau), F, dF, _stream(stream)), "lbm_adjoint_step")
@@ -366,9 +392,9 @@ def lbm_adjoint_step_local(grid: Grid, g_t: torch.Tensor, adj_next: torch.Tensor
     dforce += (dC/dF)^T lam_{t+1}."""
     N = grid.ncells
     g = grid.c_struct()
-    args = (_dev_ptr(g_t, "g_t", grid.word_dtype, grid.Q * N),
-            _dev_ptr(adj_next, "adj_next", grid.real_dtype, grid.Q * N))
-    out = _dev_ptr(chi_out, "chi_out", grid.real_dtype, grid.Q * N)
+    args = (_dev_ptr(g_t, "g_t", grid.word_dtype, grid.pop_size),
+            _dev_ptr(adj_next, "adj_next", grid.real_dtype, grid.pop_size))
+    out = _dev_ptr(chi_out, "chi_out", grid.real_dtype, grid.pop_size)
     F = _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False)
     dF = _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False)
     _check(_lib.lbm_adjoint_step_local(ctypes.byref(g), *args, 1 if adj_is_chi else 0, out, float(tau), F, dF,
@@ -379,8 +405,8 @@ def lbm_adjoint_unstream(grid: Grid, chi: torch.Tensor, lam_out: torch.Tensor, s
     """lam_out <- S^T chi."""
     N = grid.ncells
     g = grid.c_struct()
-    a = _dev_ptr(chi, "chi", grid.real_dtype, grid.Q * N)
-    b = _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.Q * N)
+    a = _dev_ptr(chi, "chi", grid.real_dtype, grid.pop_size)
+    b = _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.pop_size)
     _check(_lib.lbm_adjoint_unstream(ctypes.byref(g), a, b, _stream(stream)), "lbm_adjoint_unstream")
 
 
@@ -390,11 +416,11 @@ def lbm_moments_adjoint(grid: Grid, f: torch.Tensor, force: torch.Tensor | None,
     """lam_out <- d(rho, u)/dg ^T (dL_drho, dL_du); dforce += -dL_du/(2 rho)."""
     N = grid.ncells
     g = grid.c_struct()
-    args = (_dev_ptr(f, "f", grid.word_dtype, grid.Q * N),
+    args = (_dev_ptr(f, "f", grid.word_dtype, grid.pop_size),
             _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False),
             _dev_ptr(dL_drho, "dL_drho", grid.real_dtype, N, required=False),
             _dev_ptr(dL_du, "dL_du", grid.real_dtype, grid.D * N, required=False),
-            _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.Q * N),
+            _dev_ptr(lam_out, "lam_out", grid.real_dtype, grid.pop_size),
             _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False))
     _check(_lib.lbm_moments_adjoint(ctypes.byref(g), *args, _stream(stream)), "lbm_moments_adjoint")
 

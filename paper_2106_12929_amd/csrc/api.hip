@@ -32,6 +32,7 @@ struct Geometry {
   int D = 0, Q = 0;
   size_t word = 0;  // bytes per stored population
   size_t real = 0;  // bytes per real (force, rho, u, adjoint)
+  size_t pop = 0;   // entries of a population buffer: Q * pitch * ny * nz
   lbm::GridArgs args{};
 };
 
@@ -62,6 +63,9 @@ int check_grid(const lbm_grid* g, Geometry* geo) {
   if (g->nx > lim || g->ny > lim || g->nz > lim) return fail(LBM_ERANGE, "a grid dimension exceeds 2^31-1");
   if (g->nx * g->ny > lim || (g->nx * g->ny) * g->nz > lim)
     return fail(LBM_ERANGE, "grid has more than 2^31-1 cells");
+  if (g->pitch != 0 && g->pitch < g->nx)
+    return fail(LBM_EINVAL, "pitch must be 0 or >= nx (got %lld < %lld)", (long long)g->pitch, (long long)g->nx);
+  if (g->pitch > lim) return fail(LBM_ERANGE, "pitch exceeds 2^31-1");
   geo->D = g->lattice == LBM_D2Q9 ? 2 : 3;
   geo->Q = g->lattice == LBM_D2Q9 ? 9 : g->lattice == LBM_D3Q19 ? 19 : 27;
   geo->word = g->storage == LBM_F64 ? 8 : (g->storage == LBM_F32 || g->storage == LBM_F32S) ? 4 : 2;
@@ -74,6 +78,8 @@ int check_grid(const lbm_grid* g, Geometry* geo) {
   geo->args.z0 = 0;
   geo->args.nzl = (uint32_t)g->nz;
   geo->args.ghost = 0;
+  geo->args.pitch = (uint32_t)(g->pitch ? g->pitch : g->nx);
+  geo->pop = (size_t)geo->Q * geo->args.pitch * (size_t)g->ny * (size_t)g->nz;
   return LBM_OK;
 }
 
@@ -158,7 +164,7 @@ const char* lbm_strerror(int status) {
 
 const char* lbm_last_error(void) { return g_last_error; }
 
-int lbm_version(void) { return 10000; }
+int lbm_version(void) { return 10100; }
 
 int lbm_lattice_info(int lattice, int* D, int* Q, int* c, double* w) {
   switch (lattice) {
@@ -188,7 +194,7 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
   LBM_TRY(check_ptr(u, "u", true));
   LBM_TRY(check_ptr(f_out, "f_out", true));
   const size_t N = geo.args.ncells;
-  const size_t fbytes = geo.Q * N * geo.word;
+  const size_t fbytes = geo.pop * geo.word;
   if (overlap(f_out, fbytes, rho, N * 8) || overlap(f_out, fbytes, u, geo.D * N * 8))
     return fail(LBM_EALIAS, "f_out overlaps rho or u");
   const hipError_t e = lbm::launch_init(grid->lattice, grid->storage, rho, u, f_out, geo.args, (hipStream_t)stream);
@@ -209,7 +215,7 @@ int step_common(const lbm_grid* grid, void* f_in, void* f_out, double tau, const
   LBM_TRY(check_ptr(f_out, "f_out", true));
   LBM_TRY(check_ptr(field, force_mode == lbm::kShiftForce ? "du" : "force", force_mode == lbm::kShiftForce));
   const size_t N = geo.args.ncells;
-  const size_t fbytes = geo.Q * N * geo.word, vbytes = geo.D * N * geo.real;
+  const size_t fbytes = geo.pop * geo.word, vbytes = geo.D * N * geo.real;
   if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
   if (overlap(field, vbytes, f_in, fbytes) || overlap(field, vbytes, f_out, fbytes))
     return fail(LBM_EALIAS, "the per-cell field overlaps a population buffer");
@@ -250,8 +256,7 @@ int mrt_common(const lbm_grid* grid, void* f_in, void* f_out, const double* taus
   if (n_steps < 1) return fail(LBM_EINVAL, "n_steps must be >= 1 (got %d)", n_steps);
   LBM_TRY(check_ptr(f_in, "f_in", true));
   LBM_TRY(check_ptr(f_out, "f_out", true));
-  const size_t N = geo.args.ncells;
-  const size_t fbytes = geo.Q * N * geo.word;
+  const size_t fbytes = geo.pop * geo.word;
   if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
   if (overlap(ghost, ghost_bytes, f_in, fbytes) || overlap(ghost, ghost_bytes, f_out, fbytes))
     return fail(LBM_EALIAS, "the ghost-time source overlaps a population buffer");
@@ -310,7 +315,7 @@ int lbm_step_slab(const lbm_grid* slab, const void* f_in, void* f_out, double ta
   LBM_TRY(check_ptr(f_in, "f_in", true));
   LBM_TRY(check_ptr(f_out, "f_out", true));
   LBM_TRY(check_ptr(force, "force", false));
-  const size_t plane = (size_t)geo.Q * geo.args.nx * geo.args.ny * geo.word;
+  const size_t plane = (size_t)geo.Q * geo.args.pitch * geo.args.ny * geo.word;
   const size_t fbytes = plane * (size_t)(slab->nz + 2), vbytes = geo.D * geo.args.ncells * geo.real;
   if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
   if (overlap(force, vbytes, f_in, fbytes) || overlap(force, vbytes, f_out, fbytes))
@@ -331,8 +336,8 @@ int lbm_slab_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid
   LBM_TRY(check_grid(dst_slab, &gd));
   if (gs.D != 3) return fail(LBM_EUNSUP, "lbm_slab_halo_copy needs a 3D lattice (z-slabs)");
   if (src_slab->lattice != dst_slab->lattice || src_slab->storage != dst_slab->storage ||
-      src_slab->nx != dst_slab->nx || src_slab->ny != dst_slab->ny)
-    return fail(LBM_EINVAL, "source and destination slabs differ in lattice, storage, nx or ny");
+      src_slab->nx != dst_slab->nx || src_slab->ny != dst_slab->ny || gs.args.pitch != gd.args.pitch)
+    return fail(LBM_EINVAL, "source and destination slabs differ in lattice, storage, nx, ny or pitch");
   if (face != LBM_FACE_LOW && face != LBM_FACE_HIGH) return fail(LBM_EINVAL, "face must be 0 or 1 (got %d)", face);
   LBM_TRY(check_ptr(src, "src", true));
   LBM_TRY(check_ptr(dst, "dst", true));
@@ -343,10 +348,10 @@ int lbm_slab_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid
   const uint64_t dst_plane = face == LBM_FACE_LOW ? (uint64_t)dst_slab->nz + 1 : 0;
   int i0 = 0, n = 0;
   face_dirs(src_slab->lattice, face == LBM_FACE_LOW ? -1 : 1, &i0, &n);
-  const size_t plane = (size_t)gs.Q * gs.args.nx * gs.args.ny * gs.word;
+  const size_t plane = (size_t)gs.Q * gs.args.pitch * gs.args.ny * gs.word;
   if (overlap((const char*)src + src_plane * plane, plane, (const char*)dst + dst_plane * plane, plane))
     return fail(LBM_EALIAS, "the source plane overlaps the destination ghost plane");
-  const hipError_t e = lbm::launch_halo_copy(gs.Q, (int)gs.word, src, src_plane, dst, dst_plane, i0, n, gs.args.nx,
+  const hipError_t e = lbm::launch_halo_copy(gs.Q, (int)gs.word, src, src_plane, dst, dst_plane, i0, n, gs.args.pitch,
                                              gs.args.ny, (hipStream_t)stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_slab_halo_copy launch");
 }
@@ -356,7 +361,7 @@ int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* s
   LBM_TRY(check_grid(grid, &geo));
   LBM_TRY(check_ptr(f_in, "f_in", true));
   LBM_TRY(check_ptr(f_out, "f_out", true));
-  const size_t fbytes = geo.Q * geo.args.ncells * geo.word;
+  const size_t fbytes = geo.pop * geo.word;
   if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
   const hipError_t e = lbm::launch_stream(grid->lattice, (int)geo.word, f_in, f_out, geo.args, (hipStream_t)stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_stream_only launch");
@@ -397,7 +402,7 @@ int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rh
       return fail(LBM_EINVAL, "workspace has %zu bytes, lbm_moments needs %zu", workspace_bytes, need);
   }
   const size_t N = geo.args.ncells;
-  const size_t fbytes = geo.Q * N * geo.word;
+  const size_t fbytes = geo.pop * geo.word;
   const size_t rbytes = N * geo.real, ubytes = geo.D * N * geo.real;
   const void* ins[2] = {g, force};
   const size_t insz[2] = {fbytes, geo.D * N * geo.real};
@@ -433,7 +438,7 @@ int adjoint_common(const lbm_grid* grid, const void* g_t, const void* adj_next, 
   LBM_TRY(check_ptr(dforce, "dforce", false));
   if (dforce && !force) return fail(LBM_EUNSUP, "dforce needs the force the step used");
   const size_t N = geo.args.ncells;
-  const size_t gbytes = geo.Q * N * geo.word, lbytes = geo.Q * N * geo.real, fbytes = geo.D * N * geo.real;
+  const size_t gbytes = geo.pop * geo.word, lbytes = geo.pop * geo.real, fbytes = geo.D * N * geo.real;
   if (overlap(adj_out, lbytes, g_t, gbytes) || overlap(adj_out, lbytes, adj_next, lbytes) ||
       overlap(adj_out, lbytes, force, fbytes) || overlap(adj_out, lbytes, dforce, fbytes))
     return fail(LBM_EALIAS, "the adjoint output overlaps another argument");
@@ -467,7 +472,7 @@ int lbm_adjoint_unstream(const lbm_grid* grid, const void* chi, void* lam_out, v
   LBM_TRY(check_grid(grid, &geo));
   LBM_TRY(check_ptr(chi, "chi", true));
   LBM_TRY(check_ptr(lam_out, "lam_out", true));
-  const size_t lbytes = geo.Q * geo.args.ncells * geo.real;
+  const size_t lbytes = geo.pop * geo.real;
   if (overlap(chi, lbytes, lam_out, lbytes)) return fail(LBM_EALIAS, "chi and lam_out overlap");
   const hipError_t e = lbm::launch_unstream(grid->lattice, (int)geo.real, chi, lam_out, geo.args, (hipStream_t)stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_unstream launch");
@@ -485,7 +490,7 @@ int lbm_moments_adjoint(const lbm_grid* grid, const void* g, const void* force, 
   LBM_TRY(check_ptr(dforce, "dforce", false));
   if (dforce && !force) return fail(LBM_EUNSUP, "dforce needs the force the moments used");
   const size_t N = geo.args.ncells;
-  const size_t gbytes = geo.Q * N * geo.word, lbytes = geo.Q * N * geo.real, vbytes = geo.D * N * geo.real;
+  const size_t gbytes = geo.pop * geo.word, lbytes = geo.pop * geo.real, vbytes = geo.D * N * geo.real;
   if (overlap(lam_out, lbytes, g, gbytes) || overlap(lam_out, lbytes, force, vbytes) ||
       overlap(lam_out, lbytes, dL_drho, N * geo.real) || overlap(lam_out, lbytes, dL_du, vbytes) ||
       overlap(lam_out, lbytes, dforce, vbytes))

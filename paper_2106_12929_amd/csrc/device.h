@@ -69,10 +69,10 @@ __device__ __forceinline__ Sources sources(const Cell& c, const GridArgs& g) {
   return s;
 }
 
-// Word offset of direction row i of grid row (y, z): ((z*ny + y)*Q + i)*nx.
+// Word offset of direction row i of grid row (y, z): ((z*ny + y)*Q + i)*pitch.
 template <int Q>
 __device__ __forceinline__ uint64_t dir_row(const GridArgs& g, uint32_t y, uint32_t z, int i) {
-  return (((uint64_t)z * g.ny + y) * Q + (uint64_t)i) * g.nx;
+  return (((uint64_t)z * g.ny + y) * Q + (uint64_t)i) * g.pitch;
 }
 
 // Word offset of the pull source of direction i for the cell: g_i(x - c_i).

@@ -19,6 +19,7 @@ struct GridArgs {
   uint32_t z0, nzl;  // planes [z0, z0 + nzl) handled by the launch (0 and nz: all of them)
   uint32_t ghost;    // 0: periodic in z; 1: z-slab buffer with a ghost plane below and above
                      // the nz planes (buffer plane = z + 1, no wrap in z)
+  uint32_t pitch;    // words between direction rows of population buffers (>= nx)
 };
 
 hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
@@ -40,11 +41,11 @@ constexpr int kNeuralParams = 6 * kNeuralHidden + kNeuralHidden + 3 * kNeuralHid
 // per-cell times (kGhostField) or the network parameters (kGhostRelu, kGhostTanh).
 hipError_t launch_mrt(int storage, const void* fin, void* fout, const void* ghost, int ghost_mode, const GridArgs& g,
                       const double* scales, hipStream_t s);
-// Copies n_dir consecutive direction rows of every grid row of plane `src_plane` of
-// src into plane `dst_plane` of dst (planes in buffer coordinates), starting at
-// direction i0: the face populations of a z-slab halo exchange.
+// Copies n_dir consecutive direction rows (of `pitch` words) of every grid row of plane
+// `src_plane` of src into plane `dst_plane` of dst (planes in buffer coordinates),
+// starting at direction i0: the face populations of a z-slab halo exchange.
 hipError_t launch_halo_copy(int Q, int word_bytes, const void* src, uint64_t src_plane, void* dst, uint64_t dst_plane,
-                            int i0, int n_dir, uint32_t nx, uint32_t ny, hipStream_t s);
+                            int i0, int n_dir, uint32_t pitch, uint32_t ny, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s);
 hipError_t launch_moments_adjoint(int lattice, int storage, const void* f, const void* force, const void* drho,
                                   const void* du, void* lam_out, void* dforce, const GridArgs& g, hipStream_t s);

@@ -298,10 +298,10 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
   // acc: [0] sum drho, [1..3] sum rho u, [4] 1/2 sum |u|^2, [5] non-finite, [6] max|u|, [7] min rho
   double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 1.0e300};
   for (uint32_t r = blockIdx.x; r < rows; r += gridDim.x) {
-    const typename Storage<S>::word* row = f + (uint64_t)r * LT::Q * g.nx;
+    const typename Storage<S>::word* row = f + (uint64_t)r * LT::Q * g.pitch;
     for (uint32_t x = threadIdx.x; x < g.nx; x += 256) {
       const uint32_t n = r * g.nx + x;
-      const auto m = cell_moments<L, S>(row, force, N, g.nx, x, n);
+      const auto m = cell_moments<L, S>(row, force, N, g.pitch, x, n);
       if (rho_out) rho_out[n] = m.rho;
       if (u_out) {
 #pragma unroll
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Sto
   const size_t N = g.ncells;
   const uint32_t n = cell_index(g, c);
   const uint64_t row = dir_row<LT::Q>(g, c.y, c.z, 0);
-  const auto m = cell_moments<L, S>(f + row, force, N, g.nx, c.x, n);
+  const auto m = cell_moments<L, S>(f + row, force, N, g.pitch, c.x, n);
   const real inv = real(1) / m.rho;
   const real dr = drho_in ? drho_in[n] : real(0);
   real du[3] = {0, 0, 0};
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Sto
     if (LT::cy(j) < 0) v -= by;
     if (LT::cz(j) > 0) v += bz;
     if (LT::cz(j) < 0) v -= bz;
-    lam_out[row + (uint64_t)j * g.nx + c.x] = v;
+    lam_out[row + (uint64_t)j * g.pitch + c.x] = v;
   }
   if (dforce) {
 #pragma unroll
@@ -759,18 +759,18 @@ static void launch_halo_t(const void* src, void* dst, uint64_t sb, uint64_t db, 
 }
 
 hipError_t launch_halo_copy(int Q, int word_bytes, const void* src, uint64_t src_plane, void* dst, uint64_t dst_plane,
-                            int i0, int n_dir, uint32_t nx, uint32_t ny, hipStream_t s) {
-  const uint64_t pitch = (uint64_t)Q * nx, chunk = (uint64_t)n_dir * nx;
-  const uint64_t sb = (src_plane * ny * Q + (uint64_t)i0) * nx, db = (dst_plane * ny * Q + (uint64_t)i0) * nx;
-  if (((uint64_t)nx * word_bytes) % 16 == 0) {  // every offset is a whole number of 16-byte units
+                            int i0, int n_dir, uint32_t pitch, uint32_t ny, hipStream_t s) {
+  const uint64_t row = (uint64_t)Q * pitch, chunk = (uint64_t)n_dir * pitch;
+  const uint64_t sb = (src_plane * ny * Q + (uint64_t)i0) * pitch, db = (dst_plane * ny * Q + (uint64_t)i0) * pitch;
+  if (((uint64_t)pitch * word_bytes) % 16 == 0) {  // every offset is a whole number of 16-byte units
     const uint64_t u = 16 / word_bytes;
-    launch_halo_t<u32x4>(src, dst, sb / u, db / u, pitch / u, chunk / u, ny, s);
+    launch_halo_t<u32x4>(src, dst, sb / u, db / u, row / u, chunk / u, ny, s);
     return hipGetLastError();
   }
   switch (word_bytes) {
-    case 2: launch_halo_t<uint16_t>(src, dst, sb, db, pitch, chunk, ny, s); break;
-    case 4: launch_halo_t<uint32_t>(src, dst, sb, db, pitch, chunk, ny, s); break;
-    case 8: launch_halo_t<uint64_t>(src, dst, sb, db, pitch, chunk, ny, s); break;
+    case 2: launch_halo_t<uint16_t>(src, dst, sb, db, row, chunk, ny, s); break;
+    case 4: launch_halo_t<uint32_t>(src, dst, sb, db, row, chunk, ny, s); break;
+    case 8: launch_halo_t<uint64_t>(src, dst, sb, db, row, chunk, ny, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

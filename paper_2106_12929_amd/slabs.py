@@ -45,7 +45,7 @@ class SlabSet:
         self.grid = grid
         self.planes = planes
         self.z0 = [sum(planes[:p]) for p in range(len(planes))]
-        self.slabs = [B.Grid(grid.lattice, grid.storage, grid.nx, grid.ny, n) for n in planes]
+        self.slabs = [B.Grid(grid.lattice, grid.storage, grid.nx, grid.ny, n, grid.pitch) for n in planes]
         self.bufs = [[s.empty_slab_populations(device), s.empty_slab_populations(device)] for s in self.slabs]
         self.cur = 0
         self._halo_stream = None

@@ -52,9 +52,9 @@ def test_lattice_info_matches_oracle_tables(B, name):
     assert st.w.tolist() == w
 
 
-def _grid(B, lattice="D3Q27", storage="f32", nx=8, ny=8, nz=8):
+def _grid(B, lattice="D3Q27", storage="f32", nx=8, ny=8, nz=8, pitch=0):
     return B._CGrid(B.LATTICES.get(lattice, lattice) if isinstance(lattice, str) else lattice,
-                    B.STORAGES.get(storage, storage) if isinstance(storage, str) else storage, nx, ny, nz)
+                    B.STORAGES.get(storage, storage) if isinstance(storage, str) else storage, nx, ny, nz, pitch)
 
 
 P1 = ctypes.c_void_p(0x10000)        # aligned fake device addresses: validation
@@ -219,6 +219,16 @@ def test_slab_halo_validation(B):
     # LOW reads src plane 1 and writes dst plane nz + 1 = 9: a dst 8 planes below src
     # puts that ghost plane on top of the source plane
     assert halo(dst=ctypes.c_void_p(0x10000 - 8 * plane), face=0) == -4
+
+
+def test_pitch_validation(B):
+    lib = B._lib
+    assert _step(B, _grid(B, nx=8, pitch=7), P1, P2) == -1      # 0 < pitch < nx
+    assert _step(B, _grid(B, nx=8, pitch=2 ** 31), P1, P2) == -6
+    # with pitch 16 a buffer spans 27*16*8*8*4 bytes: f_out that far past f_in is clear,
+    # one word less overlaps (the unpadded size would not)
+    size = 27 * 16 * 8 * 8 * 4
+    assert _step(B, _grid(B, nx=8, pitch=16), P1, ctypes.c_void_p(0x10000 + size - 16)) == -4
 
 
 def test_strerror(B):
