@@ -20,25 +20,42 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // one 16-byte vect
 __device__ __forceinline__ uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
 
-// The cell of a thread.  y and z are wave-uniform (made scalar with readfirstlane).
-// Returns false for the threads of the ragged tails (x >= nx or past the last row).
+template <typename T>
+__device__ __forceinline__ void store_stream(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 struct Cell {
   uint32_t x, y, z;
 };
 
-__device__ __forceinline__ bool cell_of_thread(const GridArgs& g, Cell& c) {
+// The cell of a thread, for a kernel that writes the population-layout buffer `out` (in
+// output plane c.z + zshift).  A 256-thread block covers block_x consecutive cells of
+// 256/block_x consecutive rows; all 64 lanes of a wave share one row, so y and z are
+// wave-uniform (made scalar with readfirstlane).  Returns false past the last row and
+// for the lanes of the ragged x tail (x >= nx).  Those tail lanes that fall inside the
+// row pitch (nx <= x < pitch) first write zeros into those pad words of every direction
+// row, so that the rows' cache lines are written whole: a partly written line costs
+// the memory a read-modify-write.  With pitch == nx nothing extra happens.
+template <int Q, typename W>
+__device__ __forceinline__ bool cell_or_pad(const GridArgs& g, Cell& c, W* out, uint32_t zshift) {
   const uint32_t bx = g.block_x;
   const uint32_t blocks_x = (g.nx + bx - 1) / bx;
   const uint32_t bxi = blockIdx.x % blocks_x;
   const uint32_t byi = blockIdx.x / blocks_x;
-  // all 64 lanes of a wave share one row because block_x is a multiple of 64
   const uint32_t ty = __builtin_amdgcn_readfirstlane(threadIdx.x / bx);
   const uint32_t r = byi * (256u / bx) + ty;
   c.x = bxi * bx + threadIdx.x % bx;
   if (r >= g.ny * g.nzl) return false;
   c.y = r % g.ny;
   c.z = g.z0 + r / g.ny;
-  return c.x < g.nx;
+  if (c.x < g.nx) return true;
+  if (c.x < g.pitch) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      store_stream(&out[(((uint64_t)(c.z + zshift) * g.ny + c.y) * Q + (uint64_t)i) * g.pitch + c.x], W(0));
+  }
+  return false;
 }
 
 // Source coordinates of the pull gather: index k = c + 1 holds the coordinate of
@@ -92,10 +109,6 @@ __device__ __forceinline__ uint32_t cell_index(const GridArgs& g, const Cell& c)
   return (c.z * g.ny + c.y) * g.nx + c.x;
 }
 
-template <typename T>
-__device__ __forceinline__ void store_stream(T* p, T v) {
-  __builtin_nontemporal_store(v, p);
-}
 
 // ---------------------------------------------------------------------------------
 // BGK collision of one cell in deviation form (Eqs. 2-4), in place: d holds the

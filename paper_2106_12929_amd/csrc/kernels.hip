@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;
   Cell c;
-  if (!cell_of_thread(g, c)) return;
+  if (!cell_or_pad<Q>(g, c, fout, g.ghost)) return;
   const Sources src = sources(c, g);
   const size_t N = g.ncells;
   const uint32_t self = cell_index(g, c);
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
   using CO = Coef<kD2Q9, real>;
   constexpr int Q = 9;
   Cell c;
-  if (!cell_of_thread(g, c)) return;
+  if (!cell_or_pad<Q>(g, c, fout, 0)) return;
   const Sources src = sources(c, g);
   const size_t N = g.ncells;
 
@@ -204,7 +204,7 @@ template <int L, typename W>
 __global__ __launch_bounds__(256) void stream_kernel(const W* __restrict__ fin, W* __restrict__ fout, GridArgs g) {
   using LT = Lattice<L>;
   Cell c;
-  if (!cell_of_thread(g, c)) return;
+  if (!cell_or_pad<LT::Q>(g, c, fout, 0)) return;
   const Sources src = sources(c, g);
 #pragma unroll
   for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[src_offset<LT>(g, src, i)];
@@ -215,7 +215,7 @@ template <int L, typename W>
 __global__ __launch_bounds__(256) void unstream_kernel(const W* __restrict__ fin, W* __restrict__ fout, GridArgs g) {
   using LT = Lattice<L>;
   Cell c;
-  if (!cell_of_thread(g, c)) return;
+  if (!cell_or_pad<LT::Q>(g, c, fout, 0)) return;
   const Sources src = sources(c, g);
 #pragma unroll
   for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[rev_offset<LT>(g, src, i)];
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ rh
   using LT = Lattice<L>;
   using ST = Storage<S>;
   Cell c;
-  if (!cell_of_thread(g, c)) return;
+  if (!cell_or_pad<LT::Q>(g, c, fout, 0)) return;
   const size_t N = g.ncells;
   const uint32_t n = cell_index(g, c);
   const double rho = rho_in ? rho_in[n] : 1.0;
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;
   Cell c;
-  if (!cell_of_thread(g, c)) return;
+  if (!cell_or_pad<Q>(g, c, lam_out, 0)) return;
   const Sources src = sources(c, g);
   const size_t N = g.ncells;
   const uint32_t self = cell_index(g, c);
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Sto
   using LT = Lattice<L>;
   using real = typename Storage<S>::real;
   Cell c;
-  if (!cell_of_thread(g, c)) return;
+  if (!cell_or_pad<LT::Q>(g, c, lam_out, 0)) return;
   const size_t N = g.ncells;
   const uint32_t n = cell_index(g, c);
   const uint64_t row = dir_row<LT::Q>(g, c.y, c.z, 0);
