@@ -88,13 +88,13 @@ enum lbm_status {
  * pitch: words between consecutive direction rows of a population buffer, 0 (= nx, no
  *   padding) or >= nx.  Population buffers (and adjoint population arrays) then hold
  *   Q*pitch*ny*nz words, word (i, x, y, z) at ((z*ny + y)*Q + i)*pitch + x.  The
- *   pitch - nx pad words of a direction row are never read; a call that writes a
- *   population buffer stores zeros into the pad words that lie inside the last block
- *   segment of 64, 128 or 256 cells of its rows (so that whole cache lines are written)
- *   and leaves any further pad words untouched; lbm_slab_halo_copy moves pad words along
- *   with the face rows.  Rows whose byte length is a multiple of 256 (pitch a multiple
- *   of 64 for 4-byte words) keep the step at full bandwidth for any nx.  Real fields
- *   (rho, u, force) stay dense. */
+ *   pitch - nx pad words of a direction row are never read.  lbm_step, lbm_step_shifted
+ *   and lbm_step_slab may overwrite the pad words inside their rows' last block segment
+ *   of 64, 128 or 256 cells with unspecified values (so that whole cache lines are
+ *   written); every other entry point leaves pad words untouched, and
+ *   lbm_slab_halo_copy moves them along with the face rows.  Rows whose byte length is
+ *   a multiple of 256 (pitch a multiple of 64 for 4-byte words) keep the step near full
+ *   bandwidth for any nx.  Real fields (rho, u, force) stay dense. */
 typedef struct lbm_grid {
   int32_t lattice;
   int32_t storage;

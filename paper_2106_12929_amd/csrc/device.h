@@ -29,16 +29,14 @@ struct Cell {
   uint32_t x, y, z;
 };
 
-// The cell of a thread, for a kernel that writes the population-layout buffer `out` (in
-// output plane c.z + zshift).  A 256-thread block covers block_x consecutive cells of
+// Where a thread's cell lies.  A 256-thread block covers block_x consecutive cells of
 // 256/block_x consecutive rows; all 64 lanes of a wave share one row, so y and z are
-// wave-uniform (made scalar with readfirstlane).  Returns false past the last row and
-// for the lanes of the ragged x tail (x >= nx).  Those tail lanes that fall inside the
-// row pitch (nx <= x < pitch) first write zeros into those pad words of every direction
-// row, so that the rows' cache lines are written whole: a partly written line costs
-// the memory a read-modify-write.  With pitch == nx nothing extra happens.
-template <int Q, typename W>
-__device__ __forceinline__ bool cell_or_pad(const GridArgs& g, Cell& c, W* out, uint32_t zshift) {
+// wave-uniform (made scalar with readfirstlane).
+enum CellKind { kNoCell = 0, kLiveCell = 1, kPadCell = 2 };
+
+// kNoCell past the last row and beyond the row pitch; kPadCell for nx <= x < pitch (a
+// pad word of a padded row); kLiveCell otherwise.
+__device__ __forceinline__ int cell_kind(const GridArgs& g, Cell& c) {
   const uint32_t bx = g.block_x;
   const uint32_t blocks_x = (g.nx + bx - 1) / bx;
   const uint32_t bxi = blockIdx.x % blocks_x;
@@ -46,16 +44,16 @@ __device__ __forceinline__ bool cell_or_pad(const GridArgs& g, Cell& c, W* out, 
   const uint32_t ty = __builtin_amdgcn_readfirstlane(threadIdx.x / bx);
   const uint32_t r = byi * (256u / bx) + ty;
   c.x = bxi * bx + threadIdx.x % bx;
-  if (r >= g.ny * g.nzl) return false;
+  if (r >= g.ny * g.nzl) return kNoCell;
   c.y = r % g.ny;
   c.z = g.z0 + r / g.ny;
-  if (c.x < g.nx) return true;
-  if (c.x < g.pitch) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-      store_stream(&out[(((uint64_t)(c.z + zshift) * g.ny + c.y) * Q + (uint64_t)i) * g.pitch + c.x], W(0));
-  }
-  return false;
+  return c.x < g.nx ? kLiveCell : (c.x < g.pitch ? kPadCell : kNoCell);
+}
+
+// The cell of a thread for kernels that only compute live cells: false past the last
+// row and for the ragged x tail.
+__device__ __forceinline__ bool cell_of_thread(const GridArgs& g, Cell& c) {
+  return cell_kind(g, c) == kLiveCell;
 }
 
 // Source coordinates of the pull gather: index k = c + 1 holds the coordinate of

@@ -43,10 +43,17 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;
   Cell c;
-  if (!cell_or_pad<Q>(g, c, fout, g.ghost)) return;
-  const Sources src = sources(c, g);
+  const int kind = cell_kind(g, c);
+  if (kind == kNoCell) return;
+  // Pad lanes of a padded row (nx <= x < pitch) compute the last cell of the row again
+  // (in-bounds loads, finite values) and store the result into their pad word with the
+  // rest of the wave, so the row's last cache line is written by one store instruction
+  // instead of two partial ones.
+  Cell cs = c;
+  if (kind == kPadCell) cs.x = g.nx - 1;
+  const Sources src = sources(cs, g);
   const size_t N = g.ncells;
-  const uint32_t self = cell_index(g, c);
+  const uint32_t self = cell_index(g, cs);
 
   // Gather (pull streaming, Eq. 1): h_i(x) = g_i(x - c_i), as deviations from w_i.
   real d[Q];
@@ -122,7 +129,7 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
   using CO = Coef<kD2Q9, real>;
   constexpr int Q = 9;
   Cell c;
-  if (!cell_or_pad<Q>(g, c, fout, 0)) return;
+  if (!cell_of_thread(g, c)) return;
   const Sources src = sources(c, g);
   const size_t N = g.ncells;
 
@@ -204,7 +211,7 @@ template <int L, typename W>
 __global__ __launch_bounds__(256) void stream_kernel(const W* __restrict__ fin, W* __restrict__ fout, GridArgs g) {
   using LT = Lattice<L>;
   Cell c;
-  if (!cell_or_pad<LT::Q>(g, c, fout, 0)) return;
+  if (!cell_of_thread(g, c)) return;
   const Sources src = sources(c, g);
 #pragma unroll
   for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[src_offset<LT>(g, src, i)];
@@ -215,7 +222,7 @@ template <int L, typename W>
 __global__ __launch_bounds__(256) void unstream_kernel(const W* __restrict__ fin, W* __restrict__ fout, GridArgs g) {
   using LT = Lattice<L>;
   Cell c;
-  if (!cell_or_pad<LT::Q>(g, c, fout, 0)) return;
+  if (!cell_of_thread(g, c)) return;
   const Sources src = sources(c, g);
 #pragma unroll
   for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[rev_offset<LT>(g, src, i)];
@@ -230,7 +237,7 @@ __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ rh
   using LT = Lattice<L>;
   using ST = Storage<S>;
   Cell c;
-  if (!cell_or_pad<LT::Q>(g, c, fout, 0)) return;
+  if (!cell_of_thread(g, c)) return;
   const size_t N = g.ncells;
   const uint32_t n = cell_index(g, c);
   const double rho = rho_in ? rho_in[n] : 1.0;
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;
   Cell c;
-  if (!cell_or_pad<Q>(g, c, lam_out, 0)) return;
+  if (!cell_of_thread(g, c)) return;
   const Sources src = sources(c, g);
   const size_t N = g.ncells;
   const uint32_t self = cell_index(g, c);
@@ -513,7 +520,7 @@ __global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Sto
   using LT = Lattice<L>;
   using real = typename Storage<S>::real;
   Cell c;
-  if (!cell_or_pad<LT::Q>(g, c, lam_out, 0)) return;
+  if (!cell_of_thread(g, c)) return;
   const size_t N = g.ncells;
   const uint32_t n = cell_index(g, c);
   const uint64_t row = dir_row<LT::Q>(g, c.y, c.z, 0);

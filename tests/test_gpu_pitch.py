@@ -1,6 +1,6 @@
 """GPU checks of padded population rows (lbm_grid.pitch > nx): every kernel gives the
-same bits as on the unpadded layout, and a kernel that writes a population buffer
-leaves zeros in the pad words of its rows' last block segment (here: all of them)."""
+same bits as on the unpadded layout; the steps may write the pad words (unspecified
+values), every other kernel leaves them untouched."""
 import pytest
 import torch
 
@@ -26,13 +26,8 @@ def _sentinel(t):
     return t
 
 
-def _pads_zero(t, nx):
-    """The pad words of the rows' last block segment (at least up to the next multiple
-    of 64 cells) hold zeros; any further pad words are zero or untouched."""
-    seg = min(t.shape[-1], -(-nx // 64) * 64)
-    inside = t[..., nx:seg].contiguous().view(torch.uint8)
-    beyond = t[..., seg:].contiguous().view(torch.uint8)
-    return bool((inside == 0).all()) and bool(((beyond == 0) | (beyond == 0xA5)).all())
+def _pads_untouched(t, nx):
+    return bool((t[..., nx:].contiguous().view(torch.uint8) == 0xA5).all())
 
 
 @pytest.mark.parametrize("lat,shape", CASES)
@@ -67,7 +62,7 @@ def test_pitched_layout_matches_dense(lat, shape, kind, extra):
         return out
     a0, a1 = both(init)
     assert torch.equal(bits(pitched.from_layout(a1)), bits(dense.from_layout(a0)))
-    assert _pads_zero(a1, dense.nx)
+    assert _pads_untouched(a1, dense.nx)
     # stream only, and 3 forced steps
     for op in ("stream", "step"):
         def run(g, g_in):
@@ -82,7 +77,8 @@ def test_pitched_layout_matches_dense(lat, shape, kind, extra):
             return out
         o0, o1 = both(run)
         assert torch.equal(bits(pitched.from_layout(o1)), bits(dense.from_layout(o0))), op
-        assert _pads_zero(o1, dense.nx), op
+        if op == "stream":
+            assert _pads_untouched(o1, dense.nx)
     # moments (fields and reductions)
     def moms(g, g_in):
         rho, uu = g.empty_real(0), g.empty_real(g.D)
@@ -120,7 +116,7 @@ def test_pitched_layout_matches_dense(lat, shape, kind, extra):
     (p0, d0), (p1, d1) = both(adj)
     for k, (x0, x1) in enumerate(zip(p0, p1)):
         assert torch.equal(bits(pitched.from_layout(x1)), bits(dense.from_layout(x0))), k
-        assert _pads_zero(x1, dense.nx), k
+        assert _pads_untouched(x1, dense.nx), k
     for x0, x1 in zip(d0, d1):
         assert torch.equal(bits(x0), bits(x1))
 
