@@ -29,14 +29,12 @@ struct Cell {
   uint32_t x, y, z;
 };
 
-// Where a thread's cell lies.  A 256-thread block covers block_x consecutive cells of
+// The cell of a thread.  A 256-thread block covers block_x consecutive cells of
 // 256/block_x consecutive rows; all 64 lanes of a wave share one row, so y and z are
-// wave-uniform (made scalar with readfirstlane).
-enum CellKind { kNoCell = 0, kLiveCell = 1, kPadCell = 2 };
-
-// kNoCell past the last row and beyond the row pitch; kPadCell for nx <= x < pitch (a
-// pad word of a padded row); kLiveCell otherwise.
-__device__ __forceinline__ int cell_kind(const GridArgs& g, Cell& c) {
+// wave-uniform (made scalar with readfirstlane).  Returns false past the last row and
+// for x >= x_end (nx for kernels that compute live cells only; the row pitch for the
+// step, whose pad lanes store into the pad words).
+__device__ __forceinline__ bool cell_below(const GridArgs& g, Cell& c, uint32_t x_end) {
   const uint32_t bx = g.block_x;
   const uint32_t blocks_x = (g.nx + bx - 1) / bx;
   const uint32_t bxi = blockIdx.x % blocks_x;
@@ -44,17 +42,13 @@ __device__ __forceinline__ int cell_kind(const GridArgs& g, Cell& c) {
   const uint32_t ty = __builtin_amdgcn_readfirstlane(threadIdx.x / bx);
   const uint32_t r = byi * (256u / bx) + ty;
   c.x = bxi * bx + threadIdx.x % bx;
-  if (r >= g.ny * g.nzl) return kNoCell;
+  if (r >= g.ny * g.nzl) return false;
   c.y = r % g.ny;
   c.z = g.z0 + r / g.ny;
-  return c.x < g.nx ? kLiveCell : (c.x < g.pitch ? kPadCell : kNoCell);
+  return c.x < x_end;
 }
 
-// The cell of a thread for kernels that only compute live cells: false past the last
-// row and for the ragged x tail.
-__device__ __forceinline__ bool cell_of_thread(const GridArgs& g, Cell& c) {
-  return cell_kind(g, c) == kLiveCell;
-}
+__device__ __forceinline__ bool cell_of_thread(const GridArgs& g, Cell& c) { return cell_below(g, c, g.nx); }
 
 // Source coordinates of the pull gather: index k = c + 1 holds the coordinate of
 // x - c for c = -1, 0, +1, wrapped periodically (c = -1 reads x + 1).

@@ -43,14 +43,13 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;
   Cell c;
-  const int kind = cell_kind(g, c);
-  if (kind == kNoCell) return;
+  if (!cell_below(g, c, g.pitch)) return;
   // Pad lanes of a padded row (nx <= x < pitch) compute the last cell of the row again
   // (in-bounds loads, finite values) and store the result into their pad word with the
   // rest of the wave, so the row's last cache line is written by one store instruction
   // instead of two partial ones.
   Cell cs = c;
-  if (kind == kPadCell) cs.x = g.nx - 1;
+  cs.x = min(c.x, g.nx - 1);
   const Sources src = sources(cs, g);
   const size_t N = g.ncells;
   const uint32_t self = cell_index(g, cs);
