@@ -389,30 +389,51 @@ def measured_traffic():
     return float(fields["traffic bytes per launch"])
 
 
-def cpu_baseline(seconds_budget: float = 20.0):
+def _host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds_budget: float = 20.0, single_thread_budget: float = 4.0):
     """The FP64 oracle (plain torch CPU ops) on a bounded sample of the same
     workload: the D3Q27 Taylor-Green vortex at tau=0.51 on a 64^3 grid (the
-    256^3 grid's per-cell work, 1/64 of its cells), a few steps, all host threads."""
+    256^3 grid's per-cell work, 1/64 of its cells), a few steps, on the host threads
+    this process may use (OMP_NUM_THREADS if set), and again on one thread."""
     from oracle import lbm as olbm
     import synthetic
 
-    threads = os.cpu_count() or 1
-    torch.set_num_threads(threads)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     n = 64
     st = olbm.stencil("D3Q27")
     u = synthetic.taylor_green_3d(n, n, n, U0)
-    g = olbm.equilibrium(torch.ones(n, n, n, dtype=torch.float64), u, st)
-    g = olbm.step(g, TAU, st)  # warm-up
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds_budget and steps < 200:
-        g = olbm.step(g, TAU, st)
-        steps += 1
-    dt = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+    g0 = olbm.equilibrium(torch.ones(n, n, n, dtype=torch.float64), u, st)
+
+    def timed(nthreads, budget, max_steps):
+        torch.set_num_threads(nthreads)
+        g = olbm.step(g0, TAU, st)  # warm-up
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget and steps < max_steps:
+            g = olbm.step(g, TAU, st)
+            steps += 1
+        return steps, time.perf_counter() - t0
+
+    steps, dt = timed(threads, seconds_budget, 200)
+    used = torch.get_num_threads()
+    steps1, dt1 = timed(1, single_thread_budget, 50)
+    torch.set_num_threads(used)
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": used,
             "kind": "oracle",
             "sample": f"FP64 torch-CPU oracle, D3Q27 TGV tau={TAU} on {n}^3 cells, {steps} steps "
-                      f"({dt:.1f} s), same per-cell work as the {N}^3 run"}
+                      f"({dt:.1f} s), same per-cell work as the {N}^3 run",
+            "single_thread_value": n ** 3 * steps1 / dt1 / 1e6,
+            "host": f"{_host_cpu()}, {os.cpu_count()} logical CPUs visible"}
 
 
 def main():
