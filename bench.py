@@ -436,6 +436,58 @@ def cpu_baseline(seconds_budget: float = 20.0, single_thread_budget: float = 4.0
             "host": f"{_host_cpu()}, {os.cpu_count()} logical CPUs visible"}
 
 
+def profile_set(B, steps: int, warmup: int):
+    """Runs one fixed-size case per kernel, each a distinct kernel instantiation, so
+    that kernel traces and HBM byte counters can be attributed per kernel.  Prints one
+    JSON line per case: HIP-event ms per launch and algorithmic bytes per launch."""
+    from synthetic import taylor_green_2d, taylor_green_3d
+    u3 = taylor_green_3d(N, N, N, U0).cuda()
+    n2 = 8192
+    u2 = taylor_green_2d(n2, n2, 0.05).cuda()
+    gen = torch.Generator().manual_seed(5)
+    params = torch.cat([torch.randn(318, generator=gen, dtype=torch.float64) * 1e3,
+                        torch.randn(53, generator=gen, dtype=torch.float64) * 0.5,
+                        torch.randn(159, generator=gen, dtype=torch.float64) * 0.2])
+
+    def report(case, kernel, grid, ms, bpc):
+        print(json.dumps({"case": case, "kernel": kernel, "cells": grid.ncells, "ms": ms,
+                          "algorithmic_bytes_per_launch": bpc * grid.ncells,
+                          "gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9}), flush=True)
+
+    for storage, kname in (("f32", "step_kernel<D3Q27, F32, unforced>"), ("f16s", "step_kernel<D3Q27, F16S, unforced>"),
+                           ("f64", "step_kernel<D3Q27, F64, unforced>")):
+        r = run_forward(B, storage, steps, warmup, u3)
+        report(f"step D3Q27 {storage} {N}^3", kname, B.Grid("D3Q27", storage, N, N, N), r["ms_per_step"],
+               r["bytes_per_cell"])
+    r = run_adjoint(B, "f32", steps, warmup, u3)
+    report(f"adjoint (collision-local, chi input) D3Q27 f32 {N}^3", "adjoint_kernel<D3Q27, F32, unforced, local chi>",
+           B.Grid("D3Q27", "f32", N, N, N), r["ms_per_step"], r["bytes_per_cell"])
+    r = run_moments(B, steps, warmup, u3)
+    report(f"moments + reductions D3Q27 f32 {N}^3", "moments_kernel<D3Q27, F32>", B.Grid("D3Q27", "f32", N, N, N),
+           r["ms"], r["bytes_per_cell"])
+    del u3
+    torch.cuda.empty_cache()
+    grid = B.Grid("D2Q9", "f32", n2, n2)
+    bufs = [grid.empty_populations(), grid.empty_populations()]
+    B.lbm_init_equilibrium(grid, None, u2, bufs[0])
+    p_dev = params.float().cuda()
+    taus = [1, 1, 1, 0.6, 0.6, 0.6, 0.9, 0.8, 0.7]
+    for case, kname, fn in (
+            ("step D2Q9 f32 8192^2", "step_kernel<D2Q9, F32, unforced>",
+             lambda a, b: B.lbm_step(grid, a, b, 0.6, None, 1)),
+            ("MRT D2Q9 f32 8192^2", "mrt_step_kernel<F32, uniform ghost times>",
+             lambda a, b: B.lbm_step_mrt(grid, a, b, taus, None, 1)),
+            ("neural collision (ReLU) D2Q9 f32 8192^2", "mrt_step_kernel<F32, network ghost times (ReLU)>",
+             lambda a, b: B.lbm_step_neural(grid, a, b, 0.6, p_dev, "relu", 1))):
+        cur = [0]
+
+        def one():
+            fn(bufs[cur[0]], bufs[1 - cur[0]])
+            cur[0] ^= 1
+
+        report(case, kname, grid, time_launches(one, steps, warmup), B.bytes_per_cell_step(grid))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,6 +498,8 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=1000)
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the 384^3 precision study, the 128^3 forcing optimisation and the 512^3 adjoint run")
+    ap.add_argument("--profile-set", action="store_true",
+                    help="one fixed-size case per kernel (for kernel traces and HBM counters), one JSON line each")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy 1 GiB to another 1 GiB buffer 3 times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -471,6 +525,9 @@ def main():
     from synthetic import taylor_green_3d
 
     torch.cuda.set_device(0)
+    if args.profile_set:
+        profile_set(B, args.steps, args.warmup)
+        return
     u_dev = taylor_green_3d(N, N, N, U0).cuda()
     log(f"[bench] lib {B.LIB_PATH} version {B.lbm_version()}")
 
