@@ -8,6 +8,15 @@ import torch
 from . import binding as B
 
 
+class Diverged(RuntimeError):
+    """A run produced non-finite cells (for BGK: tau too close to 1/2 for the flow)."""
+
+    def __init__(self, steps_done: int, reductions: dict):
+        self.steps_done = steps_done
+        self.reductions = reductions
+        super().__init__(f"{int(reductions['nonfinite_cells'])} non-finite cells after {steps_done} steps")
+
+
 class Simulation:
     """Populations of one grid on one GPU.
 
@@ -61,3 +70,20 @@ class Simulation:
         B.lbm_moments(self.grid, self.f, self.force, None, None, self._red, self._ws)
         vals = self._red.cpu().tolist()
         return dict(zip(B.RED_NAMES, vals))
+
+    def run(self, n_steps: int, check_every: int = 100) -> dict:
+        """n_steps steps in chunks of check_every, reading the FP64 reductions after
+        each chunk; raises Diverged at the first check that finds non-finite cells.
+        Returns the last reductions."""
+        if n_steps < 1 or check_every < 1:
+            raise ValueError("n_steps and check_every must be >= 1")
+        left = n_steps
+        red = None
+        while left > 0:
+            k = min(check_every, left)
+            self.step(k)
+            left -= k
+            red = self.reductions()
+            if red["nonfinite_cells"] > 0:
+                raise Diverged(self.steps_done, red)
+        return red

@@ -97,6 +97,28 @@ def test_simulation_driver_and_copy():
     assert torch.equal(x, y)
 
 
+def test_run_monitor_raises_on_non_finite_cells():
+    """Failure detection forced from the host: a NaN planted in one population spreads
+    through streaming and collision, and Simulation.run raises Diverged at its first
+    check; a clean run of the same length returns finite reductions."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd.simulation import Diverged, Simulation
+
+    grid = B.Grid("D3Q27", "f32", 20, 12, 10)
+    u = synthetic.taylor_green_3d(20, 12, 10, 0.04)
+    sim = Simulation(grid, 0.6)
+    sim.init_equilibrium(u)
+    red = sim.run(30, check_every=10)
+    assert red["nonfinite_cells"] == 0 and sim.steps_done == 30
+    sim.init_equilibrium(u)
+    sim.f[3, 4, 13, 5] = float("nan")  # plane 3, row 4, rest direction, x = 5
+    with pytest.raises(Diverged) as info:
+        sim.run(30, check_every=10)
+    assert info.value.steps_done == 10
+    assert info.value.reductions["nonfinite_cells"] > 1
+
+
 def test_gradient_precision_fp32_matches_fp64():
     """The FP32 adjoint's force gradient points where the FP64 one does (48^3, 50
     steps): cosine >= 0.999."""
