@@ -96,6 +96,26 @@ __device__ __forceinline__ uint64_t rev_offset(const GridArgs& g, const Sources&
   return dir_row<LT::Q>(g, s.y[1 - LT::cy(i)], s.z[1 - LT::cz(i)], i) + s.x[1 - LT::cx(i)];
 }
 
+// Addressing split into a wave-uniform row base and a 32-bit per-lane byte offset: the
+// row base lives in scalar registers and the compiler can use the scalar-base form of
+// global loads and stores, with no per-lane 64-bit address arithmetic.
+template <typename W>
+__device__ __forceinline__ const W* at_byte(const W* row, uint32_t byte_offset) {
+  return reinterpret_cast<const W*>(reinterpret_cast<const char*>(row) + byte_offset);
+}
+template <typename W>
+__device__ __forceinline__ W* at_byte(W* row, uint32_t byte_offset) {
+  return reinterpret_cast<W*>(reinterpret_cast<char*>(row) + byte_offset);
+}
+
+// The pull source g_i(x - c_i) of the cell, given the byte offsets xb[k] of the three
+// source columns (k = c_x + 1 holds x - c_x).
+template <typename LT, typename W>
+__device__ __forceinline__ W load_src(const W* f, const GridArgs& g, const Sources& s, const uint32_t (&xb)[3],
+                                      int i) {
+  return *at_byte(f + dir_row<LT::Q>(g, s.y[LT::cy(i) + 1], s.z[LT::cz(i) + 1], i), xb[LT::cx(i) + 1]);
+}
+
 // Linear cell index of real-valued fields ([D][N] arrays).
 __device__ __forceinline__ uint32_t cell_index(const GridArgs& g, const Cell& c) {
   return (c.z * g.ny + c.y) * g.nx + c.x;

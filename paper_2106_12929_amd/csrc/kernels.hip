@@ -55,9 +55,12 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
   const uint32_t self = cell_index(g, cs);
 
   // Gather (pull streaming, Eq. 1): h_i(x) = g_i(x - c_i), as deviations from w_i.
+  using W = typename ST::word;
+  const uint32_t xb[3] = {src.x[0] * (uint32_t)sizeof(W), src.x[1] * (uint32_t)sizeof(W),
+                          src.x[2] * (uint32_t)sizeof(W)};
   real d[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(fin[src_offset<LT>(g, src, i)], CO::W(i));
+  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(load_src<LT>(fin, g, src, xb, i), CO::W(i));
 
   real Fx = 0, Fy = 0, Fz = 0;
   if constexpr (FM != kNoForce) {
@@ -66,9 +69,10 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
     if constexpr (LT::D == 3) Fz = force[2 * N + self];
   }
   bgk_collide<L, real, FM>(d, Fx, Fy, Fz, omega);
+  const uint32_t xo = c.x * (uint32_t)sizeof(W);
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    store_stream(&fout[dir_row<Q>(g, c.y, c.z + g.ghost, i) + c.x], ST::from_dev(d[i], CO::W(i)));
+    store_stream(at_byte(fout + dir_row<Q>(g, c.y, c.z + g.ghost, i), xo), ST::from_dev(d[i], CO::W(i)));
 }
 
 // ---------------------------------------------------------------------------------
