@@ -116,6 +116,20 @@ __device__ __forceinline__ W load_src(const W* f, const GridArgs& g, const Sourc
   return *at_byte(f + dir_row<LT::Q>(g, s.y[LT::cy(i) + 1], s.z[LT::cz(i) + 1], i), xb[LT::cx(i) + 1]);
 }
 
+// The word of direction i at x + c_i (the transpose of the pull gather), same addressing.
+template <typename LT, typename W>
+__device__ __forceinline__ W load_rev(const W* f, const GridArgs& g, const Sources& s, const uint32_t (&xb)[3],
+                                      int i) {
+  return *at_byte(f + dir_row<LT::Q>(g, s.y[1 - LT::cy(i)], s.z[1 - LT::cz(i)], i), xb[1 - LT::cx(i)]);
+}
+
+// Byte offsets of the three source columns of a cell for words of type W.
+template <typename W>
+__device__ __forceinline__ void column_bytes(const Sources& s, uint32_t (&xb)[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) xb[k] = s.x[k] * (uint32_t)sizeof(W);
+}
+
 // Linear cell index of real-valued fields ([D][N] arrays).
 __device__ __forceinline__ uint32_t cell_index(const GridArgs& g, const Cell& c) {
   return (c.z * g.ny + c.y) * g.nx + c.x;

@@ -56,8 +56,8 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
 
   // Gather (pull streaming, Eq. 1): h_i(x) = g_i(x - c_i), as deviations from w_i.
   using W = typename ST::word;
-  const uint32_t xb[3] = {src.x[0] * (uint32_t)sizeof(W), src.x[1] * (uint32_t)sizeof(W),
-                          src.x[2] * (uint32_t)sizeof(W)};
+  uint32_t xb[3];
+  column_bytes<W>(src, xb);
   real d[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(load_src<LT>(fin, g, src, xb, i), CO::W(i));
@@ -135,10 +135,12 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
   if (!cell_of_thread(g, c)) return;
   const Sources src = sources(c, g);
   const size_t N = g.ncells;
+  uint32_t xb[3];
+  column_bytes<typename ST::word>(src, xb);
 
   real d[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(fin[src_offset<LT>(g, src, i)], CO::W(i));
+  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(load_src<LT>(fin, g, src, xb, i), CO::W(i));
   real drho = 0, jx = 0, jy = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -427,10 +429,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   const size_t N = g.ncells;
   const uint32_t self = cell_index(g, c);
 
+  uint32_t xw[3], xr[3];  // column byte offsets for storage words and for reals
+  column_bytes<typename ST::word>(src, xw);
+  column_bytes<real>(src, xr);
   real drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const real d = ST::to_dev(gt[src_offset<LT>(g, src, i)], CO::W(i));
+    const real d = ST::to_dev(load_src<LT>(gt, g, src, xw, i), CO::W(i));
     drho += d;
     jx += real(LT::cx(i)) * d;
     jy += real(LT::cy(i)) * d;
@@ -453,7 +458,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   real mW = 0, mAx = 0, mAy = 0, mAz = 0, bxx = 0, byy = 0, bzz = 0, bxy = 0, bxz = 0, byz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    lam[i] = MODE == kAdjLocalChi ? lam_next[rev_offset<LT>(g, src, i)] : lam_next[dir_row<Q>(g, c.y, c.z, i) + c.x];
+    lam[i] = MODE == kAdjLocalChi ? load_rev<LT>(lam_next, g, src, xr, i) : *at_byte(lam_next + dir_row<Q>(g, c.y, c.z, i), xr[1]);
     const real l = lam[i];
     const real cx = LT::cx(i), cy = LT::cy(i), cz = LT::cz(i);
     const real al = CO::A(i) * l, bl = CO::B(i) * l;
