@@ -478,7 +478,9 @@ def profile_set(B, steps: int, warmup: int):
             ("MRT D2Q9 f32 8192^2", "mrt_step_kernel<F32, uniform ghost times>",
              lambda a, b: B.lbm_step_mrt(grid, a, b, taus, None, 1)),
             ("neural collision (ReLU) D2Q9 f32 8192^2", "mrt_step_kernel<F32, network ghost times (ReLU)>",
-             lambda a, b: B.lbm_step_neural(grid, a, b, 0.6, p_dev, "relu", 1))):
+             lambda a, b: B.lbm_step_neural(grid, a, b, 0.6, p_dev, "relu", 1)),
+            ("neural collision (tanh) D2Q9 f32 8192^2", "mrt_step_kernel<F32, network ghost times (tanh)>",
+             lambda a, b: B.lbm_step_neural(grid, a, b, 0.6, p_dev, "tanh", 1))):
         cur = [0]
 
         def one():

@@ -130,6 +130,16 @@ __device__ __forceinline__ void column_bytes(const Sources& s, uint32_t (&xb)[3]
   for (int k = 0; k < 3; ++k) xb[k] = s.x[k] * (uint32_t)sizeof(W);
 }
 
+// acc += k * v for an integer lattice factor k in {-1, 0, 1}: an add, a subtract or
+// nothing.  For finite v this equals the multiply-add bit for bit (one rounding of the
+// exact sum, and 0 * v adds nothing), but the compiler may not drop a multiplication by
+// 0.0 itself (it would change NaN and infinity propagation).
+template <typename real>
+__device__ __forceinline__ void add_times(real& acc, int k, real v) {
+  if (k > 0) acc += v;
+  if (k < 0) acc -= v;
+}
+
 // Linear cell index of real-valued fields ([D][N] arrays).
 __device__ __forceinline__ uint32_t cell_index(const GridArgs& g, const Cell& c) {
   return (c.z * g.ny + c.y) * g.nx + c.x;

@@ -105,12 +105,16 @@ template <typename real>
 __device__ __forceinline__ real act_tanh(real z) {
   return tanh(z);
 }
-// FP32: tanh z = 1 - 2/(e^{2z} + 1) with the hardware exponential; absolute error about
-// 1e-7 (relative error grows only where tanh z itself is below that), saturating
-// cleanly to +-1 where e^{2z} overflows or underflows.
+// FP32: tanh z = 1 - 2/(e^{2z} + 1) with the hardware base-2 exponential of
+// z * 2 log2(e) and the hardware reciprocal (each about 1 ulp; the reciprocal's
+// argument is >= 1, never denormal).  Absolute error a few 1e-8 (relative error grows
+// only where tanh z itself is below that), saturating cleanly to +-1 where e^{2z}
+// overflows (1/inf = 0) or underflows.  An IEEE division here would cost a dozen VALU
+// instructions per hidden unit, most of the network's cost in this VALU-bound kernel.
 template <>
 __device__ __forceinline__ float act_tanh<float>(float z) {
-  return 1.0f - 2.0f / (__expf(2.0f * z) + 1.0f);
+  constexpr float two_log2e = 2.0f * 1.44269504088896341f;  // exact: a power-of-two multiple
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z * two_log2e) + 1.0f);
 }
 template <typename real>
 __device__ __forceinline__ real exp_real(real z) {
@@ -145,8 +149,8 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     drho += d[i];
-    jx += real(LT::cx(i)) * d[i];
-    jy += real(LT::cy(i)) * d[i];
+    add_times(jx, LT::cx(i), d[i]);
+    add_times(jy, LT::cy(i), d[i]);
   }
   const real rho = real(1) + drho;
   const real inv_rho = real(1) / rho;
@@ -158,17 +162,20 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
   real nxx = 0, nxy = 0, nyy = 0, nN = 0, nJx = 0, nJy = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const real cu = real(LT::cx(i)) * ux + real(LT::cy(i)) * uy;
+    const int cx = LT::cx(i), cy = LT::cy(i);
+    real cu = 0;
+    add_times(cu, cx, ux);
+    add_times(cu, cy, uy);
     const real deq = CO::W(i) * drho + rho * (CO::A(i) * cu + CO::B(i) * cu * cu - CO::W(i) * usq);
     ne[i] = d[i] - deq;
-    const int cx = LT::cx(i), cy = LT::cy(i);
+    // every lattice factor below is 0, +-1, +-2 or 4: the products are exact
     const real gi = real((3 * cx * cx - 1) * (3 * cy * cy - 1));
     nxx += real(3 * cx * cx - 1) * ne[i];
-    nxy += real(cx * cy) * ne[i];
+    add_times(nxy, cx * cy, ne[i]);
     nyy += real(3 * cy * cy - 1) * ne[i];
     nN += gi * ne[i];
-    nJx += gi * real(cx) * ne[i];
-    nJy += gi * real(cy) * ne[i];
+    add_times(nJx, cx, gi * ne[i]);
+    add_times(nJy, cy, gi * ne[i]);
   }
   real s6 = real(sc.s[3]), s7 = real(sc.s[4]), s8 = real(sc.s[5]);
   if constexpr (GM == kGhostField) {
@@ -202,8 +209,13 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
   for (int i = 0; i < Q; ++i) {
     const int cx = LT::cx(i), cy = LT::cy(i);
     const real gi = real((3 * cx * cx - 1) * (3 * cy * cy - 1));
-    const real corr = real(3 * cx * cx - 1) * axx + real(cx * cy) * axy + real(3 * cy * cy - 1) * ayy +
-                      gi * (aN + real(cx) * aJx + real(cy) * aJy);
+    real corr = real(3 * cx * cx - 1) * axx;
+    add_times(corr, cx * cy, axy);
+    corr += real(3 * cy * cy - 1) * ayy;
+    real ghost_part = aN;
+    add_times(ghost_part, cx, aJx);
+    add_times(ghost_part, cy, aJy);
+    corr += gi * ghost_part;
     const real dn = d[i] - CO::W(i) * corr;
     store_stream(&fout[dir_row<Q>(g, c.y, c.z, i) + c.x], ST::from_dev(dn, CO::W(i)));
   }
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(256) void stream_kernel(const W* __restrict__ fin, 
   if (!cell_of_thread(g, c)) return;
   const Sources src = sources(c, g);
 #pragma unroll
-  for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[src_offset<LT>(g, src, i)];
+  for (int i = 0; i < LT::Q; ++i) store_stream(&fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x], fin[src_offset<LT>(g, src, i)]);
 }
 
 // The transpose of streaming, on real words: out_i(x) = in_i(x + c_i).
@@ -230,7 +242,7 @@ __global__ __launch_bounds__(256) void unstream_kernel(const W* __restrict__ fin
   if (!cell_of_thread(g, c)) return;
   const Sources src = sources(c, g);
 #pragma unroll
-  for (int i = 0; i < LT::Q; ++i) fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] = fin[rev_offset<LT>(g, src, i)];
+  for (int i = 0; i < LT::Q; ++i) store_stream(&fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x], fin[rev_offset<LT>(g, src, i)]);
 }
 
 // ---------------------------------------------------------------------------------
@@ -253,8 +265,8 @@ __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ rh
     const double cu = LT::cx(i) * ux + LT::cy(i) * uy + LT::cz(i) * uz;
     const double dev = LT::w(i) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - usq));
     // unshifted storage keeps f = W_i + dev with the base the kernels subtract again
-    fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x] =
-        ST::from_f64_dev(dev, static_cast<double>(Coef<L, typename ST::real>::W(i)));
+    store_stream(&fout[dir_row<LT::Q>(g, c.y, c.z, i) + c.x],
+                 ST::from_f64_dev(dev, static_cast<double>(Coef<L, typename ST::real>::W(i))));
   }
 }
 
@@ -281,9 +293,9 @@ __device__ __forceinline__ CellMoments<typename Storage<S>::real> cell_moments(
   for (int i = 0; i < LT::Q; ++i) {
     const real d = ST::to_dev(row[(size_t)i * nx + x], Coef<L, real>::W(i));
     drho += d;
-    j[0] += real(LT::cx(i)) * d;
-    j[1] += real(LT::cy(i)) * d;
-    j[2] += real(LT::cz(i)) * d;
+    add_times(j[0], LT::cx(i), d);
+    add_times(j[1], LT::cy(i), d);
+    add_times(j[2], LT::cz(i), d);
   }
   if (force) {
 #pragma unroll
@@ -307,17 +319,19 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
   using LT = Lattice<L>;
   const size_t N = g.ncells;
   const uint32_t rows = g.ny * g.nz;
-  // acc: [0] sum drho, [1..3] sum rho u, [4] 1/2 sum |u|^2, [5] non-finite, [6] max|u|, [7] min rho
+  // acc: [0] sum drho, [1..3] sum rho u, [4] 1/2 sum |u|^2, [5] non-finite, [6] max|u|^2 (the
+  // block's partial takes its square root once: sqrt is monotonic and correctly rounded, so
+  // that is max|u| exactly), [7] min rho
   double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 1.0e300};
   for (uint32_t r = blockIdx.x; r < rows; r += gridDim.x) {
     const typename Storage<S>::word* row = f + (uint64_t)r * LT::Q * g.pitch;
     for (uint32_t x = threadIdx.x; x < g.nx; x += 256) {
       const uint32_t n = r * g.nx + x;
       const auto m = cell_moments<L, S>(row, force, N, g.pitch, x, n);
-      if (rho_out) rho_out[n] = m.rho;
+      if (rho_out) store_stream(&rho_out[n], m.rho);
       if (u_out) {
 #pragma unroll
-        for (int a = 0; a < LT::D; ++a) u_out[a * N + n] = m.u[a];
+        for (int a = 0; a < LT::D; ++a) store_stream(&u_out[a * N + n], m.u[a]);
       }
       if (partials) {
         const double rho = m.rho;
@@ -330,7 +344,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
           acc[2] += rho * uy;
           acc[3] += rho * uz;
           acc[4] += 0.5 * usq;
-          acc[6] = fmax(acc[6], sqrt(usq));
+          acc[6] = fmax(acc[6], usq);
           acc[7] = fmin(acc[7], rho);
         } else {
           acc[5] += 1.0;
@@ -353,7 +367,8 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
     }
     __syncthreads();
   }
-  if (threadIdx.x < kNred) partials[blockIdx.x * kNred + threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < kNred)
+    partials[blockIdx.x * kNred + threadIdx.x] = threadIdx.x == 6 ? sqrt(sh[6][0]) : sh[threadIdx.x][0];
 }
 
 // One block folds the per-block partials in a fixed order; adds N to turn sum(drho)
@@ -437,9 +452,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   for (int i = 0; i < Q; ++i) {
     const real d = ST::to_dev(load_src<LT>(gt, g, src, xw, i), CO::W(i));
     drho += d;
-    jx += real(LT::cx(i)) * d;
-    jy += real(LT::cy(i)) * d;
-    jz += real(LT::cz(i)) * d;
+    add_times(jx, LT::cx(i), d);
+    add_times(jy, LT::cy(i), d);
+    add_times(jz, LT::cz(i), d);
   }
   real Fx = 0, Fy = 0, Fz = 0;
   if constexpr (FORCED) {
@@ -460,18 +475,18 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
   for (int i = 0; i < Q; ++i) {
     lam[i] = MODE == kAdjLocalChi ? load_rev<LT>(lam_next, g, src, xr, i) : *at_byte(lam_next + dir_row<Q>(g, c.y, c.z, i), xr[1]);
     const real l = lam[i];
-    const real cx = LT::cx(i), cy = LT::cy(i), cz = LT::cz(i);
+    const int cx = LT::cx(i), cy = LT::cy(i), cz = LT::cz(i);
     const real al = CO::A(i) * l, bl = CO::B(i) * l;
     mW += CO::W(i) * l;
-    mAx += cx * al;
-    mAy += cy * al;
-    mAz += cz * al;
-    bxx += cx * cx * bl;
-    byy += cy * cy * bl;
-    bzz += cz * cz * bl;
-    bxy += cx * cy * bl;
-    bxz += cx * cz * bl;
-    byz += cy * cz * bl;
+    add_times(mAx, cx, al);
+    add_times(mAy, cy, al);
+    add_times(mAz, cz, al);
+    add_times(bxx, cx * cx, bl);
+    add_times(byy, cy * cy, bl);
+    add_times(bzz, cz * cz, bl);
+    add_times(bxy, cx * cy, bl);
+    add_times(bxz, cx * cz, bl);
+    add_times(byz, cy * cz, bl);
   }
   const real mBux = bxx * ux + bxy * uy + bxz * uz;
   const real mBuy = bxy * ux + byy * uy + byz * uz;
@@ -503,7 +518,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
     if (LT::cy(j) < 0) mu -= vy;
     if (LT::cz(j) > 0) mu += vz;
     if (LT::cz(j) < 0) mu -= vz;
-    lam_out[MODE == kAdjScatter ? src_offset<LT>(g, src, j) : dir_row<Q>(g, c.y, c.z, j) + c.x] = mu;
+    real* dst = MODE == kAdjScatter
+                    ? at_byte(lam_out + dir_row<Q>(g, src.y[LT::cy(j) + 1], src.z[LT::cz(j) + 1], j), xr[LT::cx(j) + 1])
+                    : at_byte(lam_out + dir_row<Q>(g, c.y, c.z, j), xr[1]);
+    store_stream(dst, mu);
   }
   if constexpr (FORCED) {
     if (dforce) {
@@ -551,7 +569,7 @@ __global__ __launch_bounds__(256) void moments_adjoint_kernel(const typename Sto
     if (LT::cy(j) < 0) v -= by;
     if (LT::cz(j) > 0) v += bz;
     if (LT::cz(j) < 0) v -= bz;
-    lam_out[row + (uint64_t)j * g.pitch + c.x] = v;
+    store_stream(&lam_out[row + (uint64_t)j * g.pitch + c.x], v);
   }
   if (dforce) {
 #pragma unroll
