@@ -238,8 +238,14 @@ def run_moments(B, steps: int, warmup: int, u_dev):
     red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
     ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
     ms = time_launches(lambda: B.lbm_moments(grid, g, None, rho, u, red, ws), steps, warmup)
+    ms_fields = time_launches(lambda: B.lbm_moments(grid, g, None, rho, u), steps, warmup)
+    ms_red = time_launches(lambda: B.lbm_moments(grid, g, None, None, None, red, ws), steps, warmup)
     bpc = 27 * 4 + 4 * 4
     out = {"ms": ms, "bytes_per_cell": bpc, "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9,
+           "fields_only": {"ms": ms_fields, "bytes_per_cell": bpc,
+                           "hbm_gbs": bpc * grid.ncells / (ms_fields * 1e-3) / 1e9},
+           "reductions_only": {"ms": ms_red, "bytes_per_cell": 27 * 4,
+                               "hbm_gbs": 27 * 4 * grid.ncells / (ms_red * 1e-3) / 1e9},
            "reductions": dict(zip(B.RED_NAMES, red.cpu().tolist()))}
     del g, rho, u
     torch.cuda.empty_cache()
@@ -462,9 +468,18 @@ def profile_set(B, steps: int, warmup: int):
     r = run_adjoint(B, "f32", steps, warmup, u3)
     report(f"adjoint (collision-local, chi input) D3Q27 f32 {N}^3", "adjoint_kernel<D3Q27, F32, unforced, local chi>",
            B.Grid("D3Q27", "f32", N, N, N), r["ms_per_step"], r["bytes_per_cell"])
-    r = run_moments(B, steps, warmup, u3)
-    report(f"moments + reductions D3Q27 f32 {N}^3", "moments_kernel<D3Q27, F32>", B.Grid("D3Q27", "f32", N, N, N),
-           r["ms"], r["bytes_per_cell"])
+    # moments: each mode once, so that one kernel instantiation serves one case
+    g3 = B.Grid("D3Q27", "f32", N, N, N)
+    pops = g3.empty_populations()
+    B.lbm_init_equilibrium(g3, None, u3, pops)
+    rho, u = g3.empty_real(0), g3.empty_real(3)
+    red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
+    ws = torch.empty(B.lbm_moments_workspace_size(g3), dtype=torch.uint8, device="cuda")
+    report(f"moments + reductions D3Q27 f32 {N}^3", "moments_kernel<D3Q27, F32, unforced>", g3,
+           time_launches(lambda: B.lbm_moments(g3, pops, None, rho, u, red, ws), steps, warmup), 27 * 4 + 4 * 4)
+    report(f"moments fields only D3Q27 f32 {N}^3", "moments_fields_kernel<D3Q27, F32, unforced>", g3,
+           time_launches(lambda: B.lbm_moments(g3, pops, None, rho, u), steps, warmup), 27 * 4 + 4 * 4)
+    del pops, rho, u, ws
     del u3
     torch.cuda.empty_cache()
     grid = B.Grid("D2Q9", "f32", n2, n2)

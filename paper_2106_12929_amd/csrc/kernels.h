@@ -9,7 +9,7 @@ namespace lbm {
 constexpr int kNred = 8;              // reduction results of lbm_moments
 enum AdjointMode { kAdjScatter = 0, kAdjLocalLam = 1, kAdjLocalChi = 2 };
 enum ForceMode { kNoForce = 0, kGuoForce = 1, kShiftForce = 2 };
-constexpr int kMaxReduceBlocks = 1024;  // fixed reduction grid (bitwise-reproducible sums)
+constexpr int kMaxReduceBlocks = 2048;  // fixed reduction grid (bitwise-reproducible sums)
 
 // Grid geometry passed by value to every cell-parallel kernel.
 struct GridArgs {

@@ -271,36 +271,35 @@ __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ rh
 }
 
 // ---------------------------------------------------------------------------------
-// Moments (Eq. 4) and FP64 reductions.  Block b handles rows b, b + gridDim, ... with a
-// fixed grid, so that every reduction is summed in the same order on every call.
+// Moments (Eq. 4) and FP64 reductions.  With reductions, the grid is cut into items of
+// up to 256 cells (one row segment each: item t is row t / chunks, columns
+// (t % chunks)*256 + lane), and block b of a fixed grid handles items b, b + gridDim, ...,
+// so that every reduction is summed in the same order on every call.  Fields alone take
+// one thread per cell, the launch of the step kernels, with no fixed grid to respect.
 // ---------------------------------------------------------------------------------
 template <typename real>
 struct CellMoments {
   real drho, rho, u[3];
 };
 
-// Moments of the cell at column x of a row whose direction rows start at `row`
-// (word (i, x) at row[i*nx + x]); n is the cell's index in the real-valued fields.
+// Moments of one cell from its Q stored words and its force F (zero when unforced).
 template <int L, int S>
-__device__ __forceinline__ CellMoments<typename Storage<S>::real> cell_moments(
-    const typename Storage<S>::word* __restrict__ row, const typename Storage<S>::real* __restrict__ force,
-    size_t N, uint32_t nx, uint32_t x, uint32_t n) {
+__device__ __forceinline__ CellMoments<typename Storage<S>::real> moments_of_words(
+    const typename Storage<S>::word (&w)[Lattice<L>::Q], const typename Storage<S>::real (&F)[3]) {
   using LT = Lattice<L>;
   using ST = Storage<S>;
   using real = typename ST::real;
   real drho = 0, j[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 0; i < LT::Q; ++i) {
-    const real d = ST::to_dev(row[(size_t)i * nx + x], Coef<L, real>::W(i));
+    const real d = ST::to_dev(w[i], Coef<L, real>::W(i));
     drho += d;
     add_times(j[0], LT::cx(i), d);
     add_times(j[1], LT::cy(i), d);
     add_times(j[2], LT::cz(i), d);
   }
-  if (force) {
 #pragma unroll
-    for (int a = 0; a < LT::D; ++a) j[a] -= real(0.5) * force[a * N + n];
-  }
+  for (int a = 0; a < LT::D; ++a) j[a] -= real(0.5) * F[a];
   CellMoments<real> m;
   m.drho = drho;
   m.rho = real(1) + drho;
@@ -310,45 +309,84 @@ __device__ __forceinline__ CellMoments<typename Storage<S>::real> cell_moments(
   return m;
 }
 
+// The Q words of the cell at column x of a row whose direction rows start at `row`
+// (word (i, x) at row[i*pitch + x]), and, if FORCED, its force (cell index n of the
+// [D][N] field); F = 0 otherwise.
+template <int L, int S, bool FORCED>
+__device__ __forceinline__ void load_cell(const typename Storage<S>::word* __restrict__ row,
+                                          const typename Storage<S>::real* __restrict__ force, size_t N,
+                                          uint32_t pitch, uint32_t x, uint32_t n,
+                                          typename Storage<S>::word (&w)[Lattice<L>::Q],
+                                          typename Storage<S>::real (&F)[3]) {
+  using W = typename Storage<S>::word;
+  const uint32_t xo = x * (uint32_t)sizeof(W);
+#pragma unroll
+  for (int i = 0; i < Lattice<L>::Q; ++i) w[i] = *at_byte(row + (uint64_t)i * pitch, xo);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[a] = 0;
+  if constexpr (FORCED) {
+#pragma unroll
+    for (int a = 0; a < Lattice<L>::D; ++a) F[a] = force[a * N + n];
+  }
+}
+
 template <int L, int S>
+__device__ __forceinline__ CellMoments<typename Storage<S>::real> cell_moments(
+    const typename Storage<S>::word* __restrict__ row, const typename Storage<S>::real* __restrict__ force,
+    size_t N, uint32_t pitch, uint32_t x, uint32_t n) {
+  typename Storage<S>::word w[Lattice<L>::Q];
+  typename Storage<S>::real F[3];
+  if (force)
+    load_cell<L, S, true>(row, force, N, pitch, x, n, w, F);
+  else
+    load_cell<L, S, false>(row, force, N, pitch, x, n, w, F);
+  return moments_of_words<L, S>(w, F);
+}
+
+template <int L, int S, bool FORCED>
 __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>::word* __restrict__ f,
                                                       const typename Storage<S>::real* __restrict__ force,
                                                       typename Storage<S>::real* __restrict__ rho_out,
                                                       typename Storage<S>::real* __restrict__ u_out,
                                                       double* __restrict__ partials, GridArgs g) {
   using LT = Lattice<L>;
+  using W = typename Storage<S>::word;
+  using R = typename Storage<S>::real;
+  constexpr int Q = LT::Q;
   const size_t N = g.ncells;
-  const uint32_t rows = g.ny * g.nz;
+  const uint32_t chunks = (g.nx + 255) / 256;
+  const uint32_t items = g.ny * g.nz * chunks;
   // acc: [0] sum drho, [1..3] sum rho u, [4] 1/2 sum |u|^2, [5] non-finite, [6] max|u|^2 (the
   // block's partial takes its square root once: sqrt is monotonic and correctly rounded, so
   // that is max|u| exactly), [7] min rho
   double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 1.0e300};
-  for (uint32_t r = blockIdx.x; r < rows; r += gridDim.x) {
-    const typename Storage<S>::word* row = f + (uint64_t)r * LT::Q * g.pitch;
-    for (uint32_t x = threadIdx.x; x < g.nx; x += 256) {
-      const uint32_t n = r * g.nx + x;
-      const auto m = cell_moments<L, S>(row, force, N, g.pitch, x, n);
-      if (rho_out) store_stream(&rho_out[n], m.rho);
-      if (u_out) {
+  W w[Q];
+  R F[3];
+  for (uint32_t t = blockIdx.x; t < items; t += gridDim.x) {
+    const uint32_t r = t / chunks, x = (t % chunks) * 256 + threadIdx.x;
+    if (x >= g.nx) continue;
+    load_cell<L, S, FORCED>(f + (uint64_t)r * Q * g.pitch, force, N, g.pitch, x, r * g.nx + x, w, F);
+    const auto m = moments_of_words<L, S>(w, F);
+    const uint32_t xo = x * (uint32_t)sizeof(R);  // row-uniform base + lane byte offset
+    if (rho_out) store_stream(at_byte(rho_out + (uint64_t)r * g.nx, xo), m.rho);
+    if (u_out) {
 #pragma unroll
-        for (int a = 0; a < LT::D; ++a) store_stream(&u_out[a * N + n], m.u[a]);
-      }
-      if (partials) {
-        const double rho = m.rho;
-        const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
-        const double usq = ux * ux + uy * uy + uz * uz;
-        const bool finite = isfinite(rho) && isfinite(usq);
-        if (finite) {
-          acc[0] += (double)m.drho;
-          acc[1] += rho * ux;
-          acc[2] += rho * uy;
-          acc[3] += rho * uz;
-          acc[4] += 0.5 * usq;
-          acc[6] = fmax(acc[6], usq);
-          acc[7] = fmin(acc[7], rho);
-        } else {
-          acc[5] += 1.0;
-        }
+      for (int k = 0; k < LT::D; ++k) store_stream(at_byte(u_out + k * N + (uint64_t)r * g.nx, xo), m.u[k]);
+    }
+    if (partials) {
+      const double rho = m.rho;
+      const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
+      const double usq = ux * ux + uy * uy + uz * uz;
+      if (isfinite(rho) && isfinite(usq)) {
+        acc[0] += (double)m.drho;
+        acc[1] += rho * ux;
+        acc[2] += rho * uy;
+        acc[3] += rho * uz;
+        acc[4] += 0.5 * usq;
+        acc[6] = fmax(acc[6], usq);
+        acc[7] = fmin(acc[7], rho);
+      } else {
+        acc[5] += 1.0;
       }
     }
   }
@@ -369,6 +407,34 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
   }
   if (threadIdx.x < kNred)
     partials[blockIdx.x * kNred + threadIdx.x] = threadIdx.x == 6 ? sqrt(sh[6][0]) : sh[threadIdx.x][0];
+}
+
+// Moments fields only (no reductions): one thread per cell.  More waves per SIMD than the
+// fixed reduction grid keeps resident, and no loop: each wave loads, reduces and stores
+// one row segment.
+template <int L, int S, bool FORCED>
+__global__ __launch_bounds__(256) void moments_fields_kernel(const typename Storage<S>::word* __restrict__ f,
+                                                             const typename Storage<S>::real* __restrict__ force,
+                                                             typename Storage<S>::real* __restrict__ rho_out,
+                                                             typename Storage<S>::real* __restrict__ u_out,
+                                                             GridArgs g) {
+  using LT = Lattice<L>;
+  using W = typename Storage<S>::word;
+  using R = typename Storage<S>::real;
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
+  const size_t N = g.ncells;
+  const uint32_t r = c.z * g.ny + c.y;
+  W w[LT::Q];
+  R F[3];
+  load_cell<L, S, FORCED>(f + (uint64_t)r * LT::Q * g.pitch, force, N, g.pitch, c.x, r * g.nx + c.x, w, F);
+  const auto m = moments_of_words<L, S>(w, F);
+  const uint32_t xo = c.x * (uint32_t)sizeof(R);
+  if (rho_out) store_stream(at_byte(rho_out + (uint64_t)r * g.nx, xo), m.rho);
+  if (u_out) {
+#pragma unroll
+    for (int k = 0; k < LT::D; ++k) store_stream(at_byte(u_out + k * N + (uint64_t)r * g.nx, xo), m.u[k]);
+  }
 }
 
 // One block folds the per-block partials in a fixed order; adds N to turn sum(drho)
@@ -676,7 +742,17 @@ static hipError_t launch_moments_ls(const void* f, const void* force, void* rho,
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
-  moments_kernel<L, S><<<nblocks, 256, 0, s>>>((const W*)f, (const R*)force, (R*)rho, (R*)u, partials, g);
+  if (!partials) {
+    if (force)
+      moments_fields_kernel<L, S, true><<<cell_grid(g), 256, 0, s>>>((const W*)f, (const R*)force, (R*)rho, (R*)u, g);
+    else
+      moments_fields_kernel<L, S, false><<<cell_grid(g), 256, 0, s>>>((const W*)f, nullptr, (R*)rho, (R*)u, g);
+    return hipGetLastError();
+  }
+  if (force)
+    moments_kernel<L, S, true><<<nblocks, 256, 0, s>>>((const W*)f, (const R*)force, (R*)rho, (R*)u, partials, g);
+  else
+    moments_kernel<L, S, false><<<nblocks, 256, 0, s>>>((const W*)f, nullptr, (R*)rho, (R*)u, partials, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !red) return e;
   reduce_partials_kernel<<<1, 256, 0, s>>>(partials, nblocks, red, (double)g.ncells);
