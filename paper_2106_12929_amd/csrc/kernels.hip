@@ -97,8 +97,9 @@ __global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::wo
 //                  b1 [53], W2 [3][53]; every lane reads the same addresses, so they
 //                  come in through scalar loads.
 // ---------------------------------------------------------------------------------
+template <typename real>
 struct MrtScales {
-  double s[6];
+  real s[6];  // rounded to the kernel's real type on the host
 };
 
 template <typename real>
@@ -129,7 +130,7 @@ template <int S, int GM>
 __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>::word* __restrict__ fin,
                                                        typename Storage<S>::word* __restrict__ fout,
                                                        const typename Storage<S>::real* __restrict__ ghost,
-                                                       GridArgs g, MrtScales sc) {
+                                                       GridArgs g, MrtScales<typename Storage<S>::real> sc) {
   using LT = Lattice<kD2Q9>;
   using ST = Storage<S>;
   using real = typename ST::real;
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
   }
   const real axx = nxx * real(sc.s[0]), axy = nxy * real(sc.s[1]), ayy = nyy * real(sc.s[2]);
   const real aN = nN * s6, aJx = nJx * s7, aJy = nJy * s8;
+  const uint32_t xo = c.x * (uint32_t)sizeof(typename ST::word);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int cx = LT::cx(i), cy = LT::cy(i);
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
     add_times(ghost_part, cy, aJy);
     corr += gi * ghost_part;
     const real dn = d[i] - CO::W(i) * corr;
-    store_stream(&fout[dir_row<Q>(g, c.y, c.z, i) + c.x], ST::from_dev(dn, CO::W(i)));
+    store_stream(at_byte(fout + dir_row<Q>(g, c.y, c.z, i), xo), ST::from_dev(dn, CO::W(i)));
   }
 }
 
@@ -676,8 +678,8 @@ static hipError_t launch_mrt_s(const void* fin, void* fout, const void* ghost, i
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
-  MrtScales sc;
-  for (int k = 0; k < 6; ++k) sc.s[k] = scales[k];
+  MrtScales<R> sc;
+  for (int k = 0; k < 6; ++k) sc.s[k] = (R)scales[k];
   const W* a = (const W*)fin;
   W* b = (W*)fout;
   const R* gh = (const R*)ghost;
