@@ -586,10 +586,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
     if (LT::cy(j) < 0) mu -= vy;
     if (LT::cz(j) > 0) mu += vz;
     if (LT::cz(j) < 0) mu -= vz;
-    real* dst = MODE == kAdjScatter
-                    ? at_byte(lam_out + dir_row<Q>(g, src.y[LT::cy(j) + 1], src.z[LT::cz(j) + 1], j), xr[LT::cx(j) + 1])
-                    : at_byte(lam_out + dir_row<Q>(g, c.y, c.z, j), xr[1]);
-    store_stream(dst, mu);
+    if constexpr (MODE == kAdjScatter) {
+      // shifted rows: a wave's store straddles cache lines that the neighbouring wave
+      // completes, so it stays a plain (cached) store for the halves to merge in L2
+      *at_byte(lam_out + dir_row<Q>(g, src.y[LT::cy(j) + 1], src.z[LT::cz(j) + 1], j), xr[LT::cx(j) + 1]) = mu;
+    } else {
+      store_stream(at_byte(lam_out + dir_row<Q>(g, c.y, c.z, j), xr[1]), mu);
+    }
   }
   if constexpr (FORCED) {
     if (dforce) {

@@ -315,6 +315,43 @@ def test_moments_parity(lat, shape, kind, forced):
     assert abs(float(red[7]) - float(r_ref.min())) <= tol * 10
 
 
+@pytest.mark.parametrize("lat,shape", CASES)
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("forced", [False, True])
+def test_moments_fields_only_equal_fields_with_reductions(lat, shape, kind, forced):
+    """Calls without reductions take a one-thread-per-cell kernel, calls with them the
+    fixed reduction grid: rho and u agree bit for bit (both start as NaN, so a cell
+    either kernel skipped would show), also where planted NaN and inf words make
+    cells non-finite."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    grid = _grid(B, lat, kind, shape)
+    spatial = _spatial(lat, shape)
+    say(f"moments fields-only vs reductions {lat} {kind} {shape} forced={forced}")
+    s = _state(st, spatial, 33, kind)
+    s.view(st.Q, -1)[3, 5] = float("nan")
+    s.view(st.Q, -1)[0, -1] = float("inf")
+    f = grid.to_layout(s).cuda()
+    F = _force(grid, spatial, 34).cuda() if forced else None
+    outs = []
+    for with_red in (False, True):
+        rho = grid.empty_real(0).fill_(float("nan"))
+        u = grid.empty_real(grid.D).fill_(float("nan"))
+        if with_red:
+            red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
+            ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
+            B.lbm_moments(grid, f, F, rho, u, red, ws)
+            assert float(red[5].cpu()) == 2.0
+        else:
+            B.lbm_moments(grid, f, F, rho, u)
+        outs.append((rho.cpu(), u.cpu()))
+    assert torch.equal(bits(outs[0][0]), bits(outs[1][0]))
+    assert torch.equal(bits(outs[0][1]), bits(outs[1][1]))
+    finite = torch.isfinite(outs[0][0]).reshape(-1)
+    assert int((~finite).sum()) == 2  # exactly the two planted cells
+
+
 def test_nonfinite_cells_are_counted():
     need_gpu()
     B = binding()
