@@ -58,28 +58,41 @@ def time_launches(fn, steps: int, warmup: int) -> float:
     return start.elapsed_time(stop) / steps
 
 
-def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = "D3Q27"):
+def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = "D3Q27", mode: str = "none"):
+    """Step throughput; mode "guo" adds a body-force field (Guo forcing), "shift" a
+    velocity-shift field (the flow-control forcing), each D reals read per cell."""
     grid = B.Grid(lattice, storage, N, N, N)
     bufs = [grid.empty_populations(), grid.empty_populations()]
     B.lbm_init_equilibrium(grid, None, u_dev, bufs[0])
+    field = None
+    if mode != "none":
+        gen = torch.Generator(device="cuda").manual_seed(11)
+        field = torch.randn((grid.D,) + grid.spatial, generator=gen, device="cuda", dtype=torch.float64)
+        field = (field * 1e-5).to(grid.real_dtype)
     cur = [0]
 
     def one():
-        B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, None, 1)
+        if mode == "shift":
+            B.lbm_step_shifted(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, field, 1)
+        else:
+            B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, field, 1)
         cur[0] ^= 1
 
     ms = time_launches(one, steps, warmup)
     bpc = B.bytes_per_cell_step(grid)
+    if field is not None:
+        bpc += grid.D * field.element_size()
     out = {
         "lattice": lattice,
         "storage": storage,
+        "forcing": mode,
         "ms_per_step": ms,
         "mlups": grid.ncells / (ms * 1e-3) / 1e6,
         "bytes_per_cell": bpc,
         "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9,
     }
     out["hbm_frac"] = out["hbm_gbs"] / PEAK_HBM_GBS
-    del bufs
+    del bufs, field
     torch.cuda.empty_cache()
     return out
 
@@ -199,32 +212,38 @@ def run_pitch(B, steps: int, warmup: int):
     return out
 
 
-def run_adjoint(B, storage: str, steps: int, warmup: int, u_dev, local: bool = True):
+def run_adjoint(B, storage: str, steps: int, warmup: int, u_dev, local: bool = True, forced: bool = False):
     """Adjoint-step kernel throughput: the collision-local form the rollout uses
-    (gathered reads, aligned writes) or the scatter form of lbm_adjoint_step."""
+    (gathered reads, aligned writes) or the scatter form of lbm_adjoint_step.  With
+    `forced` the step has a force field and accumulates dL/dF (the workloads' case:
+    F read, dF read and written)."""
     grid = B.Grid("D3Q27", storage, N, N, N)
     g = grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, u_dev, g)
     lam = [torch.zeros(grid.population_shape(), dtype=grid.real_dtype, device="cuda") for _ in range(2)]
     lam[0].normal_()
+    F = dF = None
+    if forced:
+        F = torch.zeros((grid.D,) + grid.spatial, dtype=grid.real_dtype, device="cuda")
+        dF = torch.zeros_like(F)
     cur = [0]
 
     def one():
         if local:
-            B.lbm_adjoint_step_local(grid, g, lam[cur[0]], True, lam[1 - cur[0]], TAU)
+            B.lbm_adjoint_step_local(grid, g, lam[cur[0]], True, lam[1 - cur[0]], TAU, F, dF)
         else:
-            B.lbm_adjoint_step(grid, g, lam[cur[0]], lam[1 - cur[0]], TAU)
+            B.lbm_adjoint_step(grid, g, lam[cur[0]], lam[1 - cur[0]], TAU, F, dF)
         cur[0] ^= 1
 
     ms = time_launches(one, steps, warmup)
     wb = torch.tensor([], dtype=grid.word_dtype).element_size()
     rb = torch.tensor([], dtype=grid.real_dtype).element_size()
-    bpc = grid.Q * (wb + 2 * rb)
-    out = {"storage": storage, "form": "local" if local else "scatter", "ms_per_step": ms,
+    bpc = grid.Q * (wb + 2 * rb) + (3 * grid.D * rb if forced else 0)
+    out = {"storage": storage, "form": "local" if local else "scatter", "forced": forced, "ms_per_step": ms,
            "mlups": grid.ncells / (ms * 1e-3) / 1e6, "bytes_per_cell": bpc,
            "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9}
     out["hbm_frac"] = out["hbm_gbs"] / PEAK_HBM_GBS
-    del g, lam
+    del g, lam, F, dF
     torch.cuda.empty_cache()
     return out
 
@@ -468,9 +487,16 @@ def profile_set(B, steps: int, warmup: int):
         r = run_forward(B, storage, steps, warmup, u3)
         report(f"step D3Q27 {storage} {N}^3", kname, B.Grid("D3Q27", storage, N, N, N), r["ms_per_step"],
                r["bytes_per_cell"])
+    r = run_forward(B, "f32", steps, warmup, u3, mode="guo")
+    report(f"step D3Q27 f32 {N}^3, Guo force", "step_kernel<D3Q27, F32, Guo>", B.Grid("D3Q27", "f32", N, N, N),
+           r["ms_per_step"], r["bytes_per_cell"])
     r = run_adjoint(B, "f32", steps, warmup, u3)
     report(f"adjoint (collision-local, chi input) D3Q27 f32 {N}^3", "adjoint_kernel<D3Q27, F32, unforced, local chi>",
            B.Grid("D3Q27", "f32", N, N, N), r["ms_per_step"], r["bytes_per_cell"])
+    r = run_adjoint(B, "f16s", steps, warmup, u3, forced=True)
+    report(f"adjoint (collision-local, chi input, forced) D3Q27 f16s state {N}^3",
+           "adjoint_kernel<D3Q27, F16S, forced, local chi>", B.Grid("D3Q27", "f16s", N, N, N), r["ms_per_step"],
+           r["bytes_per_cell"])
     # moments: each mode once, so that one kernel instantiation serves one case
     g3 = B.Grid("D3Q27", "f32", N, N, N)
     pops = g3.empty_populations()
@@ -562,6 +588,9 @@ def main():
         # D3Q19, the lattice of the paper's 3D benchmark (Taylor-Green vortex, Sec. 3.3)
         detail["forward_d3q19"] = {s: run_forward(B, s, args.steps, args.warmup, u_dev, "D3Q19")
                                    for s in ("f32", "f64", "f16s")}
+        log("[bench] forced steps")
+        detail["forward_forced"] = {f"{m}_{s}": run_forward(B, s, max(20, args.steps // 4), 5, u_dev, mode=m)
+                                    for m in ("guo", "shift") for s in ("f32", "f16s")}
         log("[bench] D2Q9 8192^2 BGK and MRT")
         detail["d2q9_8192"] = run_d2q9(B, args.steps, args.warmup)
         log("[bench] unaligned rows, dense and padded")
@@ -572,6 +601,8 @@ def main():
         detail["adjoint"] = {s: run_adjoint(B, s, max(20, args.steps // 4), 5, u_dev) for s in ("f32", "f16s")}
         detail["adjoint_scatter_form"] = {s: run_adjoint(B, s, max(20, args.steps // 4), 5, u_dev, local=False)
                                           for s in ("f32", "f16s")}
+        detail["adjoint_forced"] = {s: run_adjoint(B, s, max(20, args.steps // 4), 5, u_dev, forced=True)
+                                    for s in ("f32", "f16s")}
         log("[bench] moments")
         detail["moments_f32"] = run_moments(B, 20, 3, u_dev)
         log("[bench] 64x64 D2Q9 launch-bound run")
