@@ -187,8 +187,12 @@ __device__ __forceinline__ void bgk_collide(real (&d)[Lattice<L>::Q], real Fx, r
     uz += Fz;
   }
   const real usq = real(1.5) * (ux * ux + uy * uy + uz * uz);
-  const real uF = ux * Fx + uy * Fy + uz * Fz;
+  // Guo source G_i = (1 - omega/2) (A_i c_i.F - 3 W_i u.F + 2 B_i (c_i.u)(c_i.F)), with
+  // the cell's factors taken out once: gF = (1 - omega/2) F, g3uF = 3 (1 - omega/2) u.F,
+  // so that G_i = (c_i.gF)(A_i + 2 B_i c_i.u) - W_i g3uF
   const real guo = real(1) - real(0.5) * omega;
+  const real gFx = guo * Fx, gFy = guo * Fy, gFz = guo * Fz;
+  const real g3uF = real(3) * (ux * gFx + uy * gFy + uz * gFz);
 
   // Equilibrium (Eq. 3) as a deviation, BGK relaxation (Eq. 2), Guo source.
 #pragma unroll
@@ -204,14 +208,11 @@ __device__ __forceinline__ void bgk_collide(real (&d)[Lattice<L>::Q], real Fx, r
     const real deq = CO::W(i) * drho + rho * (CO::A(i) * cu + CO::B(i) * cu * cu - CO::W(i) * usq);
     real dn = d[i] + omega * (deq - d[i]);
     if constexpr (FORCED) {
-      real cF = zero;
-      if (LT::cx(i) > 0) cF += Fx;
-      if (LT::cx(i) < 0) cF -= Fx;
-      if (LT::cy(i) > 0) cF += Fy;
-      if (LT::cy(i) < 0) cF -= Fy;
-      if (LT::cz(i) > 0) cF += Fz;
-      if (LT::cz(i) < 0) cF -= Fz;
-      dn += guo * (CO::A(i) * cF - real(3) * CO::W(i) * uF + real(2) * CO::B(i) * cu * cF);
+      real cgF = zero;
+      add_times(cgF, LT::cx(i), gFx);
+      add_times(cgF, LT::cy(i), gFy);
+      add_times(cgF, LT::cz(i), gFz);
+      dn += cgF * (CO::A(i) + real(2) * CO::B(i) * cu) - CO::W(i) * g3uF;
     }
     d[i] = dn;
   }

@@ -32,8 +32,15 @@ namespace lbm {
 // Fused pull stream + BGK collide (Eqs. 1-4), one word per lane and access.  FM selects
 // the per-cell field `force` (see bgk_collide).
 // ---------------------------------------------------------------------------------
+// Minimum waves per SIMD asked of the compiler.  The Guo-forced f16s step needs 83
+// registers unconstrained (5 waves per SIMD); asked for 6 it fits 80 with no spills.
+template <int S, int FM>
+struct StepMinWaves {
+  static constexpr int value = (FM == kGuoForce && (S == kF16S || S == kBF16S)) ? 6 : 1;
+};
+
 template <int L, int S, int FM>
-__global__ __launch_bounds__(256) void step_kernel(const typename Storage<S>::word* __restrict__ fin,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWaves<S, FM>::value))) void step_kernel(const typename Storage<S>::word* __restrict__ fin,
                                                    typename Storage<S>::word* __restrict__ fout,
                                                    const typename Storage<S>::real* __restrict__ force,
                                                    GridArgs g, typename Storage<S>::real omega) {
