@@ -153,38 +153,33 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
   real d[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(load_src<LT>(fin, g, src, xb, i), CO::W(i));
-  real drho = 0, jx = 0, jy = 0;
+  // Raw moments of the deviations d = h - w; every R_k is orthogonal to w, so these are
+  // the moments of h.  Lattice factors are 0, +-1, +-2 or 4: every product is exact.
+  real drho = 0, jx = 0, jy = 0, sx = 0, sy = 0, pxy = 0, nN = 0, nJx = 0, nJy = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
+    const int cx = LT::cx(i), cy = LT::cy(i);
     drho += d[i];
-    add_times(jx, LT::cx(i), d[i]);
-    add_times(jy, LT::cy(i), d[i]);
+    add_times(jx, cx, d[i]);
+    add_times(jy, cy, d[i]);
+    add_times(sx, cx * cx, d[i]);  // sum over c_x != 0
+    add_times(sy, cy * cy, d[i]);
+    add_times(pxy, cx * cy, d[i]);
+    const real gd = real((3 * cx * cx - 1) * (3 * cy * cy - 1)) * d[i];
+    nN += gd;
+    add_times(nJx, cx, gd);
+    add_times(nJy, cy, gd);
   }
   const real rho = real(1) + drho;
   const real inv_rho = real(1) / rho;
   const real ux = jx * inv_rho, uy = jy * inv_rho;
-  const real usq = real(1.5) * (ux * ux + uy * uy);
-
-  // non-equilibrium part and its six non-conserved moments
-  real ne[Q];
-  real nxx = 0, nxy = 0, nyy = 0, nN = 0, nJx = 0, nJy = 0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int cx = LT::cx(i), cy = LT::cy(i);
-    real cu = 0;
-    add_times(cu, cx, ux);
-    add_times(cu, cy, uy);
-    const real deq = CO::W(i) * drho + rho * (CO::A(i) * cu + CO::B(i) * cu * cu - CO::W(i) * usq);
-    ne[i] = d[i] - deq;
-    // every lattice factor below is 0, +-1, +-2 or 4: the products are exact
-    const real gi = real((3 * cx * cx - 1) * (3 * cy * cy - 1));
-    nxx += real(3 * cx * cx - 1) * ne[i];
-    add_times(nxy, cx * cy, ne[i]);
-    nyy += real(3 * cy * cy - 1) * ne[i];
-    nN += gi * ne[i];
-    add_times(nJx, cx, gi * ne[i]);
-    add_times(nJy, cy, gi * ne[i]);
-  }
+  // Non-equilibrium moments n_k = sum_i R_k(c_i) (h_i - f^eq_i): the raw moments minus
+  // those of the second-order D2Q9 equilibrium, which have closed forms:
+  // sum (3c_x^2 - 1) f^eq = 3 rho u_x^2, sum c_x c_y f^eq = rho u_x u_y, and the ghost
+  // moments N, J of f^eq vanish.  sum (3c_x^2 - 1) d = 3 sx - drho.
+  const real nxx = real(3) * sx - drho - real(3) * rho * ux * ux;
+  const real nxy = pxy - rho * ux * uy;
+  const real nyy = real(3) * sy - drho - real(3) * rho * uy * uy;
   real s6 = real(sc.s[3]), s7 = real(sc.s[4]), s8 = real(sc.s[5]);
   if constexpr (GM == kGhostField) {
     const uint32_t n = cell_index(g, c);
