@@ -270,6 +270,24 @@ int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rh
 int lbm_adjoint_step(const lbm_grid* grid, const void* g_t, const void* lam_next, void* lam_out,
                      double tau, const void* force, void* dforce, void* stream);
 
+/* The adjoint step of lbm_adjoint_step in its collision-local form, the one the
+ * checkpointed rollout runs (derivatives of the step as in Sec. 3.2).  The streaming is
+ * moved out of the step's transpose, so every write is aligned: with lam_{t+1} =
+ * adj_next (adj_is_chi = 0) or lam_{t+1} = S^T adj_next (adj_is_chi = 1: adj_next holds
+ * chi_{t+1}, read gathered as chi_{t+1,i}(x + c_i)),
+ *   chi_out = J_C(S g_t)^T lam_{t+1}       (overwritten, Q*N reals, aligned with g_t)
+ *   dforce += (dg'/dF)^T lam_{t+1}         (accumulated, D*N reals; may be NULL)
+ * and lam_t = S^T chi_t (lbm_adjoint_unstream).  adj_is_chi must be 0 or 1 (LBM_EINVAL
+ * otherwise).  Layout, tau, force, dforce, aliasing rules and errors as lbm_adjoint_step. */
+int lbm_adjoint_step_local(const lbm_grid* grid, const void* g_t, const void* adj_next, int adj_is_chi,
+                           void* chi_out, double tau, const void* force, void* dforce, void* stream);
+
+/* lam_out = S^T chi, the transpose of the pull streaming of Eq. 1: lam_out_i(x) =
+ * chi_i(x + c_i) with periodic wrap, on Q*N reals in the population layout (FP64 for
+ * FP64 storage, FP32 otherwise).  Turns the local form's chi into lam.  chi and lam_out
+ * are caller-owned device buffers and must not overlap (LBM_EALIAS). */
+int lbm_adjoint_unstream(const lbm_grid* grid, const void* chi, void* lam_out, void* stream);
+
 /* Reverse-mode derivative of lbm_moments' fields: with (rho, u) = moments(g; F),
  *   lam_out = (drho/dg)^T dL_drho + (du/dg)^T dL_du       (overwritten, Q*N reals)
  *   dforce += (du/dF)^T dL_du = -dL_du / (2 rho)           (accumulated, may be NULL)

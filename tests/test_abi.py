@@ -43,6 +43,14 @@ def test_library_exports_every_declared_symbol(B):
         assert hasattr(B._lib, n)
 
 
+def test_every_exported_entry_point_is_declared(B):
+    """The header is the whole boundary: no lbm_* symbol is exported undocumented."""
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\sT\s+(lbm_\w+)", out.stdout))
+    undeclared = sorted(exported - set(_declared()))
+    assert not undeclared, undeclared
+
+
 @pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
 def test_lattice_info_matches_oracle_tables(B, name):
     D, Q, c, w = B.lbm_lattice_info(name)
