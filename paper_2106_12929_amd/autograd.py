@@ -5,7 +5,8 @@ operation (Sec. 3.2).  Here the derivative of a whole rollout comes from the
 library's adjoint kernels instead:
 
   LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every) -> g_T
-      forward: n_steps lbm_step calls, keeping a copy of the state every K steps;
+      forward: n_steps lbm_step calls; every K-th step writes into a fresh buffer
+      that is kept as a checkpoint (no copies);
       backward: for each K-step segment, last to first, replay the segment from
       its checkpoint (keeping its K states), then run K adjoint steps backwards in
       the collision-local form (lbm_adjoint_step_local, aligned stores only) and
@@ -40,14 +41,18 @@ class LBMRollout(torch.autograd.Function):
         if n_steps < 1 or checkpoint_every < 1:
             raise ValueError("n_steps and checkpoint_every must be >= 1")
         F = _real(grid, force)
-        a = g0.detach().contiguous().clone()
-        b = torch.empty_like(a)
-        ckpts = []
+        cur = g0.detach().contiguous().clone()  # checkpoint 0 (the caller may change g0)
+        ckpts = [cur]
+        spare = [torch.empty_like(cur), torch.empty_like(cur)]
         for t in range(n_steps):
-            if t % checkpoint_every == 0:
-                ckpts.append(a.clone())
-            B.lbm_step(grid, a, b, tau, F, 1)
-            a, b = b, a
+            if (t + 1) % checkpoint_every == 0 and t + 1 < n_steps:
+                dst = torch.empty_like(cur)  # the step writes the next checkpoint itself
+                ckpts.append(dst)
+            else:
+                dst = spare[1] if cur is spare[0] else spare[0]
+            B.lbm_step(grid, cur, dst, tau, F, 1)
+            cur = dst
+        a = cur
         ctx.grid, ctx.tau, ctx.n, ctx.K = grid, tau, n_steps, checkpoint_every
         ctx.ckpts = ckpts
         ctx.force = F
@@ -61,25 +66,29 @@ class LBMRollout(torch.autograd.Function):
         # lam_{t+1} = S^T chi_{t+1}; every kernel store is aligned, and
         # lam_0 = S^T chi_0 at the end (bitwise what the scatter form gives).
         cur = lam_T.detach().to(grid.real_dtype).contiguous()
-        # zero-filled: the kernels never write the pad words of a pitched layout, whose
-        # gradient is zero
-        bufs = [torch.zeros_like(cur), torch.zeros_like(cur)]
+        # a pitched layout has pad words that the kernels never write and whose gradient
+        # is zero: its adjoint buffers start zero-filled
+        alloc = torch.zeros_like if grid.row_pitch != grid.nx else torch.empty_like
+        bufs = [alloc(cur), alloc(cur)]
         is_chi = False
         dF = torch.zeros_like(F) if ctx.force_needs_grad else None
         n_seg = len(ctx.ckpts)
-        states = [torch.empty_like(ctx.ckpts[0]) for _ in range(min(K, n))]
+        # states[0] of a segment is its checkpoint itself (read only); the replay writes
+        # the other K - 1 states
+        states = [None] + [torch.empty_like(ctx.ckpts[0]) for _ in range(min(K, n) - 1)]
         k = 0
         for seg in reversed(range(n_seg)):
             t0 = seg * K
             t1 = min(t0 + K, n)
-            states[0].copy_(ctx.ckpts[seg])
+            states[0] = ctx.ckpts[seg]
             for t in range(t0 + 1, t1):
                 B.lbm_step(grid, states[t - 1 - t0], states[t - t0], tau, F, 1)
             for t in reversed(range(t0, t1)):
                 out = bufs[k & 1]
                 B.lbm_adjoint_step_local(grid, states[t - t0], cur, is_chi, out, tau, F, dF)
                 cur, is_chi, k = out, True, k + 1
-            ctx.ckpts[seg] = None  # release the checkpoint once its segment is done
+            ctx.ckpts[seg] = None  # released once the next segment replaces states[0]
+        states = None
         lam0 = bufs[k & 1]
         B.lbm_adjoint_unstream(grid, cur, lam0)
         return lam0, dF, None, None, None, None
