@@ -26,6 +26,7 @@ class Shells:
     spatial: tuple
     order: torch.Tensor    # flat wavevector indices sorted by shell
     lengths: torch.Tensor  # wavevectors per shell, K = 0 .. K_max
+    shell: torch.Tensor    # shell of every flat wavevector
 
 
 def shell_index(spatial, device) -> Shells:
@@ -35,7 +36,7 @@ def shell_index(spatial, device) -> Shells:
     shell = torch.floor(kmag + 0.5).to(torch.int64).reshape(-1)
     order = torch.argsort(shell, stable=True)
     lengths = torch.bincount(shell)
-    return Shells(tuple(spatial), order, lengths)
+    return Shells(tuple(spatial), order, lengths, shell)
 
 
 def energy_spectrum(u: torch.Tensor, shells: Shells | None = None) -> torch.Tensor:
@@ -52,3 +53,26 @@ def log_spectrum_loss(E: torch.Tensor, E_target: torch.Tensor, k_lo: int, k_hi: 
     a = torch.log(torch.clamp(E[k_lo:k_hi + 1], min=cutoff))
     b = torch.log(torch.clamp(E_target[k_lo:k_hi + 1], min=cutoff))
     return (a - b).square().sum()
+
+
+def log_spectrum_loss_and_grad(u: torch.Tensor, shells: Shells, E_target: torch.Tensor, k_lo: int, k_hi: int,
+                               cutoff: float):
+    """log_spectrum_loss(energy_spectrum(u), ...) and its gradient with respect to u,
+    without autograd.  With u_hat = FFT(u)/N and g(k) = dR/dE_K at the shell K of k
+    (2 (ln E_K - ln max(E_target, c)) / E_K inside the band where E_K >= c, else 0):
+    dR/du = Re IFFT(g u_hat), since E_K sums 1/2 |u_hat|^2 and the FFT is linear.
+    Two FFTs, a shell sum and a gather: the loss head of a controlled step."""
+    spatial = tuple(u.shape[1:])
+    dims = tuple(range(1, u.dim()))
+    uh = torch.fft.fftn(u.to(torch.float64), dim=dims) / math.prod(spatial)
+    dens = 0.5 * (uh.real.square() + uh.imag.square()).sum(dim=0)
+    E = torch.segment_reduce(dens.reshape(-1)[shells.order], "sum", lengths=shells.lengths, unsafe=True)
+    band = slice(k_lo, k_hi + 1)
+    a = torch.log(torch.clamp(E[band], min=cutoff))
+    b = torch.log(torch.clamp(E_target[band], min=cutoff))
+    R = (a - b).square().sum()
+    dE = torch.zeros_like(E)
+    dE[band] = torch.where(E[band] >= cutoff, 2.0 * (a - b) / E[band], torch.zeros_like(a))
+    g = dE[shells.shell].reshape(spatial)
+    grad = torch.fft.ifftn(g * uh, dim=dims).real
+    return R, grad

@@ -241,8 +241,9 @@ def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-
 
     R(u) = sum_K (ln max(sigma_K(u), c) - ln max(sigma0_K, c))^2 over shells
     K = 1 .. n/2, sigma0 the spectrum of the initial field; the restrained run takes
-    every step with lbm_step_shifted and du = -kappa dR/du (gradient by torch
-    autograd through the FFT).  Returns R and the kinetic energy over time for both.
+    every step with lbm_step_shifted and du = -kappa dR/du (the closed-form gradient
+    through the FFT, two FFTs per step).  Returns R and the kinetic energy over time
+    for both.
     """
     ny, nx = u0.shape[1:]
     grid = B.Grid("D2Q9", storage, nx, ny)
@@ -272,8 +273,7 @@ def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-
             if mode == "free":
                 B.lbm_step(grid, a, b, tau, None, 1)
             else:
-                uu = u.detach().double().requires_grad_(True)
-                (grad,) = torch.autograd.grad(R_of(uu), uu)
+                _, grad = SP.log_spectrum_loss_and_grad(u, shells, sigma0, 1, kmax, cutoff)
                 du = (-kappa * grad).to(grid.real_dtype).contiguous()
                 B.lbm_step_shifted(grid, a, b, tau, du, 1)
             a, b = b, a
