@@ -260,3 +260,59 @@ def test_local_form_chain_matches_scatter_form_bitwise(lat, shape, kind, forced)
     assert torch.equal(lam, lam2)
     if forced:
         assert torch.equal(dF1, dF2)
+
+
+@pytest.mark.parametrize("kind", ["f32", "f16s"])
+@pytest.mark.parametrize("forced", [False, True])
+def test_full_size_local_adjoint_sampled(kind, forced):
+    """The collision-local adjoint step on the 256^3 D3Q27 grid the benchmark times, in
+    its launch shape (chi input): chi_out(x) = J_C(h(x))^T lam'(x) with h(x) the gathered
+    state and lam'_i(x) = chi_i(x + c_i), against the VJP of the oracle's collision at
+    4096 sampled cells and the 8 corners; with a force, also dF there."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D3Q27")
+    n, Q, tau = 256, 27, 0.51
+    grid = B.Grid("D3Q27", kind, n, n, n)
+    say(f"full-size local adjoint {kind} forced={forced}")
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, synthetic.taylor_green_3d_on("cuda", n, n, n, 0.05), a)
+    B.lbm_step(grid, a, b, tau, None, 2)  # non-equilibrium state in a
+    del b
+    gen = torch.Generator(device="cuda").manual_seed(64)
+    chi = torch.randn(grid.population_shape(), generator=gen, device="cuda", dtype=torch.float32)
+    F = (1e-4 * torch.randn((3, n, n, n), generator=gen, device="cuda")) if forced else None
+    dF = torch.zeros_like(F) if forced else None
+    out = torch.empty_like(chi)
+    B.lbm_adjoint_step_local(grid, a, chi, True, out, tau, F, dF)
+    torch.cuda.synchronize()
+    cg = torch.Generator().manual_seed(65)
+    cells = torch.cat([torch.randint(0, n, (4096, 3), generator=cg),
+                       torch.tensor([[x, y, z] for x in (0, n - 1) for y in (0, n - 1) for z in (0, n - 1)])])
+    x, y, z = (cells[:, k].cuda() for k in range(3))
+
+    def word(i, dx, dy, dz):  # flat index of direction i at (x + dx, y + dy, z + dz), periodic
+        return ((((z + dz) % n) * n + (y + dy) % n) * Q + i) * n + (x + dx) % n
+
+    c = st.c.to(torch.int64)
+    h = torch.stack([a.view(-1)[word(i, -c[i, 0], -c[i, 1], -c[i, 2])] for i in range(Q)]).cpu().double()
+    if kind == "f16s":
+        h = h + st.w.reshape(Q, 1)
+    lam = torch.stack([chi.view(-1)[word(i, c[i, 0], c[i, 1], c[i, 2])] for i in range(Q)]).cpu().double()
+    got = torch.stack([out.view(-1)[word(i, 0, 0, 0)] for i in range(Q)]).cpu().double()
+    hh = h.requires_grad_(True)
+    inputs = [hh]
+    Fc = None
+    if forced:
+        flat = ((z * n + y) * n + x)
+        Fc = torch.stack([F[k].reshape(-1)[flat] for k in range(3)]).cpu().double().requires_grad_(True)
+        inputs.append(Fc)
+    grads = torch.autograd.grad(olbm.bgk_collide(hh, tau, st, Fc), inputs, grad_outputs=lam)
+    err = float((got - grads[0]).abs().max() / grads[0].abs().max())
+    say(f"  chi rel err {err:.2e}")
+    assert err < 2e-6
+    if forced:
+        gotF = torch.stack([dF[k].reshape(-1)[flat] for k in range(3)]).cpu().double()
+        errF = float((gotF - grads[1]).abs().max() / grads[1].abs().max())
+        say(f"  dF rel err {errF:.2e}")
+        assert errF < 1e-5
