@@ -592,3 +592,53 @@ def test_full_size_sampled(kind, n):
     excess, ratio, same = _tolerance_ok(kind, st, got, ost.quantize(ref, st, kind), tau)
     say(f"  max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
     assert excess <= 0, ratio
+
+
+@pytest.mark.parametrize("kind", ["f32", "f16s"])
+def test_full_size_moments_sampled(kind):
+    """Moments of the 256^3 D3Q27 grid the benchmark times, both kernels: rho, u at 4096
+    sampled cells and the 8 corners against the oracle's Eq. 4 on the stored words;
+    the FP64 reductions against FP64 sums of the returned fields (max and min exact);
+    the fields-only kernel bit for bit equal to the reduction kernel's fields."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil("D3Q27")
+    n, Q = 256, 27
+    grid = B.Grid("D3Q27", kind, n, n, n)
+    say(f"full-size moments {kind}")
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, synthetic.taylor_green_3d_on("cuda", n, n, n, 0.05), a)
+    B.lbm_step(grid, a, b, 0.51, None, 2)  # result in a
+    del b
+    rho, u = grid.empty_real(0), grid.empty_real(3)
+    red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
+    ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
+    B.lbm_moments(grid, a, None, rho, u, red, ws)
+    rho2, u2 = grid.empty_real(0), grid.empty_real(3)
+    B.lbm_moments(grid, a, None, rho2, u2)
+    torch.cuda.synchronize()
+    assert torch.equal(bits(rho), bits(rho2)) and torch.equal(bits(u), bits(u2))
+    cg = torch.Generator().manual_seed(66)
+    cells = torch.cat([torch.randint(0, n, (4096, 3), generator=cg),
+                       torch.tensor([[x, y, z] for x in (0, n - 1) for y in (0, n - 1) for z in (0, n - 1)])])
+    x, y, z = (cells[:, k].cuda() for k in range(3))
+    words = torch.stack([a.view(-1)[(((z * n + y) * Q + i) * n + x)] for i in range(Q)]).cpu()
+    f = ost.dequantize(words, st, kind)  # [Q, M] FP64
+    flat = (z * n + y) * n + x
+    r_ref, u_ref = olbm.density(f), olbm.velocity(f, st)
+    assert float((rho.view(-1)[flat].cpu().double() - r_ref).abs().max()) < 2e-6
+    assert float((u.view(3, -1)[:, flat].cpu().double() - u_ref).abs().max()) < 2e-6
+    rd, ud = rho.double(), u.double()
+    red = red.cpu()
+    usq = (ud * ud).sum(0)
+    mass, mom, ke = float(rd.sum()), (rd * ud).sum(dim=(1, 2, 3)).cpu(), float(0.5 * usq.sum())
+    # the kernel sums N + sum(drho) in FP64; each rho field value is 1 + drho rounded to
+    # FP32, off by at most 2^-24 per cell
+    assert abs(float(red[0]) - mass) <= 2.0 ** -24 * n ** 3 + 1e-12 * mass
+    for k in range(3):  # the same FP64 products, summed in another order
+        assert abs(float(red[1 + k]) - float(mom[k])) <= 1e-12 * mass
+    assert abs(float(red[4]) - ke) <= 1e-11 * ke
+    assert float(red[5]) == 0.0
+    umax = float(usq.max().sqrt())  # the kernel's |u|^2 may round once differently (FMA)
+    assert abs(float(red[6]) - umax) <= 1e-15 * umax
+    assert float(red[7]) == float(rd.min())
