@@ -642,3 +642,50 @@ def test_full_size_moments_sampled(kind):
     umax = float(usq.max().sqrt())  # the kernel's |u|^2 may round once differently (FMA)
     assert abs(float(red[6]) - umax) <= 1e-15 * umax
     assert float(red[7]) == float(rd.min())
+
+
+@pytest.mark.parametrize("lat,kind,mode", [("D3Q19", "f32", "none"), ("D3Q19", "f16s", "none"), ("D3Q27", "f32", "guo"),
+                                           ("D3Q27", "f16s", "guo"), ("D3Q27", "f32", "shift"), ("D3Q27", "f16s", "shift")])
+def test_full_size_sampled_d3q19_and_forced(lat, kind, mode):
+    """The other 256^3 steps the benchmark times, in its launch shape: D3Q19, and D3Q27
+    with a Guo body force or a velocity-shift field (random, 1e-5): one step from a
+    Taylor-Green state two steps old, against the oracle's collision of the gathered
+    stored words at 4096 sampled cells and the 8 corners."""
+    need_gpu()
+    B = binding()
+    st = olbm.stencil(lat)
+    n, Q, tau = 256, st.Q, 0.51
+    grid = B.Grid(lat, kind, n, n, n)
+    say(f"full size {lat} {kind} {mode}")
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, synthetic.taylor_green_3d_on("cuda", n, n, n, 0.05), a)
+    B.lbm_step(grid, a, b, tau, None, 2)  # result in a
+    field = None
+    if mode != "none":
+        gen = torch.Generator(device="cuda").manual_seed(67)
+        field = 1e-5 * torch.randn((3, n, n, n), generator=gen, device="cuda")
+    if mode == "shift":
+        B.lbm_step_shifted(grid, a, b, tau, field, 1)
+    else:
+        B.lbm_step(grid, a, b, tau, field, 1)
+    torch.cuda.synchronize()
+    cg = torch.Generator().manual_seed(68)
+    cells = torch.cat([torch.randint(0, n, (4096, 3), generator=cg),
+                       torch.tensor([[x, y, z] for x in (0, n - 1) for y in (0, n - 1) for z in (0, n - 1)])])
+    x, y, z = (cells[:, k].cuda() for k in range(3))
+    c = st.c.to(torch.int64)
+
+    def word(i, dx, dy, dz):
+        return ((((z + dz) % n) * n + (y + dy) % n) * Q + i) * n + (x + dx) % n
+
+    h = ost.dequantize(torch.stack([a.view(-1)[word(i, -c[i, 0], -c[i, 1], -c[i, 2])] for i in range(Q)]).cpu(),
+                       st, kind)
+    got = torch.stack([b.view(-1)[word(i, 0, 0, 0)] for i in range(Q)]).cpu()
+    Fc = None
+    if field is not None:
+        flat = (z * n + y) * n + x
+        Fc = torch.stack([field[k].reshape(-1)[flat] for k in range(3)]).cpu().double()
+    ref = olbm.bgk_collide_shifted(h, tau, st, Fc) if mode == "shift" else olbm.bgk_collide(h, tau, st, Fc)
+    excess, ratio, same = _tolerance_ok(kind, st, got, ost.quantize(ref, st, kind), tau)
+    say(f"  max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
+    assert excess <= 0, ratio

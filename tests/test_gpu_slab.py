@@ -129,3 +129,27 @@ def test_halo_copy_moves_only_the_crossing_directions():
     assert torch.equal(bits(b[5][:, down]), bits(a[1][:, down]))
     assert (b[5][:, ~down] == 0).all()
     assert (b[1:5] == 0).all()
+
+
+@pytest.mark.parametrize("parts", [1, 2])
+def test_full_size_shard_matches_periodic_step(parts):
+    """The 512 x 512 x 64 f16s shard the benchmark times, as one slab (its own
+    neighbour) and as two: 3 steps, sequential and overlapped exchange, bit for bit the
+    periodic step of the whole grid."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd.slabs import SlabSet
+
+    nx, ny, nz = 512, 512, 64
+    grid = B.Grid("D3Q27", "f16s", nx, ny, nz)
+    say(f"full-size shard 512x512x64 f16s parts={parts}")
+    g0 = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, synthetic.taylor_green_3d_on("cuda", nx, ny, nz, 0.05), g0)
+    T = 3
+    ref = _periodic(B, grid, g0, 0.51, None, T)
+    S = SlabSet(grid, parts)
+    S.scatter(g0)
+    for t in range(T):
+        S.step(0.51, None, overlap=(t % 2 == 1))
+    torch.cuda.synchronize()
+    assert torch.equal(bits(S.gather()), bits(ref))
