@@ -262,19 +262,20 @@ def test_local_form_chain_matches_scatter_form_bitwise(lat, shape, kind, forced)
         assert torch.equal(dF1, dF2)
 
 
-@pytest.mark.parametrize("kind", ["f32", "f16s"])
-@pytest.mark.parametrize("forced", [False, True])
-def test_full_size_local_adjoint_sampled(kind, forced):
-    """The collision-local adjoint step on the 256^3 D3Q27 grid the benchmark times, in
+@pytest.mark.parametrize("kind,forced,n", [("f32", False, 256), ("f16s", False, 256), ("f32", True, 256),
+                                           ("f16s", True, 256), ("f16s", True, 512)])
+def test_full_size_local_adjoint_sampled(kind, forced, n):
+    """The collision-local adjoint step on the 256^3 D3Q27 grid the benchmark times (and
+    at 512^3, the full-scale workload's size with an f16s state and a force), in
     its launch shape (chi input): chi_out(x) = J_C(h(x))^T lam'(x) with h(x) the gathered
     state and lam'_i(x) = chi_i(x + c_i), against the VJP of the oracle's collision at
     4096 sampled cells and the 8 corners; with a force, also dF there."""
     need_gpu()
     B = binding()
     st = olbm.stencil("D3Q27")
-    n, Q, tau = 256, 27, 0.51
+    Q, tau = 27, 0.51
     grid = B.Grid("D3Q27", kind, n, n, n)
-    say(f"full-size local adjoint {kind} forced={forced}")
+    say(f"full-size local adjoint {kind} {n}^3 forced={forced}")
     a, b = grid.empty_populations(), grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, synthetic.taylor_green_3d_on("cuda", n, n, n, 0.05), a)
     B.lbm_step(grid, a, b, tau, None, 2)  # non-equilibrium state in a

@@ -562,7 +562,8 @@ def test_aligned_shapes_step_parity(lat, shape, kind, mode):
     assert excess <= 0, ratio
 
 
-@pytest.mark.parametrize("kind,n", [("f32", 256), ("f64", 256), ("f16s", 256), ("bf16s", 256), ("f16s", 512)])
+@pytest.mark.parametrize("kind,n", [("f32", 256), ("f64", 256), ("f16s", 256), ("bf16s", 256), ("f32", 384), ("f16s", 384),
+                                    ("f16s", 512)])
 def test_full_size_sampled(kind, n):
     """Full-size grids in the benchmark's launch shape: one step compared with the
     oracle's pointwise step at 4096 sampled cells (and all 8 corners of the box)."""
