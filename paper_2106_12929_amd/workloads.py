@@ -140,7 +140,7 @@ def forcing_optimisation(u0: torch.Tensor, tau: float, steps: int = 100, checkpo
 
 
 def full_scale_adjoint(u0: torch.Tensor, tau: float, forward_steps: int = 500, adjoint_steps: int = 50,
-                       checkpoint_every: int = 10):
+                       checkpoint_every: int = 10, pitch: int | None = None):
     """FP16-shifted forward run, then the gradient of the final kinetic energy
     1/2 sum |u|^2 with respect to the state `adjoint_steps` steps before the end and
     a zero force field active over those steps.
@@ -149,7 +149,7 @@ def full_scale_adjoint(u0: torch.Tensor, tau: float, forward_steps: int = 500, a
     ~185 GB of one call back to the driver and mapping it again made the next call's
     backward about 4x slower (same results), so repeated calls reuse the cached blocks."""
     n = u0.shape[-1]
-    grid = B.Grid("D3Q27", "f16s", n, n, n)
+    grid = B.Grid("D3Q27", "f16s", n, n, n, pitch)
     torch.cuda.reset_peak_memory_stats()
     a, b = grid.empty_populations(), grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, u0, a)
