@@ -100,11 +100,6 @@ int check_tau(double tau) {
   return LBM_OK;
 }
 
-int reduce_blocks(const Geometry& geo) {
-  // one block per grid row, at most kMaxReduceBlocks (blocks then take several rows)
-  const uint64_t rows = (uint64_t)geo.args.ny * geo.args.nz;
-  return (int)(rows < (uint64_t)lbm::kMaxReduceBlocks ? rows : (uint64_t)lbm::kMaxReduceBlocks);
-}
 
 template <typename LT>
 void fill_lattice(int* c, double* w) {
@@ -381,7 +376,7 @@ int lbm_moments_workspace_size(const lbm_grid* grid, size_t* bytes) {
   Geometry geo;
   LBM_TRY(check_grid(grid, &geo));
   if (!bytes) return fail(LBM_ENULL, "bytes is NULL");
-  *bytes = (size_t)reduce_blocks(geo) * lbm::kNred * sizeof(double);
+  *bytes = (size_t)lbm::moments_workspace_entries(geo.args) * lbm::kNred * sizeof(double);
   return LBM_OK;
 }
 
@@ -394,8 +389,7 @@ int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rh
   LBM_TRY(check_ptr(rho_out, "rho_out", false));
   LBM_TRY(check_ptr(u_out, "u_out", false));
   LBM_TRY(check_ptr(red, "red", false));
-  const int nblocks = reduce_blocks(geo);
-  const size_t need = (size_t)nblocks * lbm::kNred * sizeof(double);
+  const size_t need = (size_t)lbm::moments_workspace_entries(geo.args) * lbm::kNred * sizeof(double);
   if (red) {
     LBM_TRY(check_ptr(workspace, "workspace", true));
     if (workspace_bytes < need)
@@ -415,8 +409,7 @@ int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rh
       if (overlap(outs[a], outsz[a], outs[b], outsz[b])) return fail(LBM_EALIAS, "two outputs of lbm_moments overlap");
   }
   const hipError_t e = lbm::launch_moments(grid->lattice, grid->storage, g, force, rho_out, u_out,
-                                           red ? (double*)workspace : nullptr, nblocks, red, geo.args,
-                                           (hipStream_t)stream);
+                                           red ? (double*)workspace : nullptr, red, geo.args, (hipStream_t)stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments launch");
 }
 

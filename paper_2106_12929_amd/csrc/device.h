@@ -33,12 +33,13 @@ struct Cell {
 // 256/block_x consecutive rows; all 64 lanes of a wave share one row, so y and z are
 // wave-uniform (made scalar with readfirstlane).  Returns false past the last row and
 // for x >= x_end (nx for kernels that compute live cells only; the row pitch for the
-// step, whose pad lanes store into the pad words).
-__device__ __forceinline__ bool cell_below(const GridArgs& g, Cell& c, uint32_t x_end) {
+// step, whose pad lanes store into the pad words).  `block` is the index of the block
+// of cells, blockIdx.x unless a block walks several of them.
+__device__ __forceinline__ bool cell_in_block(const GridArgs& g, Cell& c, uint32_t x_end, uint32_t block) {
   const uint32_t bx = g.block_x;
   const uint32_t blocks_x = (g.nx + bx - 1) / bx;
-  const uint32_t bxi = blockIdx.x % blocks_x;
-  const uint32_t byi = blockIdx.x / blocks_x;
+  const uint32_t bxi = block % blocks_x;
+  const uint32_t byi = block / blocks_x;
   const uint32_t ty = __builtin_amdgcn_readfirstlane(threadIdx.x / bx);
   const uint32_t r = byi * (256u / bx) + ty;
   c.x = bxi * bx + threadIdx.x % bx;
@@ -46,6 +47,10 @@ __device__ __forceinline__ bool cell_below(const GridArgs& g, Cell& c, uint32_t 
   c.y = r % g.ny;
   c.z = g.z0 + r / g.ny;
   return c.x < x_end;
+}
+
+__device__ __forceinline__ bool cell_below(const GridArgs& g, Cell& c, uint32_t x_end) {
+  return cell_in_block(g, c, x_end, blockIdx.x);
 }
 
 __device__ __forceinline__ bool cell_of_thread(const GridArgs& g, Cell& c) { return cell_below(g, c, g.nx); }

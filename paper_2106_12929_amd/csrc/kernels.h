@@ -9,7 +9,7 @@ namespace lbm {
 constexpr int kNred = 8;              // reduction results of lbm_moments
 enum AdjointMode { kAdjScatter = 0, kAdjLocalLam = 1, kAdjLocalChi = 2 };
 enum ForceMode { kNoForce = 0, kGuoForce = 1, kShiftForce = 2 };
-constexpr int kMaxReduceBlocks = 2048;  // fixed reduction grid (bitwise-reproducible sums)
+constexpr int kFoldBlock = 2048;  // block partials folded by one block of the second reduction stage
 
 // Grid geometry passed by value to every cell-parallel kernel.
 struct GridArgs {
@@ -27,8 +27,12 @@ hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, co
 hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s);
 hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
                        hipStream_t s);
+// Entries (kNred doubles each) of the workspace of launch_moments with reductions: at most
+// one partial per block of the one-thread-per-cell launch, then one per kFoldBlock of
+// those.
+uint64_t moments_workspace_entries(const GridArgs& g);
 hipError_t launch_moments(int lattice, int storage, const void* f, const void* force, void* rho, void* u,
-                          double* partials, int nblocks, double* red, const GridArgs& g, hipStream_t s);
+                          double* workspace, double* red, const GridArgs& g, hipStream_t s);
 hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, const void* lam_next, void* lam_out,
                           const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s);
 hipError_t launch_unstream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g,

@@ -275,11 +275,11 @@ __global__ __launch_bounds__(256) void init_kernel(const double* __restrict__ rh
 }
 
 // ---------------------------------------------------------------------------------
-// Moments (Eq. 4) and FP64 reductions.  With reductions, the grid is cut into items of
-// up to 256 cells (one row segment each: item t is row t / chunks, columns
-// (t % chunks)*256 + lane), and block b of a fixed grid handles items b, b + gridDim, ...,
-// so that every reduction is summed in the same order on every call.  Fields alone take
-// one thread per cell, the launch of the step kernels, with no fixed grid to respect.
+// Moments (Eq. 4) and FP64 reductions, one thread per cell (the launch of the step
+// kernels).  The reductions fold in a fixed order that depends on the grid only, so every
+// call sums the same way: a DPP reduction per wave (wave_fold, total in lane 63), the
+// block's four waves in order, then blocks in consecutive runs of kFoldBlock
+// (fold_partials_kernel), then those run results (reduce_partials_kernel).
 // ---------------------------------------------------------------------------------
 template <typename real>
 struct CellMoments {
@@ -347,7 +347,43 @@ __device__ __forceinline__ CellMoments<typename Storage<S>::real> cell_moments(
   return moments_of_words<L, S>(w, F);
 }
 
-template <int L, int S, bool FORCED>
+// Reduction operator of entry k of the kNred results: max for max|u|, min for min rho,
+// sum otherwise.
+__device__ __forceinline__ double red_op(int k, double a, double b) {
+  return k == 6 ? fmax(a, b) : k == 7 ? fmin(a, b) : a + b;
+}
+
+// The value of entry k that leaves the other operand of red_op unchanged.
+__device__ __forceinline__ double red_idle(int k) { return k == 7 ? 1.0e300 : 0.0; }
+
+// A DPP move of a double (its two 32-bit halves moved alike); lanes of rows outside
+// ROWS keep `idle`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v, double idle) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v), o = __builtin_bit_cast(uint64_t, idle);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Folds entry k over the 64 lanes of a full wave; lane 63 ends with the wave's result.
+// Lane pairs (quad_perm 1,0,3,2), then quad pairs (quad_perm 2,3,0,1), then quads of a
+// 16-lane row (row_ror 4 and 8) leave each row's result in all its lanes; row_bcast15
+// adds row 0 into row 1 and row 2 into row 3, row_bcast31 adds row 1 into row 3.  These
+// are register moves between lanes, so the fold takes no LDS bandwidth.
+__device__ __forceinline__ double wave_fold(int k, double v) {
+  const double idle = red_idle(k);
+  v = red_op(k, v, dpp_move<0xB1, 0xF>(v, idle));
+  v = red_op(k, v, dpp_move<0x4E, 0xF>(v, idle));
+  v = red_op(k, v, dpp_move<0x124, 0xF>(v, idle));
+  v = red_op(k, v, dpp_move<0x128, 0xF>(v, idle));
+  v = red_op(k, v, dpp_move<0x142, 0xA>(v, idle));
+  v = red_op(k, v, dpp_move<0x143, 0xC>(v, idle));
+  return v;
+}
+
+template <int L, int S, bool FORCED, bool REDUCE, uint32_t SPAN>
 __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>::word* __restrict__ f,
                                                       const typename Storage<S>::real* __restrict__ force,
                                                       typename Storage<S>::real* __restrict__ rho_out,
@@ -358,26 +394,29 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
   using R = typename Storage<S>::real;
   constexpr int Q = LT::Q;
   const size_t N = g.ncells;
-  const uint32_t chunks = (g.nx + 255) / 256;
-  const uint32_t items = g.ny * g.nz * chunks;
   // acc: [0] sum drho, [1..3] sum rho u, [4] 1/2 sum |u|^2, [5] non-finite, [6] max|u|^2 (the
   // block's partial takes its square root once: sqrt is monotonic and correctly rounded, so
   // that is max|u| exactly), [7] min rho
   double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 1.0e300};
-  W w[Q];
-  R F[3];
-  for (uint32_t t = blockIdx.x; t < items; t += gridDim.x) {
-    const uint32_t r = t / chunks, x = (t % chunks) * 256 + threadIdx.x;
-    if (x >= g.nx) continue;
-    load_cell<L, S, FORCED>(f + (uint64_t)r * Q * g.pitch, force, N, g.pitch, x, r * g.nx + x, w, F);
+  // A block walks SPAN consecutive blocks of cells, each thread summing its cells in
+  // order, so that the fold below is paid once per SPAN cells of a thread.
+#pragma unroll 1
+  for (uint32_t j = 0; j < SPAN; ++j) {
+    Cell c;
+    // no early return: every thread joins the block's fold
+    if (!cell_in_block(g, c, g.nx, blockIdx.x * SPAN + j)) continue;
+    const uint32_t r = c.z * g.ny + c.y;
+    W w[Q];
+    R F[3];
+    load_cell<L, S, FORCED>(f + (uint64_t)r * Q * g.pitch, force, N, g.pitch, c.x, r * g.nx + c.x, w, F);
     const auto m = moments_of_words<L, S>(w, F);
-    const uint32_t xo = x * (uint32_t)sizeof(R);  // row-uniform base + lane byte offset
+    const uint32_t xo = c.x * (uint32_t)sizeof(R);  // row-uniform base + lane byte offset
     if (rho_out) store_stream(at_byte(rho_out + (uint64_t)r * g.nx, xo), m.rho);
     if (u_out) {
 #pragma unroll
       for (int k = 0; k < LT::D; ++k) store_stream(at_byte(u_out + k * N + (uint64_t)r * g.nx, xo), m.u[k]);
     }
-    if (partials) {
+    if constexpr (REDUCE) {
       const double rho = m.rho;
       const double ux = m.u[0], uy = m.u[1], uz = m.u[2];
       const double usq = ux * ux + uy * uy + uz * uz;
@@ -394,7 +433,36 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
       }
     }
   }
-  if (!partials) return;
+  if constexpr (REDUCE) {
+#pragma unroll
+    for (int k = 0; k < kNred; ++k) acc[k] = wave_fold(k, acc[k]);
+    __shared__ double sh[4][kNred];
+    if (threadIdx.x % 64 == 63) {
+#pragma unroll
+      for (int k = 0; k < kNred; ++k) sh[threadIdx.x / 64][k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < kNred) {
+      const int k = threadIdx.x;
+      double v = sh[0][k];
+      for (int wv = 1; wv < 4; ++wv) v = red_op(k, v, sh[wv][k]);
+      partials[(uint64_t)blockIdx.x * kNred + k] = k == 6 ? sqrt(v) : v;
+    }
+  }
+}
+
+// Second stage: block j folds partials [j kFoldBlock, (j + 1) kFoldBlock) into out[j]:
+// thread t takes 8 consecutive entries in order, then a fixed tree over the threads.
+__global__ __launch_bounds__(256) void fold_partials_kernel(const double* __restrict__ in, uint64_t n_in,
+                                                            double* __restrict__ out) {
+  double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 1.0e300};
+  const uint64_t base = (uint64_t)blockIdx.x * kFoldBlock + threadIdx.x * 8u;
+  for (int m = 0; m < 8; ++m) {
+    if (base + m < n_in) {
+#pragma unroll
+      for (int k = 0; k < kNred; ++k) acc[k] = red_op(k, acc[k], in[(base + m) * kNred + k]);
+    }
+  }
   __shared__ double sh[kNred][256];
 #pragma unroll
   for (int k = 0; k < kNred; ++k) sh[k][threadIdx.x] = acc[k];
@@ -402,43 +470,11 @@ __global__ __launch_bounds__(256) void moments_kernel(const typename Storage<S>:
   for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
 #pragma unroll
-      for (int k = 0; k < kNred; ++k) {
-        const double a = sh[k][threadIdx.x], b = sh[k][threadIdx.x + s];
-        sh[k][threadIdx.x] = k == 6 ? fmax(a, b) : k == 7 ? fmin(a, b) : a + b;
-      }
+      for (int k = 0; k < kNred; ++k) sh[k][threadIdx.x] = red_op(k, sh[k][threadIdx.x], sh[k][threadIdx.x + s]);
     }
     __syncthreads();
   }
-  if (threadIdx.x < kNred)
-    partials[blockIdx.x * kNred + threadIdx.x] = threadIdx.x == 6 ? sqrt(sh[6][0]) : sh[threadIdx.x][0];
-}
-
-// Moments fields only (no reductions): one thread per cell.  More waves per SIMD than the
-// fixed reduction grid keeps resident, and no loop: each wave loads, reduces and stores
-// one row segment.
-template <int L, int S, bool FORCED>
-__global__ __launch_bounds__(256) void moments_fields_kernel(const typename Storage<S>::word* __restrict__ f,
-                                                             const typename Storage<S>::real* __restrict__ force,
-                                                             typename Storage<S>::real* __restrict__ rho_out,
-                                                             typename Storage<S>::real* __restrict__ u_out,
-                                                             GridArgs g) {
-  using LT = Lattice<L>;
-  using W = typename Storage<S>::word;
-  using R = typename Storage<S>::real;
-  Cell c;
-  if (!cell_of_thread(g, c)) return;
-  const size_t N = g.ncells;
-  const uint32_t r = c.z * g.ny + c.y;
-  W w[LT::Q];
-  R F[3];
-  load_cell<L, S, FORCED>(f + (uint64_t)r * LT::Q * g.pitch, force, N, g.pitch, c.x, r * g.nx + c.x, w, F);
-  const auto m = moments_of_words<L, S>(w, F);
-  const uint32_t xo = c.x * (uint32_t)sizeof(R);
-  if (rho_out) store_stream(at_byte(rho_out + (uint64_t)r * g.nx, xo), m.rho);
-  if (u_out) {
-#pragma unroll
-    for (int k = 0; k < LT::D; ++k) store_stream(at_byte(u_out + k * N + (uint64_t)r * g.nx, xo), m.u[k]);
-  }
+  if (threadIdx.x < kNred) out[(uint64_t)blockIdx.x * kNred + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // One block folds the per-block partials in a fixed order; adds N to turn sum(drho)
@@ -743,26 +779,57 @@ static hipError_t launch_init_ls(const double* rho, const double* u, void* fout,
   return hipGetLastError();
 }
 
+// Blocks of a moments launch whose blocks walk `span` blocks of cells each.
+static uint64_t moments_blocks(const GridArgs& g, uint32_t span) { return (cell_grid(g).x + span - 1) / span; }
+
+template <int L, int S, bool FORCED, uint32_t SPAN>
+static void launch_moments_span(const typename Storage<S>::word* f, const typename Storage<S>::real* force,
+                                typename Storage<S>::real* rho, typename Storage<S>::real* u, double* partials,
+                                const GridArgs& g, hipStream_t s) {
+  moments_kernel<L, S, FORCED, true, SPAN><<<(unsigned)moments_blocks(g, SPAN), 256, 0, s>>>(f, force, rho, u,
+                                                                                             partials, g);
+}
+
 template <int L, int S>
-static hipError_t launch_moments_ls(const void* f, const void* force, void* rho, void* u, double* partials,
-                                    int nblocks, double* red, const GridArgs& g, hipStream_t s) {
+static hipError_t launch_moments_ls(const void* f, const void* force, void* rho, void* u, double* workspace,
+                                    double* red, const GridArgs& g, hipStream_t s) {
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
-  if (!partials) {
+  const W* fw = (const W*)f;
+  const R* fr = (const R*)force;
+  if (!red) {
     if (force)
-      moments_fields_kernel<L, S, true><<<cell_grid(g), 256, 0, s>>>((const W*)f, (const R*)force, (R*)rho, (R*)u, g);
+      moments_kernel<L, S, true, false, 1><<<cell_grid(g), 256, 0, s>>>(fw, fr, (R*)rho, (R*)u, nullptr, g);
     else
-      moments_fields_kernel<L, S, false><<<cell_grid(g), 256, 0, s>>>((const W*)f, nullptr, (R*)rho, (R*)u, g);
+      moments_kernel<L, S, false, false, 1><<<cell_grid(g), 256, 0, s>>>(fw, nullptr, (R*)rho, (R*)u, nullptr, g);
     return hipGetLastError();
   }
-  if (force)
-    moments_kernel<L, S, true><<<nblocks, 256, 0, s>>>((const W*)f, (const R*)force, (R*)rho, (R*)u, partials, g);
-  else
-    moments_kernel<L, S, false><<<nblocks, 256, 0, s>>>((const W*)f, nullptr, (R*)rho, (R*)u, partials, g);
+  // Span per launch, measured: the fold costs about 150 VALU instructions per wave.  With
+  // fields stored, the 3D lattices are fastest at one cell per thread and D2Q9 (fewer
+  // loads per cell to hide the fold behind) at 4; with the reductions alone, at 16.
+  const uint32_t span = (rho || u) ? (Lattice<L>::D == 2 ? 4 : 1) : 16;
+  const uint64_t p1 = moments_blocks(g, span);
+  const uint64_t p2 = (p1 + kFoldBlock - 1) / kFoldBlock;
+  double* part1 = workspace;
+  double* part2 = workspace + p1 * kNred;
+  R* rr = (R*)rho;
+  R* ur = (R*)u;
+  if (force) {
+    if (span == 1) launch_moments_span<L, S, true, 1>(fw, fr, rr, ur, part1, g, s);
+    if (span == 4) launch_moments_span<L, S, true, 4>(fw, fr, rr, ur, part1, g, s);
+    if (span == 16) launch_moments_span<L, S, true, 16>(fw, fr, rr, ur, part1, g, s);
+  } else {
+    if (span == 1) launch_moments_span<L, S, false, 1>(fw, nullptr, rr, ur, part1, g, s);
+    if (span == 4) launch_moments_span<L, S, false, 4>(fw, nullptr, rr, ur, part1, g, s);
+    if (span == 16) launch_moments_span<L, S, false, 16>(fw, nullptr, rr, ur, part1, g, s);
+  }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !red) return e;
-  reduce_partials_kernel<<<1, 256, 0, s>>>(partials, nblocks, red, (double)g.ncells);
+  if (e != hipSuccess) return e;
+  fold_partials_kernel<<<(unsigned)p2, 256, 0, s>>>(part1, p1, part2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  reduce_partials_kernel<<<1, 256, 0, s>>>(part2, (int)p2, red, (double)g.ncells);
   return hipGetLastError();
 }
 
@@ -811,9 +878,14 @@ hipError_t launch_init(int lattice, int storage, const double* rho, const double
   LBM_DISPATCH(launch_init_ls, lattice, storage, rho, u, fout, g, s);
 }
 
+uint64_t moments_workspace_entries(const GridArgs& g) {
+  const uint64_t p1 = moments_blocks(g, 1);  // the most partials of any span
+  return p1 + (p1 + kFoldBlock - 1) / kFoldBlock;
+}
+
 hipError_t launch_moments(int lattice, int storage, const void* f, const void* force, void* rho, void* u,
-                          double* partials, int nblocks, double* red, const GridArgs& g, hipStream_t s) {
-  LBM_DISPATCH(launch_moments_ls, lattice, storage, f, force, rho, u, partials, nblocks, red, g, s);
+                          double* workspace, double* red, const GridArgs& g, hipStream_t s) {
+  LBM_DISPATCH(launch_moments_ls, lattice, storage, f, force, rho, u, workspace, red, g, s);
 }
 
 hipError_t launch_moments_adjoint(int lattice, int storage, const void* f, const void* force, const void* drho,

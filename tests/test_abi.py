@@ -117,7 +117,9 @@ def test_other_entry_points_validate(B):
     assert lib.lbm_moments(gp, P1, None, None, None, red, None, 0, None) == -2    # workspace needed
     need = ctypes.c_size_t()
     assert lib.lbm_moments_workspace_size(gp, ctypes.byref(need)) == 0
-    assert need.value == 8 * 8 * 8 * 8  # one partial block per grid row (8 x 8 rows)
+    # at most one partial per block of the cell launch (8-cell rows take 64-cell segments,
+    # 4 rows per block: 16 blocks) plus one per 2048 of those: 17 entries of 8 doubles
+    assert need.value == (16 + 1) * 8 * 8
     assert lib.lbm_moments(gp, P1, None, None, None, red, P2, need.value - 1, None) == -1
     assert lib.lbm_moments(gp, P1, None, P1, None, None, None, 0, None) == -4    # rho_out overlaps g
     assert lib.lbm_adjoint_step(gp, P1, P2, P2, 0.6, None, None, None) == -4     # lam_out == lam_next

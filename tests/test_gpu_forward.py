@@ -296,7 +296,14 @@ def test_moments_parity(lat, shape, kind, forced):
     u = grid.empty_real(grid.D)
     red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
     ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device="cuda")
-    B.lbm_moments(grid, grid.to_layout(s).cuda(), None if F is None else F.cuda(), rho, u, red, ws)
+    f = grid.to_layout(s).cuda()
+    Fd = None if F is None else F.cuda()
+    B.lbm_moments(grid, f, Fd, rho, u, red, ws)
+    # a call with the reductions alone walks the cells in other blocks: the same maximum,
+    # minimum and count, sums equal to FP64 rounding
+    red_only = torch.full((B.NRED,), float("nan"), dtype=torch.float64, device="cuda")
+    B.lbm_moments(grid, f, Fd, None, None, red_only, ws)
+    red_only = red_only.cpu()
     r_ref, u_ref = olbm.state_moments(ost.dequantize(s, st, kind), st, None if F is None else F.double())
     tol = 1e-14 if kind == "f64" else 2e-6
     assert float((rho.cpu().double() - r_ref).abs().max()) < tol
@@ -313,16 +320,18 @@ def test_moments_parity(lat, shape, kind, forced):
     assert float(red[5]) == 0.0
     assert abs(float(red[6]) - float(u_ref.norm(dim=0).max())) <= tol * 10
     assert abs(float(red[7]) - float(r_ref.min())) <= tol * 10
+    assert torch.equal(red_only[5:], red[5:])
+    assert float((red_only[:5] - red[:5]).abs().max()) <= 1e-13 * mass
 
 
 @pytest.mark.parametrize("lat,shape", CASES)
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("forced", [False, True])
 def test_moments_fields_only_equal_fields_with_reductions(lat, shape, kind, forced):
-    """Calls without reductions take a one-thread-per-cell kernel, calls with them the
-    fixed reduction grid: rho and u agree bit for bit (both start as NaN, so a cell
-    either kernel skipped would show), also where planted NaN and inf words make
-    cells non-finite."""
+    """Calls without reductions take the fields-only kernel, calls with them the reducing
+    one (whose blocks may walk several blocks of cells): rho and u agree bit for bit
+    (both start as NaN, so a cell either kernel skipped would show), also where planted
+    NaN and inf words make cells non-finite."""
     need_gpu()
     B = binding()
     st = olbm.stencil(lat)
@@ -599,8 +608,9 @@ def test_full_size_sampled(kind, n):
 def test_full_size_moments_sampled(kind):
     """Moments of the 256^3 D3Q27 grid the benchmark times, both kernels: rho, u at 4096
     sampled cells and the 8 corners against the oracle's Eq. 4 on the stored words;
-    the FP64 reductions against FP64 sums of the returned fields (max and min exact);
-    the fields-only kernel bit for bit equal to the reduction kernel's fields."""
+    the FP64 reductions against FP64 sums of the returned fields (max and min exact),
+    and those of a call without fields against them; the fields-only kernel bit for bit
+    equal to the reduction kernel's fields."""
     need_gpu()
     B = binding()
     st = olbm.stencil("D3Q27")
@@ -617,6 +627,8 @@ def test_full_size_moments_sampled(kind):
     B.lbm_moments(grid, a, None, rho, u, red, ws)
     rho2, u2 = grid.empty_real(0), grid.empty_real(3)
     B.lbm_moments(grid, a, None, rho2, u2)
+    red_only = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
+    B.lbm_moments(grid, a, None, None, None, red_only, ws)
     torch.cuda.synchronize()
     assert torch.equal(bits(rho), bits(rho2)) and torch.equal(bits(u), bits(u2))
     cg = torch.Generator().manual_seed(66)
@@ -643,6 +655,9 @@ def test_full_size_moments_sampled(kind):
     umax = float(usq.max().sqrt())  # the kernel's |u|^2 may round once differently (FMA)
     assert abs(float(red[6]) - umax) <= 1e-15 * umax
     assert float(red[7]) == float(rd.min())
+    red_only = red_only.cpu()  # other blocks, other order: sums to FP64 rounding, the rest exact
+    assert torch.equal(red_only[5:], red[5:])
+    assert float((red_only[:5] - red[:5]).abs().max()) <= 1e-12 * mass
 
 
 @pytest.mark.parametrize("lat,kind,mode", [("D3Q19", "f32", "none"), ("D3Q19", "f16s", "none"), ("D3Q27", "f32", "guo"),
