@@ -397,6 +397,10 @@ def run_workloads():
     return out
 
 
+# The sources compiled into the step kernel: counters taken on other sources are stale.
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "device.h", "lattice.h", "coeffs.h")
+
+
 def measured_traffic():
     """HBM bytes per launch of the step kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
@@ -410,7 +414,7 @@ def measured_traffic():
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip()
-    for name in ("kernels.hip", "lattice.h", "coeffs.h"):
+    for name in KERNEL_SOURCES:
         src = os.path.join(ROOT, "paper_2106_12929_amd", "csrc", name)
         if fields.get(f"{name} sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
             return None
