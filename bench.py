@@ -508,9 +508,9 @@ def profile_set(B, steps: int, warmup: int):
     rho, u = g3.empty_real(0), g3.empty_real(3)
     red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
     ws = torch.empty(B.lbm_moments_workspace_size(g3), dtype=torch.uint8, device="cuda")
-    report(f"moments + reductions D3Q27 f32 {N}^3", "moments_kernel<D3Q27, F32, unforced>", g3,
+    report(f"moments + reductions D3Q27 f32 {N}^3", "moments_kernel<D3Q27, F32, unforced, reducing>", g3,
            time_launches(lambda: B.lbm_moments(g3, pops, None, rho, u, red, ws), steps, warmup), 27 * 4 + 4 * 4)
-    report(f"moments fields only D3Q27 f32 {N}^3", "moments_fields_kernel<D3Q27, F32, unforced>", g3,
+    report(f"moments fields only D3Q27 f32 {N}^3", "moments_kernel<D3Q27, F32, unforced, fields only>", g3,
            time_launches(lambda: B.lbm_moments(g3, pops, None, rho, u), steps, warmup), 27 * 4 + 4 * 4)
     del pops, rho, u, ws
     del u3

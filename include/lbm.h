@@ -251,7 +251,10 @@ int lbm_moments_workspace_size(const lbm_grid* grid, size_t* bytes);
  * red: NULL, or a device array of LBM_NRED doubles receiving, in FP64:
  *   [0] sum rho   [1..3] sum rho u_a (z = 0 in 2D)   [4] kinetic energy 1/2 sum |u|^2
  *   [5] number of cells whose rho or u is not finite   [6] max |u|   [7] min rho
- *   The reduction order is fixed, so results are bitwise reproducible.
+ *   The reduction order depends only on the grid and on whether a field is written,
+ *   so repeated calls are bitwise reproducible.  A call that writes rho_out or u_out
+ *   sums [0..4] in another order than one that writes neither: the two agree to FP64
+ *   rounding, and [5..7], which do not depend on the order, agree exactly.
  * workspace: device scratch of lbm_moments_workspace_size() bytes, required iff red is
  *   not NULL; its contents are clobbered. */
 int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rho_out,
