@@ -150,10 +150,10 @@ def run_shard(B, steps: int, warmup: int, nx: int = 512, ny: int = 512, nz: int 
     """One device's share of a z-slab decomposition of a 512^2 x (64 P) grid: the slab
     step with ghost planes, its halo exchange (here each slab is its own periodic
     neighbour, so the copies stay on the device), and the periodic step of the same
-    shape for comparison."""
+    shape for comparison, all on rows of Grid.tuned's pitch."""
     from paper_2106_12929_amd.slabs import SlabSet
     from synthetic import taylor_green_3d
-    grid = B.Grid("D3Q27", storage, nx, ny, nz)
+    grid = B.Grid.tuned("D3Q27", storage, nx, ny, nz)
     f = grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, taylor_green_3d(nx, ny, nz, U0).cuda(), f)
     S = SlabSet(grid, 1)
@@ -165,7 +165,7 @@ def run_shard(B, steps: int, warmup: int, nx: int = 512, ny: int = 512, nz: int 
         B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, None, 1)
         cur[0] ^= 1
 
-    out = {"shape": [nx, ny, nz], "storage": storage}
+    out = {"shape": [nx, ny, nz], "storage": storage, "row_pitch": grid.row_pitch}
     bpc = B.bytes_per_cell_step(grid)
     n_face = 9
     halo_bytes = 2 * n_face * nx * ny * torch.tensor([], dtype=grid.word_dtype).element_size()
@@ -189,12 +189,15 @@ def run_shard(B, steps: int, warmup: int, nx: int = 512, ny: int = 512, nz: int 
 
 
 def run_pitch(B, steps: int, warmup: int):
-    """Rows whose length is not a multiple of 64 words, stored dense and padded to a
-    256-byte row pitch (lbm_grid.pitch): the padding restores full bandwidth."""
+    """Row pitch (lbm_grid.pitch) against dense rows: FP32 rows whose length is not a
+    multiple of 64 words, dense and padded to 256 bytes; and 512-cell FP16-shifted
+    rows (1 KB), dense and with Grid.tuned's extra 128-byte line."""
     out = {}
-    for lat, shape in (("D3Q27", (255, 256, 256)), ("D2Q9", (8191, 8192, 1))):
-        for layout in ("dense", "padded"):
-            grid = B.Grid(lat, "f32", *shape) if layout == "dense" else B.Grid.padded(lat, "f32", *shape)
+    for lat, storage, shape, alt in (("D3Q27", "f32", (255, 256, 256), "padded"),
+                                     ("D2Q9", "f32", (8191, 8192, 1), "padded"),
+                                     ("D3Q27", "f16s", (512, 512, 512), "tuned")):
+        for layout in ("dense", alt):
+            grid = B.Grid(lat, storage, *shape) if layout == "dense" else getattr(B.Grid, layout)(lat, storage, *shape)
             bufs = [grid.empty_populations().zero_(), grid.empty_populations().zero_()]
             cur = [0]
 
@@ -204,7 +207,7 @@ def run_pitch(B, steps: int, warmup: int):
 
             ms = time_launches(one, steps, warmup)
             bpc = B.bytes_per_cell_step(grid)
-            out[f"{lat}_{'x'.join(map(str, shape))}_{layout}"] = {
+            out[f"{lat}_{storage}_{'x'.join(map(str, shape))}_{layout}"] = {
                 "pitch": grid.row_pitch, "ms_per_step": ms, "mlups": grid.ncells / (ms * 1e-3) / 1e6,
                 "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9}
             del bufs

@@ -101,6 +101,21 @@ class Grid:
         per = 256 // torch.tensor([], dtype=STORAGE_DTYPE[storage]).element_size()
         return Grid(lattice, storage, nx, ny, nz, -(-nx // per) * per)
 
+    @staticmethod
+    def tuned(lattice: str, storage: str, nx: int, ny: int, nz: int = 1) -> "Grid":
+        """`padded`, then one more 128-byte line on the rows of 3D lattices that measured
+        slow on MI355X: 2- or 8-byte words, a row of a power-of-two length of 1 KB or
+        more, split over several 256-cell blocks.  The D3Q27 step ran 10-11% faster with
+        that line at 1 KB and 2 KB rows of 2-byte words and at 4 KB rows of 8-byte
+        words (3% at 4 KB rows of 2-byte words; D3Q19 7%).  With 4-byte words, other
+        row lengths and D2Q9 the extra line measured slower, so those keep `padded`."""
+        g = Grid.padded(lattice, storage, nx, ny, nz)
+        word = torch.tensor([], dtype=STORAGE_DTYPE[storage]).element_size()
+        row = g.row_pitch * word
+        if lattice != "D2Q9" and word in (2, 8) and nx > 256 and row >= 1024 and row & (row - 1) == 0:
+            g = Grid(lattice, storage, nx, ny, nz, g.row_pitch + 128 // word)
+        return g
+
     @property
     def row_pitch(self) -> int:
         return self.nx if self.pitch is None else self.pitch

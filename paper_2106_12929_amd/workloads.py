@@ -52,7 +52,7 @@ def precision_study(u0: torch.Tensor, tau: float, steps: int, storages=("f64", "
     ref = None
     shells = SP.shell_index((n, n, n), u0.device)
     for storage in storages:
-        grid = B.Grid("D3Q27", storage, n, n, n)
+        grid = B.Grid.tuned("D3Q27", storage, n, n, n)
         a, b = grid.empty_populations(), grid.empty_populations()
         B.lbm_init_equilibrium(grid, None, u0, a)
         ke_hist = []
@@ -147,9 +147,10 @@ def full_scale_adjoint(u0: torch.Tensor, tau: float, forward_steps: int = 500, a
 
     Freed memory stays in torch's cache (no empty_cache) between calls: handing the
     ~185 GB of one call back to the driver and mapping it again made the next call's
-    backward about 4x slower (same results), so repeated calls reuse the cached blocks."""
+    backward about 4x slower (same results), so repeated calls reuse the cached blocks.
+    The populations take Grid.tuned's row pitch unless `pitch` is given."""
     n = u0.shape[-1]
-    grid = B.Grid("D3Q27", "f16s", n, n, n, pitch)
+    grid = B.Grid.tuned("D3Q27", "f16s", n, n, n) if pitch is None else B.Grid("D3Q27", "f16s", n, n, n, pitch)
     torch.cuda.reset_peak_memory_stats()
     a, b = grid.empty_populations(), grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, u0, a)
@@ -186,7 +187,7 @@ def full_scale_adjoint(u0: torch.Tensor, tau: float, forward_steps: int = 500, a
                "kinetic_energy_final": float(KE), "grad_finite": bool(torch.isfinite(dF).all())}
         del gT, u, F, g_start
         return res
-    out = {"grid": [n, n, n], "storage": "f16s state, f32 adjoint", "tau": tau,
+    out = {"grid": [n, n, n], "row_pitch": grid.row_pitch, "storage": "f16s state, f32 adjoint", "tau": tau,
            "forward_steps": forward_steps, "adjoint_steps": adjoint_steps, "checkpoint_every": checkpoint_every,
            "forward_mlups": n ** 3 * pre / t_fwd / 1e6,
            "tail_forward_mlups": n ** 3 * adjoint_steps / t_tail / 1e6,

@@ -44,6 +44,20 @@ def test_padded_rows_are_256_bytes(B, storage, nx, want):
     assert grid.slab_population_shape() == (5, 4, 27, want)
 
 
+@pytest.mark.parametrize("lattice,storage,nx,want", [
+    ("D3Q27", "f16s", 512, 576), ("D3Q27", "bf16s", 1024, 1088), ("D3Q27", "f16s", 500, 576),
+    ("D3Q27", "f64", 512, 528), ("D3Q19", "f16s", 512, 576), ("D3Q27", "f16s", 2048, 2112),
+    ("D3Q27", "f32", 512, 512), ("D3Q27", "f32", 256, 256), ("D3Q27", "f16s", 256, 256),
+    ("D3Q27", "f16s", 768, 768), ("D3Q27", "f64", 128, 128), ("D3Q27", "f32", 37, 64),
+    ("D2Q9", "f16s", 8192, 8192), ("D2Q9", "f64", 512, 512)])
+def test_tuned_pitch(B, lattice, storage, nx, want):
+    """One extra 128-byte line only on split power-of-two rows of 2- or 8-byte words
+    of the 3D lattices; otherwise the 256-byte padding."""
+    grid = B.Grid.tuned(lattice, storage, nx, 4, 1 if lattice == "D2Q9" else 3)
+    assert grid.row_pitch == want
+    assert grid.row_pitch * grid.word_dtype.itemsize % 128 == 0
+
+
 def test_c_struct_carries_the_pitch(B):
     assert B.Grid("D3Q27", "f32", 8, 8, 8).c_struct().pitch == 0
     assert B.Grid("D3Q27", "f32", 8, 8, 8, 12).c_struct().pitch == 12

@@ -36,9 +36,24 @@ def _pads_untouched(t, nx):
 def test_pitched_layout_matches_dense(lat, shape, kind, extra):
     need_gpu()
     B = binding()
+    pitched = B.Grid.padded(lat, kind, *shape) if extra == "padded" else B.Grid(lat, kind, *shape, shape[0] + extra)
+    _check_layout(B, lat, shape, kind, pitched)
+
+
+@pytest.mark.parametrize("lat,kind,pitch", [("D3Q27", "f16s", 576), ("D3Q27", "f64", 528), ("D3Q19", "bf16s", 576)])
+def test_tuned_layout_matches_dense(lat, kind, pitch):
+    """Grid.tuned's extra line on 512-cell rows (two blocks per row): the same bits."""
+    need_gpu()
+    B = binding()
+    shape = (512, 3, 2)
+    tuned = B.Grid.tuned(lat, kind, *shape)
+    assert tuned.row_pitch == pitch
+    _check_layout(B, lat, shape, kind, tuned)
+
+
+def _check_layout(B, lat, shape, kind, pitched):
     st = olbm.stencil(lat)
     dense = B.Grid(lat, kind, *shape)
-    pitched = B.Grid.padded(lat, kind, *shape) if extra == "padded" else B.Grid(lat, kind, *shape, shape[0] + extra)
     assert pitched.row_pitch > dense.nx
     spatial = _spatial(lat, shape)
     say(f"pitch {lat} {kind} {shape} pitch={pitched.row_pitch}")
