@@ -237,7 +237,7 @@ def gradient_precision(u0: torch.Tensor, tau: float, steps: int = 100, checkpoin
 
 
 def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-5, cutoff: float = 2e-5,
-                    record_every: int = 250, storage: str = "f32"):
+                    record_every: int = 250, storage: str = "f32", graph: bool = True):
     """Free and restrained decaying turbulence on a periodic D2Q9 grid.
 
     R(u) = sum_K (ln max(sigma_K(u), c) - ln max(sigma0_K, c))^2 over shells
@@ -245,41 +245,74 @@ def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-
     every step with lbm_step_shifted and du = -kappa dR/du (the closed-form gradient
     through the FFT, two FFTs per step).  Returns R and the kinetic energy over time
     for both.
+
+    With `graph` (and even `steps` and `record_every`), two restrained steps (a -> b,
+    b -> a: moments, loss head, shifted step, twice) are captured once as a HIP graph
+    and replayed; the free run takes record_every steps per lbm_step call.
     """
     ny, nx = u0.shape[1:]
     grid = B.Grid("D2Q9", storage, nx, ny)
     shells = SP.shell_index((ny, nx), u0.device)
     sigma0 = SP.energy_spectrum(u0.double(), shells)
     kmax = min(nx, ny) // 2
+    use_graph = graph and steps % 2 == 0 and record_every % 2 == 0
 
     def R_of(u):
         return SP.log_spectrum_loss(SP.energy_spectrum(u, shells), sigma0, 1, kmax, cutoff)
 
-    out = {"grid": [nx, ny], "tau": tau, "steps": steps, "kappa": kappa, "cutoff": cutoff, "storage": storage}
+    def controlled(src, dst, u):
+        B.lbm_moments(grid, src, None, None, u)
+        _, grad = SP.log_spectrum_loss_and_grad(u, shells, sigma0, 1, kmax, cutoff)
+        du = (-kappa * grad).to(grid.real_dtype).contiguous()
+        B.lbm_step_shifted(grid, src, dst, tau, du, 1)
+
+    out = {"grid": [nx, ny], "tau": tau, "steps": steps, "kappa": kappa, "cutoff": cutoff, "storage": storage,
+           "graph": use_graph}
     for mode in ("free", "restrained"):
         a, b = grid.empty_populations(), grid.empty_populations()
         B.lbm_init_equilibrium(grid, None, u0, a)
         u = grid.empty_real(2)
+        pair = None
+        if mode == "restrained" and use_graph:
+            # warm-up (FFT plans, allocator) on scratch buffers, then the capture
+            x, y = a.clone(), grid.empty_populations()
+            ux = grid.empty_real(2)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                controlled(x, y, ux)
+                controlled(y, x, ux)
+                pair = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(pair, stream=side):
+                    controlled(a, b, u)
+                    controlled(b, a, u)
+            torch.cuda.current_stream().wait_stream(side)
+            del x, y, ux
         hist = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for t in range(steps + 1):
-            if mode == "restrained" or t % record_every == 0:
-                B.lbm_moments(grid, a, None, None, u)
+        t = 0
+        while True:
             if t % record_every == 0:
+                B.lbm_moments(grid, a, None, None, u)
                 with torch.no_grad():
                     hist.append((t, float(R_of(u)), float(0.5 * (u.double() ** 2).sum())))
             if t == steps:
                 break
             if mode == "free":
-                B.lbm_step(grid, a, b, tau, None, 1)
+                k = min(record_every - t % record_every, steps - t)
+                if B.lbm_step(grid, a, b, tau, None, k) == 0:
+                    a, b = b, a
+                t += k
+            elif pair is not None:
+                pair.replay()  # two steps: the state is back in a
+                t += 2
             else:
-                _, grad = SP.log_spectrum_loss_and_grad(u, shells, sigma0, 1, kmax, cutoff)
-                du = (-kappa * grad).to(grid.real_dtype).contiguous()
-                B.lbm_step_shifted(grid, a, b, tau, du, 1)
-            a, b = b, a
+                controlled(a, b, u)
+                a, b = b, a
+                t += 1
         out[mode] = {"history": hist, "seconds": _sync_time(t0)}
-        del a, b
+        del a, b, pair
     return out
 
 

@@ -55,6 +55,26 @@ def test_flow_control_restrains_the_spectrum():
     assert R_ctrl < 0.25 * R_free
 
 
+def test_flow_control_graph_matches_eager():
+    """The restrained run replaying its captured two-step HIP graph (moments, FFT loss
+    head, shifted step, twice) gives the eager run's R and kinetic-energy history bit
+    for bit after every replay (each recorded eagerly, with a synchronisation, between
+    the replays)."""
+    need_gpu()
+    binding()
+    from paper_2106_12929_amd import workloads as WL
+
+    u = synthetic.isotropic_turbulence(64, 4.0, 0.04, seed=2, dim=2, device="cuda")
+    eager = WL.flow_control_2d(u, 0.51, 40, kappa=5e-3, record_every=2, graph=False)
+    graphed = WL.flow_control_2d(u, 0.51, 40, kappa=5e-3, record_every=2, graph=True)
+    assert graphed["graph"] and not eager["graph"]
+    assert len(graphed["restrained"]["history"]) == 21
+    assert graphed["restrained"]["history"] == eager["restrained"]["history"]
+    assert graphed["free"]["history"] == eager["free"]["history"]
+    # the restraint acts: R stays below the free run's
+    assert graphed["restrained"]["history"][-1][1] < graphed["free"]["history"][-1][1]
+
+
 def test_forcing_optimisation_lowers_the_loss():
     need_gpu()
     binding()
