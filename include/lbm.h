@@ -299,6 +299,47 @@ int lbm_moments_adjoint(const lbm_grid* grid, const void* g, const void* force,
                         const void* dL_drho, const void* dL_du, void* lam_out, void* dforce,
                         void* stream);
 
+/* ---- Loss head of the flow-control forcing (Sec. 3.2) ----------------------------
+ * The paper steers a decaying flow by a cost on its instantaneous energy spectrum; the
+ * controlled step needs that cost's gradient every step.  With uh_a(k) the
+ * unnormalised forward FFT of the velocity component u_a (taken by the caller), s =
+ * 1/N and shells K = floor(|k| + 1/2) of the integer wavevectors k:
+ *   E(K) = s^2/2 sum_{k in K} sum_a |uh_a(k)|^2          (shell energy spectrum)
+ *   R    = sum_{K=k_lo..k_hi} (ln max(E_K, c) - ln max(Et_K, c))^2
+ *   dR/du_a = Re IFFT(g s uh_a), g(k) = dR/dE_K at the shell of k
+ * (IFFT normalised by 1/N), so a step is: FFT, lbm_shell_energy,
+ * lbm_log_spectrum_grad, inverse FFT, lbm_real_part (-> the du of lbm_step_shifted).
+ *
+ * lbm_shells describes the wavevectors grouped by shell, all device arrays owned by the
+ * caller: order[n] the flat wavevector indices sorted by shell, offsets[nshell + 1]
+ * with shell K = order[offsets[K] .. offsets[K+1]) (offsets[0] = 0, offsets[nshell] =
+ * n), shell[n] the shell of every flat wavevector.  A table that breaks these rules
+ * gives wrong results but no access outside the arrays.  1 <= n <= 2^31 - 1 and
+ * nshell >= 1 (LBM_EINVAL / LBM_ERANGE otherwise). */
+typedef struct {
+  int64_t n;
+  int32_t nshell;
+  const int32_t* order;
+  const int32_t* offsets;
+  const int32_t* shell;
+} lbm_shells;
+
+/* E[0 .. nshell) <- s^2/2 sum over each shell of sum_a |uhat_a(k)|^2, deterministic
+ * (fixed summation order).  uhat: D*n complex doubles (interleaved re, im), component
+ * a at uhat[a*n + k]; D in 1..3.  scale = s.  E must not overlap uhat. */
+int lbm_shell_energy(const lbm_shells* shells, int D, const void* uhat, double scale, double* E, void* stream);
+
+/* uhat_a(k) *= scale * dR/dE_K (in place; K the shell of k): 2 (ln E_K - ln max(Et_K, c))
+ * / E_K for k_lo <= K <= k_hi and E_K >= c, else 0.  E, E_target: nshell doubles.  R: one
+ * double receiving R, or NULL.  0 <= k_lo <= k_hi < nshell and a finite cutoff c > 0
+ * (LBM_EINVAL otherwise); uhat must not overlap E, E_target or R. */
+int lbm_log_spectrum_grad(const lbm_shells* shells, int D, void* uhat, const double* E, const double* E_target,
+                          int k_lo, int k_hi, double cutoff, double scale, double* R, void* stream);
+
+/* out[i] = scale * Re z[i], i < count: z complex doubles, out FP32 (out_storage LBM_F32)
+ * or FP64 (LBM_F64); they must not overlap. */
+int lbm_real_part(const void* z, int64_t count, double scale, void* out, int out_storage, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

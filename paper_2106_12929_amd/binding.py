@@ -44,6 +44,11 @@ class _CGrid(ctypes.Structure):
                 ("pitch", ctypes.c_int64)]
 
 
+class _CShells(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nshell", ctypes.c_int32), ("order", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p), ("shell", ctypes.c_void_p)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2106_12929_amd.build`")
@@ -71,6 +76,9 @@ def _load() -> ctypes.CDLL:
         "lbm_copy": (i32, [vp, vp, sz, vp]),
         "lbm_step_slab": (i32, [gp, vp, vp, dbl, vp, ctypes.c_int64, ctypes.c_int64, vp]),
         "lbm_slab_halo_copy": (i32, [gp, vp, gp, vp, i32, vp]),
+        "lbm_shell_energy": (i32, [ctypes.POINTER(_CShells), i32, vp, dbl, vp, vp]),
+        "lbm_log_spectrum_grad": (i32, [ctypes.POINTER(_CShells), i32, vp, vp, vp, i32, i32, dbl, dbl, vp, vp]),
+        "lbm_real_part": (i32, [vp, ctypes.c_int64, dbl, vp, i32, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -449,5 +457,77 @@ def mlups(grid: Grid, steps: int, seconds: float) -> float:
     return grid.ncells * steps / seconds / 1e6
 
 
+@dataclass(frozen=True)
+class ShellTable:
+    """Wavevectors of a periodic grid grouped by shell, as lbm_shells wants them (int32
+    device arrays): order sorts the flat wavevector indices by shell, shell K holds
+    order[offsets[K]:offsets[K+1]], shell gives every wavevector's shell."""
+
+    n: int
+    nshell: int
+    order: torch.Tensor
+    offsets: torch.Tensor
+    shell: torch.Tensor
+
+    @staticmethod
+    def from_shells(shell: torch.Tensor) -> "ShellTable":
+        """From the shell index of every flat wavevector (non-negative integers, GPU)."""
+        flat = shell.reshape(-1).to(torch.int64)
+        counts = torch.bincount(flat)
+        offsets = torch.zeros(counts.numel() + 1, dtype=torch.int64, device=flat.device)
+        offsets[1:] = torch.cumsum(counts, 0)
+        order = torch.argsort(flat, stable=True)
+        return ShellTable(flat.numel(), counts.numel(), order.to(torch.int32).contiguous(),
+                          offsets.to(torch.int32).contiguous(), flat.to(torch.int32).contiguous())
+
+    def c_struct(self) -> _CShells:
+        _dev_ptr(self.order, "order", torch.int32, self.n)
+        _dev_ptr(self.offsets, "offsets", torch.int32, self.nshell + 1)
+        _dev_ptr(self.shell, "shell", torch.int32, self.n)
+        return _CShells(self.n, self.nshell, self.order.data_ptr(), self.offsets.data_ptr(), self.shell.data_ptr())
+
+
+def _spectral_field(t: torch.Tensor, name: str, table: ShellTable) -> tuple[int, ctypes.c_void_p]:
+    """(D, pointer) of a [D, ...] complex128 field over table.n wavevectors."""
+    D = t.shape[0] if t.dim() > 0 else 0
+    if D < 1 or D > 3:
+        raise ValueError(f"{name} must be [D, ...] with D in 1..3")
+    return D, _dev_ptr(t, name, torch.complex128, D * table.n)
+
+
+def lbm_shell_energy(table: ShellTable, uhat: torch.Tensor, scale: float, E: torch.Tensor, stream=None) -> None:
+    """E[K] <- scale^2/2 * sum over shell K of sum_a |uhat_a(k)|^2 (uhat: unnormalised
+    FFT of u, [D, *spatial] complex128; E: nshell float64)."""
+    D, p = _spectral_field(uhat, "uhat", table)
+    e = _dev_ptr(E, "E", torch.float64, table.nshell)
+    c = table.c_struct()
+    _check(_lib.lbm_shell_energy(ctypes.byref(c), D, p, float(scale), e, _stream(stream)), "lbm_shell_energy")
+
+
+def lbm_log_spectrum_grad(table: ShellTable, uhat: torch.Tensor, E: torch.Tensor, E_target: torch.Tensor,
+                          k_lo: int, k_hi: int, cutoff: float, scale: float, R: torch.Tensor | None = None,
+                          stream=None) -> None:
+    """uhat *= scale * dR/dE at each wavevector's shell, in place (R the log-spectrum
+    cost over shells k_lo..k_hi with cutoff c); R (one float64) receives the cost."""
+    D, p = _spectral_field(uhat, "uhat", table)
+    e = _dev_ptr(E, "E", torch.float64, table.nshell)
+    et = _dev_ptr(E_target, "E_target", torch.float64, table.nshell)
+    r = _dev_ptr(R, "R", torch.float64, 1, required=False)
+    c = table.c_struct()
+    _check(_lib.lbm_log_spectrum_grad(ctypes.byref(c), D, p, e, et, int(k_lo), int(k_hi), float(cutoff),
+                                      float(scale), r, _stream(stream)), "lbm_log_spectrum_grad")
+
+
+def lbm_real_part(z: torch.Tensor, scale: float, out: torch.Tensor, stream=None) -> None:
+    """out <- scale * Re z elementwise (z complex128; out float32 or float64, same count)."""
+    if out.dtype not in (torch.float32, torch.float64):
+        raise TypeError("out must be float32 or float64")
+    zp = _dev_ptr(z, "z", torch.complex128, z.numel())
+    op = _dev_ptr(out, "out", out.dtype, z.numel())
+    kind = STORAGES["f64"] if out.dtype == torch.float64 else STORAGES["f32"]
+    _check(_lib.lbm_real_part(zp, ctypes.c_int64(z.numel()), float(scale), op, kind, _stream(stream)),
+           "lbm_real_part")
+
+
 __all__ = [n for n in dir() if n.startswith("lbm_")] + ["Grid", "LbmError", "NRED", "RED_NAMES", "LIB_PATH",
-                                                        "bytes_per_cell_step", "mlups"]
+                                                        "ShellTable", "bytes_per_cell_step", "mlups"]

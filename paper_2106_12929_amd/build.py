@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ("api.hip", "kernels.hip")
+SOURCES = ("api.hip", "kernels.hip", "spectrum.hip")
 
 ARCH = "gfx950"
 FLAGS = [

@@ -496,4 +496,62 @@ int lbm_moments_adjoint(const lbm_grid* grid, const void* g, const void* force, 
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments_adjoint launch");
 }
 
+static int check_shells(const lbm_shells* sh, int D) {
+  if (!sh) return fail(LBM_ENULL, "shells is NULL");
+  if (D < 1 || D > 3) return fail(LBM_EINVAL, "D must be 1, 2 or 3 (got %d)", D);
+  if (sh->n < 1 || sh->nshell < 1) return fail(LBM_EINVAL, "shells need n >= 1 and nshell >= 1");
+  if (sh->n > 2147483647) return fail(LBM_ERANGE, "more than 2^31-1 wavevectors");
+  LBM_TRY(check_ptr(sh->order, "shells.order", true));
+  LBM_TRY(check_ptr(sh->offsets, "shells.offsets", true));
+  LBM_TRY(check_ptr(sh->shell, "shells.shell", true));
+  return LBM_OK;
+}
+
+int lbm_shell_energy(const lbm_shells* shells, int D, const void* uhat, double scale, double* E, void* stream) {
+  LBM_TRY(check_shells(shells, D));
+  LBM_TRY(check_ptr(uhat, "uhat", true));
+  LBM_TRY(check_ptr(E, "E", true));
+  if (!std::isfinite(scale)) return fail(LBM_EINVAL, "scale must be finite");
+  const size_t nb = (size_t)D * (size_t)shells->n * 16;
+  if (overlap(uhat, nb, E, (size_t)shells->nshell * 8)) return fail(LBM_EALIAS, "E overlaps uhat");
+  const hipError_t e = lbm::launch_shell_energy(uhat, D, (uint32_t)shells->n, shells->order, shells->offsets,
+                                                shells->nshell, scale, E, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_shell_energy launch");
+}
+
+int lbm_log_spectrum_grad(const lbm_shells* shells, int D, void* uhat, const double* E, const double* E_target,
+                          int k_lo, int k_hi, double cutoff, double scale, double* R, void* stream) {
+  LBM_TRY(check_shells(shells, D));
+  LBM_TRY(check_ptr(uhat, "uhat", true));
+  LBM_TRY(check_ptr(E, "E", true));
+  LBM_TRY(check_ptr(E_target, "E_target", true));
+  LBM_TRY(check_ptr(R, "R", false));
+  if (k_lo < 0 || k_hi < k_lo || k_hi >= shells->nshell)
+    return fail(LBM_EINVAL, "need 0 <= k_lo <= k_hi < nshell (got %d, %d, %d)", k_lo, k_hi, shells->nshell);
+  if (!std::isfinite(cutoff) || !(cutoff > 0)) return fail(LBM_EINVAL, "cutoff must be finite and > 0");
+  if (!std::isfinite(scale)) return fail(LBM_EINVAL, "scale must be finite");
+  const size_t nb = (size_t)D * (size_t)shells->n * 16, eb = (size_t)shells->nshell * 8;
+  if (overlap(uhat, nb, E, eb) || overlap(uhat, nb, E_target, eb) || overlap(uhat, nb, R, 8))
+    return fail(LBM_EALIAS, "uhat overlaps E, E_target or R");
+  const hipError_t e =
+      lbm::launch_log_spectrum_grad(uhat, D, (uint32_t)shells->n, shells->shell, E, E_target, shells->nshell, k_lo,
+                                    k_hi, cutoff, scale, R, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_log_spectrum_grad launch");
+}
+
+int lbm_real_part(const void* z, int64_t count, double scale, void* out, int out_storage, void* stream) {
+  LBM_TRY(check_ptr(z, "z", true));
+  LBM_TRY(check_ptr(out, "out", true));
+  if (count < 1) return fail(LBM_EINVAL, "count must be >= 1");
+  if (count > (int64_t)0xFFFFFFFF * 256) return fail(LBM_ERANGE, "count too large");
+  if (out_storage != LBM_F32 && out_storage != LBM_F64)
+    return fail(LBM_EINVAL, "out_storage must be LBM_F32 or LBM_F64 (got %d)", out_storage);
+  if (!std::isfinite(scale)) return fail(LBM_EINVAL, "scale must be finite");
+  const size_t ob = (size_t)count * (out_storage == LBM_F64 ? 8 : 4);
+  if (overlap(z, (size_t)count * 16, out, ob)) return fail(LBM_EALIAS, "out overlaps z");
+  const hipError_t e = lbm::launch_real_part(z, (uint64_t)count, scale, out, out_storage == LBM_F64,
+                                             (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_real_part launch");
+}
+
 }  // extern "C"

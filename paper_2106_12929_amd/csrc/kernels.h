@@ -54,4 +54,12 @@ hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s);
 hipError_t launch_moments_adjoint(int lattice, int storage, const void* f, const void* force, const void* drho,
                                   const void* du, void* lam_out, void* dforce, const GridArgs& g, hipStream_t s);
 
+// Loss head of the flow-control forcing (spectrum.hip).
+hipError_t launch_shell_energy(const void* uh, int D, uint32_t n, const int32_t* order, const int32_t* offsets,
+                               int nshell, double scale, double* E, hipStream_t s);
+hipError_t launch_log_spectrum_grad(void* uh, int D, uint32_t n, const int32_t* shell, const double* E,
+                                    const double* Et, int nshell, int k_lo, int k_hi, double cutoff, double scale,
+                                    double* R, hipStream_t s);
+hipError_t launch_real_part(const void* z, uint64_t count, double scale, void* out, bool f64, hipStream_t s);
+
 }  // namespace lbm

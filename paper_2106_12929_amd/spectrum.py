@@ -76,3 +76,35 @@ def log_spectrum_loss_and_grad(u: torch.Tensor, shells: Shells, E_target: torch.
     g = dE[shells.shell].reshape(spatial)
     grad = torch.fft.ifftn(g * uh, dim=dims).real
     return R, grad
+
+
+class NativeLossHead:
+    """s * dR/du of R = log_spectrum_loss(energy_spectrum(u), E_target, k_lo, k_hi,
+    cutoff), the quantity log_spectrum_loss_and_grad returns, computed by the library's
+    kernels between two FFTs: FFT(u), lbm_shell_energy, lbm_log_spectrum_grad (which
+    multiplies the coefficients by dR/dE at their shell and also writes R), inverse FFT,
+    lbm_real_part.  Five launches beside the transforms, against about twenty torch
+    launches; the shell sums take another fixed order, so the two agree to rounding."""
+
+    def __init__(self, shells: Shells, E_target: torch.Tensor, k_lo: int, k_hi: int, cutoff: float):
+        from . import binding
+
+        self._B = binding
+        self.table = binding.ShellTable.from_shells(shells.shell)
+        if E_target.numel() != self.table.nshell:
+            raise ValueError(f"E_target needs {self.table.nshell} shells (got {E_target.numel()})")
+        self.E_target = E_target.to(torch.float64).contiguous()
+        self.k_lo, self.k_hi, self.cutoff = int(k_lo), int(k_hi), float(cutoff)
+        self.inv_n = 1.0 / math.prod(shells.spatial)
+        self.E = torch.empty(self.table.nshell, dtype=torch.float64, device=E_target.device)
+        self.R = torch.empty(1, dtype=torch.float64, device=E_target.device)
+
+    def scaled_grad(self, u: torch.Tensor, scale: float, out: torch.Tensor) -> None:
+        """out <- scale * dR/du for u[D, *spatial]; out float32 or float64 of u's shape.
+        self.E and self.R hold the spectrum and the cost of u afterwards."""
+        dims = tuple(range(1, u.dim()))
+        uh = torch.fft.fftn(u.to(torch.complex128), dim=dims)
+        self._B.lbm_shell_energy(self.table, uh, self.inv_n, self.E)
+        self._B.lbm_log_spectrum_grad(self.table, uh, self.E, self.E_target, self.k_lo, self.k_hi, self.cutoff,
+                                      self.inv_n, self.R)
+        self._B.lbm_real_part(torch.fft.ifftn(uh, dim=dims), scale, out)

@@ -243,8 +243,9 @@ def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-
     R(u) = sum_K (ln max(sigma_K(u), c) - ln max(sigma0_K, c))^2 over shells
     K = 1 .. n/2, sigma0 the spectrum of the initial field; the restrained run takes
     every step with lbm_step_shifted and du = -kappa dR/du (the closed-form gradient
-    through the FFT, two FFTs per step).  Returns R and the kinetic energy over time
-    for both.
+    through the FFT, two FFTs per step, with the spectrum, its gradient multiplier and
+    the real part in the library's kernels: SP.NativeLossHead).  Returns R and the
+    kinetic energy over time for both.
 
     With `graph` (and even `steps` and `record_every`), two restrained steps (a -> b,
     b -> a: moments, loss head, shifted step, twice) are captured once as a HIP graph
@@ -260,10 +261,12 @@ def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-
     def R_of(u):
         return SP.log_spectrum_loss(SP.energy_spectrum(u, shells), sigma0, 1, kmax, cutoff)
 
+    head = SP.NativeLossHead(shells, sigma0, 1, kmax, cutoff)
+    du = grid.empty_real(2)
+
     def controlled(src, dst, u):
         B.lbm_moments(grid, src, None, None, u)
-        _, grad = SP.log_spectrum_loss_and_grad(u, shells, sigma0, 1, kmax, cutoff)
-        du = (-kappa * grad).to(grid.real_dtype).contiguous()
+        head.scaled_grad(u, -kappa, du)
         B.lbm_step_shifted(grid, src, dst, tau, du, 1)
 
     out = {"grid": [nx, ny], "tau": tau, "steps": steps, "kappa": kappa, "cutoff": cutoff, "storage": storage,

@@ -254,3 +254,39 @@ def test_binding_rejects_host_tensors(B):
     a = torch.zeros(grid.population_shape(), dtype=torch.float32)
     with pytest.raises(ValueError):
         B.lbm_step(grid, a, a.clone(), 0.6)
+
+
+def test_loss_head_entry_points_validate(B):
+    """The flow-control loss head's entry points reject bad tables, shell bands,
+    cutoffs, output kinds and overlapping buffers on the host."""
+    lib = B._lib
+    sh = B._CShells(100, 8, 0x10000, 0x20000, 0x30000)
+    sp = ctypes.byref(sh)
+    assert lib.lbm_shell_energy(None, 2, P1, 0.01, P2, None) == -2
+    assert lib.lbm_shell_energy(sp, 0, P1, 0.01, P2, None) == -1               # D in 1..3
+    assert lib.lbm_shell_energy(sp, 4, P1, 0.01, P2, None) == -1
+    assert lib.lbm_shell_energy(sp, 2, None, 0.01, P2, None) == -2
+    assert lib.lbm_shell_energy(sp, 2, MIS, 0.01, P2, None) == -3               # misaligned uhat
+    assert lib.lbm_shell_energy(sp, 2, P1, float("nan"), P2, None) == -1
+    assert lib.lbm_shell_energy(sp, 2, P1, 0.01, ctypes.c_void_p(0x10000 + 3200 - 16), None) == -4  # E inside uhat
+    bad = B._CShells(0, 8, 0x10000, 0x20000, 0x30000)
+    assert lib.lbm_shell_energy(ctypes.byref(bad), 2, P1, 0.01, P2, None) == -1
+    big = B._CShells(1 << 31, 8, 0x10000, 0x20000, 0x30000)
+    assert lib.lbm_shell_energy(ctypes.byref(big), 2, P1, 0.01, P2, None) == -6
+    nul = B._CShells(100, 8, 0x10000, None, 0x30000)
+    assert lib.lbm_shell_energy(ctypes.byref(nul), 2, P1, 0.01, P2, None) == -2
+    grad = lib.lbm_log_spectrum_grad
+    assert grad(sp, 2, P1, P2, P3, 1, 8, 1e-5, 0.01, None, None) == -1         # k_hi >= nshell
+    assert grad(sp, 2, P1, P2, P3, 3, 2, 1e-5, 0.01, None, None) == -1         # k_hi < k_lo
+    assert grad(sp, 2, P1, P2, P3, -1, 2, 1e-5, 0.01, None, None) == -1
+    assert grad(sp, 2, P1, P2, P3, 1, 7, 0.0, 0.01, None, None) == -1          # cutoff > 0
+    assert grad(sp, 2, P1, P2, P3, 1, 7, float("inf"), 0.01, None, None) == -1
+    assert grad(sp, 2, P1, P2, None, 1, 7, 1e-5, 0.01, None, None) == -2       # E_target required
+    assert grad(sp, 2, P1, P1, P3, 1, 7, 1e-5, 0.01, None, None) == -4         # E overlaps uhat
+    assert grad(sp, 2, P1, P2, P3, 1, 7, 1e-5, 0.01, P1, None) == -4           # R overlaps uhat
+    real = lib.lbm_real_part
+    assert real(P1, 100, 1.0, P2, 3, None) == -1                               # F32 or F64 only
+    assert real(P1, 0, 1.0, P2, 1, None) == -1
+    assert real(None, 100, 1.0, P2, 1, None) == -2
+    assert real(P1, 100, 1.0, ctypes.c_void_p(0x10000 + 800), 1, None) == -4   # out inside z
+    assert real(P1, 100, float("nan"), P2, 1, None) == -1

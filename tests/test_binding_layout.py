@@ -63,3 +63,15 @@ def test_c_struct_carries_the_pitch(B):
     assert B.Grid("D3Q27", "f32", 8, 8, 8, 12).c_struct().pitch == 12
     with pytest.raises(ValueError):
         B.Grid("D2Q9", "f32", 8, 8).slab_population_shape()
+
+
+def test_shell_table_layout(B):
+    """ShellTable (the lbm_shells arrays): order sorts the wavevectors by shell, stably;
+    offsets delimit the shells; shell is kept as int32."""
+    shell = torch.tensor([3, 0, 1, 1, 3, 2, 0, 1])
+    t = B.ShellTable.from_shells(shell)
+    assert (t.n, t.nshell) == (8, 4)
+    assert t.order.tolist() == [1, 6, 2, 3, 7, 5, 0, 4]
+    assert t.offsets.tolist() == [0, 2, 5, 6, 8]
+    assert t.shell.tolist() == shell.tolist()
+    assert {t.order.dtype, t.offsets.dtype, t.shell.dtype} == {torch.int32}
