@@ -8,6 +8,9 @@ import torch
 from . import binding as B
 
 
+_FORMAT = "lbm-simulation-1"
+
+
 class Diverged(RuntimeError):
     """A run produced non-finite cells (for BGK: tau too close to 1/2 for the flow)."""
 
@@ -50,6 +53,42 @@ class Simulation:
     def load(self, f: torch.Tensor) -> None:
         """Set the state from stored words of the right dtype and shape."""
         self.bufs[self.cur].copy_(f.to(self.device))
+
+    def save(self, path: str) -> None:
+        """Writes the current state (the storage words, bit for bit), the grid, tau, the
+        force and the step count to a safetensors file; Simulation.restore continues
+        from it exactly as the uninterrupted run would (the steps are deterministic)."""
+        from safetensors.torch import save_file
+
+        g = self.grid
+        tensors = {"populations": self.f.contiguous().view(torch.uint8).reshape(-1).cpu()}
+        if self.force is not None:
+            tensors["force"] = self.force.contiguous().cpu()
+        meta = {"format": _FORMAT, "lattice": g.lattice, "storage": g.storage, "nx": str(g.nx), "ny": str(g.ny),
+                "nz": str(g.nz), "pitch": str(g.row_pitch), "tau": repr(self.tau), "steps_done": str(self.steps_done)}
+        save_file(tensors, path, metadata=meta)
+
+    @classmethod
+    def restore(cls, path: str, device="cuda") -> "Simulation":
+        """A Simulation holding the state, grid, tau, force and step count of a file
+        written by save (read with safetensors: nothing in the file is executed)."""
+        from safetensors import safe_open
+
+        with safe_open(path, framework="pt") as fh:
+            meta = fh.metadata() or {}
+            if meta.get("format") != _FORMAT:
+                raise ValueError(f"{path} is not a saved simulation ({meta.get('format')!r})")
+            words = fh.get_tensor("populations")
+            force = fh.get_tensor("force") if "force" in fh.keys() else None
+        nx, pitch = int(meta["nx"]), int(meta["pitch"])
+        grid = B.Grid(meta["lattice"], meta["storage"], nx, int(meta["ny"]), int(meta["nz"]),
+                      None if pitch == nx else pitch)
+        if words.numel() != grid.pop_size * torch.tensor([], dtype=grid.word_dtype).element_size():
+            raise ValueError(f"{path}: population bytes do not match the grid")
+        sim = cls(grid, float(meta["tau"]), None if force is None else force.to(device), device)
+        sim.load(words.view(grid.word_dtype).reshape(grid.population_shape()))
+        sim.steps_done = int(meta["steps_done"])
+        return sim
 
     def step(self, n_steps: int = 1) -> None:
         src, dst = self.bufs[self.cur], self.bufs[1 - self.cur]
