@@ -236,8 +236,9 @@ int lbm_step_neural(const lbm_grid* grid, void* f_in, void* f_out, double tau_sh
 int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* stream);
 
 /* Plain device-to-device copy of `bytes` (a multiple of 16) with one 16-byte word per
- * thread and streaming stores: the practical HBM bandwidth reference that the step
- * kernel's GB/s are compared with (no part of the method).  Buffers must not overlap. */
+ * thread, nontemporal loads and stores: the practical HBM bandwidth reference that the
+ * step kernel's GB/s are compared with (no part of the method).  Buffers must not
+ * overlap. */
 int lbm_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Bytes of device workspace lbm_moments needs when it computes reductions. */

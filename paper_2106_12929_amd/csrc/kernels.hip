@@ -913,12 +913,14 @@ hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fou
   return hipErrorInvalidValue;
 }
 
-// Plain streaming copy (16-byte words, one per thread): the practical HBM bandwidth
-// reference the step kernel is compared with.
+// Plain streaming copy (16-byte words, one per thread, nontemporal loads and stores):
+// the practical HBM bandwidth reference the step kernel is compared with.  Of the copy
+// shapes measured (1, 2 or 4 words per thread, 256 or 512 threads, grid-stride loops,
+// cached loads) this one moved the most bytes per second.
 
 __global__ __launch_bounds__(256) void copy16_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) __builtin_nontemporal_store(src[i], &dst[i]);
+  if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
 hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s) {
