@@ -49,7 +49,8 @@ __global__ __launch_bounds__(256) void shell_energy_kernel(const double2* __rest
 
 // uh_a(k) *= scale * dR/dE_K at the shell K of k: 2 (ln E_K - ln max(Et_K, c)) / E_K
 // inside the band where E_K >= c, zero elsewhere (the clamp at c is flat below it).
-// Thread 0 also writes R, summing the band in shell order.
+// If R is given, block 0 also writes the cost: thread t sums the band's shells t,
+// t + 256, ... in order, then a fixed tree over the threads.
 __global__ __launch_bounds__(256) void log_spectrum_grad_kernel(double2* __restrict__ uh, int D, uint32_t n,
                                                                 const int32_t* __restrict__ shell,
                                                                 const double* __restrict__ E,
@@ -57,13 +58,20 @@ __global__ __launch_bounds__(256) void log_spectrum_grad_kernel(double2* __restr
                                                                 int k_hi, double c, double scale,
                                                                 double* __restrict__ R) {
   const uint64_t k = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  if (R && k == 0) {
+  if (R && blockIdx.x == 0) {  // uniform over the block: every thread reaches the barriers
     double r = 0;
-    for (int K = k_lo; K <= k_hi; ++K) {
+    for (int K = k_lo + (int)threadIdx.x; K <= k_hi; K += 256) {
       const double d = log(fmax(E[K], c)) - log(fmax(Et[K], c));
       r += d * d;
     }
-    *R = r;
+    __shared__ double sh[256];
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *R = sh[0];
   }
   if (k >= n) return;
   const int K = shell[k];

@@ -99,12 +99,12 @@ class NativeLossHead:
         self.E = torch.empty(self.table.nshell, dtype=torch.float64, device=E_target.device)
         self.R = torch.empty(1, dtype=torch.float64, device=E_target.device)
 
-    def scaled_grad(self, u: torch.Tensor, scale: float, out: torch.Tensor) -> None:
+    def scaled_grad(self, u: torch.Tensor, scale: float, out: torch.Tensor, with_cost: bool = False) -> None:
         """out <- scale * dR/du for u[D, *spatial]; out float32 or float64 of u's shape.
-        self.E and self.R hold the spectrum and the cost of u afterwards."""
+        self.E holds the spectrum of u afterwards, and self.R its cost if with_cost."""
         dims = tuple(range(1, u.dim()))
         uh = torch.fft.fftn(u.to(torch.complex128), dim=dims)
         self._B.lbm_shell_energy(self.table, uh, self.inv_n, self.E)
         self._B.lbm_log_spectrum_grad(self.table, uh, self.E, self.E_target, self.k_lo, self.k_hi, self.cutoff,
-                                      self.inv_n, self.R)
+                                      self.inv_n, self.R if with_cost else None)
         self._B.lbm_real_part(torch.fft.ifftn(uh, dim=dims), scale, out)

@@ -43,7 +43,7 @@ def test_native_loss_head_matches_oracle(spatial, cut_quantile):
     shells = SP.shell_index(spatial, "cuda")
     head = SP.NativeLossHead(shells, Et.cuda(), k_lo, k_hi, c)
     out = torch.empty((len(spatial),) + spatial, dtype=torch.float64, device="cuda")
-    head.scaled_grad(u.cuda(), 1.0, out)
+    head.scaled_grad(u.cuda(), 1.0, out, with_cost=True)
     E = head.E.cpu()
     assert E.numel() == E_ref.numel()
     assert float((E - E_ref).abs().max()) <= 1e-13 * float(E_ref.max())
@@ -72,7 +72,7 @@ def test_native_loss_head_matches_torch_head():
     R_t, g_t = SP.log_spectrum_loss_and_grad(u, shells, Et, 1, 64, 2e-5)
     head = SP.NativeLossHead(shells, Et, 1, 64, 2e-5)
     out = torch.empty((2, 128, 128), dtype=torch.float64, device="cuda")
-    head.scaled_grad(u, 1.0, out)
+    head.scaled_grad(u, 1.0, out, with_cost=True)
     assert float(R_t) > 1.0
     assert abs(float(head.R) - float(R_t)) <= 1e-11 * float(R_t)
     assert float((out - g_t).abs().max()) <= 1e-10 * float(g_t.abs().max())
