@@ -105,6 +105,8 @@ class NativeLossHead:
         dims = tuple(range(1, u.dim()))
         uh = torch.fft.fftn(u.to(torch.complex128), dim=dims)
         self._B.lbm_shell_energy(self.table, uh, self.inv_n, self.E)
+        # the inverse transform's 1/N is folded into the multiplier: norm="forward"
+        # leaves the inverse unscaled, which saves torch's separate scaling launch
         self._B.lbm_log_spectrum_grad(self.table, uh, self.E, self.E_target, self.k_lo, self.k_hi, self.cutoff,
-                                      self.inv_n, self.R if with_cost else None)
-        self._B.lbm_real_part(torch.fft.ifftn(uh, dim=dims), scale, out)
+                                      self.inv_n * self.inv_n, self.R if with_cost else None)
+        self._B.lbm_real_part(torch.fft.ifftn(uh, dim=dims, norm="forward"), scale, out)
