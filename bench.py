@@ -543,12 +543,13 @@ def profile_set(B, steps: int, warmup: int):
     torch.cuda.empty_cache()
 
     # the flow-control step (128^2 D2Q9 FP32): moments, the loss head between two FFTs
-    # and the shifted step, replayed as a graph of two steps (eager for an odd count)
+    # and the shifted step, replayed as a graph of two steps (eager for an odd count);
+    # the restrained run only, since the free run's step is the D2Q9 case's kernel
     from paper_2106_12929_amd import workloads as WL
     from synthetic import isotropic_turbulence
     uf = isotropic_turbulence(128, 4.0, 0.04, seed=0, dim=2, device="cuda")
     n_fc = 2 * max(1, steps // 2) * 10
-    fc = WL.flow_control_2d(uf, 0.5018, n_fc, kappa=5e-4, record_every=n_fc)
+    fc = WL.flow_control_2d(uf, 0.5018, n_fc, kappa=5e-4, record_every=n_fc, modes=("restrained",))
     print(json.dumps({"case": "flow control 128^2 controlled step", "graph": fc["graph"], "steps": n_fc,
                       "ms_per_step": 1e3 * fc["restrained"]["seconds"] / n_fc}), flush=True)
 

@@ -237,7 +237,8 @@ def gradient_precision(u0: torch.Tensor, tau: float, steps: int = 100, checkpoin
 
 
 def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-5, cutoff: float = 2e-5,
-                    record_every: int = 250, storage: str = "f32", graph: bool = True):
+                    record_every: int = 250, storage: str = "f32", graph: bool = True,
+                    modes=("free", "restrained")):
     """Free and restrained decaying turbulence on a periodic D2Q9 grid.
 
     R(u) = sum_K (ln max(sigma_K(u), c) - ln max(sigma0_K, c))^2 over shells
@@ -249,7 +250,8 @@ def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-
 
     With `graph` (and even `steps` and `record_every`), two restrained steps (a -> b,
     b -> a: moments, loss head, shifted step, twice) are captured once as a HIP graph
-    and replayed; the free run takes record_every steps per lbm_step call.
+    and replayed; the free run takes record_every steps per lbm_step call.  `modes`
+    selects the runs ("free", "restrained").
     """
     ny, nx = u0.shape[1:]
     grid = B.Grid("D2Q9", storage, nx, ny)
@@ -271,7 +273,9 @@ def flow_control_2d(u0: torch.Tensor, tau: float, steps: int, kappa: float = 5e-
 
     out = {"grid": [nx, ny], "tau": tau, "steps": steps, "kappa": kappa, "cutoff": cutoff, "storage": storage,
            "graph": use_graph}
-    for mode in ("free", "restrained"):
+    for mode in modes:
+        if mode not in ("free", "restrained"):
+            raise ValueError(f"unknown mode {mode!r}")
         a, b = grid.empty_populations(), grid.empty_populations()
         B.lbm_init_equilibrium(grid, None, u0, a)
         u = grid.empty_real(2)
