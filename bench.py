@@ -549,6 +549,7 @@ def profile_set(B, steps: int, warmup: int):
     from synthetic import isotropic_turbulence
     uf = isotropic_turbulence(128, 4.0, 0.04, seed=0, dim=2, device="cuda")
     n_fc = 2 * max(1, steps // 2) * 10
+    WL.flow_control_2d(uf, 0.5018, 4, kappa=5e-4, record_every=2, modes=("restrained",))  # first-use costs
     fc = WL.flow_control_2d(uf, 0.5018, n_fc, kappa=5e-4, record_every=n_fc, modes=("restrained",))
     print(json.dumps({"case": "flow control 128^2 controlled step", "graph": fc["graph"], "steps": n_fc,
                       "ms_per_step": 1e3 * fc["restrained"]["seconds"] / n_fc}), flush=True)
