@@ -77,3 +77,41 @@ def test_native_loss_head_matches_torch_head():
     assert abs(float(head.R) - float(R_t)) <= 1e-11 * float(R_t)
     assert float((out - g_t).abs().max()) <= 1e-10 * float(g_t.abs().max())
 
+
+
+def test_flow_control_step_at_workload_size():
+    """The flow-control configuration itself (D2Q9 FP32, 128^2, tau 0.5018, the paper's
+    kappa and cutoff): the native loss head's shift du = -kappa dR/du against autograd
+    through the oracle's spectrum, then lbm_step_shifted with that shift against the
+    oracle's shifted step on the whole grid."""
+    need_gpu()
+    B = binding()
+    from oracle import lbm as olbm
+    from oracle import storage as ost
+    from paper_2106_12929_amd import spectrum as SP
+    from test_gpu_forward import _tolerance_ok
+
+    n, tau, kappa, cutoff = 128, 0.5018, 5e-5, 2e-5
+    st = olbm.stencil("D2Q9")
+    grid = B.Grid("D2Q9", "f32", n, n)
+    u0 = synthetic.isotropic_turbulence(n, 4.0, 0.04, seed=0, dim=2, device="cpu").double()
+    s = ost.quantize(olbm.equilibrium(torch.ones((n, n), dtype=torch.float64), u0, st), st, "f32")
+    _, u = olbm.state_moments(ost.dequantize(s, st, "f32"), st, None)
+    u32 = u.to(torch.float32)
+    target = ospec.energy_spectrum(_field((n, n), 9))
+    kmax = n // 2
+    # oracle shift: autograd through the oracle's spectrum and cost, at the FP32 field
+    uo = u32.double().clone().requires_grad_(True)
+    ospec.log_spectrum_loss(ospec.energy_spectrum(uo), target, 1, kmax, cutoff).backward()
+    du_ref = -kappa * uo.grad
+    head = SP.NativeLossHead(SP.shell_index((n, n), "cuda"), target.cuda(), 1, kmax, cutoff)
+    du = torch.empty((2, n, n), dtype=torch.float32, device="cuda")
+    head.scaled_grad(u32.cuda(), -kappa, du)
+    du_cpu = du.cpu().double()
+    assert float((du_cpu - du_ref).abs().max()) <= 1e-6 * float(du_ref.abs().max())  # FP32 output
+    out = grid.empty_populations()
+    assert B.lbm_step_shifted(grid, grid.to_layout(s).cuda(), out, tau, du, 1) == 0
+    ref = ost.step_emulated(s, tau, st, "f32", du=du_cpu)
+    excess, ratio, same = _tolerance_ok("f32", st, grid.from_layout(out.cpu()), ref, tau)
+    say(f"flow-control step 128^2: max err / bound = {ratio:.3f}, bit-identical fraction = {same:.4f}")
+    assert excess <= 0, ratio
