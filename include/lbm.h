@@ -327,13 +327,15 @@ typedef struct {
 
 /* E[0 .. nshell) <- s^2/2 sum over each shell of sum_a |uhat_a(k)|^2, deterministic
  * (fixed summation order).  uhat: D*n complex doubles (interleaved re, im), component
- * a at uhat[a*n + k]; D in 1..3.  scale = s.  E must not overlap uhat. */
+ * a at uhat[a*n + k]; D in 1..3.  scale = s.  E must not overlap uhat or the shell
+ * table (LBM_EALIAS). */
 int lbm_shell_energy(const lbm_shells* shells, int D, const void* uhat, double scale, double* E, void* stream);
 
 /* uhat_a(k) *= scale * dR/dE_K (in place; K the shell of k): 2 (ln E_K - ln max(Et_K, c))
  * / E_K for k_lo <= K <= k_hi and E_K >= c, else 0.  E, E_target: nshell doubles.  R: one
  * double receiving R, or NULL.  0 <= k_lo <= k_hi < nshell and a finite cutoff c > 0
- * (LBM_EINVAL otherwise); uhat must not overlap E, E_target or R. */
+ * (LBM_EINVAL otherwise); uhat and R must not overlap each other, E, E_target or the
+ * shell table (LBM_EALIAS). */
 int lbm_log_spectrum_grad(const lbm_shells* shells, int D, void* uhat, const double* E, const double* E_target,
                           int k_lo, int k_hi, double cutoff, double scale, double* R, void* stream);
 

@@ -507,6 +507,12 @@ static int check_shells(const lbm_shells* sh, int D) {
   return LBM_OK;
 }
 
+// An output of the loss-head calls may not overlap the shell table it is computed with.
+static bool overlaps_table(const lbm_shells* sh, const void* p, size_t bytes) {
+  const size_t nb = (size_t)sh->n * 4, ob = ((size_t)sh->nshell + 1) * 4;
+  return overlap(p, bytes, sh->order, nb) || overlap(p, bytes, sh->offsets, ob) || overlap(p, bytes, sh->shell, nb);
+}
+
 int lbm_shell_energy(const lbm_shells* shells, int D, const void* uhat, double scale, double* E, void* stream) {
   LBM_TRY(check_shells(shells, D));
   LBM_TRY(check_ptr(uhat, "uhat", true));
@@ -514,6 +520,7 @@ int lbm_shell_energy(const lbm_shells* shells, int D, const void* uhat, double s
   if (!std::isfinite(scale)) return fail(LBM_EINVAL, "scale must be finite");
   const size_t nb = (size_t)D * (size_t)shells->n * 16;
   if (overlap(uhat, nb, E, (size_t)shells->nshell * 8)) return fail(LBM_EALIAS, "E overlaps uhat");
+  if (overlaps_table(shells, E, (size_t)shells->nshell * 8)) return fail(LBM_EALIAS, "E overlaps the shell table");
   const hipError_t e = lbm::launch_shell_energy(uhat, D, (uint32_t)shells->n, shells->order, shells->offsets,
                                                 shells->nshell, scale, E, (hipStream_t)stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_shell_energy launch");
@@ -533,6 +540,9 @@ int lbm_log_spectrum_grad(const lbm_shells* shells, int D, void* uhat, const dou
   const size_t nb = (size_t)D * (size_t)shells->n * 16, eb = (size_t)shells->nshell * 8;
   if (overlap(uhat, nb, E, eb) || overlap(uhat, nb, E_target, eb) || overlap(uhat, nb, R, 8))
     return fail(LBM_EALIAS, "uhat overlaps E, E_target or R");
+  if (overlaps_table(shells, uhat, nb) || overlaps_table(shells, R, 8))
+    return fail(LBM_EALIAS, "uhat or R overlaps the shell table");
+  if (overlap(R, 8, E, eb) || overlap(R, 8, E_target, eb)) return fail(LBM_EALIAS, "R overlaps E or E_target");
   const hipError_t e =
       lbm::launch_log_spectrum_grad(uhat, D, (uint32_t)shells->n, shells->shell, E, E_target, shells->nshell, k_lo,
                                     k_hi, cutoff, scale, R, (hipStream_t)stream);

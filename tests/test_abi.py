@@ -284,6 +284,10 @@ def test_loss_head_entry_points_validate(B):
     assert grad(sp, 2, P1, P2, None, 1, 7, 1e-5, 0.01, None, None) == -2       # E_target required
     assert grad(sp, 2, P1, P1, P3, 1, 7, 1e-5, 0.01, None, None) == -4         # E overlaps uhat
     assert grad(sp, 2, P1, P2, P3, 1, 7, 1e-5, 0.01, P1, None) == -4           # R overlaps uhat
+    assert grad(sp, 2, ctypes.c_void_p(0x30000), P2, P3, 1, 7, 1e-5, 0.01, None, None) == -4  # uhat on shell[]
+    assert grad(sp, 2, P1, P2, P3, 1, 7, 1e-5, 0.01, ctypes.c_void_p(0x20010), None) == -4    # R on offsets[]
+    assert grad(sp, 2, P1, P2, P3, 1, 7, 1e-5, 0.01, P2, None) == -4           # R overlaps E
+    assert lib.lbm_shell_energy(sp, 2, P1, 0.01, ctypes.c_void_p(0x20000), None) == -4  # E on offsets[]
     real = lib.lbm_real_part
     assert real(P1, 100, 1.0, P2, 3, None) == -1                               # F32 or F64 only
     assert real(P1, 0, 1.0, P2, 1, None) == -1
