@@ -262,20 +262,23 @@ def test_local_form_chain_matches_scatter_form_bitwise(lat, shape, kind, forced)
         assert torch.equal(dF1, dF2)
 
 
-@pytest.mark.parametrize("kind,forced,n", [("f32", False, 256), ("f16s", False, 256), ("f32", True, 256),
-                                           ("f16s", True, 256), ("f16s", True, 512)])
-def test_full_size_local_adjoint_sampled(kind, forced, n):
+@pytest.mark.parametrize("kind,forced,n,tuned", [("f32", False, 256, False), ("f16s", False, 256, False),
+                                                 ("f32", True, 256, False), ("f16s", True, 256, False),
+                                                 ("f16s", True, 512, False), ("f16s", True, 512, True)])
+def test_full_size_local_adjoint_sampled(kind, forced, n, tuned):
     """The collision-local adjoint step on the 256^3 D3Q27 grid the benchmark times (and
     at 512^3, the full-scale workload's size with an f16s state and a force), in
     its launch shape (chi input): chi_out(x) = J_C(h(x))^T lam'(x) with h(x) the gathered
     state and lam'_i(x) = chi_i(x + c_i), against the VJP of the oracle's collision at
-    4096 sampled cells and the 8 corners; with a force, also dF there."""
+    4096 sampled cells and the 8 corners; with a force, also dF there.  The tuned case
+    takes Grid.tuned's 576-word rows, as the 512^3 workload does."""
     need_gpu()
     B = binding()
     st = olbm.stencil("D3Q27")
     Q, tau = 27, 0.51
-    grid = B.Grid("D3Q27", kind, n, n, n)
-    say(f"full-size local adjoint {kind} {n}^3 forced={forced}")
+    grid = B.Grid.tuned("D3Q27", kind, n, n, n) if tuned else B.Grid("D3Q27", kind, n, n, n)
+    p = grid.row_pitch
+    say(f"full-size local adjoint {kind} {n}^3 forced={forced} pitch {p}")
     a, b = grid.empty_populations(), grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, synthetic.taylor_green_3d_on("cuda", n, n, n, 0.05), a)
     B.lbm_step(grid, a, b, tau, None, 2)  # non-equilibrium state in a
@@ -293,7 +296,7 @@ def test_full_size_local_adjoint_sampled(kind, forced, n):
     x, y, z = (cells[:, k].cuda() for k in range(3))
 
     def word(i, dx, dy, dz):  # flat index of direction i at (x + dx, y + dy, z + dz), periodic
-        return ((((z + dz) % n) * n + (y + dy) % n) * Q + i) * n + (x + dx) % n
+        return ((((z + dz) % n) * n + (y + dy) % n) * Q + i) * p + (x + dx) % n
 
     c = st.c.to(torch.int64)
     h = torch.stack([a.view(-1)[word(i, -c[i, 0], -c[i, 1], -c[i, 2])] for i in range(Q)]).cpu().double()
