@@ -20,7 +20,11 @@
  *   The rest velocity is i = Q/2 and the opposite of i is Q-1-i.  lbm_lattice_info()
  *   publishes c and w.
  *
- * Grid: nx, ny, nz >= 1 cells (nz = 1 for D2Q9), N = nx*ny*nz <= 2^31 - 1.
+ * Grid: nx, ny, nz >= 1 cells (nz = 1 for D2Q9), N = nx*ny*nz <= 2^31 - 1, and a row
+ *   below 4 GiB: pitch * r < 2^32 bytes with r = 8 for LBM_F64 and r = 4 otherwise (the
+ *   width of the grid's real type, its widest element), i.e. nx (or pitch) < 2^29
+ *   for LBM_F64 and < 2^30 for the other kinds.  The kernels address a word inside a
+ *   row by a 32-bit byte offset from the row's base.
  *   Cell (x, y, z) has linear index n = (z*ny + y)*nx + x (x fastest).
  *
  * Population buffers ("f", "g"): row-interleaved SoA.  The grid is nz*ny rows of nx
@@ -80,7 +84,8 @@ enum lbm_status {
   LBM_EALIGN = -3, /* a pointer is not 16-byte aligned */
   LBM_EALIAS = -4, /* an output buffer overlaps an input buffer it must not overlap */
   LBM_EUNSUP = -5, /* unsupported combination of arguments */
-  LBM_ERANGE = -6, /* grid too large: N > 2^31 - 1 or a dimension > 2^31 - 1 */
+  LBM_ERANGE = -6, /* grid too large: N > 2^31 - 1, a dimension > 2^31 - 1, or a row
+                      of 4 GiB or more (pitch * real bytes >= 2^32, see Grid) */
   LBM_EHIP = -7    /* a HIP runtime call failed; lbm_last_error() has the text */
 };
 
@@ -292,10 +297,17 @@ int lbm_adjoint_step_local(const lbm_grid* grid, const void* g_t, const void* ad
  * are caller-owned device buffers and must not overlap (LBM_EALIAS). */
 int lbm_adjoint_unstream(const lbm_grid* grid, const void* chi, void* lam_out, void* stream);
 
-/* Reverse-mode derivative of lbm_moments' fields: with (rho, u) = moments(g; F),
+/* Reverse-mode derivative of lbm_moments' fields (Eq. 4's moments, rho = sum_i g_i and
+ * rho u = sum_i c_i g_i - F/2; the terminal step of the automatic differentiation of
+ * Sec. 3.2, where the cost is a function of the velocity field): with
+ * (rho, u) = moments(g; F),
  *   lam_out = (drho/dg)^T dL_drho + (du/dg)^T dL_du       (overwritten, Q*N reals)
  *   dforce += (du/dF)^T dL_du = -dL_du / (2 rho)           (accumulated, may be NULL)
- * dL_drho: N reals or NULL (zero); dL_du: D*N reals or NULL (zero). */
+ * i.e. lam_out_i = dL_drho + (c_i - u).dL_du / rho per cell.
+ * dL_drho: N reals or NULL (zero); dL_du: D*N reals or NULL (zero), in the real type
+ * and SoA layout above.  g is read, lam_out written in the population layout.  lam_out
+ * and dforce must not overlap any other argument (LBM_EALIAS); dforce needs force
+ * (LBM_EUNSUP).  Errors as lbm_moments. */
 int lbm_moments_adjoint(const lbm_grid* grid, const void* g, const void* force,
                         const void* dL_drho, const void* dL_du, void* lam_out, void* dforce,
                         void* stream);

@@ -80,6 +80,12 @@ int check_grid(const lbm_grid* g, Geometry* geo) {
   geo->args.ghost = 0;
   geo->args.pitch = (uint32_t)(g->pitch ? g->pitch : g->nx);
   geo->pop = (size_t)geo->Q * geo->args.pitch * (size_t)g->ny * (size_t)g->nz;
+  // Inside a row the kernels address a lane's word as a 32-bit byte offset from the
+  // row base (populations, adjoint arrays and real fields alike), so a row of pitch
+  // words of the widest element the grid uses must stay below 4 GiB.
+  if ((uint64_t)geo->args.pitch * geo->real >= (uint64_t(1) << 32))
+    return fail(LBM_ERANGE, "a row of %u words of %zu bytes spans 4 GiB or more (row offsets are 32-bit)",
+                geo->args.pitch, geo->real);
   return LBM_OK;
 }
 

@@ -99,6 +99,23 @@ def test_grid_validation(B, dims, code):
     assert _step(B, g, P1, P2) == code
 
 
+@pytest.mark.parametrize("storage,limit", [("f64", 1 << 29), ("f32", 1 << 30), ("f32s", 1 << 30),
+                                           ("f16s", 1 << 30), ("bf16s", 1 << 30)])
+def test_row_offsets_stay_32_bit(B, storage, limit):
+    """A row (nx, or the pitch) whose byte length in the grid's widest element reaches
+    2^32 is rejected: inside a row the kernels use 32-bit byte offsets.  One word less
+    is accepted (checked through the validation-only workspace query)."""
+    lib = B._lib
+    need = ctypes.c_size_t()
+    for nx, pitch, code in ((limit - 1, 0, 0), (limit, 0, -6), (limit + 1, 0, -6),
+                            (8, limit - 1, 0), (8, limit, -6)):
+        g = _grid(B, lattice="D2Q9", storage=storage, nx=nx, ny=1, nz=1, pitch=pitch)
+        assert lib.lbm_moments_workspace_size(ctypes.byref(g), ctypes.byref(need)) == code, (nx, pitch)
+        if code:
+            assert _step(B, g, P1, P2) == code
+            assert b"4 GiB" in lib.lbm_last_error()
+
+
 def test_lattice_storage_validation(B):
     assert _step(B, _grid(B, lattice=5), P1, P2) == -1
     assert _step(B, _grid(B, storage=9), P1, P2) == -1
