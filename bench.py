@@ -9,12 +9,14 @@ n_steps = 1: pull streaming, moments, equilibrium, BGK relaxation, store).  The
 inputs are resident in HBM before the timed region; the timed region is K
 back-to-back steps bracketed by HIP events on the stream the kernels run on.
 
-Printed: one JSON line with MLUPS as `value`, the HBM roofline of the step kernel
-(algorithmic bytes 2*Q*sizeof(storage) per cell), the oracle's CPU throughput on a
-bounded sample, and in `detail` the other storage formats (FP64, shifted FP32,
-shifted FP16/BF16), the adjoint step, the moments kernel, a plain device copy for
-the practical bandwidth ceiling, and the velocity error of each format against the
-FP64 run after 1000 steps.
+Printed: one JSON line (a few KB) with MLUPS as `value`, the HBM roofline of the step
+kernel (algorithmic bytes 2*Q*sizeof(storage) per cell), the oracle's CPU throughput
+(the full 256^3 grid when host memory allows) and a flat `summary` of the other
+measurements: the other storage formats (FP64, shifted FP32, shifted FP16/BF16) with
+their error against the FP64 run after 1000 steps, D3Q19, the forced steps, the
+adjoint step, the moments kernel, a plain device copy for the practical bandwidth
+ceiling, and the workloads with the relaxation time each actually ran at.  The full
+record of every measurement goes to --detail-out (gpurun_out/bench_detail.json).
 """
 from __future__ import annotations
 
@@ -435,40 +437,68 @@ def _host_cpu() -> str:
     return "unknown"
 
 
+def _mem_available_bytes() -> int:
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return 0
+
+
+# Peak host memory of one oracle step, in multiples of the FP64 population buffer
+# (measured: about 8.8x at 128^3, torch.roll copies plus the collision's temporaries).
+ORACLE_PEAK_BUFFERS = 10
+
+
 def cpu_baseline(seconds_budget: float = 20.0, single_thread_budget: float = 4.0):
-    """The FP64 oracle (plain torch CPU ops) on a bounded sample of the same
-    workload: the D3Q27 Taylor-Green vortex at tau=0.51 on a 64^3 grid (the
-    256^3 grid's per-cell work, 1/64 of its cells), a few steps, on the host threads
-    this process may use (OMP_NUM_THREADS if set), and again on one thread."""
+    """The FP64 oracle (plain torch CPU ops) on the same workload: the D3Q27
+    Taylor-Green vortex at tau=0.51 on the full 256^3 grid when the host has memory
+    for it (else the largest of 128^3 and 64^3 that fits), for as many steps as fit
+    the time budget, on the host threads this process may use (OMP_NUM_THREADS if
+    set); and on one thread on a 64^3 sample."""
     from oracle import lbm as olbm
     import synthetic
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    n = 64
+    avail = _mem_available_bytes()
     st = olbm.stencil("D3Q27")
-    u = synthetic.taylor_green_3d(n, n, n, U0)
-    g0 = olbm.equilibrium(torch.ones(n, n, n, dtype=torch.float64), u, st)
 
-    def timed(nthreads, budget, max_steps):
+    def fits(n):
+        return ORACLE_PEAK_BUFFERS * 27 * 8 * n ** 3 < avail
+
+    n = next((m for m in (N, 128) if fits(m)), 64)
+
+    def timed(n, nthreads, budget, max_steps):
         torch.set_num_threads(nthreads)
-        g = olbm.step(g0, TAU, st)  # warm-up
+        u = synthetic.taylor_green_3d(n, n, n, U0)
+        g = olbm.equilibrium(torch.ones(n, n, n, dtype=torch.float64), u, st)
+        del u
+        g = olbm.step(g, TAU, st)  # warm-up
         steps = 0
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < budget and steps < max_steps:
+        while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < budget):
             g = olbm.step(g, TAU, st)
             steps += 1
-        return steps, time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        del g
+        return steps, dt
 
-    steps, dt = timed(threads, seconds_budget, 200)
+    steps, dt = timed(n, threads, seconds_budget, 200)
     used = torch.get_num_threads()
-    steps1, dt1 = timed(1, single_thread_budget, 50)
+    n1 = 64
+    steps1, dt1 = timed(n1, 1, single_thread_budget, 50)
     torch.set_num_threads(used)
     return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": used,
             "kind": "oracle",
-            "sample": f"FP64 torch-CPU oracle, D3Q27 TGV tau={TAU} on {n}^3 cells, {steps} steps "
-                      f"({dt:.1f} s), same per-cell work as the {N}^3 run",
-            "single_thread_value": n ** 3 * steps1 / dt1 / 1e6,
-            "host": f"{_host_cpu()}, {os.cpu_count()} logical CPUs visible"}
+            "sample": f"FP64 torch-CPU oracle, D3Q27 TGV tau={TAU} on {n}^3 cells"
+                      f"{' (the full grid)' if n == N else ''}, {steps} steps ({dt:.1f} s)",
+            "single_thread_value": n1 ** 3 * steps1 / dt1 / 1e6,
+            "single_thread_sample": f"{n1}^3 cells, {steps1} steps ({dt1:.1f} s)",
+            "host": f"{_host_cpu()}, {os.cpu_count()} logical CPUs visible, "
+                    f"{avail / 2 ** 30:.0f} GiB available"}
 
 
 def profile_set(B, steps: int, warmup: int):
@@ -567,6 +597,8 @@ def main():
                     help="skip the 384^3 precision study, the 128^3 forcing optimisation and the 512^3 adjoint run")
     ap.add_argument("--profile-set", action="store_true",
                     help="one fixed-size case per kernel (for kernel traces and HBM counters), one JSON line each")
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full measurement record ('' for none); the printed line is a summary")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy 1 GiB to another 1 GiB buffer 3 times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -641,13 +673,133 @@ def main():
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline()
 
-    line = {
+    detail_path = write_detail(detail, args.detail_out)
+    line = summary_line(head, detail, cpu, args.steps, args.warmup, measured_traffic(), detail_path)
+    print(json.dumps(line, separators=(",", ":")), flush=True)
+
+
+def write_detail(detail: dict, path: str):
+    """Every measurement of the run, in full, as a JSON file (the printed line carries a
+    summary).  Returns the path written, or None."""
+    if not path:
+        return None
+    path = path if os.path.isabs(path) else os.path.join(ROOT, path)
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(detail, fh)
+    except OSError as e:
+        log(f"[bench] could not write {path}: {e}")
+        return None
+    return os.path.relpath(path, ROOT)
+
+
+def _r(x, digits: int = 4):
+    """x rounded to `digits` significant digits (None and non-numbers unchanged)."""
+    if isinstance(x, bool) or not isinstance(x, (int, float)) or x == 0 or not math.isfinite(x):
+        return x
+    return float(f"{x:.{digits}g}")
+
+
+def _get(d, *keys):
+    for k in keys:
+        if not isinstance(d, dict) or k not in d:
+            return None
+        d = d[k]
+    return d
+
+
+def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic, detail_path) -> dict:
+    """The one JSON line bench.py prints: the headline step (value, ms, roofline), the
+    CPU baseline, and a flat summary of the other measurements (a few KB at most; the
+    full record is in the detail file)."""
+    fwd = detail.get("forward", {})
+    summ = {}
+    for k in ("f16s", "bf16s", "f32s", "f64"):
+        if k in fwd:
+            summ[f"{k}_mlups"] = _r(fwd[k]["mlups"])
+            summ[f"{k}_hbm_frac"] = _r(fwd[k]["hbm_frac"])
+    for k in ("f16s", "bf16s"):
+        if k in fwd:
+            summ[f"{k}_speedup_vs_f32"] = _r(fwd[k]["mlups"] / head["mlups"])
+    acc = _get(detail, "accuracy_vs_f64_gpu", "errors") or {}
+    for k in ("f32", "f32s", "f16s", "bf16s"):
+        if k in acc:
+            summ[f"{k}_u_rel_l2_vs_f64"] = _r(acc[k]["u_rel_l2"], 3)
+            summ[f"{k}_ke_rel_err_vs_f64"] = _r(acc[k]["ke_rel_err"], 3)
+    if acc:
+        summ["accuracy_steps"] = _get(detail, "accuracy_vs_f64_gpu", "steps")
+    for k, v in (detail.get("forward_d3q19") or {}).items():
+        summ[f"d3q19_{k}_mlups"] = _r(v["mlups"])
+    for k, v in (detail.get("forward_forced") or {}).items():
+        summ[f"forced_{k}_mlups"] = _r(v["mlups"])
+    for name, key in (("adjoint_local", "adjoint"), ("adjoint_scatter", "adjoint_scatter_form"),
+                      ("adjoint_local_forced", "adjoint_forced")):
+        for k, v in (detail.get(key) or {}).items():
+            summ[f"{name}_{k}_mlups"] = _r(v["mlups"])
+            summ[f"{name}_{k}_hbm_frac"] = _r(v["hbm_frac"])
+    d2 = detail.get("d2q9_8192") or {}
+    for k in ("bgk_f32", "bgk_f16s", "bgk_f64", "mrt_f32", "neural_relu_f32"):
+        if k in d2:
+            summ[f"d2q9_8192_{k}_mlups"] = _r(d2[k]["mlups"])
+    if "moments_f32" in detail:
+        summ["moments_f32_gbs"] = _r(detail["moments_f32"]["hbm_gbs"])
+    if "device_copy" in detail:
+        summ["copy_gbs"] = _r(detail["device_copy"]["gbs"])
+        summ["headline_frac_of_copy"] = _r(head["hbm_gbs"] / detail["device_copy"]["gbs"])
+    if "shard_512x512x64_f16s" in detail:
+        summ["shard_512x512x64_f16s_slab_mlups"] = _r(detail["shard_512x512x64_f16s"]["slab_step_sequential"]["mlups"])
+    if "tgv2d_64_f64" in detail:
+        summ["tgv2d_64_f64_graph_us_per_step"] = _r(detail["tgv2d_64_f64"]["graph_us_per_step"])
+    wl = detail.get("workloads") or {}
+    if "precision_384" in wl:
+        rows = []
+        for res in wl["precision_384"]:
+            runs = res["runs"]
+            row = {"tau": res["tau"], "f64_blew_up_at": runs["f64"]["blew_up_at"]}
+            for k in ("f32", "f16s", "bf16s"):
+                if k in runs:
+                    row[f"{k}_mlups"] = _r(runs[k]["mlups"])
+                    if "ke_rel_err_final" in runs[k]:
+                        row[f"{k}_ke_rel_err"] = _r(runs[k]["ke_rel_err_final"], 3)
+                        row[f"{k}_spectrum_err_median"] = _r(runs[k]["spectrum_rel_err_median"], 3)
+            rows.append(row)
+        summ["precision_384"] = rows
+    if "forcing_128" in wl:
+        fo = wl["forcing_128"]
+        summ["forcing_128"] = {"tau": fo["tau"], "loss_first": _r(fo["loss_first"]), "loss_last": _r(fo["loss_last"]),
+                               "ms_per_iteration": _r(1e3 * fo["seconds_per_iteration"])}
+    if "gradient_precision_128" in wl:
+        summ["gradient_cosine_vs_f64_128"] = {k: _r(1 - v["cosine_vs_f64"], 3)
+                                              for k, v in wl["gradient_precision_128"]["runs"].items()
+                                              if "cosine_vs_f64" in v}
+        summ["gradient_cosine_vs_f64_128_is"] = "1 - cosine"
+    if "flow_control_128_2d" in wl:
+        summ["flow_control_128_2d"] = [
+            {"kappa": fc["kappa"], "R_free": _r(fc["free"]["history"][-1][1], 3),
+             "R_restrained": _r(fc["restrained"]["history"][-1][1], 3)} for fc in wl["flow_control_128_2d"]]
+    if "adjoint_512" in wl:
+        rows = []
+        for res in wl["adjoint_512"]:
+            row = {"tau": res["tau"]}
+            if "diverged_before_step" in res:
+                row["f16s_diverged_before_step"] = res["diverged_before_step"]
+                row["f16s_finite_at_step"] = res.get("finite_at_step")
+                if "f64_check" in res:
+                    row["f64_blew_up_at"] = res["f64_check"]["blew_up_at"]
+            else:
+                for k in ("forward_mlups", "tail_forward_mlups", "backward_mlups", "peak_memory_gb"):
+                    row[k] = _r(res[k])
+                row["grad_finite"] = res["grad_finite"]
+            rows.append(row)
+        summ["adjoint_512"] = rows
+    return {
         "metric": METRIC,
         "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -657,13 +809,13 @@ def main():
         "config": {"workload": WORKLOAD, "lattice": "D3Q27", "grid": [N, N, N], "storage": "f32",
                    "tau": TAU, "u0": U0, "cells": N ** 3},
         "roofline": {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": head["hbm_frac"], "traffic": measured_traffic(),
-                     "kernel": "lbm::step_kernel<D3Q27, F32, unforced>",
+                     "frac": head["hbm_frac"], "traffic": traffic,
+                     "kernel": head.get("kernel", "lbm::step_kernel<D3Q27, F32, unforced>"),
                      "algorithmic_bytes_per_launch": head["bytes_per_cell"] * N ** 3},
         "cpu_baseline": cpu,
-        "detail": detail,
+        "summary": summ,
+        "detail_file": detail_path,
     }
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
