@@ -31,6 +31,9 @@ hipError_t launch_init(int lattice, int storage, const double* rho, const double
 // one partial per block of the one-thread-per-cell launch, then one per kFoldBlock of
 // those.
 uint64_t moments_workspace_entries(const GridArgs& g);
+// Entries the reducing launch for this lattice actually uses (its span depends on the
+// lattice and on whether fields are written): at most moments_workspace_entries.
+uint64_t moments_entries_used(int lattice, const GridArgs& g, bool fields);
 hipError_t launch_moments(int lattice, int storage, const void* f, const void* force, void* rho, void* u,
                           double* workspace, double* red, const GridArgs& g, hipStream_t s);
 hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, const void* lam_next, void* lam_out,

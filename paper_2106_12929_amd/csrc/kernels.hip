@@ -696,18 +696,78 @@ static dim3 cell_grid(const GridArgs& g) {
   return dim3((unsigned)(blocks_x * ((rows + rows_per_block - 1) / rows_per_block)));
 }
 
+// ---------------------------------------------------------------------------------
+// Resident-block caps.  Several kernels move more bytes per second with fewer blocks
+// resident on a CU than their register use would allow (FP64 steps 69% -> 74% of
+// 8 TB/s at two blocks instead of five, the forced collision-local adjoints 70-72% ->
+// 73-76% at three): how fast HBM serves a kernel depends on how many rows are read and
+// written at once, not only on how many loads are in flight.  The cap is a dynamic LDS
+// reservation that the kernels never touch: with 160 KB of LDS per CU, a block that
+// reserves 64, 48, 36, 30 or 24 KB leaves room for at most 2, 3, 4, 5 or 6 blocks.
+// Each table entry is the cap that measured fastest for that instantiation at its
+// benchmark size (256^3 for the 3D lattices, 8192^2 for D2Q9; caps 1-6 against none,
+// then the chosen cap against none again on a near-equilibrium state, three passes; the
+// figures quoted are those of the second measurement).  0 keeps the register-limited
+// occupancy, which won or tied everywhere else: the FP32 D3Q27 step, the 16-bit steps,
+// whose gain on zero-filled buffers (up to 4%) did not hold on a real state, and the
+// D2Q9 FP32 step, whose 1% gain on a random state turned into a 5% loss on the
+// benchmark's Taylor-Green state.
+// ---------------------------------------------------------------------------------
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t reserve_for_cap(int cap) {
+  return cap == 2 ? 64 * 1024 : cap == 3 ? 48 * 1024 : cap == 4 ? 36 * 1024 : cap == 5 ? 30 * 1024
+       : cap == 6 ? 24 * 1024 : 0;
+}
+static_assert(2 * reserve_for_cap(2) <= kLdsPerCu && 3 * reserve_for_cap(2) > kLdsPerCu, "cap 2");
+static_assert(3 * (reserve_for_cap(3) + 256) <= kLdsPerCu && 4 * reserve_for_cap(3) > kLdsPerCu, "cap 3");
+static_assert(4 * reserve_for_cap(4) <= kLdsPerCu && 5 * reserve_for_cap(4) > kLdsPerCu, "cap 4");
+static_assert(5 * reserve_for_cap(5) <= kLdsPerCu && 6 * reserve_for_cap(5) > kLdsPerCu, "cap 5");
+static_assert(6 * reserve_for_cap(6) <= kLdsPerCu && 7 * reserve_for_cap(6) > kLdsPerCu, "cap 6");
+
+template <int L, int S, int FM>
+constexpr int step_cap() {
+  if (S == kF64) return L == kD2Q9 ? 3 : 2;  // D3Q27 68.5 -> 73.4%, forced 70 -> 74.7%, D3Q19 70.2 -> 75.0%, D2Q9 72.6 -> 77.8%
+  if (L == kD3Q27 && FM == kGuoForce && S == kF32S) return 2;  // 72.4 -> 75.3%
+  return 0;
+}
+
+template <int L, int S, bool FORCED, int MODE>
+constexpr int adjoint_cap() {
+  if (L != kD3Q27) return 0;
+  if (MODE == kAdjScatter) return (S == kF32 || S == kF16S) ? 2 : 0;  // 65.4 -> 67.4%, 66.5 -> 70.1%
+  if (MODE == kAdjLocalLam) return 0;
+  if (S == kF64) return 2;  // 70.9 -> 73.8%, forced 68.1 -> 73.9%
+  return FORCED ? 3 : 0;    // forced f32 69.8 -> 72.8%, f16s 71.8 -> 75.5%, bf16s 71.8 -> 74.0%
+}
+
+template <int S, int GM>
+constexpr int mrt_cap() {
+  return (S == kF64 && GM == kGhostUniform) ? 3 : 0;  // 73.0 -> 77.7%
+}
+
+template <int L, int S, bool FORCED, bool REDUCE, uint32_t SPAN>
+constexpr int moments_cap() {
+  if (L != kD3Q27 || FORCED || SPAN != 1) return 0;
+  if (REDUCE) return S == kF32 ? 3 : 0;                         // 69.1 -> 74.2%
+  return S == kF32 ? 2 : S == kF16S ? 4 : S == kF64 ? 2 : 0;  // 70.2 -> 76.8%, 72.7 -> 77.6%, 72.0 -> 74.4%
+}
+
 template <int L, int S>
 static hipError_t launch_step_ls(const void* fin, void* fout, const void* force, int force_mode, const GridArgs& g,
                                  double omega, hipStream_t s) {
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
+  const dim3 grid = cell_grid(g);
   if (!force || force_mode == kNoForce)
-    step_kernel<L, S, kNoForce><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, nullptr, g, (R)omega);
+    step_kernel<L, S, kNoForce><<<grid, 256, reserve_for_cap(step_cap<L, S, kNoForce>()), s>>>(
+        (const W*)fin, (W*)fout, nullptr, g, (R)omega);
   else if (force_mode == kGuoForce)
-    step_kernel<L, S, kGuoForce><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, (R)omega);
+    step_kernel<L, S, kGuoForce><<<grid, 256, reserve_for_cap(step_cap<L, S, kGuoForce>()), s>>>(
+        (const W*)fin, (W*)fout, (const R*)force, g, (R)omega);
   else if (force_mode == kShiftForce)
-    step_kernel<L, S, kShiftForce><<<cell_grid(g), 256, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, (R)omega);
+    step_kernel<L, S, kShiftForce><<<grid, 256, reserve_for_cap(step_cap<L, S, kShiftForce>()), s>>>(
+        (const W*)fin, (W*)fout, (const R*)force, g, (R)omega);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -725,7 +785,10 @@ static hipError_t launch_mrt_s(const void* fin, void* fout, const void* ghost, i
   W* b = (W*)fout;
   const R* gh = (const R*)ghost;
   switch (ghost_mode) {
-    case kGhostUniform: mrt_step_kernel<S, kGhostUniform><<<cell_grid(g), 256, 0, s>>>(a, b, nullptr, g, sc); break;
+    case kGhostUniform:
+      mrt_step_kernel<S, kGhostUniform><<<cell_grid(g), 256, reserve_for_cap(mrt_cap<S, kGhostUniform>()), s>>>(
+          a, b, nullptr, g, sc);
+      break;
     case kGhostField: mrt_step_kernel<S, kGhostField><<<cell_grid(g), 256, 0, s>>>(a, b, gh, g, sc); break;
     case kGhostRelu: mrt_step_kernel<S, kGhostRelu><<<cell_grid(g), 256, 0, s>>>(a, b, gh, g, sc); break;
     case kGhostTanh: mrt_step_kernel<S, kGhostTanh><<<cell_grid(g), 256, 0, s>>>(a, b, gh, g, sc); break;
@@ -753,11 +816,11 @@ static hipError_t launch_adjoint_lsm(const void* gt, const void* lam_next, void*
   using W = typename ST::word;
   using R = typename ST::real;
   if (force)
-    adjoint_kernel<L, S, true, MODE><<<cell_grid(g), 256, 0, s>>>((const W*)gt, (const R*)lam_next, (R*)lam_out,
-                                                                   (const R*)force, (R*)dforce, g, (R)omega);
+    adjoint_kernel<L, S, true, MODE><<<cell_grid(g), 256, reserve_for_cap(adjoint_cap<L, S, true, MODE>()), s>>>(
+        (const W*)gt, (const R*)lam_next, (R*)lam_out, (const R*)force, (R*)dforce, g, (R)omega);
   else
-    adjoint_kernel<L, S, false, MODE><<<cell_grid(g), 256, 0, s>>>((const W*)gt, (const R*)lam_next, (R*)lam_out,
-                                                                    nullptr, nullptr, g, (R)omega);
+    adjoint_kernel<L, S, false, MODE><<<cell_grid(g), 256, reserve_for_cap(adjoint_cap<L, S, false, MODE>()), s>>>(
+        (const W*)gt, (const R*)lam_next, (R*)lam_out, nullptr, nullptr, g, (R)omega);
   return hipGetLastError();
 }
 
@@ -782,11 +845,18 @@ static hipError_t launch_init_ls(const double* rho, const double* u, void* fout,
 // Blocks of a moments launch whose blocks walk `span` blocks of cells each.
 static uint64_t moments_blocks(const GridArgs& g, uint32_t span) { return (cell_grid(g).x + span - 1) / span; }
 
+// Span of a reducing moments launch, measured: the fold costs about 150 VALU
+// instructions per wave.  With fields stored, the 3D lattices are fastest at one cell per
+// thread and D2Q9 (fewer loads per cell to hide the fold behind) at 4; with the
+// reductions alone, at 16.
+static uint32_t moments_span(int D, bool fields) { return fields ? (D == 2 ? 4 : 1) : 16; }
+
 template <int L, int S, bool FORCED, uint32_t SPAN>
 static void launch_moments_span(const typename Storage<S>::word* f, const typename Storage<S>::real* force,
                                 typename Storage<S>::real* rho, typename Storage<S>::real* u, double* partials,
                                 const GridArgs& g, hipStream_t s) {
-  moments_kernel<L, S, FORCED, true, SPAN><<<(unsigned)moments_blocks(g, SPAN), 256, 0, s>>>(f, force, rho, u,
+  moments_kernel<L, S, FORCED, true, SPAN><<<(unsigned)moments_blocks(g, SPAN), 256,
+                                             reserve_for_cap(moments_cap<L, S, FORCED, true, SPAN>()), s>>>(f, force, rho, u,
                                                                                              partials, g);
 }
 
@@ -800,15 +870,14 @@ static hipError_t launch_moments_ls(const void* f, const void* force, void* rho,
   const R* fr = (const R*)force;
   if (!red) {
     if (force)
-      moments_kernel<L, S, true, false, 1><<<cell_grid(g), 256, 0, s>>>(fw, fr, (R*)rho, (R*)u, nullptr, g);
+      moments_kernel<L, S, true, false, 1><<<cell_grid(g), 256, reserve_for_cap(moments_cap<L, S, true, false, 1>()),
+                                             s>>>(fw, fr, (R*)rho, (R*)u, nullptr, g);
     else
-      moments_kernel<L, S, false, false, 1><<<cell_grid(g), 256, 0, s>>>(fw, nullptr, (R*)rho, (R*)u, nullptr, g);
+      moments_kernel<L, S, false, false, 1><<<cell_grid(g), 256, reserve_for_cap(moments_cap<L, S, false, false, 1>()),
+                                              s>>>(fw, nullptr, (R*)rho, (R*)u, nullptr, g);
     return hipGetLastError();
   }
-  // Span per launch, measured: the fold costs about 150 VALU instructions per wave.  With
-  // fields stored, the 3D lattices are fastest at one cell per thread and D2Q9 (fewer
-  // loads per cell to hide the fold behind) at 4; with the reductions alone, at 16.
-  const uint32_t span = (rho || u) ? (Lattice<L>::D == 2 ? 4 : 1) : 16;
+  const uint32_t span = moments_span(Lattice<L>::D, rho || u);
   const uint64_t p1 = moments_blocks(g, span);
   const uint64_t p2 = (p1 + kFoldBlock - 1) / kFoldBlock;
   double* part1 = workspace;
@@ -880,6 +949,11 @@ hipError_t launch_init(int lattice, int storage, const double* rho, const double
 
 uint64_t moments_workspace_entries(const GridArgs& g) {
   const uint64_t p1 = moments_blocks(g, 1);  // the most partials of any span
+  return p1 + (p1 + kFoldBlock - 1) / kFoldBlock;
+}
+
+uint64_t moments_entries_used(int lattice, const GridArgs& g, bool fields) {
+  const uint64_t p1 = moments_blocks(g, moments_span(lattice == kD2Q9 ? 2 : 3, fields));
   return p1 + (p1 + kFoldBlock - 1) / kFoldBlock;
 }
 
