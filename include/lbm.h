@@ -267,6 +267,25 @@ int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rh
                 void* u_out, double* red, void* workspace, size_t workspace_bytes,
                 void* stream);
 
+/* lbm_moments without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as lbm_moments with the workspace
+ * left out: the fields and the reductions are bitwise those of lbm_moments on the same
+ * inputs.  The reduction partials go to a fixed 8 MiB device array inside the library
+ * (131072 partials of LBM_NRED doubles), one per GPU, set up on the first call on that
+ * GPU and held until the process ends; the call allocates nothing and frees nothing.
+ * Grids whose reduction needs more partials than that return LBM_ERANGE (use
+ * lbm_moments): with red != NULL, the partials are one per 256 cells (3D lattices
+ * writing rho_out or u_out: up to about 33.5 million cells), per 1024 cells (D2Q9
+ * writing fields: about 134 million) or per 4096 cells (no field written: about 536
+ * million), plus one per 2048 partials.  Every call on a GPU shares that GPU's array and
+ * overwrites what it needs before reading it (nothing has to start at zero), so calls
+ * that overlap on one GPU (on different streams without ordering, or from several
+ * threads) race and give wrong reductions.  The first call on a GPU may return LBM_EHIP
+ * if the array's address cannot be obtained. */
+int lbm_moments_noalloc(const lbm_grid* grid, const void* g, const void* force, void* rho_out, void* u_out,
+                        double* red, void* stream);
+
 /* Reverse-mode derivative of one lbm_step (hand-written adjoint; the paper obtains the
  * same quantity by automatic differentiation, Sec. 3.2).  With g' = C(S g_t; F):
  *   lam_out = (dg'/dg_t)^T lam_next          (overwritten, Q*N reals)

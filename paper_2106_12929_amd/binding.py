@@ -69,6 +69,7 @@ def _load() -> ctypes.CDLL:
         "lbm_stream_only": (i32, [gp, vp, vp, vp]),
         "lbm_moments_workspace_size": (i32, [gp, ctypes.POINTER(sz)]),
         "lbm_moments": (i32, [gp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lbm_moments_noalloc": (i32, [gp, vp, vp, vp, vp, vp, vp]),
         "lbm_adjoint_step": (i32, [gp, vp, vp, vp, dbl, vp, vp, vp]),
         "lbm_moments_adjoint": (i32, [gp, vp, vp, vp, vp, vp, vp, vp]),
         "lbm_adjoint_step_local": (i32, [gp, vp, vp, i32, vp, dbl, vp, vp, vp]),
@@ -393,6 +394,21 @@ def lbm_moments(grid: Grid, f: torch.Tensor, force: torch.Tensor | None = None,
             _dev_ptr(red, "red", torch.float64, NRED, required=False))
     _check(_lib.lbm_moments(ctypes.byref(g), *args, ws_ptr, ctypes.c_size_t(ws_bytes), _stream(stream)),
            "lbm_moments")
+
+
+def lbm_moments_noalloc(grid: Grid, f: torch.Tensor, force: torch.Tensor | None = None,
+                        rho_out: torch.Tensor | None = None, u_out: torch.Tensor | None = None,
+                        red: torch.Tensor | None = None, stream=None) -> None:
+    """lbm_moments with the reduction partials in the library's fixed device scratch
+    (no workspace, no allocation; calls on one GPU must not overlap)."""
+    N = grid.ncells
+    g = grid.c_struct()
+    args = (_dev_ptr(f, "f", grid.word_dtype, grid.pop_size),
+            _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False),
+            _dev_ptr(rho_out, "rho_out", grid.real_dtype, N, required=False),
+            _dev_ptr(u_out, "u_out", grid.real_dtype, grid.D * N, required=False),
+            _dev_ptr(red, "red", torch.float64, NRED, required=False))
+    _check(_lib.lbm_moments_noalloc(ctypes.byref(g), *args, _stream(stream)), "lbm_moments_noalloc")
 
 
 def lbm_adjoint_step(grid: Grid, g_t: torch.Tensor, lam_next: torch.Tensor, lam_out: torch.Tensor, tau: float,

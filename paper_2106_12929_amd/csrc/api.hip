@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "kernels.h"
 #include "lattice.h"
@@ -417,6 +418,80 @@ int lbm_moments(const lbm_grid* grid, const void* g, const void* force, void* rh
   const hipError_t e = lbm::launch_moments(grid->lattice, grid->storage, g, force, rho_out, u_out,
                                            red ? (double*)workspace : nullptr, red, geo.args, (hipStream_t)stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments launch");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Fixed device scratch of lbm_moments_noalloc: the reduction partials live in this
+// file-scope array (one copy per GPU, kept until the process ends) instead of a caller
+// workspace.  In host code `scratch` only names the symbol; its device address on the
+// current GPU comes from hipGetSymbolAddress, looked up once per device on the first
+// call there and kept in g_scratch_dev.
+// ---------------------------------------------------------------------------------
+static constexpr uint64_t kScratchEntries = 131072;  // kNred doubles each: 8 MiB
+static __device__ __align__(256) double scratch[kScratchEntries * lbm::kNred];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_on_current_device(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EUNSUP, "device ordinal %d beyond %d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_dev[dev]);
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_moments_noalloc(const lbm_grid* grid, const void* g, const void* force, void* rho_out, void* u_out,
+                        double* red, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_ptr(g, "g", true));
+  LBM_TRY(check_ptr(force, "force", false));
+  LBM_TRY(check_ptr(rho_out, "rho_out", false));
+  LBM_TRY(check_ptr(u_out, "u_out", false));
+  LBM_TRY(check_ptr(red, "red", false));
+  const bool fields = rho_out || u_out;
+  const uint64_t need = red ? lbm::moments_entries_used(grid->lattice, geo.args, fields) : 0;
+  if (need > kScratchEntries)
+    return fail(LBM_ERANGE, "the reduction needs %llu partials, the fixed scratch holds %llu (use lbm_moments)",
+                (unsigned long long)need, (unsigned long long)kScratchEntries);
+  const size_t N = geo.args.ncells;
+  const size_t fbytes = geo.pop * geo.word;
+  const size_t rbytes = N * geo.real, ubytes = geo.D * N * geo.real;
+  const void* ins[2] = {g, force};
+  const size_t insz[2] = {fbytes, geo.D * N * geo.real};
+  void* outs[3] = {rho_out, u_out, red};
+  const size_t outsz[3] = {rbytes, ubytes, lbm::kNred * sizeof(double)};
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 2; ++b)
+      if (overlap(outs[a], outsz[a], ins[b], insz[b]))
+        return fail(LBM_EALIAS, "an output of lbm_moments_noalloc overlaps an input");
+    for (int b = a + 1; b < 3; ++b)
+      if (overlap(outs[a], outsz[a], outs[b], outsz[b]))
+        return fail(LBM_EALIAS, "two outputs of lbm_moments_noalloc overlap");
+  }
+  double* ws = nullptr;
+  if (red) LBM_TRY(scratch_on_current_device(&ws));
+  const hipError_t e = lbm::launch_moments(grid->lattice, grid->storage, g, force, rho_out, u_out, ws, red, geo.args,
+                                           (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments_noalloc launch");
 }
 
 }  // extern "C"

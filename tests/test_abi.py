@@ -311,3 +311,19 @@ def test_loss_head_entry_points_validate(B):
     assert real(None, 100, 1.0, P2, 1, None) == -2
     assert real(P1, 100, 1.0, ctypes.c_void_p(0x10000 + 800), 1, None) == -4   # out inside z
     assert real(P1, 100, float("nan"), P2, 1, None) == -1
+
+
+def test_moments_noalloc_validation(B):
+    """lbm_moments_noalloc validates like lbm_moments, and rejects on the host a
+    reduction whose partials would not fit the library's fixed scratch (a 512^3 D3Q27
+    grid writing fields needs one partial per 256 cells: 524,544 > 131,072).  Only
+    calls that fail before the first HIP call are made here."""
+    lib = B._lib
+    gp = ctypes.byref(_grid(B, nx=512, ny=512, nz=512))
+    red = ctypes.c_void_p(0x100000)
+    assert lib.lbm_moments_noalloc(gp, None, None, None, None, red, None) == -2            # g required
+    assert lib.lbm_moments_noalloc(gp, MIS, None, None, None, red, None) == -3
+    assert lib.lbm_moments_noalloc(gp, P1, None, P1, None, None, None) == -4              # rho_out overlaps g
+    assert lib.lbm_moments_noalloc(gp, P1, None, P2, None, red, None) == -6               # scratch too small
+    assert b"fixed scratch" in lib.lbm_last_error()
+    assert lib.lbm_moments_noalloc(None, P1, None, None, None, red, None) == -2
