@@ -10,6 +10,8 @@
   with a learnable force field in place of the velocity shift).
 * `full_scale_adjoint`: a long FP16-shifted forward run at full HBM scale, then the
   checkpointed adjoint over its last steps; reports throughput and peak memory.
+* `stability_study`: where and when a long forward run first speeds up beyond a
+  threshold, per storage format (attribution of a BGK blow-up).
 * `flow_control_2d`: the paper's own flow control (Sec. 3.2): every step the
   equilibrium is taken at u + du with du = -kappa grad_u R(u), R the log-spectrum
   deviation from the initial spectrum with cut-off c; a free run alongside.
@@ -137,6 +139,56 @@ def forcing_optimisation(u0: torch.Tensor, tau: float, steps: int = 100, checkpo
             "loss_curve": losses, "seconds_per_iteration": per_iter_s,
             "forward_plus_backward_mlups": n ** 3 * steps / per_iter_s / 1e6,
             "max_abs_force": float(F.detach().abs().max())}
+
+
+def stability_study(u0: torch.Tensor, tau: float, storage: str, steps: int, check_every: int = 25,
+                    pitch: int | None = None, threshold: float = 0.2):
+    """A forward run that records, every `check_every` steps, the kinetic energy, the
+    largest speed and the cell where it occurs, with that cell's row offset in bytes in
+    the population buffer; and the first check at which the largest speed passes
+    `threshold`.  It tells a blow-up caused by the storage format from one tied to the
+    addressing (row ends, high planes, words beyond 4 GiB of the buffer).  Rows take
+    Grid.tuned's pitch unless `pitch` is given; the run stops at non-finite cells."""
+    n = u0.shape[-1]
+    grid = (B.Grid.tuned("D3Q27", storage, n, n, n) if pitch is None
+            else B.Grid("D3Q27", storage, n, n, n, pitch))
+    a, b = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u0, a)
+    word = a.element_size()
+    hist, first_over = [], None
+    done, t_run = 0, 0.0
+    u = grid.empty_real(3)
+    while done < steps:
+        k = min(check_every, steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if B.lbm_step(grid, a, b, tau, None, k) == 0:
+            a, b = b, a
+        t_run += _sync_time(t0)
+        done += k
+        red = torch.zeros(B.NRED, dtype=torch.float64, device=u0.device)
+        ws = torch.empty(B.lbm_moments_workspace_size(grid), dtype=torch.uint8, device=u0.device)
+        B.lbm_moments(grid, a, None, None, u, red, ws)
+        red = dict(zip(B.RED_NAMES, red.cpu().tolist()))
+        speed2 = (u.double() ** 2).sum(dim=0)
+        flat = int(torch.argmax(speed2))
+        z, y, x = flat // (n * n), (flat // n) % n, flat % n
+        row_bytes = ((z * n + y) * grid.Q) * grid.row_pitch * word
+        rec = [done, red["kinetic_energy"], red["max_speed"], x, y, z, row_bytes]
+        hist.append(rec)
+        del speed2
+        if first_over is None and red["max_speed"] > threshold:
+            first_over = {"step": done, "max_speed": red["max_speed"], "cell_xyz": [x, y, z],
+                          "row_byte_offset": row_bytes, "beyond_4GiB": row_bytes >= 1 << 32}
+        if red["nonfinite_cells"] > 0:
+            break
+    out = {"grid": [n, n, n], "storage": storage, "tau": tau, "row_pitch": grid.row_pitch, "steps": done,
+           "mlups": n ** 3 * done / t_run / 1e6, "buffer_bytes": a.numel() * word,
+           "history_step_ke_maxspeed_xyz_rowbytes": hist, "first_over_threshold": first_over,
+           "threshold": threshold}
+    del a, b, u
+    torch.cuda.empty_cache()
+    return out
 
 
 def full_scale_adjoint(u0: torch.Tensor, tau: float, forward_steps: int = 500, adjoint_steps: int = 50,

@@ -59,6 +59,10 @@ def _fake_detail():
                                                    for k in ("f32", "f16s", "bf16s")}}},
             "flow_control_128_2d": [{"kappa": k, "free": {"history": hist}, "restrained": {"history": hist}}
                                     for k in (5e-5, 5e-4, 5e-3)],
+            "stability_512": [{"storage": k, "steps": 500, "first_over_threshold": {"step": 350},
+                               "history_step_ke_maxspeed_xyz_rowbytes": [[t, v(), v(), 1, 2, 3, 4]
+                                                                         for t in range(25, 501, 25)]}
+                              for k in ("f16s", "bf16s", "f32s")],
             "adjoint_512": [{"tau": 0.505, "diverged_before_step": 500, "finite_at_step": 450,
                              "f64_check": {"blew_up_at": None}},
                             {"tau": 0.51, "forward_mlups": v(), "tail_forward_mlups": v(), "backward_mlups": v(),
