@@ -531,6 +531,27 @@ def profile_set(B, steps: int, warmup: int):
     r = run_forward(B, "f32", steps, warmup, u3, mode="guo")
     report(f"step D3Q27 f32 {N}^3, Guo force", "step_kernel<D3Q27, F32, Guo>", B.Grid("D3Q27", "f32", N, N, N),
            r["ms_per_step"], r["bytes_per_cell"])
+    # the 512^3 FP16-shifted step of the full-scale workload, on Grid.tuned's rows and
+    # on dense rows (the same kernel instantiation as the 256^3 f16s case: the trace
+    # tells the launches apart by their order)
+    from synthetic import taylor_green_3d_on
+    n5 = 512
+    u5 = taylor_green_3d_on("cuda", n5, n5, n5, U0)
+    for layout in ("tuned", "dense"):
+        g5 = B.Grid.tuned("D3Q27", "f16s", n5, n5, n5) if layout == "tuned" else B.Grid("D3Q27", "f16s", n5, n5, n5)
+        bufs = [g5.empty_populations(), g5.empty_populations()]
+        B.lbm_init_equilibrium(g5, None, u5, bufs[0])
+        cur = [0]
+
+        def one5():
+            B.lbm_step(g5, bufs[cur[0]], bufs[1 - cur[0]], TAU, None, 1)
+            cur[0] ^= 1
+
+        report(f"step D3Q27 f16s {n5}^3, {layout} rows (pitch {g5.row_pitch})", "step_kernel<D3Q27, F16S, unforced>",
+               g5, time_launches(one5, steps, warmup), B.bytes_per_cell_step(g5))
+        del bufs
+        torch.cuda.empty_cache()
+    del u5
     r = run_adjoint(B, "f32", steps, warmup, u3)
     report(f"adjoint (collision-local, chi input) D3Q27 f32 {N}^3", "adjoint_kernel<D3Q27, F32, unforced, local chi>",
            B.Grid("D3Q27", "f32", N, N, N), r["ms_per_step"], r["bytes_per_cell"])
