@@ -62,3 +62,34 @@ def test_noalloc_moments_equal_workspace_moments(seq):
                 continue
             assert torch.equal(bits(a), bits(b)), (name, lat, kind, shape)
         assert torch.isfinite(got[2]).all() and float(got[2][5]) == 0.0
+
+
+@pytest.mark.gpu
+def test_noalloc_moments_replayed_in_a_graph():
+    """The use the entry point exists for: captured once in a HIP graph (no allocation
+    inside the capture), replayed several times with eager work and synchronisations in
+    between (the state changes between replays); every replay equals an eager
+    lbm_moments call on the same state, bit for bit."""
+    need_gpu()
+    B = binding()
+    say("lbm_moments_noalloc under graph capture, D3Q27 f32 (40, 24, 20), 3 replays")
+    grid, g, _ = _inputs(B, "D3Q27", "f32", (40, 24, 20), False, 90)
+    rho, u = grid.empty_real(0), grid.empty_real(3)
+    red = torch.zeros(B.NRED, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.lbm_moments_noalloc(grid, g, None, rho, u, red)  # first call on the device: symbol lookup
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            B.lbm_moments_noalloc(grid, g, None, rho, u, red)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.mul_(1.0 + 1e-3 * (k + 1))  # eager work on the captured input
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        ref = _moments(B, grid, g, None, True, noalloc=False)
+        for name, a, b in zip(("rho", "u", "red"), (rho.cpu(), u.cpu(), red.cpu()), ref):
+            assert torch.equal(bits(a), bits(b)), (name, k)
