@@ -222,10 +222,21 @@ int step_common(const lbm_grid* grid, void* f_in, void* f_out, double tau, const
   if (overlap(field, vbytes, f_in, fbytes) || overlap(field, vbytes, f_out, fbytes))
     return fail(LBM_EALIAS, "the per-cell field overlaps a population buffer");
   const double omega = 1.0 / tau;
+  const int mode = field ? force_mode : lbm::kNoForce;
+  // Pairs of steps run as one launch where the kernel supports the grid.  An even
+  // number of such launches leaves the result where n_steps single steps leave it, so
+  // up to three steps run singly (first).
+  const int pairs = lbm::step2_supported(grid->lattice, grid->storage, geo.args) ? 2 * (n_steps / 4) : 0;
   void* bufs[2] = {f_in, f_out};
-  for (int k = 0; k < n_steps; ++k) {
-    const hipError_t e = lbm::launch_step(grid->lattice, grid->storage, bufs[k & 1], bufs[(k + 1) & 1], field,
-                                          field ? force_mode : lbm::kNoForce, geo.args, omega, (hipStream_t)stream);
+  int cur = 0;
+  for (int k = 0; k < n_steps - 2 * pairs; ++k, cur ^= 1) {
+    const hipError_t e = lbm::launch_step(grid->lattice, grid->storage, bufs[cur], bufs[cur ^ 1], field, mode,
+                                          geo.args, omega, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, name);
+  }
+  for (int k = 0; k < pairs; ++k, cur ^= 1) {
+    const hipError_t e = lbm::launch_step2(grid->lattice, grid->storage, bufs[cur], bufs[cur ^ 1], field, mode,
+                                           geo.args, omega, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, name);
   }
   return (n_steps & 1) ? 0 : 1;

@@ -165,9 +165,16 @@ __device__ __forceinline__ uint32_t cell_index(const GridArgs& g, const Cell& c)
 //   kGuoForce    body force F (Guo: u = (sum c h + F/2)/rho in f^eq, plus the source)
 //   kShiftForce  velocity shift du: f^eq(rho, u + du) with u = sum c h / rho (the
 //                flow-control forcing of Sec. 3.2)
+//
+// Products are fused into multiply-adds only within one expression (contract "on",
+// not the default "fast", which lets the compiler fuse across statements depending on
+// the code around the call): every kernel that inlines the collision then rounds
+// identically, which the two-step kernel needs to reproduce two launches of the
+// one-step kernel bit for bit.
 // ---------------------------------------------------------------------------------
 template <int L, typename real, int FM>
 __device__ __forceinline__ void bgk_collide(real (&d)[Lattice<L>::Q], real Fx, real Fy, real Fz, real omega) {
+#pragma clang fp contract(on)
   using LT = Lattice<L>;
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;

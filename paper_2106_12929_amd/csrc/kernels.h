@@ -24,6 +24,21 @@ struct GridArgs {
 
 hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
                        const GridArgs& g, double omega, hipStream_t s);
+
+// Launch geometry of the two-step kernel (step2_kernel).
+struct Step2Args {
+  uint32_t tiles_x, tiles_y;  // tiles of the grid's (x, y) columns
+  uint32_t lz;                // planes per z chunk (the last chunk may be shorter)
+  uint32_t row_bytes;         // one direction row: pitch words
+  uint32_t yrow_bytes;        // the Q direction rows of one grid row
+  uint32_t plane_bytes;       // the ny grid rows of one z plane (< 2^32)
+};
+// Whether two steps of this lattice, storage kind and grid can run in one launch
+// (launch_step2); when they can, launch_step2(fin -> fout) equals launch_step twice
+// (fin -> tmp -> fout) bit for bit.
+bool step2_supported(int lattice, int storage, const GridArgs& g);
+hipError_t launch_step2(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
+                        const GridArgs& g, double omega, hipStream_t s);
 hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s);
 hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
                        hipStream_t s);

@@ -22,6 +22,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <type_traits>
+
 #include "device.h"
 #include "kernels.h"
 #include "lattice.h"
@@ -80,6 +83,198 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWave
 #pragma unroll
   for (int i = 0; i < Q; ++i)
     store_stream(at_byte(fout + dir_row<Q>(g, c.y, c.z + g.ghost, i), xo), ST::from_dev(d[i], CO::W(i)));
+}
+
+// ---------------------------------------------------------------------------------
+// Two time steps per launch for the 3D lattices (Eqs. 1-4 applied twice), with the
+// intermediate populations kept in LDS: each word of the state is read from HBM once
+// and written once per two steps, where two launches of step_kernel move it twice.
+//
+// A block owns a TX x TY tile of (x, y) columns and a chunk of z planes [zb, ze), and
+// marches along z.  Per plane p it computes step t+1 on the tile plus a one-cell ring
+// ((TX+2) x (TY+2) columns, gathered from HBM) and puts the rounded storage words into
+// LDS; step t+2 of plane p-1 then gathers its Q populations from the LDS copies of
+// planes p-2, p-1 and p.  Step t+1 of the ring columns is also computed by the
+// neighbouring tiles: the price of keeping the tiles independent.
+//
+// The waves are specialised.  NP producer waves (one ring column per lane) load,
+// collide and write plane k into LDS slot k & 1 while the NC consumer waves (one output
+// cell per lane) read plane k-1 from the other slot and complete step t+2; one barrier
+// per plane separates the two slots' uses.  A consumer keeps the populations of the
+// two planes above its current output that it has already read (9 and 18 values): a
+// plane contributes the c_z = -1 directions to the output plane below it, c_z = 0 to
+// its own plane and c_z = +1 to the plane above.  The producers load plane k+1 while
+// they collide plane k.
+//
+// Each collision is bgk_collide on the words the one-step kernel would have read, and
+// the intermediate words are rounded to storage exactly as its stores are, so the
+// result equals two launches of step_kernel bit for bit.
+//
+// Tiles are 32 x 8 cells for 4-byte words (a direction row of a tile is one 128-byte
+// line).  Consecutive tiles of a chunk go to the same XCD (blocks are dealt to the 8
+// XCDs in turn), so the ring rows and columns a block shares with its neighbours are
+// mostly served by that XCD's L2: 1.39x of the state's bytes are fetched from memory
+// at 256^3 against 2x for two single steps.
+// ---------------------------------------------------------------------------------
+template <int L, int S>
+struct Step2Shape {
+  static constexpr int TX = 32, TY = 8;
+  static constexpr int NSX = TX + 2, NS = NSX * (TY + 2);  // ring-tile columns
+  static constexpr int NP = (NS + 63) / 64;                 // producer waves
+  static constexpr int NC = TX * TY / 64;                   // consumer waves
+  static constexpr int NT = 64 * (NP + NC);
+};
+
+template <int L, int S, int FM>
+__global__ __launch_bounds__((Step2Shape<L, S>::NT)) __attribute__((amdgpu_waves_per_eu(5))) void step2_kernel(
+    const typename Storage<S>::word* __restrict__ fin, typename Storage<S>::word* __restrict__ fout,
+    const typename Storage<S>::real* __restrict__ force, GridArgs g, Step2Args a, typename Storage<S>::real omega) {
+  using LT = Lattice<L>;
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using real = typename ST::real;
+  using CO = Coef<L, real>;
+  using SH = Step2Shape<L, S>;
+  constexpr int Q = LT::Q;
+  constexpr int TX = SH::TX, NSX = SH::NSX, NS = SH::NS, NP = SH::NP;
+  __shared__ W slot[2][Q][NS];
+
+  // XCD-aware block order: blocks b, b + 8, b + 16, ... run on one XCD and take
+  // consecutive tiles (a bijection of [0, nb) for any nb).
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t per = nb / 8, extra = nb % 8, xcd = b % 8, pos = b / 8;
+  const uint32_t lin = xcd < extra ? xcd * (per + 1) + pos : extra * (per + 1) + (xcd - extra) * per + pos;
+  const uint32_t tx = lin % a.tiles_x, ty = (lin / a.tiles_x) % a.tiles_y, zc = lin / (a.tiles_x * a.tiles_y);
+  const uint32_t x0 = tx * TX, y0 = ty * SH::TY;
+  const uint32_t zb = zc * a.lz;
+  const uint32_t ze = min(zb + a.lz, g.nz);
+  const uint32_t nplanes = ze - zb + 2;  // step t+1 on planes zb-1 .. ze
+  const uint32_t t = threadIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(t / 64);
+  const char* fb = reinterpret_cast<const char*>(fin);
+  char* ob = reinterpret_cast<char*>(fout);
+  const uint32_t plane_cells = g.nx * g.ny;
+  // planes zb-2 .. ze+2 wrapped (nz >= 3)
+  auto wrapz = [&](int z) -> uint32_t {
+    return (uint32_t)(z < 0 ? z + (int)g.nz : (z >= (int)g.nz ? z - (int)g.nz : z));
+  };
+  auto load_force = [&](uint32_t z, uint32_t col, real& Fx, real& Fy, real& Fz) {
+    if constexpr (FM != kNoForce) {
+      const real* f = force + (uint64_t)z * plane_cells + col;
+      Fx = f[0];
+      Fy = f[g.ncells];
+      Fz = f[2 * g.ncells];
+    }
+  };
+
+  if (wave < (uint32_t)NP) {
+    // Producer lane: ring column s (clamped lanes past the ring compute column NS - 1
+    // again and write nothing).
+    const bool live = t < (uint32_t)NS;
+    const uint32_t s = min(t, (uint32_t)NS - 1);
+    int xi = (int)x0 - 1 + (int)(s % NSX);
+    int yi = (int)y0 - 1 + (int)(s / NSX);
+    xi += xi < 0 ? (int)g.nx : (xi >= (int)g.nx ? -(int)g.nx : 0);
+    yi += yi < 0 ? (int)g.ny : (yi >= (int)g.ny ? -(int)g.ny : 0);
+    const uint32_t x = xi, y = yi, col = y * g.nx + x;
+    // byte offsets inside a plane of the three source columns and rows (index c + 1
+    // holds x - c, y - c)
+    const uint32_t xb[3] = {wrap_inc(x, g.nx) * (uint32_t)sizeof(W), x * (uint32_t)sizeof(W),
+                            wrap_dec(x, g.nx) * (uint32_t)sizeof(W)};
+    const uint32_t yb[3] = {wrap_inc(y, g.ny) * a.yrow_bytes, y * a.yrow_bytes, wrap_dec(y, g.ny) * a.yrow_bytes};
+    auto load = [&](int pz, W (&r)[Q]) {
+      const char* base[3] = {fb + (uint64_t)wrapz(pz + 1) * a.plane_bytes, fb + (uint64_t)wrapz(pz) * a.plane_bytes,
+                             fb + (uint64_t)wrapz(pz - 1) * a.plane_bytes};
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        r[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * a.row_bytes +
+                                           (yb[LT::cy(i) + 1] + xb[LT::cx(i) + 1]));
+    };
+    auto produce = [&](int pz, W (&r)[Q], auto sl) {
+      constexpr int SL = decltype(sl)::value;
+      real d[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
+      real Fx = 0, Fy = 0, Fz = 0;
+      load_force(wrapz(pz), col, Fx, Fy, Fz);
+      bgk_collide<L, real, FM>(d, Fx, Fy, Fz, omega);
+      if (live) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) slot[SL][i][s] = ST::from_dev(d[i], CO::W(i));
+      }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    W r0[Q], r1[Q];
+    load((int)zb - 1, r0);
+    uint32_t k = 0;
+    for (; k + 1 < nplanes; k += 2) {  // plane zb-1+k into slot 0, the next into slot 1
+      load((int)(zb + k), r1);
+      produce((int)(zb + k) - 1, r0, I0());
+      __syncthreads();
+      load((int)(zb + k) + 1, r0);  // one plane past ze on the last pass: read, unused
+      produce((int)(zb + k), r1, I1());
+      __syncthreads();
+    }
+    if (k < nplanes) {
+      produce((int)(zb + k) - 1, r0, I0());
+      __syncthreads();
+    }
+    __syncthreads();  // the consumers' last plane
+  } else {
+    // Consumer lane: output cell (x0 + ox, y0 + oy).
+    const uint32_t u = t - 64u * NP;
+    const uint32_t ox = u % TX, oy = u / TX;
+    const uint32_t out_off = (y0 + oy) * a.yrow_bytes + (x0 + ox) * (uint32_t)sizeof(W);
+    const uint32_t col = (y0 + oy) * g.nx + x0 + ox;
+    const uint32_t l0 = (oy + 1) * NSX + ox + 1;  // own column in the ring tile
+    real dA[Q], dB[Q], dC[Q];  // outputs q - 1, q, q + 1 of the plane q just read
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dA[i] = dB[i] = dC[i] = 0;
+    auto consume = [&](int q, auto sl, auto emit) {
+      constexpr int SL = decltype(sl)::value;
+      constexpr bool EMIT = decltype(emit)::value;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const real v = ST::to_dev(slot[SL][i][l0 - (LT::cy(i) * NSX + LT::cx(i))], CO::W(i));
+        if (LT::cz(i) < 0) dA[i] = v;
+        if (LT::cz(i) == 0) dB[i] = v;
+        if (LT::cz(i) > 0) dC[i] = v;
+      }
+      if constexpr (EMIT) {
+        real Fx = 0, Fy = 0, Fz = 0;
+        load_force((uint32_t)(q - 1), col, Fx, Fy, Fz);
+        bgk_collide<L, real, FM>(dA, Fx, Fy, Fz, omega);
+        char* o = ob + (uint64_t)(q - 1) * a.plane_bytes + out_off;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes), ST::from_dev(dA[i], CO::W(i)));
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (LT::cz(i) >= 0) dA[i] = dB[i];
+        if (LT::cz(i) > 0) dB[i] = dC[i];
+      }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    __syncthreads();  // plane zb-1 written
+    consume((int)zb - 1, I0(), std::false_type());
+    __syncthreads();
+    consume((int)zb, I1(), std::false_type());
+    __syncthreads();
+    uint32_t k = 2;  // planes read so far; plane zb-1+k completes output zb-2+k
+    for (; k + 1 < nplanes; k += 2) {
+      consume((int)(zb + k) - 1, I0(), std::true_type());
+      __syncthreads();
+      consume((int)(zb + k), I1(), std::true_type());
+      __syncthreads();
+    }
+    if (k < nplanes) {
+      consume((int)(zb + k) - 1, I0(), std::true_type());
+      __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -773,6 +968,99 @@ static hipError_t launch_step_ls(const void* fin, void* fout, const void* force,
   return hipGetLastError();
 }
 
+// Two-step launches (step2_kernel): FP32 and shifted-FP32 words on the 3D lattices,
+// where one launch runs 1.45-1.5x faster than two of step_kernel.  The 16-bit kinds
+// are left to step_kernel: their two-step form is bound by its arithmetic and ran no
+// faster than two single steps.
+template <int L, int S>
+constexpr bool step2_enabled() {
+  return (L == kD3Q27 || L == kD3Q19) && (S == kF32 || S == kF32S);
+}
+
+template <int L, int S>
+static bool step2_fits(const GridArgs& g) {
+  if constexpr (!step2_enabled<L, S>()) {
+    return false;
+  } else {
+    using SH = Step2Shape<L, S>;
+    const uint64_t plane = (uint64_t)g.ny * Lattice<L>::Q * g.pitch * sizeof(typename Storage<S>::word);
+    return g.ghost == 0 && g.z0 == 0 && g.nzl == g.nz && g.nx % SH::TX == 0 && g.ny % SH::TY == 0 && g.nz >= 3 &&
+           plane < (uint64_t(1) << 32);
+  }
+}
+
+// Compute units of the current device (cached per device).
+static uint32_t device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int n = cache[dev].load(std::memory_order_relaxed);
+  if (n <= 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev].store(n, std::memory_order_relaxed);
+  }
+  return (uint32_t)n;
+}
+
+// Planes per z chunk: the length that minimises rounds * (lz + 2), the duration of the
+// launch if each block takes lz + 2 plane-times (its chunk plus the two planes of step
+// t+1 below and above it) and `slots` blocks run at once.
+static uint32_t step2_chunk(uint64_t tiles, uint32_t nz, uint64_t slots) {
+  uint32_t best = nz;
+  uint64_t best_cost = ~uint64_t(0);
+  for (uint32_t lz = 8;; lz += 8) {
+    const uint32_t l = lz < nz ? lz : nz;
+    const uint64_t blocks = tiles * ((nz + l - 1) / l);
+    const uint64_t cost = ((blocks + slots - 1) / slots) * (l + 2);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = l;
+    }
+    if (l == nz) break;
+  }
+  return best;
+}
+
+template <int L, int S>
+static hipError_t launch_step2_ls(const void* fin, void* fout, const void* force, int force_mode, const GridArgs& g,
+                                  double omega, hipStream_t s) {
+  if constexpr (!step2_enabled<L, S>()) {
+    return hipErrorInvalidValue;
+  } else {
+    using ST = Storage<S>;
+    using W = typename ST::word;
+    using R = typename ST::real;
+    using SH = Step2Shape<L, S>;
+    if (!step2_fits<L, S>(g)) return hipErrorInvalidValue;
+    Step2Args a;
+    a.tiles_x = g.nx / SH::TX;
+    a.tiles_y = g.ny / SH::TY;
+    a.row_bytes = g.pitch * (uint32_t)sizeof(W);
+    a.yrow_bytes = Lattice<L>::Q * a.row_bytes;
+    a.plane_bytes = g.ny * a.yrow_bytes;
+    const uint64_t tiles = (uint64_t)a.tiles_x * a.tiles_y;
+    a.lz = step2_chunk(tiles, g.nz, 2ull * device_cus());  // two blocks per CU (73 KB of LDS each)
+    const dim3 grid((unsigned)(tiles * ((g.nz + a.lz - 1) / a.lz)));
+    const W* in = (const W*)fin;
+    W* out = (W*)fout;
+    if (!force || force_mode == kNoForce)
+      step2_kernel<L, S, kNoForce><<<grid, SH::NT, 0, s>>>(in, out, nullptr, g, a, (R)omega);
+    else if (force_mode == kGuoForce)
+      step2_kernel<L, S, kGuoForce><<<grid, SH::NT, 0, s>>>(in, out, (const R*)force, g, a, (R)omega);
+    else if (force_mode == kShiftForce)
+      step2_kernel<L, S, kShiftForce><<<grid, SH::NT, 0, s>>>(in, out, (const R*)force, g, a, (R)omega);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+}
+
+template <int L, int S>
+static hipError_t step2_fits_ls(const GridArgs& g, bool* ok) {
+  *ok = step2_fits<L, S>(g);
+  return hipSuccess;
+}
+
 template <int S>
 static hipError_t launch_mrt_s(const void* fin, void* fout, const void* ghost, int ghost_mode, const GridArgs& g,
                                const double* scales, hipStream_t s) {
@@ -935,6 +1223,17 @@ static hipError_t launch_moments_adjoint_ls(const void* f, const void* force, co
 hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
                        const GridArgs& g, double omega, hipStream_t s) {
   LBM_DISPATCH(launch_step_ls, lattice, storage, fin, fout, force, force_mode, g, omega, s);
+}
+
+bool step2_supported(int lattice, int storage, const GridArgs& g) {
+  bool ok = false;
+  auto check = [&]() -> hipError_t { LBM_DISPATCH(step2_fits_ls, lattice, storage, g, &ok); };
+  return check() == hipSuccess && ok;
+}
+
+hipError_t launch_step2(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
+                        const GridArgs& g, double omega, hipStream_t s) {
+  LBM_DISPATCH(launch_step2_ls, lattice, storage, fin, fout, force, force_mode, g, omega, s);
 }
 
 hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, const void* lam_next, void* lam_out,
