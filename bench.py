@@ -4,13 +4,17 @@
 
 Workload (headline line): D3Q27 BGK Taylor-Green vortex on a 256^3 periodic grid,
 FP32 populations, tau = 0.51, u0 = 0.05, populations initialised to equilibrium.
-One benchmark step is one lattice update of the whole grid (lbm_step with
-n_steps = 1: pull streaming, moments, equilibrium, BGK relaxation, store).  The
-inputs are resident in HBM before the timed region; the timed region is K
-back-to-back steps bracketed by HIP events on the stream the kernels run on.
+One benchmark step is one lattice update of the whole grid (pull streaming, moments,
+equilibrium, BGK relaxation, store).  The timed region is one lbm_step call of K steps,
+which the library runs as K/2 two-step launches (the intermediate state of each pair
+stays on chip; results equal single steps bit for bit); the one-step kernel (K calls
+of lbm_step with n_steps = 1) is measured beside it.  The inputs are resident in HBM
+before the timed region, which is bracketed by HIP events on the stream the kernels
+run on.
 
-Printed: one JSON line (a few KB) with MLUPS as `value`, the HBM roofline of the step
-kernel (algorithmic bytes 2*Q*sizeof(storage) per cell), the oracle's CPU throughput
+Printed: one JSON line (a few KB) with MLUPS as `value`, the HBM roofline of the
+dominant kernel (algorithmic bytes 2*Q*sizeof(storage) per cell and step, and the
+bytes a two-step launch has to move), the oracle's CPU throughput
 (the full 256^3 grid when host memory allows) and a flat `summary` of the other
 measurements: the other storage formats (FP64, shifted FP32, shifted FP16/BF16) with
 their error against the FP64 run after 1000 steps, D3Q19, the forced steps, the
@@ -60,9 +64,18 @@ def time_launches(fn, steps: int, warmup: int) -> float:
     return start.elapsed_time(stop) / steps
 
 
-def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = "D3Q27", mode: str = "none"):
+def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = "D3Q27", mode: str = "none",
+                one_call: bool = True):
     """Step throughput; mode "guo" adds a body-force field (Guo forcing), "shift" a
-    velocity-shift field (the flow-control forcing), each D reals read per cell."""
+    velocity-shift field (the flow-control forcing), each D reals read per cell.
+
+    one_call: the timed region is one lbm_step call of `steps` steps, which the library
+    splits into two-step launches where the grid allows (lbm_step_launches); otherwise
+    `steps` calls of one step each (the one-step kernel alone).
+
+    hbm_gbs is the per-step accounting 2*Q*sizeof(storage) bytes per cell and step;
+    hbm_moved_gbs counts the bytes the launches have to move (a two-step launch reads
+    and writes the state once)."""
     grid = B.Grid(lattice, storage, N, N, N)
     bufs = [grid.empty_populations(), grid.empty_populations()]
     B.lbm_init_equilibrium(grid, None, u_dev, bufs[0])
@@ -72,18 +85,22 @@ def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = 
         field = torch.randn((grid.D,) + grid.spatial, generator=gen, device="cuda", dtype=torch.float64)
         field = (field * 1e-5).to(grid.real_dtype)
     cur = [0]
+    step = B.lbm_step_shifted if mode == "shift" else B.lbm_step
 
-    def one():
-        if mode == "shift":
-            B.lbm_step_shifted(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, field, 1)
-        else:
-            B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, field, 1)
-        cur[0] ^= 1
+    def run(n):
+        if step(grid, bufs[cur[0]], bufs[1 - cur[0]], TAU, field, n) == 0:
+            cur[0] ^= 1
 
-    ms = time_launches(one, steps, warmup)
+    if one_call:
+        ms = time_launches(lambda: run(steps), 1, 1) / steps  # the warm-up call is `steps` steps too
+        single, paired = B.lbm_step_launches(grid, steps)
+    else:
+        ms = time_launches(lambda: run(1), steps, warmup)
+        single, paired = steps, 0
     bpc = B.bytes_per_cell_step(grid)
     if field is not None:
         bpc += grid.D * field.element_size()
+    total_s = ms * 1e-3 * steps
     out = {
         "lattice": lattice,
         "storage": storage,
@@ -92,8 +109,13 @@ def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = 
         "mlups": grid.ncells / (ms * 1e-3) / 1e6,
         "bytes_per_cell": bpc,
         "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9,
+        "launches": {"one_step": single, "two_step": paired},
+        "hbm_moved_gbs": bpc * grid.ncells * (single + paired) / total_s / 1e9,
     }
+    if paired and not single:
+        out["ms_per_two_step_launch"] = total_s * 1e3 / paired
     out["hbm_frac"] = out["hbm_gbs"] / PEAK_HBM_GBS
+    out["hbm_moved_frac"] = out["hbm_moved_gbs"] / PEAK_HBM_GBS
     del bufs, field
     torch.cuda.empty_cache()
     return out
@@ -411,11 +433,12 @@ KERNEL_SOURCES = ("kernels.hip", "kernels.h", "device.h", "lattice.h", "coeffs.h
 
 
 def measured_traffic():
-    """HBM bytes per launch of the step kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources (else None)."""
+    """HBM bytes per launch of the headline's two-step kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel sources (else
+    None)."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "step_kernel_d3q27_f32_256_counters.md")
+    path = os.path.join(ROOT, "profiles", "step2_kernel_d3q27_f32_256_counters.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -523,12 +546,19 @@ def profile_set(B, steps: int, warmup: int):
                           "algorithmic_bytes_per_launch": bpc * grid.ncells,
                           "gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9}), flush=True)
 
+    # the two-step kernel: one lbm_step call of 2 * (steps // 2) steps (two-step launches
+    # only when that is a multiple of 4; the bytes it must move are the state read and
+    # written once per launch)
+    n2s = 4 * max(1, steps // 4)
+    r = run_forward(B, "f32", n2s, warmup, u3)
+    report(f"two-step D3Q27 f32 {N}^3", "step2_kernel<D3Q27, F32, unforced>", B.Grid("D3Q27", "f32", N, N, N),
+           r["ms_per_two_step_launch"], r["bytes_per_cell"])
     for storage, kname in (("f32", "step_kernel<D3Q27, F32, unforced>"), ("f16s", "step_kernel<D3Q27, F16S, unforced>"),
                            ("f64", "step_kernel<D3Q27, F64, unforced>")):
-        r = run_forward(B, storage, steps, warmup, u3)
+        r = run_forward(B, storage, steps, warmup, u3, one_call=False)
         report(f"step D3Q27 {storage} {N}^3", kname, B.Grid("D3Q27", storage, N, N, N), r["ms_per_step"],
                r["bytes_per_cell"])
-    r = run_forward(B, "f32", steps, warmup, u3, mode="guo")
+    r = run_forward(B, "f32", steps, warmup, u3, mode="guo", one_call=False)
     report(f"step D3Q27 f32 {N}^3, Guo force", "step_kernel<D3Q27, F32, Guo>", B.Grid("D3Q27", "f32", N, N, N),
            r["ms_per_step"], r["bytes_per_cell"])
     # the 512^3 FP16-shifted step of the full-scale workload, on Grid.tuned's rows and
@@ -657,17 +687,23 @@ def main():
 
     log("[bench] forward f32")
     head = run_forward(B, "f32", args.steps, args.warmup, u_dev)
-    detail = {"forward": {"f32": head}}
+    log("[bench] forward f32, one-step kernel")
+    one = run_forward(B, "f32", args.steps, args.warmup, u_dev, one_call=False)
+    detail = {"forward": {"f32": head}, "forward_one_step_kernel": {"f32": one}}
     if not args.quick:
         for storage in ("f16s", "bf16s", "f32s", "f64"):
             log(f"[bench] forward {storage}")
             detail["forward"][storage] = run_forward(B, storage, args.steps, args.warmup, u_dev)
         detail["fp16s_speedup_vs_f32"] = detail["forward"]["f16s"]["mlups"] / head["mlups"]
+        for storage in ("f32s", "f16s"):
+            log(f"[bench] forward {storage}, one-step kernel")
+            detail["forward_one_step_kernel"][storage] = run_forward(B, storage, args.steps, args.warmup, u_dev,
+                                                                     one_call=False)
         # D3Q19, the lattice of the paper's 3D benchmark (Taylor-Green vortex, Sec. 3.3)
         detail["forward_d3q19"] = {s: run_forward(B, s, args.steps, args.warmup, u_dev, "D3Q19")
                                    for s in ("f32", "f64", "f16s")}
         log("[bench] forced steps")
-        detail["forward_forced"] = {f"{m}_{s}": run_forward(B, s, max(20, args.steps // 4), 5, u_dev, mode=m)
+        detail["forward_forced"] = {f"{m}_{s}": run_forward(B, s, 4 * max(5, args.steps // 16), 5, u_dev, mode=m)
                                     for m in ("guo", "shift") for s in ("f32", "f16s")}
         log("[bench] D2Q9 8192^2 BGK and MRT")
         detail["d2q9_8192"] = run_d2q9(B, args.steps, args.warmup)
@@ -734,6 +770,30 @@ def _get(d, *keys):
     return d
 
 
+def roofline(head: dict, traffic) -> dict:
+    """Roofline of the headline's dominant kernel.  achieved = algorithmic bytes
+    (2*Q*sizeof(storage) per cell and step) times the cell-steps of the timed region,
+    over its duration, i.e. per launch for launches of one kind; the two-step kernel
+    exceeds the per-step roofline, because the intermediate state of a launch never goes
+    to HBM.  moved_frac counts the bytes the launches have to move (a two-step launch
+    reads and writes the state once) against the same peak: the kernel's own distance
+    from the bandwidth bound.  traffic: HBM bytes per two-step launch from the rocprofv3
+    counters."""
+    cells = N ** 3
+    launches = head.get("launches", {"one_step": 1, "two_step": 0})
+    paired = bool(launches["two_step"])
+    only_paired = paired and not launches["one_step"]
+    per_launch = 2 if paired else 1
+    out = {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": head["hbm_frac"], "traffic": traffic if only_paired else None,
+           "kernel": ("lbm::step2_kernel<D3Q27, F32, unforced>" if paired else "lbm::step_kernel<D3Q27, F32, unforced>"),
+           "steps_per_launch": per_launch,
+           "ms_per_launch": head["ms_per_two_step_launch"] if only_paired else head["ms_per_step"],
+           "algorithmic_bytes_per_launch": head["bytes_per_cell"] * cells * per_launch,
+           "moved_frac": head.get("hbm_moved_frac", head["hbm_frac"])}
+    return out
+
+
 def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic, detail_path) -> dict:
     """The one JSON line bench.py prints: the headline step (value, ms, roofline), the
     CPU baseline, and a flat summary of the other measurements (a few KB at most; the
@@ -748,6 +808,14 @@ def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic
     for k in ("f16s", "bf16s"):
         if k in fwd:
             summ[f"{k}_speedup_vs_f32"] = _r(fwd[k]["mlups"] / head["mlups"])
+    one = detail.get("forward_one_step_kernel") or {}
+    for k in ("f32", "f16s"):
+        if k in one:
+            summ[f"one_step_kernel_{k}_mlups"] = _r(one[k]["mlups"])
+    if "f32" in one:
+        summ["one_step_kernel_f32_hbm_frac"] = _r(one["f32"]["hbm_frac"])
+    if "f32" in one and "f16s" in one:
+        summ["one_step_kernels_f16s_speedup_vs_f32"] = _r(one["f16s"]["mlups"] / one["f32"]["mlups"])
     acc = _get(detail, "accuracy_vs_f64_gpu", "errors") or {}
     for k in ("f32", "f32s", "f16s", "bf16s"):
         if k in acc:
@@ -763,7 +831,7 @@ def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic
                       ("adjoint_local_forced", "adjoint_forced")):
         for k, v in (detail.get(key) or {}).items():
             summ[f"{name}_{k}_mlups"] = _r(v["mlups"])
-            if name != "adjoint_scatter":
+            if name == "adjoint_local":
                 summ[f"{name}_{k}_hbm_frac"] = _r(v["hbm_frac"])
     d2 = detail.get("d2q9_8192") or {}
     for k in ("bgk_f32", "bgk_f16s", "bgk_f64"):
@@ -839,10 +907,7 @@ def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "lattice": "D3Q27", "grid": [N, N, N], "storage": "f32",
                    "tau": TAU, "u0": U0, "cells": N ** 3},
-        "roofline": {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": head["hbm_frac"], "traffic": traffic,
-                     "kernel": head.get("kernel", "lbm::step_kernel<D3Q27, F32, unforced>"),
-                     "algorithmic_bytes_per_launch": head["bytes_per_cell"] * N ** 3},
+        "roofline": roofline(head, traffic),
         "cpu_baseline": cpu,
         "summary": summ,
         "detail_file": detail_path,

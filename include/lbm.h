@@ -147,9 +147,22 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
  *   (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F.
  * f_in and f_out must not overlap; force must not overlap either.
  * Returns 0 if the result is in f_out (odd n_steps), 1 if it is in f_in (even
- * n_steps), or a negative lbm_status. */
+ * n_steps), or a negative lbm_status.
+ * Launches: where the grid allows it (D3Q27 or D3Q19, FP32 or shifted-FP32 words, nx a
+ * multiple of 32, ny of 8, nz >= 3, one z plane of words < 4 GiB), pairs of steps run
+ * as one launch of a kernel that keeps the intermediate state on chip: the state is
+ * read and written once per two steps.  Its results equal single steps bit for bit;
+ * the first n_steps mod 4 steps run singly so that the result stays in the buffer
+ * named above.  Paired launches leave pad words untouched.  lbm_step_launches tells
+ * how a call is split. */
 int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force,
              int n_steps, void* stream);
+
+/* How lbm_step (and lbm_step_shifted) split n_steps >= 1 into launches: *single
+ * one-step launches followed by *paired two-step launches (single + 2 * paired =
+ * n_steps; paired is even).  Host-only (no device work).  LBM_EINVAL for n_steps < 1 or
+ * NULL outputs, grid errors as lbm_step. */
+int lbm_step_launches(const lbm_grid* grid, int n_steps, int* single, int* paired);
 
 /* lbm_step with the flow-control forcing of Sec. 3.2 instead of a body force: the
  * equilibrium is evaluated at a locally shifted velocity, f^eq(rho, u + du), with

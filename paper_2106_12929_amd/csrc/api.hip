@@ -207,6 +207,13 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
 
 namespace {
 
+// Two-step launches of a call of n_steps: pairs of steps run as one launch where the
+// kernel supports the grid.  An even number of such launches leaves the result where
+// n_steps single steps leave it, so up to three steps run singly (first).
+int paired_launches(const lbm_grid* grid, const Geometry& geo, int n_steps) {
+  return lbm::step2_supported(grid->lattice, grid->storage, geo.args) ? 2 * (n_steps / 4) : 0;
+}
+
 int step_common(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* field, int force_mode,
                 int n_steps, void* stream, const char* name) {
   Geometry geo;
@@ -223,10 +230,7 @@ int step_common(const lbm_grid* grid, void* f_in, void* f_out, double tau, const
     return fail(LBM_EALIAS, "the per-cell field overlaps a population buffer");
   const double omega = 1.0 / tau;
   const int mode = field ? force_mode : lbm::kNoForce;
-  // Pairs of steps run as one launch where the kernel supports the grid.  An even
-  // number of such launches leaves the result where n_steps single steps leave it, so
-  // up to three steps run singly (first).
-  const int pairs = lbm::step2_supported(grid->lattice, grid->storage, geo.args) ? 2 * (n_steps / 4) : 0;
+  const int pairs = paired_launches(grid, geo, n_steps);
   void* bufs[2] = {f_in, f_out};
   int cur = 0;
   for (int k = 0; k < n_steps - 2 * pairs; ++k, cur ^= 1) {
@@ -254,6 +258,16 @@ int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const vo
 int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* du, int n_steps,
                      void* stream) {
   return step_common(grid, f_in, f_out, tau, du, lbm::kShiftForce, n_steps, stream, "lbm_step_shifted launch");
+}
+
+int lbm_step_launches(const lbm_grid* grid, int n_steps, int* single, int* paired) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  if (n_steps < 1) return fail(LBM_EINVAL, "n_steps must be >= 1 (got %d)", n_steps);
+  if (!single || !paired) return fail(LBM_ENULL, "single and paired must not be NULL");
+  *paired = paired_launches(grid, geo, n_steps);
+  *single = n_steps - 2 * *paired;
+  return LBM_OK;
 }
 
 }  // extern "C"

@@ -126,7 +126,7 @@ struct Step2Shape {
 };
 
 template <int L, int S, int FM>
-__global__ __launch_bounds__((Step2Shape<L, S>::NT)) __attribute__((amdgpu_waves_per_eu(5))) void step2_kernel(
+__global__ __launch_bounds__((Step2Shape<L, S>::NT)) __attribute__((amdgpu_waves_per_eu(4))) void step2_kernel(
     const typename Storage<S>::word* __restrict__ fin, typename Storage<S>::word* __restrict__ fout,
     const typename Storage<S>::real* __restrict__ force, GridArgs g, Step2Args a, typename Storage<S>::real omega) {
   using LT = Lattice<L>;
@@ -1021,37 +1021,53 @@ static uint32_t step2_chunk(uint64_t tiles, uint32_t nz, uint64_t slots) {
   return best;
 }
 
+// Blocks of one two-step instantiation resident per CU (its registers and LDS decide;
+// the D3Q27 forms take one 10-wave block per CU at 101-114 registers).
+template <int L, int S, int FM>
+static uint32_t step2_blocks_per_cu() {
+  static std::atomic<int> cached{0};
+  int n = cached.load(std::memory_order_relaxed);
+  if (n <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2_kernel<L, S, FM>, Step2Shape<L, S>::NT, 0) !=
+            hipSuccess ||
+        n <= 0)
+      n = 1;
+    cached.store(n, std::memory_order_relaxed);
+  }
+  return (uint32_t)n;
+}
+
+template <int L, int S, int FM>
+static hipError_t launch_step2_lsf(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
+                                   hipStream_t s) {
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using R = typename ST::real;
+  using SH = Step2Shape<L, S>;
+  Step2Args a;
+  a.tiles_x = g.nx / SH::TX;
+  a.tiles_y = g.ny / SH::TY;
+  a.row_bytes = g.pitch * (uint32_t)sizeof(W);
+  a.yrow_bytes = Lattice<L>::Q * a.row_bytes;
+  a.plane_bytes = g.ny * a.yrow_bytes;
+  const uint64_t tiles = (uint64_t)a.tiles_x * a.tiles_y;
+  a.lz = step2_chunk(tiles, g.nz, (uint64_t)step2_blocks_per_cu<L, S, FM>() * device_cus());
+  const dim3 grid((unsigned)(tiles * ((g.nz + a.lz - 1) / a.lz)));
+  step2_kernel<L, S, FM><<<grid, SH::NT, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, a, (R)omega);
+  return hipGetLastError();
+}
+
 template <int L, int S>
 static hipError_t launch_step2_ls(const void* fin, void* fout, const void* force, int force_mode, const GridArgs& g,
                                   double omega, hipStream_t s) {
   if constexpr (!step2_enabled<L, S>()) {
     return hipErrorInvalidValue;
   } else {
-    using ST = Storage<S>;
-    using W = typename ST::word;
-    using R = typename ST::real;
-    using SH = Step2Shape<L, S>;
     if (!step2_fits<L, S>(g)) return hipErrorInvalidValue;
-    Step2Args a;
-    a.tiles_x = g.nx / SH::TX;
-    a.tiles_y = g.ny / SH::TY;
-    a.row_bytes = g.pitch * (uint32_t)sizeof(W);
-    a.yrow_bytes = Lattice<L>::Q * a.row_bytes;
-    a.plane_bytes = g.ny * a.yrow_bytes;
-    const uint64_t tiles = (uint64_t)a.tiles_x * a.tiles_y;
-    a.lz = step2_chunk(tiles, g.nz, 2ull * device_cus());  // two blocks per CU (73 KB of LDS each)
-    const dim3 grid((unsigned)(tiles * ((g.nz + a.lz - 1) / a.lz)));
-    const W* in = (const W*)fin;
-    W* out = (W*)fout;
-    if (!force || force_mode == kNoForce)
-      step2_kernel<L, S, kNoForce><<<grid, SH::NT, 0, s>>>(in, out, nullptr, g, a, (R)omega);
-    else if (force_mode == kGuoForce)
-      step2_kernel<L, S, kGuoForce><<<grid, SH::NT, 0, s>>>(in, out, (const R*)force, g, a, (R)omega);
-    else if (force_mode == kShiftForce)
-      step2_kernel<L, S, kShiftForce><<<grid, SH::NT, 0, s>>>(in, out, (const R*)force, g, a, (R)omega);
-    else
-      return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (!force || force_mode == kNoForce) return launch_step2_lsf<L, S, kNoForce>(fin, fout, nullptr, g, omega, s);
+    if (force_mode == kGuoForce) return launch_step2_lsf<L, S, kGuoForce>(fin, fout, force, g, omega, s);
+    if (force_mode == kShiftForce) return launch_step2_lsf<L, S, kShiftForce>(fin, fout, force, g, omega, s);
+    return hipErrorInvalidValue;
   }
 }
 

@@ -327,3 +327,47 @@ def test_moments_noalloc_validation(B):
     assert lib.lbm_moments_noalloc(gp, P1, None, P2, None, red, None) == -6               # scratch too small
     assert b"fixed scratch" in lib.lbm_last_error()
     assert lib.lbm_moments_noalloc(None, P1, None, None, None, red, None) == -2
+
+
+def _launches(B, g, n):
+    single, paired = ctypes.c_int(-1), ctypes.c_int(-1)
+    rc = B._lib.lbm_step_launches(ctypes.byref(g), n, ctypes.byref(single), ctypes.byref(paired))
+    return rc, single.value, paired.value
+
+
+@pytest.mark.parametrize("lattice,storage,dims,pitch,pairs", [
+    ("D3Q27", "f32", (256, 256, 256), 0, True),
+    ("D3Q27", "f32s", (32, 8, 3), 0, True),
+    ("D3Q19", "f32", (64, 16, 11), 128, True),
+    ("D3Q27", "f16s", (256, 256, 256), 0, False),   # the 16-bit kinds step singly
+    ("D3Q27", "bf16s", (256, 256, 256), 0, False),
+    ("D3Q27", "f64", (256, 256, 256), 0, False),
+    ("D2Q9", "f32", (256, 256, 1), 0, False),       # 2D
+    ("D3Q27", "f32", (48, 16, 8), 0, False),        # nx off the 32-cell tiles
+    ("D3Q27", "f32", (32, 12, 8), 0, False),        # ny off the 8-row tiles
+    ("D3Q27", "f32", (32, 8, 2), 0, False),         # nz < 3
+    ("D3Q27", "f32", (32, 8, 4), 4971027, False),   # one z plane of words: 2^32 + 32 bytes
+    ("D3Q27", "f32", (32, 8, 4), 4971026, True),    # 2^32 - 832 bytes
+])
+def test_step_launch_plan(B, lattice, storage, dims, pitch, pairs):
+    """lbm_step's split into one-step and two-step launches: an even number of paired
+    launches after n_steps mod 4 single steps, on the grids the two-step kernel takes;
+    single steps everywhere else."""
+    g = _grid(B, lattice=lattice, storage=storage, nx=dims[0], ny=dims[1], nz=dims[2], pitch=pitch)
+    for n in (1, 2, 3, 4, 5, 6, 7, 8, 9, 1000, 1001, 1003):
+        rc, single, paired = _launches(B, g, n)
+        assert rc == 0
+        assert single + 2 * paired == n
+        if pairs:
+            assert (single, paired) == (n % 4, 2 * (n // 4)), n
+        else:
+            assert (single, paired) == (n, 0), n
+    if pairs:
+        assert B.lbm_step_launches(B.Grid(lattice, storage, *dims, pitch or None), 1000) == (0, 500)
+
+
+def test_step_launch_plan_validation(B):
+    g = _grid(B)
+    assert _launches(B, g, 0)[0] == -1
+    assert B._lib.lbm_step_launches(ctypes.byref(g), 4, None, None) == -2
+    assert _launches(B, _grid(B, nx=0), 4)[0] == -1

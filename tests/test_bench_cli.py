@@ -26,7 +26,9 @@ def _fake_detail():
         return rnd.uniform(1.0, 9.0) * 10 ** rnd.randint(-4, 4) + 1e-9 / 3
 
     def fw():
-        return {"ms_per_step": v(), "mlups": v(), "bytes_per_cell": 216, "hbm_gbs": v(), "hbm_frac": v()}
+        return {"ms_per_step": v(), "mlups": v(), "bytes_per_cell": 216, "hbm_gbs": v(), "hbm_frac": v(),
+                "launches": {"one_step": 0, "two_step": 100}, "hbm_moved_gbs": v(), "hbm_moved_frac": v(),
+                "ms_per_two_step_launch": v()}
 
     hist = [[t, v(), v()] for t in range(0, 4001, 250)]
     runs = {k: {"mlups": v(), "kinetic_energy": [[t, v()] for t in range(0, 2001, 100)], "blew_up_at": None,
@@ -34,6 +36,7 @@ def _fake_detail():
                 "spectrum_rel_err_median": v(), "u_rel_l2": v()} for k in ("f64", "f32", "f16s", "bf16s")}
     return {
         "forward": {k: fw() for k in ("f32", "f16s", "bf16s", "f32s", "f64")},
+        "forward_one_step_kernel": {k: fw() for k in ("f32", "f32s", "f16s")},
         "fp16s_speedup_vs_f32": v(),
         "forward_d3q19": {k: fw() for k in ("f32", "f64", "f16s")},
         "forward_forced": {f"{m}_{s}": fw() for m in ("guo", "shift") for s in ("f32", "f16s")},
@@ -94,11 +97,16 @@ def test_bench_line_is_small_and_complete():
               "config", "summary", "n_gpus", "higher_is_better", "vs_baseline", "data", "scaling"):
         assert k in line, k
     assert line["config"]["workload"].startswith("D3Q27 BGK Taylor-Green vortex 256^3")
-    assert set(line["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
+    assert set(line["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic", "moved_frac",
+                                     "steps_per_launch"}
     assert line["roofline"]["frac"] == head["hbm_frac"]
+    assert line["roofline"]["steps_per_launch"] == 2
+    assert line["roofline"]["kernel"].startswith("lbm::step2_kernel")
+    assert line["roofline"]["traffic"] == 3624615676.0
     s = line["summary"]
     for k in ("f16s_speedup_vs_f32", "bf16s_speedup_vs_f32", "f16s_u_rel_l2_vs_f64", "adjoint_local_f32_mlups",
-              "f64_mlups", "d3q19_f32_mlups", "precision_384", "adjoint_512"):
+              "f64_mlups", "d3q19_f32_mlups", "precision_384", "adjoint_512", "one_step_kernel_f32_mlups",
+              "one_step_kernel_f32_hbm_frac", "one_step_kernels_f16s_speedup_vs_f32"):
         assert k in s, k
     assert [r["tau"] for r in s["precision_384"]] == [0.5015, 0.505]
     assert [r["tau"] for r in s["adjoint_512"]] == [0.505, 0.51]
@@ -115,3 +123,4 @@ def test_bench_line_without_optional_measurements():
     head = {"ms_per_step": 0.62, "mlups": 27000.0, "bytes_per_cell": 216, "hbm_gbs": 5800.0, "hbm_frac": 0.725}
     line = bench.summary_line(head, {"forward": {"f32": head}}, None, 50, 5, None, None)
     assert line["value"] == 27000.0 and line["summary"] == {} and line["cpu_baseline"] is None
+    assert line["roofline"]["steps_per_launch"] == 1 and line["roofline"]["frac"] == 0.725
