@@ -112,9 +112,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWave
 //
 // Tiles are 32 x 8 cells for 4-byte words (a direction row of a tile is one 128-byte
 // line).  Consecutive tiles of a chunk go to the same XCD (blocks are dealt to the 8
-// XCDs in turn), so the ring rows and columns a block shares with its neighbours are
-// mostly served by that XCD's L2: 1.39x of the state's bytes are fetched from memory
-// at 256^3 against 2x for two single steps.
+// XCDs in turn), so the ring rows and line ends a block shares with its neighbours
+// are mostly served by that XCD's L2: a launch fetches about 1.4 times the state's
+// bytes (two single steps fetch them twice); the excess is ring rows read again when
+// a neighbouring tile is at another plane.
 // ---------------------------------------------------------------------------------
 template <int L, int S>
 struct Step2Shape {
