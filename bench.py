@@ -546,10 +546,10 @@ def profile_set(B, steps: int, warmup: int):
                           "algorithmic_bytes_per_launch": bpc * grid.ncells,
                           "gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9}), flush=True)
 
-    # the two-step kernel: one lbm_step call of 2 * (steps // 2) steps (two-step launches
-    # only when that is a multiple of 4; the bytes it must move are the state read and
-    # written once per launch)
-    n2s = 4 * max(1, steps // 4)
+    # the two-step kernel: one lbm_step call of 4 * steps steps (2 * steps two-step
+    # launches, after a warm-up call as long: the first launches of a run are slower);
+    # the bytes it must move are the state read and written once per launch
+    n2s = 4 * max(1, steps)
     r = run_forward(B, "f32", n2s, warmup, u3)
     report(f"two-step D3Q27 f32 {N}^3", "step2_kernel<D3Q27, F32, unforced>", B.Grid("D3Q27", "f32", N, N, N),
            r["ms_per_two_step_launch"], r["bytes_per_cell"])
