@@ -178,53 +178,94 @@ __device__ __forceinline__ void bgk_collide(real (&d)[Lattice<L>::Q], real Fx, r
   using LT = Lattice<L>;
   using CO = Coef<L, real>;
   constexpr int Q = LT::Q;
-  // Moments (Eq. 4) in deviation form: rho = 1 + sum d, rho u = sum c d (+ F/2).
-  real drho = 0, jx = 0, jy = 0, jz = 0;
+  constexpr bool D3 = LT::D == 3;
+  // -0 is an exact additive identity (-0 + x == x for every x, signed zeros included),
+  // so sums that start from it cost no instruction for their first term.
+  constexpr real nzero = -0.0;
+  // Moments (Eq. 4) in deviation form, rho = 1 + sum d, rho u = sum c d (+ F/2), from
+  // partial sums: each row of velocities with equal (c_y, c_z) gives its sum and its
+  // c_x-weighted sum, each plane of rows its sum and c_y-weighted sum.
+  real drho = nzero, jx = nzero, jy = nzero, jz = nzero;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    drho += d[i];
-    if (LT::cx(i) > 0) jx += d[i];
-    if (LT::cx(i) < 0) jx -= d[i];
-    if (LT::cy(i) > 0) jy += d[i];
-    if (LT::cy(i) < 0) jy -= d[i];
-    if (LT::cz(i) > 0) jz += d[i];
-    if (LT::cz(i) < 0) jz -= d[i];
+  for (int zc = (D3 ? -1 : 0); zc <= (D3 ? 1 : 0); ++zc) {
+    real sp = nzero, yp = nzero;
+#pragma unroll
+    for (int yc = -1; yc <= 1; ++yc) {
+      real sr = nzero, xr = nzero;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (LT::cy(i) != yc || LT::cz(i) != zc) continue;
+        sr += d[i];
+        if (LT::cx(i) > 0) xr += d[i];
+        if (LT::cx(i) < 0) xr -= d[i];
+      }
+      sp += sr;
+      if (yc > 0) yp += sr;
+      if (yc < 0) yp -= sr;
+      jx += xr;
+    }
+    drho += sp;
+    jy += yp;
+    if (zc > 0) jz += sp;
+    if (zc < 0) jz -= sp;
   }
   constexpr bool FORCED = FM == kGuoForce;
   if constexpr (FORCED) {
     jx += real(0.5) * Fx;
     jy += real(0.5) * Fy;
-    jz += real(0.5) * Fz;
+    if constexpr (D3) jz += real(0.5) * Fz;
   }
   const real rho = real(1) + drho;
   const real inv_rho = real(1) / rho;
-  real ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+  real ux = jx * inv_rho, uy = jy * inv_rho, uz = 0;
+  if constexpr (D3) uz = jz * inv_rho;
   if constexpr (FM == kShiftForce) {
     ux += Fx;
     uy += Fy;
-    uz += Fz;
+    if constexpr (D3) uz += Fz;
   }
-  const real usq = real(1.5) * (ux * ux + uy * uy + uz * uz);
+  const real usq = D3 ? real(1.5) * (ux * ux + uy * uy + uz * uz) : real(1.5) * (ux * ux + uy * uy);
   // Guo source G_i = (1 - omega/2) (A_i c_i.F - 3 W_i u.F + 2 B_i (c_i.u)(c_i.F)), with
   // the cell's factors taken out once: gF = (1 - omega/2) F, g3uF = 3 (1 - omega/2) u.F,
   // so that G_i = (c_i.gF)(A_i + 2 B_i c_i.u) - W_i g3uF
   const real guo = real(1) - real(0.5) * omega;
   const real gFx = guo * Fx, gFy = guo * Fy, gFz = guo * Fz;
-  const real g3uF = real(3) * (ux * gFx + uy * gFy + uz * gFz);
+  const real g3uF = D3 ? real(3) * (ux * gFx + uy * gFy + uz * gFz) : real(3) * (ux * gFx + uy * gFy);
 
-  // Equilibrium (Eq. 3) as a deviation, BGK relaxation (Eq. 2), Guo source.
+  // c_i.u: computed for the first half of the velocities; the opposite velocity
+  // (index Q-1-i in every lattice's order) takes its negation.
+  real cuv[Q / 2];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    constexpr real zero = 0;
-    real cu = zero;
+  for (int i = 0; i < Q / 2; ++i) {
+    real cu = nzero;
     if (LT::cx(i) > 0) cu += ux;
     if (LT::cx(i) < 0) cu -= ux;
     if (LT::cy(i) > 0) cu += uy;
     if (LT::cy(i) < 0) cu -= uy;
     if (LT::cz(i) > 0) cu += uz;
     if (LT::cz(i) < 0) cu -= uz;
-    const real deq = CO::W(i) * drho + rho * (CO::A(i) * cu + CO::B(i) * cu * cu - CO::W(i) * usq);
-    real dn = d[i] + omega * (deq - d[i]);
+    cuv[i] = cu;
+  }
+  // Equilibrium (Eq. 3) as a deviation,
+  //   f^eq_i - w_i = W_i q + rho c.u (A_i + B_i c.u),   q = drho - rho usq,
+  // and BGK relaxation (Eq. 2) as d + omega (deq - d): near equilibrium deq - d is
+  // small and exact, which keeps the rounding of the relaxed value at half an ulp
+  // (the equivalent (1 - omega) d + omega deq rounds twice on terms larger than the
+  // result).  The class coefficients W_i, A_i, B_i enter only as factors of per-cell
+  // values; a product of two run-wide constants (omega W_i, say) would carry one
+  // rounding error into every collision and drift the momentum step after step.
+  const real q = drho - rho * usq;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    constexpr real zero = 0;
+    const real base = CO::W(i) * q;
+    real deq = base;
+    real cu = zero;
+    if (LT::c2(i) != 0) {
+      cu = i < Q / 2 ? cuv[i] : -cuv[Q - 1 - i];
+      deq = rho * (cu * (CO::B(i) * cu + CO::A(i))) + base;
+    }
+    real dn = omega * (deq - d[i]) + d[i];
     if constexpr (FORCED) {
       real cgF = zero;
       add_times(cgF, LT::cx(i), gFx);

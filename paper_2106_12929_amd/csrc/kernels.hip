@@ -110,8 +110,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWave
 // the intermediate words are rounded to storage exactly as its stores are, so the
 // result equals two launches of step_kernel bit for bit.
 //
-// Tiles are 32 x 8 cells for 4-byte words (a direction row of a tile is one 128-byte
-// line).  Consecutive tiles of a chunk go to the same XCD (blocks are dealt to the 8
+// Tiles are 32 x 8 cells for 4-byte words and 64 x 4 for 2-byte words (a direction row
+// of a tile is one 128-byte line).  Consecutive tiles of a chunk go to the same XCD (blocks are dealt to the 8
 // XCDs in turn), so the ring rows and line ends a block shares with its neighbours
 // are mostly served by that XCD's L2: a launch fetches about 1.4 times the state's
 // bytes (two single steps fetch them twice); the excess is ring rows read again when
@@ -119,7 +119,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWave
 // ---------------------------------------------------------------------------------
 template <int L, int S>
 struct Step2Shape {
-  static constexpr int TX = 32, TY = 8;
+  // a tile's direction row is one 128-byte line: 32 x 8 cells for 4-byte words,
+  // 64 x 4 for 2-byte words
+  static constexpr int TX = sizeof(typename Storage<S>::word) == 2 ? 64 : 32, TY = 256 / TX;
   static constexpr int NSX = TX + 2, NS = NSX * (TY + 2);  // ring-tile columns
   static constexpr int NP = (NS + 63) / 64;                 // producer waves
   static constexpr int NC = TX * TY / 64;                   // consumer waves
@@ -127,7 +129,7 @@ struct Step2Shape {
 };
 
 template <int L, int S, int FM>
-__global__ __launch_bounds__((Step2Shape<L, S>::NT)) __attribute__((amdgpu_waves_per_eu(4))) void step2_kernel(
+__global__ __launch_bounds__((Step2Shape<L, S>::NT)) __attribute__((amdgpu_waves_per_eu(3))) void step2_kernel(
     const typename Storage<S>::word* __restrict__ fin, typename Storage<S>::word* __restrict__ fout,
     const typename Storage<S>::real* __restrict__ force, GridArgs g, Step2Args a, typename Storage<S>::real omega) {
   using LT = Lattice<L>;
@@ -969,13 +971,13 @@ static hipError_t launch_step_ls(const void* fin, void* fout, const void* force,
   return hipGetLastError();
 }
 
-// Two-step launches (step2_kernel): FP32 and shifted-FP32 words on the 3D lattices,
-// where one launch runs 1.45-1.5x faster than two of step_kernel.  The 16-bit kinds
-// are left to step_kernel: their two-step form is bound by its arithmetic and ran no
-// faster than two single steps.
+// Two-step launches (step2_kernel) on the 3D lattices: FP32 and shifted-FP32 words
+// (one launch 1.47-1.59x faster than two of step_kernel at 256^3) and shifted FP16
+// (1.13-1.30x).  Shifted BF16 is left to step_kernel: its software rounding makes the
+// two-step form bound by its arithmetic, 4% slower than two single steps.
 template <int L, int S>
 constexpr bool step2_enabled() {
-  return (L == kD3Q27 || L == kD3Q19) && (S == kF32 || S == kF32S);
+  return (L == kD3Q27 || L == kD3Q19) && (S == kF32 || S == kF32S || S == kF16S);
 }
 
 template <int L, int S>
@@ -1023,7 +1025,8 @@ static uint32_t step2_chunk(uint64_t tiles, uint32_t nz, uint64_t slots) {
 }
 
 // Blocks of one two-step instantiation resident per CU (its registers and LDS decide;
-// the D3Q27 forms take one 10-wave block per CU at 101-114 registers).
+// the D3Q27 forms take one block of 10 or 11 waves per CU at 99-168 registers, the
+// D3Q19 forms up to two).
 template <int L, int S, int FM>
 static uint32_t step2_blocks_per_cu() {
   static std::atomic<int> cached{0};

@@ -339,8 +339,10 @@ def _launches(B, g, n):
     ("D3Q27", "f32", (256, 256, 256), 0, True),
     ("D3Q27", "f32s", (32, 8, 3), 0, True),
     ("D3Q19", "f32", (64, 16, 11), 128, True),
-    ("D3Q27", "f16s", (256, 256, 256), 0, False),   # the 16-bit kinds step singly
-    ("D3Q27", "bf16s", (256, 256, 256), 0, False),
+    ("D3Q27", "f16s", (256, 256, 256), 0, True),    # 2-byte words: 64 x 4 tiles
+    ("D3Q27", "f16s", (32, 8, 8), 0, False),
+    ("D3Q19", "f16s", (64, 4, 3), 0, True),
+    ("D3Q27", "bf16s", (256, 256, 256), 0, False),  # shifted BF16 steps singly
     ("D3Q27", "f64", (256, 256, 256), 0, False),
     ("D2Q9", "f32", (256, 256, 1), 0, False),       # 2D
     ("D3Q27", "f32", (48, 16, 8), 0, False),        # nx off the 32-cell tiles

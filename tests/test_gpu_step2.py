@@ -1,8 +1,8 @@
 """Two time steps per launch.
 
 For n_steps >= 4, lbm_step runs pairs of steps as one LDS-blocked launch on 3D grids
-whose nx is a multiple of 32 and ny a multiple of 8 (FP32 and shifted-FP32 words; the
-first n_steps mod 4 steps run singly).  Each collision of that kernel is the one-step
+(FP32 and shifted-FP32 words with nx a multiple of 32 and ny of 8, shifted FP16 with nx
+a multiple of 64 and ny of 4; the first n_steps mod 4 steps run singly).  Each collision of that kernel is the one-step
 kernel's, applied to the same rounded storage words, so the result must equal the same
 number of single-step launches bit for bit; the single steps are tied to the oracle
 (Eqs. 1-4) by the one-step parity tests, and the last test here ties the paired
@@ -34,6 +34,8 @@ CASES = [  # lattice, (nx, ny, nz), pitch (None = nx)
     ("D3Q27", (48, 16, 6), None),  # nx off the tile grid: single steps only
     ("D3Q27", (32, 12, 6), None),  # ny off the tile grid
     ("D3Q27", (32, 8, 2), None),   # nz < 3
+    ("D3Q27", (64, 4, 9), 128),    # 2-byte words: one 64 x 4 tile, padded rows
+    ("D3Q27", (128, 12, 5), None),
 ]
 
 
@@ -69,7 +71,7 @@ def _singles(B, grid, g, tau, field, mode, n):
 
 
 @pytest.mark.parametrize("lat,shape,pitch", CASES)
-@pytest.mark.parametrize("kind", ["f32", "f32s", "f16s", "f64"])
+@pytest.mark.parametrize("kind", ["f32", "f32s", "f16s", "bf16s", "f64"])
 @pytest.mark.parametrize("mode", ["none", "guo", "shift"])
 def test_paired_steps_equal_single_steps(lat, shape, pitch, kind, mode):
     need_gpu()
@@ -99,11 +101,11 @@ def test_paired_steps_leave_pad_words_alone():
     assert torch.all(torch.isfinite(rows[:, :, :32]))
 
 
-@pytest.mark.parametrize("kind", ["f32", "f32s"])
+@pytest.mark.parametrize("kind", ["f32", "f32s", "f16s"])
 def test_paired_steps_full_size_equal_single_steps(kind):
-    """256^3 in the launch shape of the benchmark (tiles of 32 x 8 columns, chunks of
-    128 planes, 512 blocks): four steps as two paired launches against four single
-    steps, every word compared."""
+    """256^3 in the launch shape of the benchmark (one chunk of 256 planes per tile,
+    tiles of 32 x 8 columns, 64 x 4 for FP16): four steps as two paired launches
+    against four single steps, every word compared."""
     need_gpu()
     B = binding()
     n = 256
@@ -127,10 +129,10 @@ def test_paired_steps_full_size_equal_single_steps(kind):
     assert torch.equal(bits(p), bits(ref))
 
 
-@pytest.mark.parametrize("kind,bound", [("f32", 1e-5), ("f32s", 1e-5)])
+@pytest.mark.parametrize("kind,bound", [("f32", 1e-5), ("f32s", 1e-5), ("f16s", 1e-2)])
 def test_paired_steps_vs_oracle(kind, bound):
     """A decaying Taylor-Green vortex on 64 x 32 x 24 cells, 200 steps (100 paired
-    launches) against the FP64 oracle."""
+    launches) against the FP64 oracle (FP16: a sanity bound on the storage noise)."""
     need_gpu()
     B = binding()
     nx, ny, nz = 64, 32, 24
