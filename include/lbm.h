@@ -148,9 +148,10 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
  * f_in and f_out must not overlap; force must not overlap either.
  * Returns 0 if the result is in f_out (odd n_steps), 1 if it is in f_in (even
  * n_steps), or a negative lbm_status.
- * Launches: where the grid allows it (D3Q27 or D3Q19; FP32 or shifted-FP32 words with nx
+ * Launches: where the grid allows it (D3Q27 or D3Q19: FP32 or shifted-FP32 words with nx
  * a multiple of 32 and ny of 8, or shifted-FP16 words with nx a multiple of 64 and ny of
- * 4; nz >= 3; one z plane of words < 4 GiB), pairs of steps run
+ * 4, nz >= 3, one z plane of words < 4 GiB; D2Q9: any kind but shifted BF16, nx a
+ * multiple of 64, ny >= 3), pairs of steps run
  * as one launch of a kernel that keeps the intermediate state on chip: the state is
  * read and written once per two steps.  Its results equal single steps bit for bit;
  * the first n_steps mod 4 steps run singly so that the result stays in the buffer

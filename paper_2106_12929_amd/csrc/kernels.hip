@@ -281,6 +281,165 @@ __global__ __launch_bounds__((Step2Shape<L, S>::NT)) __attribute__((amdgpu_waves
 }
 
 // ---------------------------------------------------------------------------------
+// Two time steps per launch for D2Q9: the 2D form of step2_kernel.  A block owns a
+// segment of TX cells of x and a chunk of rows [yb, ye), and marches along y: per row p
+// its producer waves compute step t+1 on the segment and one cell on each side (TX + 2
+// columns, 1.008x the segment for TX = 256) into LDS slot k & 1, and its consumer waves
+// complete step t+2 of row p-1 from the LDS copies of rows p-2..p (a row gives the
+// c_y = -1 directions to the row below it, c_y = 0 to itself, c_y = +1 to the row
+// above).  Same rounding and collision as step_kernel, so the result equals two of its
+// launches bit for bit.
+// ---------------------------------------------------------------------------------
+template <int TX>
+struct Step2Shape2D {
+  static constexpr int NS = TX + 2;          // segment plus one cell on each side
+  static constexpr int NP = (NS + 63) / 64;  // producer waves
+  static constexpr int NC = TX / 64;         // consumer waves
+  static constexpr int NT = 64 * (NP + NC);
+};
+
+template <int S, int FM, int TX>
+__global__ __launch_bounds__((Step2Shape2D<TX>::NT)) void step2_2d_kernel(
+    const typename Storage<S>::word* __restrict__ fin, typename Storage<S>::word* __restrict__ fout,
+    const typename Storage<S>::real* __restrict__ force, GridArgs g, Step2Args a, typename Storage<S>::real omega) {
+  using LT = Lattice<kD2Q9>;
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using real = typename ST::real;
+  using CO = Coef<kD2Q9, real>;
+  using SH = Step2Shape2D<TX>;
+  constexpr int Q = LT::Q;
+  constexpr int NS = SH::NS, NP = SH::NP;
+  __shared__ W slot[2][Q][NS];
+
+  // XCD-aware block order, as in step2_kernel: consecutive segments on one XCD
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t per = nb / 8, extra = nb % 8, xcd = b % 8, pos = b / 8;
+  const uint32_t lin = xcd < extra ? xcd * (per + 1) + pos : extra * (per + 1) + (xcd - extra) * per + pos;
+  const uint32_t tx = lin % a.tiles_x, yc = lin / a.tiles_x;
+  const uint32_t x0 = tx * TX;
+  const uint32_t yb = yc * a.lz;
+  const uint32_t ye = min(yb + a.lz, g.ny);
+  const uint32_t nrows = ye - yb + 2;  // step t+1 on rows yb-1 .. ye
+  const uint32_t t = threadIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(t / 64);
+  const char* fb = reinterpret_cast<const char*>(fin);
+  char* ob = reinterpret_cast<char*>(fout);
+  // rows yb-2 .. ye+2 wrapped (ny >= 3)
+  auto wrapy = [&](int y) -> uint32_t {
+    return (uint32_t)(y < 0 ? y + (int)g.ny : (y >= (int)g.ny ? y - (int)g.ny : y));
+  };
+  auto load_force = [&](uint32_t y, uint32_t x, real& Fx, real& Fy) {
+    if constexpr (FM != kNoForce) {
+      const real* f = force + (uint64_t)y * g.nx + x;
+      Fx = f[0];
+      Fy = f[g.ncells];
+    }
+  };
+
+  if (wave < (uint32_t)NP) {
+    // Producer lane: column s of the segment with its ring (lanes past it compute
+    // column NS - 1 again and write nothing).
+    const bool live = t < (uint32_t)NS;
+    const uint32_t s = min(t, (uint32_t)NS - 1);
+    int xi = (int)x0 - 1 + (int)s;
+    xi += xi < 0 ? (int)g.nx : (xi >= (int)g.nx ? -(int)g.nx : 0);
+    const uint32_t x = xi;
+    const uint32_t xb[3] = {wrap_inc(x, g.nx) * (uint32_t)sizeof(W), x * (uint32_t)sizeof(W),
+                            wrap_dec(x, g.nx) * (uint32_t)sizeof(W)};
+    auto load = [&](int py, W (&r)[Q]) {
+      const char* base[3] = {fb + (uint64_t)wrapy(py + 1) * a.yrow_bytes, fb + (uint64_t)wrapy(py) * a.yrow_bytes,
+                             fb + (uint64_t)wrapy(py - 1) * a.yrow_bytes};
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        r[i] = *reinterpret_cast<const W*>(base[LT::cy(i) + 1] + (uint64_t)i * a.row_bytes + xb[LT::cx(i) + 1]);
+    };
+    auto produce = [&](int py, W (&r)[Q], auto sl) {
+      constexpr int SL = decltype(sl)::value;
+      real d[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
+      real Fx = 0, Fy = 0;
+      load_force(wrapy(py), x, Fx, Fy);
+      bgk_collide<kD2Q9, real, FM>(d, Fx, Fy, real(0), omega);
+      if (live) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) slot[SL][i][s] = ST::from_dev(d[i], CO::W(i));
+      }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    W r0[Q], r1[Q];
+    load((int)yb - 1, r0);
+    uint32_t k = 0;
+    for (; k + 1 < nrows; k += 2) {  // row yb-1+k into slot 0, the next into slot 1
+      load((int)(yb + k), r1);
+      produce((int)(yb + k) - 1, r0, I0());
+      __syncthreads();
+      load((int)(yb + k) + 1, r0);  // one row past ye on the last pass: read, unused
+      produce((int)(yb + k), r1, I1());
+      __syncthreads();
+    }
+    if (k < nrows) {
+      produce((int)(yb + k) - 1, r0, I0());
+      __syncthreads();
+    }
+    __syncthreads();  // the consumers' last row
+  } else {
+    // Consumer lane: output cell x0 + u.
+    const uint32_t u = t - 64u * NP;
+    const uint32_t out_off = (x0 + u) * (uint32_t)sizeof(W);
+    const uint32_t l0 = u + 1;  // own column in the LDS segment
+    real dA[Q], dB[Q], dC[Q];  // outputs q - 1, q, q + 1 of the row q just read
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dA[i] = dB[i] = dC[i] = 0;
+    auto consume = [&](int qy, auto sl, auto emit) {
+      constexpr int SL = decltype(sl)::value;
+      constexpr bool EMIT = decltype(emit)::value;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const real v = ST::to_dev(slot[SL][i][l0 - LT::cx(i)], CO::W(i));
+        if (LT::cy(i) < 0) dA[i] = v;
+        if (LT::cy(i) == 0) dB[i] = v;
+        if (LT::cy(i) > 0) dC[i] = v;
+      }
+      if constexpr (EMIT) {
+        real Fx = 0, Fy = 0;
+        load_force((uint32_t)(qy - 1), x0 + u, Fx, Fy);
+        bgk_collide<kD2Q9, real, FM>(dA, Fx, Fy, real(0), omega);
+        char* o = ob + (uint64_t)(qy - 1) * a.yrow_bytes + out_off;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes), ST::from_dev(dA[i], CO::W(i)));
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (LT::cy(i) >= 0) dA[i] = dB[i];
+        if (LT::cy(i) > 0) dB[i] = dC[i];
+      }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    __syncthreads();  // row yb-1 written
+    consume((int)yb - 1, I0(), std::false_type());
+    __syncthreads();
+    consume((int)yb, I1(), std::false_type());
+    __syncthreads();
+    uint32_t k = 2;  // rows read so far; row yb-1+k completes output yb-2+k
+    for (; k + 1 < nrows; k += 2) {
+      consume((int)(yb + k) - 1, I0(), std::true_type());
+      __syncthreads();
+      consume((int)(yb + k), I1(), std::true_type());
+      __syncthreads();
+    }
+    if (k < nrows) {
+      consume((int)(yb + k) - 1, I0(), std::true_type());
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // D2Q9 multiple-relaxation-time step (Sec. 3.1, Eq. 5) in the Dellar basis.
 //
 // The basis {1, c_x, c_y, c_x^2, c_x c_y, c_y^2, g, g c_x, g c_y}, g = (3c_x^2-1)(3c_y^2-1),
@@ -977,13 +1136,21 @@ static hipError_t launch_step_ls(const void* fin, void* fout, const void* force,
 // two-step form bound by its arithmetic, 4% slower than two single steps.
 template <int L, int S>
 constexpr bool step2_enabled() {
+  if (L == kD2Q9) return S != kBF16S;
   return (L == kD3Q27 || L == kD3Q19) && (S == kF32 || S == kF32S || S == kF16S);
+}
+
+// Segment width of the D2Q9 two-step kernel for a grid (0: none fits).
+static uint32_t step2_2d_width(const GridArgs& g) {
+  return g.nx % 256 == 0 ? 256 : g.nx % 64 == 0 ? 64 : 0;
 }
 
 template <int L, int S>
 static bool step2_fits(const GridArgs& g) {
   if constexpr (!step2_enabled<L, S>()) {
     return false;
+  } else if constexpr (L == kD2Q9) {
+    return g.ghost == 0 && g.z0 == 0 && g.nzl == g.nz && step2_2d_width(g) != 0 && g.ny >= 3;
   } else {
     using SH = Step2Shape<L, S>;
     const uint64_t plane = (uint64_t)g.ny * Lattice<L>::Q * g.pitch * sizeof(typename Storage<S>::word);
@@ -1027,18 +1194,41 @@ static uint32_t step2_chunk(uint64_t tiles, uint32_t nz, uint64_t slots) {
 // Blocks of one two-step instantiation resident per CU (its registers and LDS decide;
 // the D3Q27 forms take one block of 10 or 11 waves per CU at 99-168 registers, the
 // D3Q19 forms up to two).
-template <int L, int S, int FM>
-static uint32_t step2_blocks_per_cu() {
-  static std::atomic<int> cached{0};
+template <typename K>
+static uint32_t blocks_per_cu(std::atomic<int>& cached, K kernel, int threads) {
   int n = cached.load(std::memory_order_relaxed);
   if (n <= 0) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2_kernel<L, S, FM>, Step2Shape<L, S>::NT, 0) !=
-            hipSuccess ||
-        n <= 0)
-      n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n <= 0) n = 1;
     cached.store(n, std::memory_order_relaxed);
   }
   return (uint32_t)n;
+}
+
+template <int L, int S, int FM>
+static uint32_t step2_blocks_per_cu() {
+  static std::atomic<int> cached{0};
+  return blocks_per_cu(cached, step2_kernel<L, S, FM>, Step2Shape<L, S>::NT);
+}
+
+template <int S, int FM, int TX>
+static hipError_t launch_step2_2d(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
+                                  hipStream_t s) {
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using R = typename ST::real;
+  static std::atomic<int> cached{0};
+  Step2Args a;
+  a.tiles_x = g.nx / TX;
+  a.tiles_y = 1;
+  a.row_bytes = g.pitch * (uint32_t)sizeof(W);
+  a.yrow_bytes = Lattice<kD2Q9>::Q * a.row_bytes;
+  a.plane_bytes = 0;
+  const uint64_t slots = (uint64_t)blocks_per_cu(cached, step2_2d_kernel<S, FM, TX>, Step2Shape2D<TX>::NT) * device_cus();
+  a.lz = step2_chunk(a.tiles_x, g.ny, slots);
+  const dim3 grid((unsigned)(a.tiles_x * ((g.ny + a.lz - 1) / a.lz)));
+  step2_2d_kernel<S, FM, TX><<<grid, Step2Shape2D<TX>::NT, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, a,
+                                                                    (R)omega);
+  return hipGetLastError();
 }
 
 template <int L, int S, int FM>
@@ -1068,10 +1258,23 @@ static hipError_t launch_step2_ls(const void* fin, void* fout, const void* force
     return hipErrorInvalidValue;
   } else {
     if (!step2_fits<L, S>(g)) return hipErrorInvalidValue;
-    if (!force || force_mode == kNoForce) return launch_step2_lsf<L, S, kNoForce>(fin, fout, nullptr, g, omega, s);
-    if (force_mode == kGuoForce) return launch_step2_lsf<L, S, kGuoForce>(fin, fout, force, g, omega, s);
-    if (force_mode == kShiftForce) return launch_step2_lsf<L, S, kShiftForce>(fin, fout, force, g, omega, s);
-    return hipErrorInvalidValue;
+    if (force_mode != kNoForce && force_mode != kGuoForce && force_mode != kShiftForce) return hipErrorInvalidValue;
+    const int fm = force ? force_mode : kNoForce;
+    if constexpr (L == kD2Q9) {
+      const bool wide = step2_2d_width(g) == 256;
+      if (fm == kNoForce)
+        return wide ? launch_step2_2d<S, kNoForce, 256>(fin, fout, nullptr, g, omega, s)
+                    : launch_step2_2d<S, kNoForce, 64>(fin, fout, nullptr, g, omega, s);
+      if (fm == kGuoForce)
+        return wide ? launch_step2_2d<S, kGuoForce, 256>(fin, fout, force, g, omega, s)
+                    : launch_step2_2d<S, kGuoForce, 64>(fin, fout, force, g, omega, s);
+      return wide ? launch_step2_2d<S, kShiftForce, 256>(fin, fout, force, g, omega, s)
+                  : launch_step2_2d<S, kShiftForce, 64>(fin, fout, force, g, omega, s);
+    } else {
+      if (fm == kNoForce) return launch_step2_lsf<L, S, kNoForce>(fin, fout, nullptr, g, omega, s);
+      if (fm == kGuoForce) return launch_step2_lsf<L, S, kGuoForce>(fin, fout, force, g, omega, s);
+      return launch_step2_lsf<L, S, kShiftForce>(fin, fout, force, g, omega, s);
+    }
   }
 }
 

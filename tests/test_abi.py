@@ -344,7 +344,12 @@ def _launches(B, g, n):
     ("D3Q19", "f16s", (64, 4, 3), 0, True),
     ("D3Q27", "bf16s", (256, 256, 256), 0, False),  # shifted BF16 steps singly
     ("D3Q27", "f64", (256, 256, 256), 0, False),
-    ("D2Q9", "f32", (256, 256, 1), 0, False),       # 2D
+    ("D2Q9", "f32", (256, 256, 1), 0, True),        # 2D: segments of 256 cells
+    ("D2Q9", "f64", (64, 64, 1), 0, True),          # segments of 64 cells
+    ("D2Q9", "f16s", (8192, 8192, 1), 0, True),
+    ("D2Q9", "f32", (96, 8, 1), 0, False),          # nx off the 64-cell segments
+    ("D2Q9", "f32", (64, 2, 1), 0, False),          # ny < 3
+    ("D2Q9", "bf16s", (256, 256, 1), 0, False),
     ("D3Q27", "f32", (48, 16, 8), 0, False),        # nx off the 32-cell tiles
     ("D3Q27", "f32", (32, 12, 8), 0, False),        # ny off the 8-row tiles
     ("D3Q27", "f32", (32, 8, 2), 0, False),         # nz < 3

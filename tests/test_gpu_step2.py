@@ -10,8 +10,9 @@ launches to the oracle directly.
 
 The shapes cover one tile (every neighbour wraps onto the tile itself), several tiles
 in x and y, the smallest nz (3), odd nz and z chunks with a ragged last chunk, padded
-rows, D3Q19, and shapes the kernel does not take (nx or ny off the tile grid, nz < 3),
-which must run as single steps with the same results.
+rows, D3Q19, D2Q9 (segments of x marching along y; nx a multiple of 64, ny >= 3), and
+shapes the kernels do not take (nx or ny off the tile grid, nz < 3), which must run as
+single steps with the same results.
 """
 import pytest
 import torch
@@ -36,21 +37,25 @@ CASES = [  # lattice, (nx, ny, nz), pitch (None = nx)
     ("D3Q27", (32, 8, 2), None),   # nz < 3
     ("D3Q27", (64, 4, 9), 128),    # 2-byte words: one 64 x 4 tile, padded rows
     ("D3Q27", (128, 12, 5), None),
+    ("D2Q9", (256, 20, 1), None),  # 2D: one 256-cell segment per row, chunks of rows
+    ("D2Q9", (64, 37, 1), None),   # 64-cell segments, odd ny
+    ("D2Q9", (128, 3, 1), 192),    # ny = 3, padded rows
+    ("D2Q9", (96, 8, 1), None),    # nx off the segments: single steps only
 ]
 
 
 def _setup(B, lat, shape, pitch, kind, mode, seed=31):
     st = olbm.stencil(lat)
     nx, ny, nz = shape
-    spatial = (nz, ny, nx)
+    spatial = (ny, nx) if st.D == 2 else (nz, ny, nx)
     grid = B.Grid(lat, kind, nx, ny, nz, pitch)
-    rho, u = synthetic.random_fields(spatial, 3, seed, drho=0.03, umax=0.06)
+    rho, u = synthetic.random_fields(spatial, st.D, seed, drho=0.03, umax=0.06)
     f = olbm.equilibrium(rho, u, st) * (1 + synthetic.random_normal((st.Q,) + spatial, seed + 1, 0.02))
     g = grid.to_layout(ost.quantize(f, st, kind)).cuda()
     field = None
     if mode != "none":
         scale = 1e-4 if mode == "guo" else 1e-3
-        field = synthetic.random_normal((3,) + spatial, seed + 2, scale).to(grid.real_dtype).cuda()
+        field = synthetic.random_normal((st.D,) + spatial, seed + 2, scale).to(grid.real_dtype).cuda()
     return st, grid, g, field
 
 
@@ -84,6 +89,34 @@ def test_paired_steps_equal_single_steps(lat, shape, pitch, kind, mode):
         ref = _singles(B, grid, g, 0.55, field, mode, n)
         same = torch.equal(bits(grid.from_layout(got.cpu())), bits(grid.from_layout(ref.cpu())))
         assert same, f"n_steps={n}"
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64", "f16s"])
+def test_paired_steps_d2q9_full_size_equal_single_steps(kind):
+    """8192^2 D2Q9 (the 2D benchmark grid, 32 segments of 256 cells per row): four steps
+    as two paired launches against four single steps, every word compared."""
+    need_gpu()
+    B = binding()
+    n = 8192
+    grid = B.Grid("D2Q9", kind, n, n)
+    say(f"paired steps D2Q9 {kind} {n}^2")
+    u = synthetic.taylor_green_2d(n, n, 0.05)
+    a = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u.cuda(), a)
+    del u
+    b = grid.empty_populations()
+    assert B.lbm_step(grid, a, b, 0.6, None, 1) == 0
+    start = b.clone()
+    x, y = b, a
+    for _ in range(4):
+        B.lbm_step(grid, x, y, 0.6, None, 1)
+        x, y = y, x
+    ref = x.clone()
+    p, q = start.clone(), y
+    assert B.lbm_step_launches(grid, 4) == (0, 2)
+    assert B.lbm_step(grid, p, q, 0.6, None, 4) == 1
+    torch.cuda.synchronize()
+    assert torch.equal(bits(p), bits(ref))
 
 
 def test_paired_steps_leave_pad_words_alone():
