@@ -93,7 +93,7 @@ def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = 
 
     if one_call:
         ms = time_launches(lambda: run(steps), 1, 1) / steps  # the warm-up call is `steps` steps too
-        single, paired = B.lbm_step_launches(grid, steps)
+        single, paired, _ = B.lbm_step_launches(grid, steps)  # 3D grids: at most two steps per launch
     else:
         ms = time_launches(lambda: run(1), steps, warmup)
         single, paired = steps, 0
@@ -164,6 +164,20 @@ def run_d2q9(B, steps: int, warmup: int, n: int = 8192):
             gbs = bpc * grid.ncells / (ms * 1e-3) / 1e9
             out[f"{kind}_{storage}"] = {"ms_per_step": ms, "mlups": grid.ncells / (ms * 1e-3) / 1e6,
                                         "bytes_per_cell": bpc, "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+            if kind == "bgk":  # the BGK step as one lbm_step call of `steps` steps (multi-step launches)
+                k4 = 8 * max(1, steps // 8)
+
+                def call():
+                    if B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], 0.6, None, k4) == 0:
+                        cur[0] ^= 1
+
+                ms2 = time_launches(call, 1, 1) / k4
+                gbs2 = bpc * grid.ncells / (ms2 * 1e-3) / 1e9
+                out[f"bgk_paired_{storage}"] = {"ms_per_step": ms2, "mlups": grid.ncells / (ms2 * 1e-3) / 1e6,
+                                                "bytes_per_cell": bpc, "hbm_gbs": gbs2,
+                                                "hbm_frac": gbs2 / PEAK_HBM_GBS,
+                                                "launches": dict(zip(("one_step", "two_step", "four_step"),
+                                                                     B.lbm_step_launches(grid, k4)))}
         del bufs, tg
         torch.cuda.empty_cache()
     out["grid"] = [n, n]
@@ -608,6 +622,16 @@ def profile_set(B, steps: int, warmup: int):
     B.lbm_init_equilibrium(grid, None, u2, bufs[0])
     p_dev = params.float().cuda()
     taus = [1, 1, 1, 0.6, 0.6, 0.6, 0.9, 0.8, 0.7]
+    # the D2Q9 two-step kernel: one lbm_step call of 4 * steps steps, after a warm-up
+    # call as long (bytes: the state read and written once per launch)
+    cur2 = [0]
+
+    def call2():
+        if B.lbm_step(grid, bufs[cur2[0]], bufs[1 - cur2[0]], 0.6, None, 4 * max(1, steps)) == 0:
+            cur2[0] ^= 1
+
+    report("two-step D2Q9 f32 8192^2", "step2_2d_kernel<F32, unforced, 256>", grid,
+           time_launches(call2, 1, 1) / (2 * max(1, steps)), B.bytes_per_cell_step(grid))
     for case, kname, fn in (
             ("step D2Q9 f32 8192^2", "step_kernel<D2Q9, F32, unforced>",
              lambda a, b: B.lbm_step(grid, a, b, 0.6, None, 1)),
@@ -834,7 +858,7 @@ def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic
             if name == "adjoint_local":
                 summ[f"{name}_{k}_hbm_frac"] = _r(v["hbm_frac"])
     d2 = detail.get("d2q9_8192") or {}
-    for k in ("bgk_f32", "bgk_f16s", "bgk_f64"):
+    for k in ("bgk_paired_f32", "bgk_paired_f16s", "bgk_paired_f64", "bgk_f32"):
         if k in d2:
             summ[f"d2q9_8192_{k}_mlups"] = _r(d2[k]["mlups"])
     if "moments_f32" in detail:

@@ -148,23 +148,26 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
  * f_in and f_out must not overlap; force must not overlap either.
  * Returns 0 if the result is in f_out (odd n_steps), 1 if it is in f_in (even
  * n_steps), or a negative lbm_status.
- * Launches: where the grid allows it (D3Q27 or D3Q19: FP32 or shifted-FP32 words with nx
- * a multiple of 32 and ny of 8, or shifted-FP16 words with nx a multiple of 64 and ny of
- * 4, nz >= 3, one z plane of words < 4 GiB; D2Q9: any kind but shifted BF16, nx a
- * multiple of 64, ny >= 3), pairs of steps run
- * as one launch of a kernel that keeps the intermediate state on chip: the state is
- * read and written once per two steps.  Its results equal single steps bit for bit;
- * the first n_steps mod 4 steps run singly so that the result stays in the buffer
- * named above.  Paired launches leave pad words untouched.  lbm_step_launches tells
- * how a call is split. */
+ * Launches: where the grid allows it, several steps run as one launch of a kernel that
+ * keeps the intermediate states on chip, so the state is read and written once per
+ * launch: two steps on D3Q27 and D3Q19 (FP32 or shifted-FP32 words with nx a multiple
+ * of 32 and ny of 8, or shifted-FP16 words with nx a multiple of 64 and ny of 4; nz >= 3;
+ * one z plane of words < 4 GiB), two or four on D2Q9 (any kind but shifted BF16, four
+ * for FP64, FP32 and shifted FP32; nx a multiple of 64; ny >= 3 for two, ny >= 5 for
+ * four).  Results equal single steps bit
+ * for bit.  Multi-step launches come in pairs of one kind (n_steps = 8 a + 4 b + c:
+ * 2a launches of four steps, 2b of two, c < 4 single steps first), so the result stays
+ * in the buffer named above.  Multi-step launches leave pad words untouched.
+ * lbm_step_launches tells how a call is split. */
 int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force,
              int n_steps, void* stream);
 
 /* How lbm_step (and lbm_step_shifted) split n_steps >= 1 into launches: *single
- * one-step launches followed by *paired two-step launches (single + 2 * paired =
- * n_steps; paired is even).  Host-only (no device work).  LBM_EINVAL for n_steps < 1 or
- * NULL outputs, grid errors as lbm_step. */
-int lbm_step_launches(const lbm_grid* grid, int n_steps, int* single, int* paired);
+ * one-step launches, then *paired two-step launches, then *quad four-step launches
+ * (single + 2 paired + 4 quad = n_steps; paired and quad are even).  Host-only (no
+ * device work).  LBM_EINVAL for n_steps < 1, LBM_ENULL for NULL outputs, grid errors as
+ * lbm_step. */
+int lbm_step_launches(const lbm_grid* grid, int n_steps, int* single, int* paired, int* quad);
 
 /* lbm_step with the flow-control forcing of Sec. 3.2 instead of a body force: the
  * equilibrium is evaluated at a locally shifted velocity, f^eq(rho, u + du), with

@@ -64,7 +64,7 @@ def _load() -> ctypes.CDLL:
         "lbm_init_equilibrium": (i32, [gp, vp, vp, vp, vp]),
         "lbm_step": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
         "lbm_step_shifted": (i32, [gp, vp, vp, dbl, vp, i32, vp]),
-        "lbm_step_launches": (i32, [gp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "lbm_step_launches": (i32, [gp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "lbm_step_mrt": (i32, [gp, vp, vp, ctypes.POINTER(dbl), vp, i32, vp]),
         "lbm_step_neural": (i32, [gp, vp, vp, dbl, vp, i32, i32, vp]),
         "lbm_stream_only": (i32, [gp, vp, vp, vp]),
@@ -365,13 +365,13 @@ def lbm_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
 
 
 def lbm_step_launches(grid: Grid, n_steps: int) -> tuple:
-    """(single, paired): how lbm_step splits n_steps into one-step launches and
-    two-step launches (host-side, no device work)."""
+    """(single, paired, quad): how lbm_step splits n_steps into one-step, two-step and
+    four-step launches (host-side, no device work)."""
     g = grid.c_struct()
-    single, paired = ctypes.c_int(), ctypes.c_int()
-    _check(_lib.lbm_step_launches(ctypes.byref(g), int(n_steps), ctypes.byref(single), ctypes.byref(paired)),
-           "lbm_step_launches")
-    return single.value, paired.value
+    single, paired, quad = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lib.lbm_step_launches(ctypes.byref(g), int(n_steps), ctypes.byref(single), ctypes.byref(paired),
+                                  ctypes.byref(quad)), "lbm_step_launches")
+    return single.value, paired.value, quad.value
 
 
 def lbm_moments_workspace_size(grid: Grid) -> int:

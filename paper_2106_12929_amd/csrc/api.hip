@@ -207,11 +207,21 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
 
 namespace {
 
-// Two-step launches of a call of n_steps: pairs of steps run as one launch where the
-// kernel supports the grid.  An even number of such launches leaves the result where
-// n_steps single steps leave it, so up to three steps run singly (first).
-int paired_launches(const lbm_grid* grid, const Geometry& geo, int n_steps) {
-  return lbm::step2_supported(grid->lattice, grid->storage, geo.args) ? 2 * (n_steps / 4) : 0;
+// Launches of a call of n_steps: steps run four (D2Q9) or two at a time where a kernel
+// takes the grid.  Each launch swaps the buffers, so the multi-step launches come in
+// pairs of equal kind, which leaves the result where n_steps single steps leave it:
+// n = 8 quads/2 + 4 pairs/2 + singles, with the singles (at most three) first.
+struct Plan {
+  int single, paired, quad;
+};
+Plan launch_plan(const lbm_grid* grid, const Geometry& geo, int n_steps) {
+  const int most = lbm::max_steps_per_launch(grid->lattice, grid->storage, geo.args);
+  Plan p{};
+  p.quad = most >= 4 ? 2 * (n_steps / 8) : 0;
+  const int rest = n_steps - 4 * p.quad;
+  p.paired = most >= 2 ? 2 * (rest / 4) : 0;
+  p.single = rest - 2 * p.paired;
+  return p;
 }
 
 int step_common(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* field, int force_mode,
@@ -230,18 +240,20 @@ int step_common(const lbm_grid* grid, void* f_in, void* f_out, double tau, const
     return fail(LBM_EALIAS, "the per-cell field overlaps a population buffer");
   const double omega = 1.0 / tau;
   const int mode = field ? force_mode : lbm::kNoForce;
-  const int pairs = paired_launches(grid, geo, n_steps);
+  const Plan plan = launch_plan(grid, geo, n_steps);
   void* bufs[2] = {f_in, f_out};
   int cur = 0;
-  for (int k = 0; k < n_steps - 2 * pairs; ++k, cur ^= 1) {
+  for (int k = 0; k < plan.single; ++k, cur ^= 1) {
     const hipError_t e = lbm::launch_step(grid->lattice, grid->storage, bufs[cur], bufs[cur ^ 1], field, mode,
                                           geo.args, omega, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, name);
   }
-  for (int k = 0; k < pairs; ++k, cur ^= 1) {
-    const hipError_t e = lbm::launch_step2(grid->lattice, grid->storage, bufs[cur], bufs[cur ^ 1], field, mode,
-                                           geo.args, omega, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, name);
+  for (int nst : {2, 4}) {
+    for (int k = 0; k < (nst == 2 ? plan.paired : plan.quad); ++k, cur ^= 1) {
+      const hipError_t e = lbm::launch_stepn(grid->lattice, grid->storage, nst, bufs[cur], bufs[cur ^ 1], field,
+                                             mode, geo.args, omega, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, name);
+    }
   }
   return (n_steps & 1) ? 0 : 1;
 }
@@ -260,13 +272,15 @@ int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, 
   return step_common(grid, f_in, f_out, tau, du, lbm::kShiftForce, n_steps, stream, "lbm_step_shifted launch");
 }
 
-int lbm_step_launches(const lbm_grid* grid, int n_steps, int* single, int* paired) {
+int lbm_step_launches(const lbm_grid* grid, int n_steps, int* single, int* paired, int* quad) {
   Geometry geo;
   LBM_TRY(check_grid(grid, &geo));
   if (n_steps < 1) return fail(LBM_EINVAL, "n_steps must be >= 1 (got %d)", n_steps);
-  if (!single || !paired) return fail(LBM_ENULL, "single and paired must not be NULL");
-  *paired = paired_launches(grid, geo, n_steps);
-  *single = n_steps - 2 * *paired;
+  if (!single || !paired || !quad) return fail(LBM_ENULL, "single, paired and quad must not be NULL");
+  const Plan p = launch_plan(grid, geo, n_steps);
+  *single = p.single;
+  *paired = p.paired;
+  *quad = p.quad;
   return LBM_OK;
 }
 

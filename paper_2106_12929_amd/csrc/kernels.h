@@ -33,12 +33,12 @@ struct Step2Args {
   uint32_t yrow_bytes;        // the Q direction rows of one grid row
   uint32_t plane_bytes;       // the ny grid rows of one z plane (< 2^32)
 };
-// Whether two steps of this lattice, storage kind and grid can run in one launch
-// (launch_step2); when they can, launch_step2(fin -> fout) equals launch_step twice
-// (fin -> tmp -> fout) bit for bit.
-bool step2_supported(int lattice, int storage, const GridArgs& g);
-hipError_t launch_step2(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
-                        const GridArgs& g, double omega, hipStream_t s);
+// The most steps one launch can advance for this lattice, storage kind and grid: 4
+// (the D2Q9 multi-step kernel), 2 (the two-step kernels) or 1.  For nst = 2 or 4 up to
+// that, launch_stepn(fin -> fout) equals nst launches of launch_step bit for bit.
+int max_steps_per_launch(int lattice, int storage, const GridArgs& g);
+hipError_t launch_stepn(int lattice, int storage, int nst, const void* fin, void* fout, const void* force,
+                        int force_mode, const GridArgs& g, double omega, hipStream_t s);
 hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s);
 hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
                        hipStream_t s);

@@ -281,25 +281,34 @@ __global__ __launch_bounds__((Step2Shape<L, S>::NT)) __attribute__((amdgpu_waves
 }
 
 // ---------------------------------------------------------------------------------
-// Two time steps per launch for D2Q9: the 2D form of step2_kernel.  A block owns a
-// segment of TX cells of x and a chunk of rows [yb, ye), and marches along y: per row p
-// its producer waves compute step t+1 on the segment and one cell on each side (TX + 2
-// columns, 1.008x the segment for TX = 256) into LDS slot k & 1, and its consumer waves
-// complete step t+2 of row p-1 from the LDS copies of rows p-2..p (a row gives the
-// c_y = -1 directions to the row below it, c_y = 0 to itself, c_y = +1 to the row
-// above).  Same rounding and collision as step_kernel, so the result equals two of its
-// launches bit for bit.
+// NST time steps per launch for D2Q9 (NST = 2 or 4): the 2D form of step2_kernel, with
+// a pipeline of NST stages.  A block owns a segment of TX cells of x and a chunk of
+// rows [yb, ye), and marches along y.  Stage s (s = 1..NST) advances the state by its
+// s-th step on the segment widened by NST - s cells on each side: stage 1 gathers from
+// HBM, stages 2..NST gather from the LDS ring the stage before wrote, the last stage
+// writes the result.  Each stage is a group of waves, one column per lane, and runs a
+// row behind the stage before: in iteration k it reads the row that stage completed in
+// iteration k - 1 (a row gives the c_y = -1 directions to the row below it, c_y = 0 to
+// itself, c_y = +1 to the row above; a lane keeps 3 + 6 values it has already read),
+// completes the row below it and writes it to its own ring (slot k & 1).  One barrier
+// per iteration.  Stage 1 loads the next row while it collides the current one.  The
+// intermediate words are rounded to storage as step_kernel stores them and each
+// collision is bgk_collide, so the result equals NST launches of step_kernel bit for
+// bit.  The widened segments recompute 2 (NST - s) cells per row and stage: 1.008x of
+// the work for NST = 2, TX = 256 and 1.023x for NST = 4, TX = 128.
 // ---------------------------------------------------------------------------------
-template <int TX>
-struct Step2Shape2D {
-  static constexpr int NS = TX + 2;          // segment plus one cell on each side
-  static constexpr int NP = (NS + 63) / 64;  // producer waves
-  static constexpr int NC = TX / 64;         // consumer waves
-  static constexpr int NT = 64 * (NP + NC);
+template <int TX, int NST>
+struct StepNShape2D {
+  static constexpr int width(int s) { return TX + 2 * (NST - s); }  // columns of stage s
+  static constexpr int waves(int s) { return (width(s) + 63) / 64; }
+  static constexpr int first_wave(int s) { return s == 1 ? 0 : first_wave(s - 1) + waves(s - 1); }
+  static constexpr int ring(int s) { return s == 1 ? 0 : ring(s - 1) + 2 * 9 * width(s - 1); }  // words
+  static constexpr int NT = 64 * first_wave(NST + 1);
+  static constexpr int LDS_WORDS = ring(NST);  // rings of stages 1 .. NST-1
 };
 
-template <int S, int FM, int TX>
-__global__ __launch_bounds__((Step2Shape2D<TX>::NT)) void step2_2d_kernel(
+template <int S, int FM, int TX, int NST>
+__global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
     const typename Storage<S>::word* __restrict__ fin, typename Storage<S>::word* __restrict__ fout,
     const typename Storage<S>::real* __restrict__ force, GridArgs g, Step2Args a, typename Storage<S>::real omega) {
   using LT = Lattice<kD2Q9>;
@@ -307,10 +316,9 @@ __global__ __launch_bounds__((Step2Shape2D<TX>::NT)) void step2_2d_kernel(
   using W = typename ST::word;
   using real = typename ST::real;
   using CO = Coef<kD2Q9, real>;
-  using SH = Step2Shape2D<TX>;
+  using SH = StepNShape2D<TX, NST>;
   constexpr int Q = LT::Q;
-  constexpr int NS = SH::NS, NP = SH::NP;
-  __shared__ W slot[2][Q][NS];
+  __shared__ W lds[SH::LDS_WORDS];
 
   // XCD-aware block order, as in step2_kernel: consecutive segments on one XCD
   const uint32_t nb = gridDim.x, b = blockIdx.x;
@@ -320,14 +328,18 @@ __global__ __launch_bounds__((Step2Shape2D<TX>::NT)) void step2_2d_kernel(
   const uint32_t x0 = tx * TX;
   const uint32_t yb = yc * a.lz;
   const uint32_t ye = min(yb + a.lz, g.ny);
-  const uint32_t nrows = ye - yb + 2;  // step t+1 on rows yb-1 .. ye
+  const uint32_t iters = (ye - yb) + 3 * (NST - 1);
+  const int r0 = (int)yb - (NST - 1);  // stage 1 produces row r0 + k in iteration k
   const uint32_t t = threadIdx.x;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(t / 64);
   const char* fb = reinterpret_cast<const char*>(fin);
   char* ob = reinterpret_cast<char*>(fout);
-  // rows yb-2 .. ye+2 wrapped (ny >= 3)
+  // rows yb-NST .. ye+NST wrapped (ny > NST)
   auto wrapy = [&](int y) -> uint32_t {
     return (uint32_t)(y < 0 ? y + (int)g.ny : (y >= (int)g.ny ? y - (int)g.ny : y));
+  };
+  auto wrapx = [&](int x) -> uint32_t {
+    return (uint32_t)(x < 0 ? x + (int)g.nx : (x >= (int)g.nx ? x - (int)g.nx : x));
   };
   auto load_force = [&](uint32_t y, uint32_t x, real& Fx, real& Fy) {
     if constexpr (FM != kNoForce) {
@@ -336,105 +348,135 @@ __global__ __launch_bounds__((Step2Shape2D<TX>::NT)) void step2_2d_kernel(
       Fy = f[g.ncells];
     }
   };
+  // word of direction i, column j of the ring of stage s, slot sl
+  auto ring_at = [&](int s, int sl, int i, int j) -> W& {
+    return lds[SH::ring(s) + (sl * Q + i) * SH::width(s) + j];
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
 
-  if (wave < (uint32_t)NP) {
-    // Producer lane: column s of the segment with its ring (lanes past it compute
-    // column NS - 1 again and write nothing).
-    const bool live = t < (uint32_t)NS;
-    const uint32_t s = min(t, (uint32_t)NS - 1);
-    int xi = (int)x0 - 1 + (int)s;
-    xi += xi < 0 ? (int)g.nx : (xi >= (int)g.nx ? -(int)g.nx : 0);
-    const uint32_t x = xi;
+  if (wave < (uint32_t)SH::waves(1)) {
+    // Stage 1: column s1 of the widest segment, from HBM.
+    constexpr int WID = SH::width(1);
+    const bool live = t < (uint32_t)WID;
+    const uint32_t j = min(t, (uint32_t)WID - 1);
+    const uint32_t x = wrapx((int)x0 - (NST - 1) + (int)j);
     const uint32_t xb[3] = {wrap_inc(x, g.nx) * (uint32_t)sizeof(W), x * (uint32_t)sizeof(W),
                             wrap_dec(x, g.nx) * (uint32_t)sizeof(W)};
+    const uint32_t rows = (ye - yb) + 2 * (NST - 1);
     auto load = [&](int py, W (&r)[Q]) {
+      py = min(py, r0 + (int)rows - 1);  // the loads past the last row read that row again
       const char* base[3] = {fb + (uint64_t)wrapy(py + 1) * a.yrow_bytes, fb + (uint64_t)wrapy(py) * a.yrow_bytes,
                              fb + (uint64_t)wrapy(py - 1) * a.yrow_bytes};
 #pragma unroll
       for (int i = 0; i < Q; ++i)
         r[i] = *reinterpret_cast<const W*>(base[LT::cy(i) + 1] + (uint64_t)i * a.row_bytes + xb[LT::cx(i) + 1]);
     };
-    auto produce = [&](int py, W (&r)[Q], auto sl) {
+    auto produce = [&](uint32_t k, W (&r)[Q], auto sl) {
       constexpr int SL = decltype(sl)::value;
-      real d[Q];
+      if (k < rows) {
+        real d[Q];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
-      real Fx = 0, Fy = 0;
-      load_force(wrapy(py), x, Fx, Fy);
-      bgk_collide<kD2Q9, real, FM>(d, Fx, Fy, real(0), omega);
-      if (live) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) slot[SL][i][s] = ST::from_dev(d[i], CO::W(i));
-      }
-    };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    W r0[Q], r1[Q];
-    load((int)yb - 1, r0);
-    uint32_t k = 0;
-    for (; k + 1 < nrows; k += 2) {  // row yb-1+k into slot 0, the next into slot 1
-      load((int)(yb + k), r1);
-      produce((int)(yb + k) - 1, r0, I0());
-      __syncthreads();
-      load((int)(yb + k) + 1, r0);  // one row past ye on the last pass: read, unused
-      produce((int)(yb + k), r1, I1());
-      __syncthreads();
-    }
-    if (k < nrows) {
-      produce((int)(yb + k) - 1, r0, I0());
-      __syncthreads();
-    }
-    __syncthreads();  // the consumers' last row
-  } else {
-    // Consumer lane: output cell x0 + u.
-    const uint32_t u = t - 64u * NP;
-    const uint32_t out_off = (x0 + u) * (uint32_t)sizeof(W);
-    const uint32_t l0 = u + 1;  // own column in the LDS segment
-    real dA[Q], dB[Q], dC[Q];  // outputs q - 1, q, q + 1 of the row q just read
-#pragma unroll
-    for (int i = 0; i < Q; ++i) dA[i] = dB[i] = dC[i] = 0;
-    auto consume = [&](int qy, auto sl, auto emit) {
-      constexpr int SL = decltype(sl)::value;
-      constexpr bool EMIT = decltype(emit)::value;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const real v = ST::to_dev(slot[SL][i][l0 - LT::cx(i)], CO::W(i));
-        if (LT::cy(i) < 0) dA[i] = v;
-        if (LT::cy(i) == 0) dB[i] = v;
-        if (LT::cy(i) > 0) dC[i] = v;
-      }
-      if constexpr (EMIT) {
+        for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
         real Fx = 0, Fy = 0;
-        load_force((uint32_t)(qy - 1), x0 + u, Fx, Fy);
-        bgk_collide<kD2Q9, real, FM>(dA, Fx, Fy, real(0), omega);
-        char* o = ob + (uint64_t)(qy - 1) * a.yrow_bytes + out_off;
+        load_force(wrapy(r0 + (int)k), x, Fx, Fy);
+        bgk_collide<kD2Q9, real, FM>(d, Fx, Fy, real(0), omega);
+        if (live) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-          store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes), ST::from_dev(dA[i], CO::W(i)));
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        if (LT::cy(i) >= 0) dA[i] = dB[i];
-        if (LT::cy(i) > 0) dB[i] = dC[i];
+          for (int i = 0; i < Q; ++i) ring_at(1, SL, i, j) = ST::from_dev(d[i], CO::W(i));
+        }
       }
     };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    __syncthreads();  // row yb-1 written
-    consume((int)yb - 1, I0(), std::false_type());
-    __syncthreads();
-    consume((int)yb, I1(), std::false_type());
-    __syncthreads();
-    uint32_t k = 2;  // rows read so far; row yb-1+k completes output yb-2+k
-    for (; k + 1 < nrows; k += 2) {
-      consume((int)(yb + k) - 1, I0(), std::true_type());
+    W ra[Q], rb[Q];
+    load(r0, ra);
+    uint32_t k = 0;
+    for (; k + 1 < iters; k += 2) {
+      load(r0 + (int)k + 1, rb);
+      produce(k, ra, I0());
       __syncthreads();
-      consume((int)(yb + k), I1(), std::true_type());
+      load(r0 + (int)k + 2, ra);
+      produce(k + 1, rb, I1());
       __syncthreads();
     }
-    if (k < nrows) {
-      consume((int)(yb + k) - 1, I0(), std::true_type());
+    if (k < iters) {
+      produce(k, ra, I0());
       __syncthreads();
+    }
+  } else {
+    // Stages 2 .. NST: find this wave's stage (wave-uniform).
+    auto run_stage = [&](auto stage) {
+      constexpr int ST_ = decltype(stage)::value;
+      constexpr int WID = SH::width(ST_), PWID = SH::width(ST_ - 1);
+      constexpr bool LAST = ST_ == NST;
+      const uint32_t lane = t - 64u * SH::first_wave(ST_);
+      const bool live = lane < (uint32_t)WID;
+      const uint32_t j = min(lane, (uint32_t)WID - 1);
+      const uint32_t x = wrapx((int)x0 - (NST - ST_) + (int)j);
+      const uint32_t out_off = x * (uint32_t)sizeof(W);
+      // reads rows completed by stage ST_-1 in iterations [3 (ST_-2), ...), i.e. from
+      // iteration k0 = 3 (ST_-2) + 1, and completes a row from iteration k0 + 2
+      constexpr uint32_t k0 = 3 * (ST_ - 2) + 1;
+      const uint32_t rows = (ye - yb) + 2 * (NST - ST_);
+      real dA[Q], dB[Q], dC[Q];  // rows q - 1, q, q + 1 of the row q just read
+#pragma unroll
+      for (int i = 0; i < Q; ++i) dA[i] = dB[i] = dC[i] = 0;
+      auto step = [&](uint32_t k, auto sl) {
+        constexpr int SL = decltype(sl)::value;  // slot written in iteration k (k & 1)
+        if (k < k0 || k >= k0 + 2 + rows) return;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const real v = ST::to_dev(ring_at(ST_ - 1, 1 - SL, i, (int)j + 1 - LT::cx(i)), CO::W(i));
+          if (LT::cy(i) < 0) dA[i] = v;
+          if (LT::cy(i) == 0) dB[i] = v;
+          if (LT::cy(i) > 0) dC[i] = v;
+        }
+        if (k >= k0 + 2) {
+          // the row completed here: stage ST_ produces row r0 + k - 2 (ST_ - 1)
+          const int row = r0 + (int)k - 2 * (ST_ - 1);
+          real Fx = 0, Fy = 0;
+          load_force(wrapy(row), x, Fx, Fy);
+          bgk_collide<kD2Q9, real, FM>(dA, Fx, Fy, real(0), omega);
+          if constexpr (LAST) {
+            if (live) {
+              char* o = ob + (uint64_t)row * a.yrow_bytes + out_off;
+#pragma unroll
+              for (int i = 0; i < Q; ++i)
+                store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes), ST::from_dev(dA[i], CO::W(i)));
+            }
+          } else if (live) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) ring_at(ST_, SL, i, j) = ST::from_dev(dA[i], CO::W(i));
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          if (LT::cy(i) >= 0) dA[i] = dB[i];
+          if (LT::cy(i) > 0) dB[i] = dC[i];
+        }
+      };
+      uint32_t k = 0;
+      for (; k + 1 < iters; k += 2) {
+        step(k, I0());
+        __syncthreads();
+        step(k + 1, I1());
+        __syncthreads();
+      }
+      if (k < iters) {
+        step(k, I0());
+        __syncthreads();
+      }
+      (void)PWID;
+    };
+    if constexpr (NST == 2) {
+      run_stage(std::integral_constant<int, 2>());
+    } else {
+      static_assert(NST == 4, "2 or 4 stages");
+      if (wave < (uint32_t)SH::first_wave(3))
+        run_stage(std::integral_constant<int, 2>());
+      else if (wave < (uint32_t)SH::first_wave(4))
+        run_stage(std::integral_constant<int, 3>());
+      else
+        run_stage(std::integral_constant<int, 4>());
     }
   }
 }
@@ -1140,8 +1182,10 @@ constexpr bool step2_enabled() {
   return (L == kD3Q27 || L == kD3Q19) && (S == kF32 || S == kF32S || S == kF16S);
 }
 
-// Segment width of the D2Q9 two-step kernel for a grid (0: none fits).
-static uint32_t step2_2d_width(const GridArgs& g) {
+// Segment width of the D2Q9 multi-step kernel advancing nst steps (0: none fits).
+static uint32_t stepn_2d_width(const GridArgs& g, int nst) {
+  if (g.ny < (uint32_t)nst + 1) return 0;  // rows wrap once at most
+  if (nst == 4) return g.nx % 128 == 0 ? 128 : g.nx % 64 == 0 ? 64 : 0;
   return g.nx % 256 == 0 ? 256 : g.nx % 64 == 0 ? 64 : 0;
 }
 
@@ -1150,7 +1194,7 @@ static bool step2_fits(const GridArgs& g) {
   if constexpr (!step2_enabled<L, S>()) {
     return false;
   } else if constexpr (L == kD2Q9) {
-    return g.ghost == 0 && g.z0 == 0 && g.nzl == g.nz && step2_2d_width(g) != 0 && g.ny >= 3;
+    return g.ghost == 0 && g.z0 == 0 && g.nzl == g.nz && stepn_2d_width(g, 2) != 0;
   } else {
     using SH = Step2Shape<L, S>;
     const uint64_t plane = (uint64_t)g.ny * Lattice<L>::Q * g.pitch * sizeof(typename Storage<S>::word);
@@ -1172,16 +1216,17 @@ static uint32_t device_cus() {
   return (uint32_t)n;
 }
 
-// Planes per z chunk: the length that minimises rounds * (lz + 2), the duration of the
-// launch if each block takes lz + 2 plane-times (its chunk plus the two planes of step
-// t+1 below and above it) and `slots` blocks run at once.
-static uint32_t step2_chunk(uint64_t tiles, uint32_t nz, uint64_t slots) {
+// Planes (rows in 2D) per chunk: the length that minimises rounds * (lz + extra), the
+// duration of the launch if each block takes lz + extra plane-times (its chunk plus the
+// planes its pipeline fills and drains: 2 for the 3D two-step kernel, 3 (NST - 1) for
+// the 2D NST-step kernel) and `slots` blocks run at once.
+static uint32_t step2_chunk(uint64_t tiles, uint32_t nz, uint64_t slots, uint32_t extra) {
   uint32_t best = nz;
   uint64_t best_cost = ~uint64_t(0);
   for (uint32_t lz = 8;; lz += 8) {
     const uint32_t l = lz < nz ? lz : nz;
     const uint64_t blocks = tiles * ((nz + l - 1) / l);
-    const uint64_t cost = ((blocks + slots - 1) / slots) * (l + 2);
+    const uint64_t cost = ((blocks + slots - 1) / slots) * (l + extra);
     if (cost < best_cost) {
       best_cost = cost;
       best = l;
@@ -1210,8 +1255,8 @@ static uint32_t step2_blocks_per_cu() {
   return blocks_per_cu(cached, step2_kernel<L, S, FM>, Step2Shape<L, S>::NT);
 }
 
-template <int S, int FM, int TX>
-static hipError_t launch_step2_2d(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
+template <int S, int FM, int TX, int NST>
+static hipError_t launch_stepn_2d(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
                                   hipStream_t s) {
   using ST = Storage<S>;
   using W = typename ST::word;
@@ -1223,12 +1268,21 @@ static hipError_t launch_step2_2d(const void* fin, void* fout, const void* force
   a.row_bytes = g.pitch * (uint32_t)sizeof(W);
   a.yrow_bytes = Lattice<kD2Q9>::Q * a.row_bytes;
   a.plane_bytes = 0;
-  const uint64_t slots = (uint64_t)blocks_per_cu(cached, step2_2d_kernel<S, FM, TX>, Step2Shape2D<TX>::NT) * device_cus();
-  a.lz = step2_chunk(a.tiles_x, g.ny, slots);
+  const uint64_t slots =
+      (uint64_t)blocks_per_cu(cached, stepn_2d_kernel<S, FM, TX, NST>, StepNShape2D<TX, NST>::NT) * device_cus();
+  a.lz = step2_chunk(a.tiles_x, g.ny, slots, 3 * (NST - 1));
   const dim3 grid((unsigned)(a.tiles_x * ((g.ny + a.lz - 1) / a.lz)));
-  step2_2d_kernel<S, FM, TX><<<grid, Step2Shape2D<TX>::NT, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, a,
-                                                                    (R)omega);
+  stepn_2d_kernel<S, FM, TX, NST><<<grid, StepNShape2D<TX, NST>::NT, 0, s>>>((const W*)fin, (W*)fout,
+                                                                             (const R*)force, g, a, (R)omega);
   return hipGetLastError();
+}
+
+template <int S, int FM, int NST>
+static hipError_t launch_stepn_2d_w(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
+                                    hipStream_t s) {
+  constexpr int WIDE = NST == 4 ? 128 : 256;
+  if (stepn_2d_width(g, NST) == WIDE) return launch_stepn_2d<S, FM, WIDE, NST>(fin, fout, force, g, omega, s);
+  return launch_stepn_2d<S, FM, 64, NST>(fin, fout, force, g, omega, s);
 }
 
 template <int L, int S, int FM>
@@ -1245,32 +1299,33 @@ static hipError_t launch_step2_lsf(const void* fin, void* fout, const void* forc
   a.yrow_bytes = Lattice<L>::Q * a.row_bytes;
   a.plane_bytes = g.ny * a.yrow_bytes;
   const uint64_t tiles = (uint64_t)a.tiles_x * a.tiles_y;
-  a.lz = step2_chunk(tiles, g.nz, (uint64_t)step2_blocks_per_cu<L, S, FM>() * device_cus());
+  a.lz = step2_chunk(tiles, g.nz, (uint64_t)step2_blocks_per_cu<L, S, FM>() * device_cus(), 2);
   const dim3 grid((unsigned)(tiles * ((g.nz + a.lz - 1) / a.lz)));
   step2_kernel<L, S, FM><<<grid, SH::NT, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, a, (R)omega);
   return hipGetLastError();
 }
 
 template <int L, int S>
-static hipError_t launch_step2_ls(const void* fin, void* fout, const void* force, int force_mode, const GridArgs& g,
-                                  double omega, hipStream_t s) {
+static hipError_t launch_stepn_ls(int nst, const void* fin, void* fout, const void* force, int force_mode,
+                                  const GridArgs& g, double omega, hipStream_t s) {
   if constexpr (!step2_enabled<L, S>()) {
     return hipErrorInvalidValue;
   } else {
-    if (!step2_fits<L, S>(g)) return hipErrorInvalidValue;
+    if (!step2_fits<L, S>(g) || (nst != 2 && nst != 4)) return hipErrorInvalidValue;
+    if (nst == 4 && (L != kD2Q9 || stepn_2d_width(g, 4) == 0)) return hipErrorInvalidValue;
     if (force_mode != kNoForce && force_mode != kGuoForce && force_mode != kShiftForce) return hipErrorInvalidValue;
     const int fm = force ? force_mode : kNoForce;
     if constexpr (L == kD2Q9) {
-      const bool wide = step2_2d_width(g) == 256;
-      if (fm == kNoForce)
-        return wide ? launch_step2_2d<S, kNoForce, 256>(fin, fout, nullptr, g, omega, s)
-                    : launch_step2_2d<S, kNoForce, 64>(fin, fout, nullptr, g, omega, s);
-      if (fm == kGuoForce)
-        return wide ? launch_step2_2d<S, kGuoForce, 256>(fin, fout, force, g, omega, s)
-                    : launch_step2_2d<S, kGuoForce, 64>(fin, fout, force, g, omega, s);
-      return wide ? launch_step2_2d<S, kShiftForce, 256>(fin, fout, force, g, omega, s)
-                  : launch_step2_2d<S, kShiftForce, 64>(fin, fout, force, g, omega, s);
+      if (nst == 4) {
+        if (fm == kNoForce) return launch_stepn_2d_w<S, kNoForce, 4>(fin, fout, nullptr, g, omega, s);
+        if (fm == kGuoForce) return launch_stepn_2d_w<S, kGuoForce, 4>(fin, fout, force, g, omega, s);
+        return launch_stepn_2d_w<S, kShiftForce, 4>(fin, fout, force, g, omega, s);
+      }
+      if (fm == kNoForce) return launch_stepn_2d_w<S, kNoForce, 2>(fin, fout, nullptr, g, omega, s);
+      if (fm == kGuoForce) return launch_stepn_2d_w<S, kGuoForce, 2>(fin, fout, force, g, omega, s);
+      return launch_stepn_2d_w<S, kShiftForce, 2>(fin, fout, force, g, omega, s);
     } else {
+      if (nst != 2) return hipErrorInvalidValue;
       if (fm == kNoForce) return launch_step2_lsf<L, S, kNoForce>(fin, fout, nullptr, g, omega, s);
       if (fm == kGuoForce) return launch_step2_lsf<L, S, kGuoForce>(fin, fout, force, g, omega, s);
       return launch_step2_lsf<L, S, kShiftForce>(fin, fout, force, g, omega, s);
@@ -1278,9 +1333,14 @@ static hipError_t launch_step2_ls(const void* fin, void* fout, const void* force
   }
 }
 
+// Four steps per launch on D2Q9 for FP64, FP32 and shifted FP32 (8192^2: 2.8-3.2x two
+// single steps' rate, against 1.7-1.8x for two steps per launch); shifted FP16 ran
+// slower with four (226.6k against 243.7k MLUPS: its conversions make the deeper
+// pipeline arithmetic-bound) and takes two.
 template <int L, int S>
-static hipError_t step2_fits_ls(const GridArgs& g, bool* ok) {
-  *ok = step2_fits<L, S>(g);
+static hipError_t max_steps_ls(const GridArgs& g, int* n) {
+  constexpr bool FOUR = L == kD2Q9 && (S == kF64 || S == kF32 || S == kF32S);
+  *n = !step2_fits<L, S>(g) ? 1 : (FOUR && stepn_2d_width(g, 4) != 0) ? 4 : 2;
   return hipSuccess;
 }
 
@@ -1448,15 +1508,15 @@ hipError_t launch_step(int lattice, int storage, const void* fin, void* fout, co
   LBM_DISPATCH(launch_step_ls, lattice, storage, fin, fout, force, force_mode, g, omega, s);
 }
 
-bool step2_supported(int lattice, int storage, const GridArgs& g) {
-  bool ok = false;
-  auto check = [&]() -> hipError_t { LBM_DISPATCH(step2_fits_ls, lattice, storage, g, &ok); };
-  return check() == hipSuccess && ok;
+int max_steps_per_launch(int lattice, int storage, const GridArgs& g) {
+  int n = 1;
+  auto check = [&]() -> hipError_t { LBM_DISPATCH(max_steps_ls, lattice, storage, g, &n); };
+  return check() == hipSuccess ? n : 1;
 }
 
-hipError_t launch_step2(int lattice, int storage, const void* fin, void* fout, const void* force, int force_mode,
-                        const GridArgs& g, double omega, hipStream_t s) {
-  LBM_DISPATCH(launch_step2_ls, lattice, storage, fin, fout, force, force_mode, g, omega, s);
+hipError_t launch_stepn(int lattice, int storage, int nst, const void* fin, void* fout, const void* force,
+                        int force_mode, const GridArgs& g, double omega, hipStream_t s) {
+  LBM_DISPATCH(launch_stepn_ls, lattice, storage, nst, fin, fout, force, force_mode, g, omega, s);
 }
 
 hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, const void* lam_next, void* lam_out,

@@ -330,51 +330,56 @@ def test_moments_noalloc_validation(B):
 
 
 def _launches(B, g, n):
-    single, paired = ctypes.c_int(-1), ctypes.c_int(-1)
-    rc = B._lib.lbm_step_launches(ctypes.byref(g), n, ctypes.byref(single), ctypes.byref(paired))
-    return rc, single.value, paired.value
+    single, paired, quad = ctypes.c_int(-1), ctypes.c_int(-1), ctypes.c_int(-1)
+    rc = B._lib.lbm_step_launches(ctypes.byref(g), n, ctypes.byref(single), ctypes.byref(paired), ctypes.byref(quad))
+    return rc, single.value, paired.value, quad.value
 
 
-@pytest.mark.parametrize("lattice,storage,dims,pitch,pairs", [
-    ("D3Q27", "f32", (256, 256, 256), 0, True),
-    ("D3Q27", "f32s", (32, 8, 3), 0, True),
-    ("D3Q19", "f32", (64, 16, 11), 128, True),
-    ("D3Q27", "f16s", (256, 256, 256), 0, True),    # 2-byte words: 64 x 4 tiles
-    ("D3Q27", "f16s", (32, 8, 8), 0, False),
-    ("D3Q19", "f16s", (64, 4, 3), 0, True),
-    ("D3Q27", "bf16s", (256, 256, 256), 0, False),  # shifted BF16 steps singly
-    ("D3Q27", "f64", (256, 256, 256), 0, False),
-    ("D2Q9", "f32", (256, 256, 1), 0, True),        # 2D: segments of 256 cells
-    ("D2Q9", "f64", (64, 64, 1), 0, True),          # segments of 64 cells
-    ("D2Q9", "f16s", (8192, 8192, 1), 0, True),
-    ("D2Q9", "f32", (96, 8, 1), 0, False),          # nx off the 64-cell segments
-    ("D2Q9", "f32", (64, 2, 1), 0, False),          # ny < 3
-    ("D2Q9", "bf16s", (256, 256, 1), 0, False),
-    ("D3Q27", "f32", (48, 16, 8), 0, False),        # nx off the 32-cell tiles
-    ("D3Q27", "f32", (32, 12, 8), 0, False),        # ny off the 8-row tiles
-    ("D3Q27", "f32", (32, 8, 2), 0, False),         # nz < 3
-    ("D3Q27", "f32", (32, 8, 4), 4971027, False),   # one z plane of words: 2^32 + 32 bytes
-    ("D3Q27", "f32", (32, 8, 4), 4971026, True),    # 2^32 - 832 bytes
+@pytest.mark.parametrize("lattice,storage,dims,pitch,most", [
+    ("D3Q27", "f32", (256, 256, 256), 0, 2),
+    ("D3Q27", "f32s", (32, 8, 3), 0, 2),
+    ("D3Q19", "f32", (64, 16, 11), 128, 2),
+    ("D3Q27", "f16s", (256, 256, 256), 0, 2),    # 2-byte words: 64 x 4 tiles
+    ("D3Q27", "f16s", (32, 8, 8), 0, 1),
+    ("D3Q19", "f16s", (64, 4, 3), 0, 2),
+    ("D3Q27", "bf16s", (256, 256, 256), 0, 1),   # shifted BF16 steps singly
+    ("D3Q27", "f64", (256, 256, 256), 0, 1),
+    ("D2Q9", "f32", (256, 256, 1), 0, 4),        # 2D: four steps per launch
+    ("D2Q9", "f64", (64, 64, 1), 0, 4),
+    ("D2Q9", "f16s", (8192, 8192, 1), 0, 2),     # shifted FP16: two steps per launch
+    ("D2Q9", "f32", (128, 4, 1), 0, 2),          # ny < 5: two steps per launch
+    ("D2Q9", "f32", (64, 3, 1), 192, 2),
+    ("D2Q9", "f32", (96, 8, 1), 0, 1),           # nx off the 64-cell segments
+    ("D2Q9", "f32", (64, 2, 1), 0, 1),           # ny < 3
+    ("D2Q9", "bf16s", (256, 256, 1), 0, 1),
+    ("D3Q27", "f32", (48, 16, 8), 0, 1),         # nx off the 32-cell tiles
+    ("D3Q27", "f32", (32, 12, 8), 0, 1),         # ny off the 8-row tiles
+    ("D3Q27", "f32", (32, 8, 2), 0, 1),          # nz < 3
+    ("D3Q27", "f32", (32, 8, 4), 4971027, 1),    # one z plane of words: 2^32 + 32 bytes
+    ("D3Q27", "f32", (32, 8, 4), 4971026, 2),    # 2^32 - 832 bytes
 ])
-def test_step_launch_plan(B, lattice, storage, dims, pitch, pairs):
-    """lbm_step's split into one-step and two-step launches: an even number of paired
-    launches after n_steps mod 4 single steps, on the grids the two-step kernel takes;
-    single steps everywhere else."""
+def test_step_launch_plan(B, lattice, storage, dims, pitch, most):
+    """lbm_step's split into one-, two- and four-step launches: the multi-step
+    launches in pairs of one kind (so that the result stays where single steps leave it)
+    after n_steps mod 4 single steps, on the grids the kernels take; single steps
+    everywhere else."""
     g = _grid(B, lattice=lattice, storage=storage, nx=dims[0], ny=dims[1], nz=dims[2], pitch=pitch)
-    for n in (1, 2, 3, 4, 5, 6, 7, 8, 9, 1000, 1001, 1003):
-        rc, single, paired = _launches(B, g, n)
+    for n in (1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 19, 1000, 1001, 1003):
+        rc, single, paired, quad = _launches(B, g, n)
         assert rc == 0
-        assert single + 2 * paired == n
-        if pairs:
-            assert (single, paired) == (n % 4, 2 * (n // 4)), n
+        assert single + 2 * paired + 4 * quad == n
+        if most == 4:
+            assert (quad, paired, single) == (2 * (n // 8), 2 * ((n % 8) // 4), n % 4), n
+        elif most == 2:
+            assert (quad, paired, single) == (0, 2 * (n // 4), n % 4), n
         else:
-            assert (single, paired) == (n, 0), n
-    if pairs:
-        assert B.lbm_step_launches(B.Grid(lattice, storage, *dims, pitch or None), 1000) == (0, 500)
+            assert (quad, paired, single) == (0, 0, n), n
+    expect = {4: (0, 0, 250), 2: (0, 500, 0), 1: (1000, 0, 0)}[most]
+    assert B.lbm_step_launches(B.Grid(lattice, storage, *dims, pitch or None), 1000) == expect
 
 
 def test_step_launch_plan_validation(B):
     g = _grid(B)
     assert _launches(B, g, 0)[0] == -1
-    assert B._lib.lbm_step_launches(ctypes.byref(g), 4, None, None) == -2
+    assert B._lib.lbm_step_launches(ctypes.byref(g), 4, None, None, None) == -2
     assert _launches(B, _grid(B, nx=0), 4)[0] == -1

@@ -41,6 +41,8 @@ CASES = [  # lattice, (nx, ny, nz), pitch (None = nx)
     ("D2Q9", (64, 37, 1), None),   # 64-cell segments, odd ny
     ("D2Q9", (128, 3, 1), 192),    # ny = 3, padded rows
     ("D2Q9", (96, 8, 1), None),    # nx off the segments: single steps only
+    ("D2Q9", (128, 5, 1), 192),    # four steps per launch at the smallest ny
+    ("D2Q9", (64, 4, 1), None),    # ny = 4: two steps per launch only
 ]
 
 
@@ -83,7 +85,7 @@ def test_paired_steps_equal_single_steps(lat, shape, pitch, kind, mode):
     B = binding()
     say(f"paired steps {lat} {shape} pitch {pitch} {kind} {mode}")
     st, grid, g, field = _setup(B, lat, shape, pitch, kind, mode)
-    for n in (4, 7, 8, 10):
+    for n in (4, 7, 8, 10, 19):
         got, where = _run(B, grid, g, 0.55, field, mode, n)
         assert where == (0 if n % 2 else 1), n
         ref = _singles(B, grid, g, 0.55, field, mode, n)
@@ -93,8 +95,10 @@ def test_paired_steps_equal_single_steps(lat, shape, pitch, kind, mode):
 
 @pytest.mark.parametrize("kind", ["f32", "f64", "f16s"])
 def test_paired_steps_d2q9_full_size_equal_single_steps(kind):
-    """8192^2 D2Q9 (the 2D benchmark grid, 32 segments of 256 cells per row): four steps
-    as two paired launches against four single steps, every word compared."""
+    """8192^2 D2Q9 (the 2D benchmark grid): eight steps as two four-step launches (64
+    segments of 128 cells per row; four two-step launches for shifted FP16) and four
+    steps as two two-step launches (32 segments of 256 cells), against single steps,
+    every word compared."""
     need_gpu()
     B = binding()
     n = 8192
@@ -107,16 +111,19 @@ def test_paired_steps_d2q9_full_size_equal_single_steps(kind):
     b = grid.empty_populations()
     assert B.lbm_step(grid, a, b, 0.6, None, 1) == 0
     start = b.clone()
-    x, y = b, a
-    for _ in range(4):
-        B.lbm_step(grid, x, y, 0.6, None, 1)
-        x, y = y, x
-    ref = x.clone()
-    p, q = start.clone(), y
-    assert B.lbm_step_launches(grid, 4) == (0, 2)
-    assert B.lbm_step(grid, p, q, 0.6, None, 4) == 1
-    torch.cuda.synchronize()
-    assert torch.equal(bits(p), bits(ref))
+    for n, plan in ((4, (0, 2, 0)), (8, (0, 4, 0) if kind == "f16s" else (0, 0, 2))):
+        x, y = start.clone(), a
+        for _ in range(n):
+            B.lbm_step(grid, x, y, 0.6, None, 1)
+            x, y = y, x
+        ref = x.clone()
+        del x
+        p, q = start.clone(), y
+        assert B.lbm_step_launches(grid, n) == plan
+        assert B.lbm_step(grid, p, q, 0.6, None, n) == 1
+        torch.cuda.synchronize()
+        assert torch.equal(bits(p), bits(ref)), n
+        del p, ref
 
 
 def test_paired_steps_leave_pad_words_alone():
