@@ -622,16 +622,17 @@ def profile_set(B, steps: int, warmup: int):
     B.lbm_init_equilibrium(grid, None, u2, bufs[0])
     p_dev = params.float().cuda()
     taus = [1, 1, 1, 0.6, 0.6, 0.6, 0.9, 0.8, 0.7]
-    # the D2Q9 two-step kernel: one lbm_step call of 4 * steps steps, after a warm-up
-    # call as long (bytes: the state read and written once per launch)
+    # the D2Q9 four-step kernel: one lbm_step call of 8 * steps steps (2 * steps
+    # four-step launches), after a warm-up call as long (bytes: the state read and
+    # written once per launch)
     cur2 = [0]
 
-    def call2():
-        if B.lbm_step(grid, bufs[cur2[0]], bufs[1 - cur2[0]], 0.6, None, 4 * max(1, steps)) == 0:
+    def call4():
+        if B.lbm_step(grid, bufs[cur2[0]], bufs[1 - cur2[0]], 0.6, None, 8 * max(1, steps)) == 0:
             cur2[0] ^= 1
 
-    report("two-step D2Q9 f32 8192^2", "step2_2d_kernel<F32, unforced, 256>", grid,
-           time_launches(call2, 1, 1) / (2 * max(1, steps)), B.bytes_per_cell_step(grid))
+    report("four-step D2Q9 f32 8192^2", "stepn_2d_kernel<F32, unforced, 128 cells, 4 steps>", grid,
+           time_launches(call4, 1, 1) / (2 * max(1, steps)), B.bytes_per_cell_step(grid))
     for case, kname, fn in (
             ("step D2Q9 f32 8192^2", "step_kernel<D2Q9, F32, unforced>",
              lambda a, b: B.lbm_step(grid, a, b, 0.6, None, 1)),
