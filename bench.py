@@ -728,7 +728,7 @@ def main():
         detail["forward_d3q19"] = {s: run_forward(B, s, args.steps, args.warmup, u_dev, "D3Q19")
                                    for s in ("f32", "f64", "f16s")}
         log("[bench] forced steps")
-        detail["forward_forced"] = {f"{m}_{s}": run_forward(B, s, 4 * max(5, args.steps // 16), 5, u_dev, mode=m)
+        detail["forward_forced"] = {f"{m}_{s}": run_forward(B, s, args.steps, args.warmup, u_dev, mode=m)
                                     for m in ("guo", "shift") for s in ("f32", "f16s")}
         log("[bench] D2Q9 8192^2 BGK and MRT")
         detail["d2q9_8192"] = run_d2q9(B, args.steps, args.warmup)
