@@ -5,8 +5,9 @@ operation (Sec. 3.2).  Here the derivative of a whole rollout comes from the
 library's adjoint kernels instead:
 
   LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every) -> g_T
-      forward: n_steps lbm_step calls; every K-th step writes into a fresh buffer
-      that is kept as a checkpoint (no copies);
+      forward: per segment of K steps, its first step, then the steps between in one
+      lbm_step call (several steps per launch where the library can), then the K-th
+      step, which writes into a fresh buffer kept as a checkpoint (no copies);
       backward: for each K-step segment, last to first, replay the segment from
       its checkpoint (keeping its K states), then run K adjoint steps backwards in
       the collision-local form (lbm_adjoint_step_local, aligned stores only) and
@@ -44,14 +45,28 @@ class LBMRollout(torch.autograd.Function):
         cur = g0.detach().contiguous().clone()  # checkpoint 0 (the caller may change g0)
         ckpts = [cur]
         spare = [torch.empty_like(cur), torch.empty_like(cur)]
-        for t in range(n_steps):
-            if (t + 1) % checkpoint_every == 0 and t + 1 < n_steps:
-                dst = torch.empty_like(cur)  # the step writes the next checkpoint itself
+        K = checkpoint_every
+        t = 0
+        while t < n_steps:
+            steps = min(K, n_steps - t)
+            last_ckpt = t + steps < n_steps  # this segment ends in a new checkpoint
+            # the segment's first step leaves the checkpoint it starts from untouched;
+            # the steps between run in one lbm_step call on the two spare buffers (the
+            # library takes several steps per launch there); the last step writes the
+            # next checkpoint itself
+            mid = steps - 1 - (1 if last_ckpt else 0)
+            if steps - (1 if last_ckpt else 0) >= 1:
+                B.lbm_step(grid, cur, spare[0], tau, F, 1)
+                cur = spare[0]
+            if mid >= 1:
+                where = B.lbm_step(grid, spare[0], spare[1], tau, F, mid)
+                cur = spare[1] if where == 0 else spare[0]
+            if last_ckpt:
+                dst = torch.empty_like(cur)
                 ckpts.append(dst)
-            else:
-                dst = spare[1] if cur is spare[0] else spare[0]
-            B.lbm_step(grid, cur, dst, tau, F, 1)
-            cur = dst
+                B.lbm_step(grid, cur, dst, tau, F, 1)
+                cur = dst
+            t += steps
         a = cur
         ctx.grid, ctx.tau, ctx.n, ctx.K = grid, tau, n_steps, checkpoint_every
         ctx.ckpts = ckpts
