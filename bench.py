@@ -253,14 +253,23 @@ def run_pitch(B, steps: int, warmup: int):
     return out
 
 
-def run_adjoint(B, storage: str, steps: int, warmup: int, u_dev, local: bool = True, forced: bool = False):
+def run_adjoint(B, storage: str, steps: int, warmup: int, u_dev, local: bool = True, forced: bool = False,
+                paired: bool = False):
     """Adjoint-step kernel throughput: the collision-local form the rollout uses
     (gathered reads, aligned writes) or the scatter form of lbm_adjoint_step.  With
     `forced` the step has a force field and accumulates dL/dF (the workloads' case:
-    F read, dF read and written)."""
+    F read, dF read and written).  With `paired` every launch is two steps
+    (lbm_adjoint_step2_local, the rollout's backward pass where the grid allows):
+    `steps` launches are timed, ms_per_step is per adjoint step, and bytes_per_cell
+    counts what one launch moves (two states and the force read, chi read and
+    written once, the force gradient read and written once)."""
     grid = B.Grid("D3Q27", storage, N, N, N)
     g = grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, u_dev, g)
+    g2 = None
+    if paired:
+        g2 = grid.empty_populations()
+        B.lbm_step(grid, g, g2, TAU, None, 1)
     lam = [torch.zeros(grid.population_shape(), dtype=grid.real_dtype, device="cuda") for _ in range(2)]
     lam[0].normal_()
     F = dF = None
@@ -270,21 +279,27 @@ def run_adjoint(B, storage: str, steps: int, warmup: int, u_dev, local: bool = T
     cur = [0]
 
     def one():
-        if local:
+        if paired:
+            B.lbm_adjoint_step2_local(grid, g2, g, lam[cur[0]], lam[1 - cur[0]], TAU, F, dF)
+        elif local:
             B.lbm_adjoint_step_local(grid, g, lam[cur[0]], True, lam[1 - cur[0]], TAU, F, dF)
         else:
             B.lbm_adjoint_step(grid, g, lam[cur[0]], lam[1 - cur[0]], TAU, F, dF)
         cur[0] ^= 1
 
-    ms = time_launches(one, steps, warmup)
+    ms_launch = time_launches(one, steps, warmup)
+    ms = ms_launch / 2 if paired else ms_launch
     wb = torch.tensor([], dtype=grid.word_dtype).element_size()
     rb = torch.tensor([], dtype=grid.real_dtype).element_size()
-    bpc = grid.Q * (wb + 2 * rb) + (3 * grid.D * rb if forced else 0)
+    bpc = grid.Q * ((2 if paired else 1) * wb + 2 * rb) + (3 * grid.D * rb if forced else 0)
     out = {"storage": storage, "form": "local" if local else "scatter", "forced": forced, "ms_per_step": ms,
            "mlups": grid.ncells / (ms * 1e-3) / 1e6, "bytes_per_cell": bpc,
-           "hbm_gbs": bpc * grid.ncells / (ms * 1e-3) / 1e9}
+           "hbm_gbs": bpc * grid.ncells / (ms_launch * 1e-3) / 1e9}
+    if paired:
+        out["ms_per_launch"] = ms_launch
+        out["steps_per_launch"] = 2
     out["hbm_frac"] = out["hbm_gbs"] / PEAK_HBM_GBS
-    del g, lam, F, dF
+    del g, g2, lam, F, dF
     torch.cuda.empty_cache()
     return out
 
@@ -603,6 +618,12 @@ def profile_set(B, steps: int, warmup: int):
     report(f"adjoint (collision-local, chi input, forced) D3Q27 f16s state {N}^3",
            "adjoint_kernel<D3Q27, F16S, forced, local chi>", B.Grid("D3Q27", "f16s", N, N, N), r["ms_per_step"],
            r["bytes_per_cell"])
+    r = run_adjoint(B, "f32", steps, warmup, u3, paired=True)
+    report(f"two adjoint steps per launch D3Q27 f32 {N}^3", "adjoint2_kernel<D3Q27, F32, unforced>",
+           B.Grid("D3Q27", "f32", N, N, N), r["ms_per_launch"], r["bytes_per_cell"])
+    r = run_adjoint(B, "f16s", steps, warmup, u3, forced=True, paired=True)
+    report(f"two adjoint steps per launch, forced, D3Q27 f16s state {N}^3", "adjoint2_kernel<D3Q27, F16S, forced>",
+           B.Grid("D3Q27", "f16s", N, N, N), r["ms_per_launch"], r["bytes_per_cell"])
     # moments: each mode once, so that one kernel instantiation serves one case
     g3 = B.Grid("D3Q27", "f32", N, N, N)
     pops = g3.empty_populations()
@@ -742,6 +763,10 @@ def main():
                                           for s in ("f32", "f16s")}
         detail["adjoint_forced"] = {s: run_adjoint(B, s, max(20, args.steps // 4), 5, u_dev, forced=True)
                                     for s in ("f32", "f16s")}
+        detail["adjoint_paired"] = {s: run_adjoint(B, s, max(20, args.steps // 8), 5, u_dev, paired=True)
+                                    for s in ("f32", "f16s")}
+        detail["adjoint_paired_forced"] = {s: run_adjoint(B, s, max(20, args.steps // 8), 5, u_dev, forced=True,
+                                                          paired=True) for s in ("f32", "f16s")}
         log("[bench] moments")
         detail["moments_f32"] = run_moments(B, 20, 3, u_dev)
         log("[bench] 64x64 D2Q9 launch-bound run")
@@ -852,12 +877,11 @@ def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic
         summ[f"d3q19_{k}_mlups"] = _r(v["mlups"])
     for k, v in (detail.get("forward_forced") or {}).items():
         summ[f"forced_{k}_mlups"] = _r(v["mlups"])
-    for name, key in (("adjoint_local", "adjoint"), ("adjoint_scatter", "adjoint_scatter_form"),
-                      ("adjoint_local_forced", "adjoint_forced")):
+    # (the scatter form and the bandwidth fractions are in the detail file)
+    for name, key in (("adjoint_local", "adjoint"), ("adjoint_local_forced", "adjoint_forced"),
+                      ("adjoint_paired", "adjoint_paired"), ("adjoint_paired_forced", "adjoint_paired_forced")):
         for k, v in (detail.get(key) or {}).items():
             summ[f"{name}_{k}_mlups"] = _r(v["mlups"])
-            if name == "adjoint_local":
-                summ[f"{name}_{k}_hbm_frac"] = _r(v["hbm_frac"])
     d2 = detail.get("d2q9_8192") or {}
     for k in ("bgk_paired_f32", "bgk_paired_f16s", "bgk_paired_f64", "bgk_f32"):
         if k in d2:

@@ -328,6 +328,26 @@ int lbm_adjoint_step(const lbm_grid* grid, const void* g_t, const void* lam_next
 int lbm_adjoint_step_local(const lbm_grid* grid, const void* g_t, const void* adj_next, int adj_is_chi,
                            void* chi_out, double tau, const void* force, void* dforce, void* stream);
 
+/* Two steps of lbm_adjoint_step_local with chi in and chi out, in one launch that keeps
+ * the intermediate chi on chip (derivatives of the step as in Sec. 3.2; two steps of
+ * the rollout's backward pass):
+ *   chi_out = J_C(S g_tm1)^T S^T [ J_C(S g_t)^T S^T chi_next ]
+ *   dforce += the two steps' contributions, added in the order of two calls (step t
+ *             first), so that the result equals lbm_adjoint_step_local(g_t, chi_next,
+ *             1, tmp) followed by lbm_adjoint_step_local(g_tm1, tmp, 1, chi_out) bit for
+ *             bit.
+ * g_t, g_tm1: the states of steps t and t-1 (Q*N storage words each).  chi_next,
+ * chi_out: Q*N reals.  tau, force, dforce as lbm_adjoint_step.  chi_out must not
+ * overlap any other argument, dforce none but chi_out's.  LBM_EUNSUP where the grid or
+ * storage kind is not taken (3D lattices, every kind but FP64, nx a multiple of 32, ny
+ * of 8, nz >= 3: lbm_adjoint_step2_available). */
+int lbm_adjoint_step2_local(const lbm_grid* grid, const void* g_t, const void* g_tm1, const void* chi_next,
+                            void* chi_out, double tau, const void* force, void* dforce, void* stream);
+
+/* *available = 1 if lbm_adjoint_step2_local takes this grid and storage kind, else 0.
+ * Host-only.  Grid errors as lbm_step; LBM_ENULL for a NULL output. */
+int lbm_adjoint_step2_available(const lbm_grid* grid, int* available);
+
 /* lam_out = S^T chi, the transpose of the pull streaming of Eq. 1: lam_out_i(x) =
  * chi_i(x + c_i) with periodic wrap, on Q*N reals in the population layout (FP64 for
  * FP64 storage, FP32 otherwise).  Turns the local form's chi into lam.  chi and lam_out

@@ -4,15 +4,17 @@ The paper differentiates its solver by PyTorch autograd through every tensor
 operation (Sec. 3.2).  Here the derivative of a whole rollout comes from the
 library's adjoint kernels instead:
 
-  LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every) -> g_T
+  LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every[, pair_adjoint]) -> g_T
       forward: per segment of K steps, its first step, then the steps between in one
       lbm_step call (several steps per launch where the library can), then the K-th
       step, which writes into a fresh buffer kept as a checkpoint (no copies);
       backward: for each K-step segment, last to first, replay the segment from
       its checkpoint (keeping its K states), then run K adjoint steps backwards in
-      the collision-local form (lbm_adjoint_step_local, aligned stores only) and
-      finish with one lbm_adjoint_unstream; the force gradient accumulates in
-      place in the kernels.
+      the collision-local form (lbm_adjoint_step_local, aligned stores only; after
+      the rollout's last step, two steps per lbm_adjoint_step2_local launch where the
+      library takes the grid and pair_adjoint is set, bitwise the same) and finish
+      with one lbm_adjoint_unstream; the force gradient accumulates in place in the
+      kernels.
       Memory: ceil(n/K) checkpoints + K segment states + 2 adjoint buffers.
       Forward and adjoint kernels are deterministic (no atomics), so the gradient
       is bitwise independent of K.
@@ -38,7 +40,8 @@ def _real(grid: B.Grid, t: torch.Tensor | None) -> torch.Tensor | None:
 
 class LBMRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, g0, force, grid: B.Grid, tau: float, n_steps: int, checkpoint_every: int):
+    def forward(ctx, g0, force, grid: B.Grid, tau: float, n_steps: int, checkpoint_every: int,
+                pair_adjoint: bool = True):
         if n_steps < 1 or checkpoint_every < 1:
             raise ValueError("n_steps and checkpoint_every must be >= 1")
         F = _real(grid, force)
@@ -69,6 +72,7 @@ class LBMRollout(torch.autograd.Function):
             t += steps
         a = cur
         ctx.grid, ctx.tau, ctx.n, ctx.K = grid, tau, n_steps, checkpoint_every
+        ctx.pair = bool(pair_adjoint) and B.lbm_adjoint_step2_available(grid)
         ctx.ckpts = ckpts
         ctx.force = F
         ctx.force_needs_grad = force is not None and ctx.needs_input_grad[1]
@@ -98,15 +102,22 @@ class LBMRollout(torch.autograd.Function):
             states[0] = ctx.ckpts[seg]
             for t in range(t0 + 1, t1):
                 B.lbm_step(grid, states[t - 1 - t0], states[t - t0], tau, F, 1)
-            for t in reversed(range(t0, t1)):
+            t = t1 - 1
+            while t >= t0:
                 out = bufs[k & 1]
-                B.lbm_adjoint_step_local(grid, states[t - t0], cur, is_chi, out, tau, F, dF)
+                if ctx.pair and is_chi and t - 1 >= t0:
+                    # steps t and t - 1 in one launch, chi_t kept on chip
+                    B.lbm_adjoint_step2_local(grid, states[t - t0], states[t - 1 - t0], cur, out, tau, F, dF)
+                    t -= 2
+                else:
+                    B.lbm_adjoint_step_local(grid, states[t - t0], cur, is_chi, out, tau, F, dF)
+                    t -= 1
                 cur, is_chi, k = out, True, k + 1
             ctx.ckpts[seg] = None  # released once the next segment replaces states[0]
         states = None
         lam0 = bufs[k & 1]
         B.lbm_adjoint_unstream(grid, cur, lam0)
-        return lam0, dF, None, None, None, None
+        return lam0, dF, None, None, None, None, None
 
 
 class LBMMoments(torch.autograd.Function):
@@ -133,9 +144,9 @@ class LBMMoments(torch.autograd.Function):
 
 
 def rollout(grid: B.Grid, g0: torch.Tensor, force: torch.Tensor | None, tau: float, n_steps: int,
-            checkpoint_every: int = 10) -> torch.Tensor:
+            checkpoint_every: int = 10, pair_adjoint: bool = True) -> torch.Tensor:
     """Differentiable n-step rollout from g0 under a constant force field."""
-    return LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every)
+    return LBMRollout.apply(g0, force, grid, tau, n_steps, checkpoint_every, pair_adjoint)
 
 
 def moments(grid: B.Grid, g: torch.Tensor, force: torch.Tensor | None = None):

@@ -75,6 +75,8 @@ def _load() -> ctypes.CDLL:
         "lbm_moments_adjoint": (i32, [gp, vp, vp, vp, vp, vp, vp, vp]),
         "lbm_adjoint_step_local": (i32, [gp, vp, vp, i32, vp, dbl, vp, vp, vp]),
         "lbm_adjoint_unstream": (i32, [gp, vp, vp, vp]),
+        "lbm_adjoint_step2_local": (i32, [gp, vp, vp, vp, vp, dbl, vp, vp, vp]),
+        "lbm_adjoint_step2_available": (i32, [gp, ctypes.POINTER(i32)]),
         "lbm_copy": (i32, [vp, vp, sz, vp]),
         "lbm_step_slab": (i32, [gp, vp, vp, dbl, vp, ctypes.c_int64, ctypes.c_int64, vp]),
         "lbm_slab_halo_copy": (i32, [gp, vp, gp, vp, i32, vp]),
@@ -449,6 +451,31 @@ def lbm_adjoint_step_local(grid: Grid, g_t: torch.Tensor, adj_next: torch.Tensor
     dF = _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False)
     _check(_lib.lbm_adjoint_step_local(ctypes.byref(g), *args, 1 if adj_is_chi else 0, out, float(tau), F, dF,
                                        _stream(stream)), "lbm_adjoint_step_local")
+
+
+def lbm_adjoint_step2_local(grid: Grid, g_t: torch.Tensor, g_tm1: torch.Tensor, chi_next: torch.Tensor,
+                            chi_out: torch.Tensor, tau: float, force: torch.Tensor | None = None,
+                            dforce: torch.Tensor | None = None, stream=None) -> None:
+    """chi_out <- two collision-local adjoint steps (states g_t, then g_tm1) from chi_next;
+    dforce += both steps' force gradients, in the order of two one-step calls."""
+    N = grid.ncells
+    g = grid.c_struct()
+    a = _dev_ptr(g_t, "g_t", grid.word_dtype, grid.pop_size)
+    b = _dev_ptr(g_tm1, "g_tm1", grid.word_dtype, grid.pop_size)
+    c = _dev_ptr(chi_next, "chi_next", grid.real_dtype, grid.pop_size)
+    out = _dev_ptr(chi_out, "chi_out", grid.real_dtype, grid.pop_size)
+    F = _dev_ptr(force, "force", grid.real_dtype, grid.D * N, required=False)
+    dF = _dev_ptr(dforce, "dforce", grid.real_dtype, grid.D * N, required=False)
+    _check(_lib.lbm_adjoint_step2_local(ctypes.byref(g), a, b, c, out, float(tau), F, dF, _stream(stream)),
+           "lbm_adjoint_step2_local")
+
+
+def lbm_adjoint_step2_available(grid: Grid) -> bool:
+    """Whether lbm_adjoint_step2_local takes this grid and storage kind (host-only)."""
+    g = grid.c_struct()
+    v = ctypes.c_int32(0)
+    _check(_lib.lbm_adjoint_step2_available(ctypes.byref(g), ctypes.byref(v)), "lbm_adjoint_step2_available")
+    return bool(v.value)
 
 
 def lbm_adjoint_unstream(grid: Grid, chi: torch.Tensor, lam_out: torch.Tensor, stream=None) -> None:

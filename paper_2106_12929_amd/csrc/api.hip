@@ -580,6 +580,43 @@ int lbm_adjoint_step_local(const lbm_grid* grid, const void* g_t, const void* ad
                         adj_is_chi ? lbm::kAdjLocalChi : lbm::kAdjLocalLam, stream, "lbm_adjoint_step_local launch");
 }
 
+int lbm_adjoint_step2_available(const lbm_grid* grid, int* available) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  if (!available) return fail(LBM_ENULL, "available is NULL");
+  *available = lbm::adjoint2_supported(grid->lattice, grid->storage, geo.args) ? 1 : 0;
+  return LBM_OK;
+}
+
+int lbm_adjoint_step2_local(const lbm_grid* grid, const void* g_t, const void* g_tm1, const void* chi_next,
+                            void* chi_out, double tau, const void* force, void* dforce, void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(grid, &geo));
+  LBM_TRY(check_tau(tau));
+  LBM_TRY(check_ptr(g_t, "g_t", true));
+  LBM_TRY(check_ptr(g_tm1, "g_tm1", true));
+  LBM_TRY(check_ptr(chi_next, "chi_next", true));
+  LBM_TRY(check_ptr(chi_out, "chi_out", true));
+  LBM_TRY(check_ptr(force, "force", false));
+  LBM_TRY(check_ptr(dforce, "dforce", false));
+  if (dforce && !force) return fail(LBM_EUNSUP, "dforce needs the force the steps used");
+  if (!lbm::adjoint2_supported(grid->lattice, grid->storage, geo.args))
+    return fail(LBM_EUNSUP, "two adjoint steps per launch do not take this grid or storage kind "
+                            "(lbm_adjoint_step2_available)");
+  const size_t N = geo.args.ncells;
+  const size_t gbytes = geo.pop * geo.word, lbytes = geo.pop * geo.real, fbytes = geo.D * N * geo.real;
+  if (overlap(chi_out, lbytes, g_t, gbytes) || overlap(chi_out, lbytes, g_tm1, gbytes) ||
+      overlap(chi_out, lbytes, chi_next, lbytes) || overlap(chi_out, lbytes, force, fbytes) ||
+      overlap(chi_out, lbytes, dforce, fbytes))
+    return fail(LBM_EALIAS, "chi_out overlaps another argument");
+  if (overlap(dforce, fbytes, g_t, gbytes) || overlap(dforce, fbytes, g_tm1, gbytes) ||
+      overlap(dforce, fbytes, chi_next, lbytes) || overlap(dforce, fbytes, force, fbytes))
+    return fail(LBM_EALIAS, "dforce overlaps another argument");
+  const hipError_t e = lbm::launch_adjoint2(grid->lattice, grid->storage, g_t, g_tm1, chi_next, chi_out, force, dforce,
+                                            geo.args, 1.0 / tau, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step2_local launch");
+}
+
 int lbm_adjoint_unstream(const lbm_grid* grid, const void* chi, void* lam_out, void* stream) {
   Geometry geo;
   LBM_TRY(check_grid(grid, &geo));

@@ -53,6 +53,13 @@ hipError_t launch_moments(int lattice, int storage, const void* f, const void* f
                           double* workspace, double* red, const GridArgs& g, hipStream_t s);
 hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, const void* lam_next, void* lam_out,
                           const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s);
+// Two collision-local adjoint steps, chi_next -> chi_out through g_t and g_t-1
+// (adjoint2_kernel), where the grid and storage kind allow; equal to two launch_adjoint
+// calls in mode kAdjLocalChi bit for bit, the force gradient included.
+bool adjoint2_supported(int lattice, int storage, const GridArgs& g);
+hipError_t launch_adjoint2(int lattice, int storage, const void* gt, const void* gtm1, const void* chi_next,
+                           void* chi_out, const void* force, void* dforce, const GridArgs& g, double omega,
+                           hipStream_t s);
 hipError_t launch_unstream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g,
                            hipStream_t s);
 // Source of the MRT ghost times tau_6..8 (see mrt_step_kernel).

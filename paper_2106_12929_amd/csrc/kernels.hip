@@ -931,54 +931,57 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
 //                   chi_t(x) = mu (aligned)
 // In the local ("chi") form every store is aligned; lam_t = S^T chi_t.
 // ---------------------------------------------------------------------------------
-template <int L, int S, bool FORCED, int MODE>
-__global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>::word* __restrict__ gt,
-                                                      const typename Storage<S>::real* __restrict__ lam_next,
-                                                      typename Storage<S>::real* __restrict__ lam_out,
-                                                      const typename Storage<S>::real* __restrict__ force,
-                                                      typename Storage<S>::real* __restrict__ dforce, GridArgs g,
-                                                      typename Storage<S>::real omega) {
-  using LT = Lattice<L>;
-  using ST = Storage<S>;
-  using real = typename ST::real;
-  using CO = Coef<L, real>;
-  constexpr int Q = LT::Q;
-  Cell c;
-  if (!cell_of_thread(g, c)) return;
-  const Sources src = sources(c, g);
-  const size_t N = g.ncells;
-  const uint32_t self = cell_index(g, c);
+// J_C(h)^T of one cell's BGK collision (with Guo force when FORCED), applied in place:
+// d holds the pulled populations h_i - w_i, lam the adjoint lambda_{t+1} at the cell on
+// entry and mu = J_C(h)^T lambda_{t+1} on exit; (ax, ay, az) returns (dg'/dF)^T lambda,
+// the cell's force-gradient contribution.  The Jacobian depends on h through rho and u
+// only, so the work splits into adjoint_moments (of d) and adjoint_apply (on lam).
+// Products are fused only within an expression, so every kernel that inlines them
+// rounds identically.
+template <typename real>
+struct AdjMoments {
+  real rho, inv_rho, ux, uy, uz;
+};
 
-  uint32_t xw[3], xr[3];  // column byte offsets for storage words and for reals
-  column_bytes<typename ST::word>(src, xw);
-  column_bytes<real>(src, xr);
+template <int L, typename real, bool FORCED>
+__device__ __forceinline__ AdjMoments<real> adjoint_moments(const real (&d)[Lattice<L>::Q], real Fx, real Fy,
+                                                            real Fz) {
+#pragma clang fp contract(on)
+  using LT = Lattice<L>;
+  constexpr int Q = LT::Q;
   real drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const real d = ST::to_dev(load_src<LT>(gt, g, src, xw, i), CO::W(i));
-    drho += d;
-    add_times(jx, LT::cx(i), d);
-    add_times(jy, LT::cy(i), d);
-    add_times(jz, LT::cz(i), d);
+    drho += d[i];
+    add_times(jx, LT::cx(i), d[i]);
+    add_times(jy, LT::cy(i), d[i]);
+    add_times(jz, LT::cz(i), d[i]);
   }
-  real Fx = 0, Fy = 0, Fz = 0;
   if constexpr (FORCED) {
-    Fx = force[self];
-    Fy = force[N + self];
-    if constexpr (LT::D == 3) Fz = force[2 * N + self];
     jx += real(0.5) * Fx;
     jy += real(0.5) * Fy;
     jz += real(0.5) * Fz;
   }
-  const real rho = real(1) + drho;
-  const real inv_rho = real(1) / rho;
-  const real ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+  AdjMoments<real> m;
+  m.rho = real(1) + drho;
+  m.inv_rho = real(1) / m.rho;
+  m.ux = jx * m.inv_rho;
+  m.uy = jy * m.inv_rho;
+  m.uz = jz * m.inv_rho;
+  return m;
+}
 
-  real lam[Q];
+template <int L, typename real, bool FORCED>
+__device__ __forceinline__ void adjoint_apply(const AdjMoments<real>& m, real (&lam)[Lattice<L>::Q], real Fx, real Fy,
+                                              real Fz, real omega, real& ax, real& ay, real& az) {
+#pragma clang fp contract(on)
+  using LT = Lattice<L>;
+  using CO = Coef<L, real>;
+  constexpr int Q = LT::Q;
+  const real rho = m.rho, inv_rho = m.inv_rho, ux = m.ux, uy = m.uy, uz = m.uz;
   real mW = 0, mAx = 0, mAy = 0, mAz = 0, bxx = 0, byy = 0, bzz = 0, bxy = 0, bxz = 0, byz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    lam[i] = MODE == kAdjLocalChi ? load_rev<LT>(lam_next, g, src, xr, i) : *at_byte(lam_next + dir_row<Q>(g, c.y, c.z, i), xr[1]);
     const real l = lam[i];
     const int cx = LT::cx(i), cy = LT::cy(i), cz = LT::cz(i);
     const real al = CO::A(i) * l, bl = CO::B(i) * l;
@@ -1023,21 +1026,313 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
     if (LT::cy(j) < 0) mu -= vy;
     if (LT::cz(j) > 0) mu += vz;
     if (LT::cz(j) < 0) mu -= vz;
+    lam[j] = mu;
+  }
+  if constexpr (FORCED) {
+    const real half_inv = real(0.5) * inv_rho;
+    ax = guo * (mAx - real(3) * ux * mW + real(2) * mBux) + Vx * half_inv;
+    ay = guo * (mAy - real(3) * uy * mW + real(2) * mBuy) + Vy * half_inv;
+    az = guo * (mAz - real(3) * uz * mW + real(2) * mBuz) + Vz * half_inv;
+  } else {
+    ax = ay = az = 0;
+  }
+}
+
+template <int L, typename real, bool FORCED>
+__device__ __forceinline__ void adjoint_collide(const real (&d)[Lattice<L>::Q], real (&lam)[Lattice<L>::Q], real Fx,
+                                                real Fy, real Fz, real omega, real& ax, real& ay, real& az) {
+  adjoint_apply<L, real, FORCED>(adjoint_moments<L, real, FORCED>(d, Fx, Fy, Fz), lam, Fx, Fy, Fz, omega, ax, ay, az);
+}
+
+template <int L, int S, bool FORCED, int MODE>
+__global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>::word* __restrict__ gt,
+                                                      const typename Storage<S>::real* __restrict__ lam_next,
+                                                      typename Storage<S>::real* __restrict__ lam_out,
+                                                      const typename Storage<S>::real* __restrict__ force,
+                                                      typename Storage<S>::real* __restrict__ dforce, GridArgs g,
+                                                      typename Storage<S>::real omega) {
+  using LT = Lattice<L>;
+  using ST = Storage<S>;
+  using real = typename ST::real;
+  using CO = Coef<L, real>;
+  constexpr int Q = LT::Q;
+  Cell c;
+  if (!cell_of_thread(g, c)) return;
+  const Sources src = sources(c, g);
+  const size_t N = g.ncells;
+  const uint32_t self = cell_index(g, c);
+
+  uint32_t xw[3], xr[3];  // column byte offsets for storage words and for reals
+  column_bytes<typename ST::word>(src, xw);
+  column_bytes<real>(src, xr);
+  real d[Q], lam[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(load_src<LT>(gt, g, src, xw, i), CO::W(i));
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    lam[i] = MODE == kAdjLocalChi ? load_rev<LT>(lam_next, g, src, xr, i)
+                                  : *at_byte(lam_next + dir_row<Q>(g, c.y, c.z, i), xr[1]);
+  real Fx = 0, Fy = 0, Fz = 0;
+  if constexpr (FORCED) {
+    Fx = force[self];
+    Fy = force[N + self];
+    if constexpr (LT::D == 3) Fz = force[2 * N + self];
+  }
+  real ax, ay, az;
+  adjoint_collide<L, real, FORCED>(d, lam, Fx, Fy, Fz, omega, ax, ay, az);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
     if constexpr (MODE == kAdjScatter) {
       // shifted rows: a wave's store straddles cache lines that the neighbouring wave
       // completes, so it stays a plain (cached) store for the halves to merge in L2
-      *at_byte(lam_out + dir_row<Q>(g, src.y[LT::cy(j) + 1], src.z[LT::cz(j) + 1], j), xr[LT::cx(j) + 1]) = mu;
+      *at_byte(lam_out + dir_row<Q>(g, src.y[LT::cy(j) + 1], src.z[LT::cz(j) + 1], j), xr[LT::cx(j) + 1]) = lam[j];
     } else {
-      store_stream(at_byte(lam_out + dir_row<Q>(g, c.y, c.z, j), xr[1]), mu);
+      store_stream(at_byte(lam_out + dir_row<Q>(g, c.y, c.z, j), xr[1]), lam[j]);
     }
   }
   if constexpr (FORCED) {
     if (dforce) {
-      const real half_inv = real(0.5) * inv_rho;
-      dforce[self] += guo * (mAx - real(3) * ux * mW + real(2) * mBux) + Vx * half_inv;
-      dforce[N + self] += guo * (mAy - real(3) * uy * mW + real(2) * mBuy) + Vy * half_inv;
-      if constexpr (LT::D == 3)
-        dforce[2 * N + self] += guo * (mAz - real(3) * uz * mW + real(2) * mBuz) + Vz * half_inv;
+      dforce[self] += ax;
+      dforce[N + self] += ay;
+      if constexpr (LT::D == 3) dforce[2 * N + self] += az;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Two adjoint steps per launch (collision-local form, chi in and chi out):
+//   chi_t   = J_C(S g_t)^T   S^T chi_{t+1}   (on a tile plus a one-cell ring, into LDS)
+//   chi_t-1 = J_C(S g_t-1)^T S^T chi_t       (on the tile, from LDS, to HBM)
+// with the force gradient of both steps added in the order of two one-step launches,
+// (dF + a_t) + a_t-1.  The structure is step2_kernel's (tiles of 32 x 8 columns marching
+// along z, producer and consumer waves, two LDS slots, one barrier per plane), with the
+// adjoint's transposed streaming: lambda_i(x) = chi_i(x + c_i), so a plane of chi_t
+// gives its c_z = +1 directions to the output plane below it.  Producers gather the
+// state g_t (pull) and chi_t+1 (transposed) from HBM, one plane ahead; consumers gather
+// g_t-1 from HBM (also one plane ahead) and chi_t from LDS.  The producers also leave a_t of the
+// tile's own cells in LDS for the consumers.  Each cell's arithmetic is
+// adjoint_collide, as in adjoint_kernel, so the result equals two of its launches bit
+// for bit.
+// ---------------------------------------------------------------------------------
+template <int L, int S, bool FORCED>
+__global__ __launch_bounds__((Step2Shape<L, kF32>::NT)) __attribute__((amdgpu_waves_per_eu(3))) void adjoint2_kernel(
+    const typename Storage<S>::word* __restrict__ gt, const typename Storage<S>::word* __restrict__ gtm1,
+    const typename Storage<S>::real* __restrict__ chi_next, typename Storage<S>::real* __restrict__ chi_out,
+    const typename Storage<S>::real* __restrict__ force, typename Storage<S>::real* __restrict__ dforce, GridArgs g,
+    Step2Args aw, Step2Args ar, typename Storage<S>::real omega) {
+  using LT = Lattice<L>;
+  using ST = Storage<S>;
+  using W = typename ST::word;
+  using real = typename ST::real;
+  using CO = Coef<L, real>;
+  using SH = Step2Shape<L, kF32>;  // tiles by the 4-byte adjoint reals
+  constexpr int Q = LT::Q;
+  constexpr int TX = SH::TX, TY = SH::TY, NSX = SH::NSX, NS = SH::NS, NP = SH::NP;
+  __shared__ real slot[2][Q][NS];
+  __shared__ real stash[2][3][TX * TY];  // a_t of the tile's cells, by plane
+
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t per = nb / 8, extra = nb % 8, xcd = b % 8, pos = b / 8;
+  const uint32_t lin = xcd < extra ? xcd * (per + 1) + pos : extra * (per + 1) + (xcd - extra) * per + pos;
+  const uint32_t tx = lin % ar.tiles_x, ty = (lin / ar.tiles_x) % ar.tiles_y, zc = lin / (ar.tiles_x * ar.tiles_y);
+  const uint32_t x0 = tx * TX, y0 = ty * TY;
+  const uint32_t zb = zc * ar.lz;
+  const uint32_t ze = min(zb + ar.lz, g.nz);
+  const uint32_t nplanes = ze - zb + 2;  // chi_t on planes zb-1 .. ze
+  const uint32_t t = threadIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(t / 64);
+  const char* fbt = reinterpret_cast<const char*>(gt);
+  const char* fbm = reinterpret_cast<const char*>(gtm1);
+  const char* cbn = reinterpret_cast<const char*>(chi_next);
+  char* cbo = reinterpret_cast<char*>(chi_out);
+  const uint32_t plane_cells = g.nx * g.ny;
+  const bool grad = FORCED && dforce != nullptr;
+  auto wrapz = [&](int z) -> uint32_t {
+    return (uint32_t)(z < 0 ? z + (int)g.nz : (z >= (int)g.nz ? z - (int)g.nz : z));
+  };
+  auto load_force = [&](uint32_t z, uint32_t col, real& Fx, real& Fy, real& Fz) {
+    if constexpr (FORCED) {
+      const real* f = force + (uint64_t)z * plane_cells + col;
+      Fx = f[0];
+      Fy = f[g.ncells];
+      Fz = f[2 * g.ncells];
+    }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+
+  if (wave < (uint32_t)NP) {
+    // Producer lane: ring column s.
+    const bool live = t < (uint32_t)NS;
+    const uint32_t s = min(t, (uint32_t)NS - 1);
+    const uint32_t sx = s % NSX, sy = s / NSX;
+    int xi = (int)x0 - 1 + (int)sx;
+    int yi = (int)y0 - 1 + (int)sy;
+    xi += xi < 0 ? (int)g.nx : (xi >= (int)g.nx ? -(int)g.nx : 0);
+    yi += yi < 0 ? (int)g.ny : (yi >= (int)g.ny ? -(int)g.ny : 0);
+    const uint32_t x = xi, y = yi, col = y * g.nx + x;
+    // own cell of the tile (its a_t is kept for the consumers)
+    const bool own = live && sx >= 1 && sx <= (uint32_t)TX && sy >= 1 && sy <= (uint32_t)TY;
+    const uint32_t own_idx = (sy - 1) * TX + (sx - 1);
+    // index c + 1: pull sources x - c (words), transposed sources x + c (reals)
+    const uint32_t xw[3] = {wrap_inc(x, g.nx) * (uint32_t)sizeof(W), x * (uint32_t)sizeof(W),
+                            wrap_dec(x, g.nx) * (uint32_t)sizeof(W)};
+    const uint32_t yw[3] = {wrap_inc(y, g.ny) * aw.yrow_bytes, y * aw.yrow_bytes, wrap_dec(y, g.ny) * aw.yrow_bytes};
+    const uint32_t xr[3] = {wrap_dec(x, g.nx) * (uint32_t)sizeof(real), x * (uint32_t)sizeof(real),
+                            wrap_inc(x, g.nx) * (uint32_t)sizeof(real)};
+    const uint32_t yr[3] = {wrap_dec(y, g.ny) * ar.yrow_bytes, y * ar.yrow_bytes, wrap_inc(y, g.ny) * ar.yrow_bytes};
+    // the gathers of plane pz: state words pulled from g_t, chi_t+1 transposed, force
+    auto load = [&](int pz, W (&rw)[Q], real (&rc)[Q], real (&rf)[3]) {
+      const char* base[3] = {fbt + (uint64_t)wrapz(pz + 1) * aw.plane_bytes, fbt + (uint64_t)wrapz(pz) * aw.plane_bytes,
+                             fbt + (uint64_t)wrapz(pz - 1) * aw.plane_bytes};
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        rw[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * aw.row_bytes +
+                                            (yw[LT::cy(i) + 1] + xw[LT::cx(i) + 1]));
+      const char* cb[3] = {cbn + (uint64_t)wrapz(pz - 1) * ar.plane_bytes, cbn + (uint64_t)wrapz(pz) * ar.plane_bytes,
+                           cbn + (uint64_t)wrapz(pz + 1) * ar.plane_bytes};
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        rc[i] = *reinterpret_cast<const real*>(cb[LT::cz(i) + 1] + (uint64_t)i * ar.row_bytes +
+                                               (yr[LT::cy(i) + 1] + xr[LT::cx(i) + 1]));
+      load_force(wrapz(pz), col, rf[0], rf[1], rf[2]);
+    };
+    auto moments = [&](const W (&rw)[Q], const real (&rf)[3]) {
+      real d[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(rw[i], CO::W(i));
+      return adjoint_moments<L, real, FORCED>(d, rf[0], rf[1], rf[2]);
+    };
+    auto finish = [&](const AdjMoments<real>& m, real (&lam)[Q], const real (&rf)[3], auto sl) {
+      constexpr int SL = decltype(sl)::value;
+      real ax, ay, az;
+      adjoint_apply<L, real, FORCED>(m, lam, rf[0], rf[1], rf[2], omega, ax, ay, az);
+      if (live) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) slot[SL][i][s] = lam[i];
+      }
+      if (grad && own) {
+        stash[SL][0][own_idx] = ax;
+        stash[SL][1][own_idx] = ay;
+        stash[SL][2][own_idx] = az;
+      }
+    };
+    // A plane's state words are reduced to rho and u before the next plane's gathers
+    // are issued (fewer registers held); those gathers are then in flight while the
+    // plane's adjoint is applied and the barrier waited on.
+    W w0[Q], w1[Q];
+    real c0[Q], c1[Q];
+    real f0[3] = {0, 0, 0}, f1[3] = {0, 0, 0};
+    load((int)zb - 1, w0, c0, f0);
+    uint32_t k = 0;
+    for (; k + 1 < nplanes; k += 2) {
+      const AdjMoments<real> m0 = moments(w0, f0);
+      load((int)(zb + k), w1, c1, f1);
+      finish(m0, c0, f0, I0());
+      __syncthreads();
+      const AdjMoments<real> m1 = moments(w1, f1);
+      load((int)(zb + k) + 1, w0, c0, f0);  // one plane past ze on the last pass: read, unused
+      finish(m1, c1, f1, I1());
+      __syncthreads();
+    }
+    if (k < nplanes) {
+      const AdjMoments<real> m0 = moments(w0, f0);
+      finish(m0, c0, f0, I0());
+      __syncthreads();
+    }
+    __syncthreads();  // the consumers' last plane
+  } else {
+    // Consumer lane: output cell (x0 + ox, y0 + oy).
+    const uint32_t u = t - 64u * NP;
+    const uint32_t ox = u % TX, oy = u / TX;
+    const uint32_t x = x0 + ox, y = y0 + oy, col = y * g.nx + x;
+    const uint32_t out_off = y * ar.yrow_bytes + x * (uint32_t)sizeof(real);
+    const uint32_t l0 = (oy + 1) * NSX + ox + 1;
+    const uint32_t xw[3] = {wrap_inc(x, g.nx) * (uint32_t)sizeof(W), x * (uint32_t)sizeof(W),
+                            wrap_dec(x, g.nx) * (uint32_t)sizeof(W)};
+    const uint32_t yw[3] = {wrap_inc(y, g.ny) * aw.yrow_bytes, y * aw.yrow_bytes, wrap_dec(y, g.ny) * aw.yrow_bytes};
+    real dA[Q], dB[Q], dC[Q];  // lambda of outputs q - 1, q, q + 1 for the chi_t plane q just read
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dA[i] = dB[i] = dC[i] = 0;
+    // the next output plane's gathers, issued a plane ahead: g_t-1 pulled (raw words),
+    // its force and the force gradient it adds to
+    W st[Q];
+    real sf[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
+    auto load_next = [&](int oz) {
+      const char* base[3] = {fbm + (uint64_t)wrapz(oz + 1) * aw.plane_bytes, fbm + (uint64_t)wrapz(oz) * aw.plane_bytes,
+                             fbm + (uint64_t)wrapz(oz - 1) * aw.plane_bytes};
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        st[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * aw.row_bytes +
+                                            (yw[LT::cy(i) + 1] + xw[LT::cx(i) + 1]));
+      load_force((uint32_t)oz, col, sf[0], sf[1], sf[2]);
+      if (grad) {
+        const real* f = dforce + (uint64_t)oz * plane_cells + col;
+        sg[0] = f[0];
+        sg[1] = f[g.ncells];
+        sg[2] = f[2 * g.ncells];
+      }
+    };
+    real atx = 0, aty = 0, atz = 0;  // a_t of the next output plane
+    real ntx = 0, nty = 0, ntz = 0;
+    auto consume = [&](int qz, auto sl, auto emit) {
+      constexpr int SL = decltype(sl)::value;
+      constexpr bool EMIT = decltype(emit)::value;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const real v = slot[SL][i][l0 + (LT::cy(i) * NSX + LT::cx(i))];
+        if (LT::cz(i) > 0) dA[i] = v;
+        if (LT::cz(i) == 0) dB[i] = v;
+        if (LT::cz(i) < 0) dC[i] = v;
+      }
+      if (grad) {
+        ntx = stash[SL][0][u];
+        nty = stash[SL][1][u];
+        ntz = stash[SL][2][u];
+      }
+      if constexpr (EMIT) {
+        const int oz = qz - 1;  // the output plane completed by plane qz
+        real d[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(st[i], CO::W(i));
+        real ax, ay, az;
+        adjoint_collide<L, real, FORCED>(d, dA, sf[0], sf[1], sf[2], omega, ax, ay, az);
+        char* o = cbo + (uint64_t)oz * ar.plane_bytes + out_off;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) store_stream(reinterpret_cast<real*>(o + (uint64_t)i * ar.row_bytes), dA[i]);
+        if (grad) {
+          real* f = dforce + (uint64_t)oz * plane_cells + col;
+          f[0] = (sg[0] + atx) + ax;
+          f[g.ncells] = (sg[1] + aty) + ay;
+          f[2 * g.ncells] = (sg[2] + atz) + az;
+        }
+        if (oz + 1 < (int)ze) load_next(oz + 1);
+      }
+      atx = ntx;
+      aty = nty;
+      atz = ntz;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (LT::cz(i) <= 0) dA[i] = dB[i];
+        if (LT::cz(i) < 0) dB[i] = dC[i];
+      }
+    };
+    load_next((int)zb);  // the first output plane
+    __syncthreads();  // plane zb-1 written
+    consume((int)zb - 1, I0(), std::false_type());
+    __syncthreads();
+    consume((int)zb, I1(), std::false_type());
+    __syncthreads();
+    uint32_t k = 2;  // planes read so far; plane zb-1+k completes output zb-2+k
+    for (; k + 1 < nplanes; k += 2) {
+      consume((int)(zb + k) - 1, I0(), std::true_type());
+      __syncthreads();
+      consume((int)(zb + k), I1(), std::true_type());
+      __syncthreads();
+    }
+    if (k < nplanes) {
+      consume((int)(zb + k) - 1, I0(), std::true_type());
+      __syncthreads();
     }
   }
 }
@@ -1406,6 +1701,68 @@ static hipError_t launch_adjoint_ls(int mode, const void* gt, const void* lam_ne
   return hipErrorInvalidValue;
 }
 
+// Two adjoint steps per launch (adjoint2_kernel): the 3D lattices, every storage kind
+// of the state but FP64 (the adjoint reals are FP32 then), on the grids the two-step
+// forward kernel's 32 x 8 tiles take.
+template <int L, int S>
+static bool adjoint2_fits(const GridArgs& g) {
+  if constexpr ((L != kD3Q27 && L != kD3Q19) || S == kF64) {
+    return false;
+  } else {
+    using SH = Step2Shape<L, kF32>;
+    const uint64_t plane = (uint64_t)g.ny * Lattice<L>::Q * g.pitch * sizeof(typename Storage<S>::real);
+    return g.ghost == 0 && g.z0 == 0 && g.nzl == g.nz && g.nx % SH::TX == 0 && g.ny % SH::TY == 0 && g.nz >= 3 &&
+           plane < (uint64_t(1) << 32);
+  }
+}
+
+template <int L, int S>
+static hipError_t adjoint2_fits_ls(const GridArgs& g, bool* ok) {
+  *ok = adjoint2_fits<L, S>(g);
+  return hipSuccess;
+}
+
+template <int L, int S, bool FORCED>
+static uint32_t adjoint2_blocks_per_cu() {
+  static std::atomic<int> cached{0};
+  return blocks_per_cu(cached, adjoint2_kernel<L, S, FORCED>, Step2Shape<L, kF32>::NT);
+}
+
+template <int L, int S>
+static hipError_t launch_adjoint2_ls(const void* gt, const void* gtm1, const void* chi_next, void* chi_out,
+                                     const void* force, void* dforce, const GridArgs& g, double omega, hipStream_t s) {
+  if constexpr ((L != kD3Q27 && L != kD3Q19) || S == kF64) {
+    return hipErrorInvalidValue;
+  } else {
+    using ST = Storage<S>;
+    using W = typename ST::word;
+    using R = typename ST::real;
+    using SH = Step2Shape<L, kF32>;
+    if (!adjoint2_fits<L, S>(g)) return hipErrorInvalidValue;
+    Step2Args aw, ar;
+    aw.tiles_x = ar.tiles_x = g.nx / SH::TX;
+    aw.tiles_y = ar.tiles_y = g.ny / SH::TY;
+    aw.row_bytes = g.pitch * (uint32_t)sizeof(W);
+    ar.row_bytes = g.pitch * (uint32_t)sizeof(R);
+    aw.yrow_bytes = Lattice<L>::Q * aw.row_bytes;
+    ar.yrow_bytes = Lattice<L>::Q * ar.row_bytes;
+    aw.plane_bytes = g.ny * aw.yrow_bytes;
+    ar.plane_bytes = g.ny * ar.yrow_bytes;
+    const uint64_t tiles = (uint64_t)ar.tiles_x * ar.tiles_y;
+    const uint32_t per_cu = force ? adjoint2_blocks_per_cu<L, S, true>() : adjoint2_blocks_per_cu<L, S, false>();
+    ar.lz = aw.lz = step2_chunk(tiles, g.nz, (uint64_t)per_cu * device_cus(), 2);
+    const dim3 grid((unsigned)(tiles * ((g.nz + ar.lz - 1) / ar.lz)));
+    if (force)
+      adjoint2_kernel<L, S, true><<<grid, SH::NT, 0, s>>>((const W*)gt, (const W*)gtm1, (const R*)chi_next,
+                                                          (R*)chi_out, (const R*)force, (R*)dforce, g, aw, ar,
+                                                          (R)omega);
+    else
+      adjoint2_kernel<L, S, false><<<grid, SH::NT, 0, s>>>((const W*)gt, (const W*)gtm1, (const R*)chi_next,
+                                                           (R*)chi_out, nullptr, nullptr, g, aw, ar, (R)omega);
+    return hipGetLastError();
+  }
+}
+
 template <int L, int S>
 static hipError_t launch_init_ls(const double* rho, const double* u, void* fout, const GridArgs& g, hipStream_t s) {
   using W = typename Storage<S>::word;
@@ -1517,6 +1874,18 @@ int max_steps_per_launch(int lattice, int storage, const GridArgs& g) {
 hipError_t launch_stepn(int lattice, int storage, int nst, const void* fin, void* fout, const void* force,
                         int force_mode, const GridArgs& g, double omega, hipStream_t s) {
   LBM_DISPATCH(launch_stepn_ls, lattice, storage, nst, fin, fout, force, force_mode, g, omega, s);
+}
+
+bool adjoint2_supported(int lattice, int storage, const GridArgs& g) {
+  bool ok = false;
+  auto check = [&]() -> hipError_t { LBM_DISPATCH(adjoint2_fits_ls, lattice, storage, g, &ok); };
+  return check() == hipSuccess && ok;
+}
+
+hipError_t launch_adjoint2(int lattice, int storage, const void* gt, const void* gtm1, const void* chi_next,
+                           void* chi_out, const void* force, void* dforce, const GridArgs& g, double omega,
+                           hipStream_t s) {
+  LBM_DISPATCH(launch_adjoint2_ls, lattice, storage, gt, gtm1, chi_next, chi_out, force, dforce, g, omega, s);
 }
 
 hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, const void* lam_next, void* lam_out,

@@ -24,7 +24,7 @@ def B():
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_entry_points():
@@ -180,6 +180,42 @@ def test_local_adjoint_validation(B):
     assert lib.lbm_adjoint_step_local(gp, P1, P2, 0, P3, 0.5, None, None, None) == -1
     assert lib.lbm_adjoint_unstream(gp, P1, P1, None) == -4
     assert lib.lbm_adjoint_unstream(gp, None, P1, None) == -2
+
+
+def test_two_step_adjoint_validation(B):
+    lib = B._lib
+    P4 = ctypes.c_void_p(0xC000000000)
+    P5 = ctypes.c_void_p(0x10000000000)
+    g = _grid(B, nx=64, ny=16, nz=8)
+    gp = ctypes.byref(g)
+    f = lib.lbm_adjoint_step2_local
+    assert f(gp, None, P2, P3, P4, 0.6, None, None, None) == -2
+    assert f(gp, P1, P2, P3, None, 0.6, None, None, None) == -2
+    assert f(gp, P1, MIS, P3, P4, 0.6, None, None, None) == -3
+    assert f(gp, P1, P2, P3, P4, 0.5, None, None, None) == -1
+    assert f(gp, P1, P2, P3, P3, 0.6, None, None, None) == -4       # chi_out == chi_next
+    assert f(gp, P1, P2, P3, P4, 0.6, None, P5, None) == -5         # dforce without force
+    assert f(gp, P1, P2, P3, P4, 0.6, P5, P4, None) == -4           # dforce == chi_out
+    for storage, dims in (("f64", (64, 16, 8)), ("f32", (48, 16, 8)), ("f32", (64, 12, 8)), ("f32", (64, 16, 2))):
+        h = _grid(B, storage=storage, nx=dims[0], ny=dims[1], nz=dims[2])
+        assert f(ctypes.byref(h), P1, P2, P3, P4, 0.6, None, None, None) == -5, (storage, dims)
+    h = _grid(B, "D2Q9", nx=64, ny=16, nz=1)
+    assert f(ctypes.byref(h), P1, P2, P3, P4, 0.6, None, None, None) == -5
+    v = ctypes.c_int32(7)
+    assert lib.lbm_adjoint_step2_available(gp, None) == -2
+    assert lib.lbm_adjoint_step2_available(ctypes.byref(_grid(B, nx=0)), ctypes.byref(v)) == -1
+
+
+@pytest.mark.parametrize("lattice,storage,dims,ok", [
+    ("D3Q27", "f32", (64, 16, 8), True), ("D3Q19", "f16s", (32, 8, 3), True), ("D3Q27", "f32s", (32, 8, 3), True),
+    ("D3Q27", "bf16s", (256, 256, 256), True), ("D3Q27", "f64", (64, 16, 8), False),
+    ("D3Q27", "f32", (48, 16, 8), False), ("D3Q27", "f32", (32, 8, 2), False), ("D2Q9", "f32", (64, 16, 1), False)])
+def test_two_step_adjoint_availability(B, lattice, storage, dims, ok):
+    v = ctypes.c_int32(7)
+    g = _grid(B, lattice, storage, *dims)
+    assert B._lib.lbm_adjoint_step2_available(ctypes.byref(g), ctypes.byref(v)) == 0
+    assert v.value == int(ok)
+    assert B.lbm_adjoint_step2_available(B.Grid(lattice, storage, *dims)) == ok
 
 
 def test_copy_validation(B):

@@ -48,6 +48,8 @@ def _fake_detail():
         "adjoint": {k: fw() for k in ("f32", "f16s")},
         "adjoint_scatter_form": {k: fw() for k in ("f32", "f16s")},
         "adjoint_forced": {k: fw() for k in ("f32", "f16s")},
+        "adjoint_paired": {k: fw() for k in ("f32", "f16s")},
+        "adjoint_paired_forced": {k: fw() for k in ("f32", "f16s")},
         "moments_f32": {"ms": v(), "hbm_gbs": v()},
         "tgv2d_64_f64": {"graph_us_per_step": v(), "launch_loop_us_per_step": v()},
         "device_copy": {"gbs": v(), "torch_copy_gbs": v()},
@@ -104,7 +106,7 @@ def test_bench_line_is_small_and_complete():
     assert line["roofline"]["kernel"].startswith("lbm::step2_kernel")
     assert line["roofline"]["traffic"] == 3624615676.0
     s = line["summary"]
-    for k in ("f16s_speedup_vs_f32", "bf16s_speedup_vs_f32", "f16s_u_rel_l2_vs_f64", "adjoint_local_f32_mlups",
+    for k in ("f16s_speedup_vs_f32", "bf16s_speedup_vs_f32", "f16s_u_rel_l2_vs_f64", "adjoint_local_f32_mlups", "adjoint_paired_f16s_mlups",
               "f64_mlups", "d3q19_f32_mlups", "precision_384", "adjoint_512", "one_step_kernel_f32_mlups",
               "one_step_kernel_f32_hbm_frac", "one_step_kernels_f16s_speedup_vs_f32"):
         assert k in s, k
