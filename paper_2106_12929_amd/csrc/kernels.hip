@@ -120,16 +120,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWave
 template <int L, int S>
 struct Step2Shape {
   // a tile's direction row is one 128-byte line: 32 x 8 cells for 4-byte words,
-  // 64 x 4 for 2-byte words
-  static constexpr int TX = sizeof(typename Storage<S>::word) == 2 ? 64 : 32, TY = 256 / TX;
+  // 64 x 4 for 2-byte words.  8-byte words take 32 x 4 tiles (rows of two lines): 6
+  // waves, so that at 2 waves per SIMD a lane may hold the 256 registers the FP64
+  // collisions need.
+  static constexpr int WB = sizeof(typename Storage<S>::word);
+  static constexpr int TX = WB == 2 ? 64 : 32, TY = WB == 8 ? 4 : 256 / TX;
   static constexpr int NSX = TX + 2, NS = NSX * (TY + 2);  // ring-tile columns
   static constexpr int NP = (NS + 63) / 64;                 // producer waves
   static constexpr int NC = TX * TY / 64;                   // consumer waves
   static constexpr int NT = 64 * (NP + NC);
+  static constexpr int WAVES_PER_EU = WB == 8 ? 2 : 3;
 };
 
 template <int L, int S, int FM>
-__global__ __launch_bounds__((Step2Shape<L, S>::NT)) __attribute__((amdgpu_waves_per_eu(3))) void step2_kernel(
+__global__ __launch_bounds__((Step2Shape<L, S>::NT))
+__attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_kernel(
     const typename Storage<S>::word* __restrict__ fin, typename Storage<S>::word* __restrict__ fout,
     const typename Storage<S>::real* __restrict__ force, GridArgs g, Step2Args a, typename Storage<S>::real omega) {
   using LT = Lattice<L>;
@@ -1474,7 +1479,7 @@ static hipError_t launch_step_ls(const void* fin, void* fout, const void* force,
 template <int L, int S>
 constexpr bool step2_enabled() {
   if (L == kD2Q9) return S != kBF16S;
-  return (L == kD3Q27 || L == kD3Q19) && (S == kF32 || S == kF32S || S == kF16S);
+  return (L == kD3Q27 || L == kD3Q19) && (S == kF32 || S == kF32S || S == kF16S || S == kF64);
 }
 
 // Segment width of the D2Q9 multi-step kernel advancing nst steps (0: none fits).

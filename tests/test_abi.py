@@ -379,7 +379,12 @@ def _launches(B, g, n):
     ("D3Q27", "f16s", (32, 8, 8), 0, 1),
     ("D3Q19", "f16s", (64, 4, 3), 0, 2),
     ("D3Q27", "bf16s", (256, 256, 256), 0, 1),   # shifted BF16 steps singly
-    ("D3Q27", "f64", (256, 256, 256), 0, 1),
+    ("D3Q27", "f64", (256, 256, 256), 0, 2),     # 8-byte words: 32 x 4 tiles
+    ("D3Q27", "f64", (32, 4, 3), 0, 2),
+    ("D3Q19", "f64", (64, 8, 5), 96, 2),
+    ("D3Q27", "f64", (32, 6, 3), 0, 1),          # ny off the 4-row tiles
+    ("D3Q27", "f64", (32, 4, 4), 4971027, 1),    # one z plane of words: 2^32 + 32 bytes
+    ("D3Q27", "f64", (32, 4, 4), 4971026, 2),    # 2^32 - 832 bytes
     ("D2Q9", "f32", (256, 256, 1), 0, 4),        # 2D: four steps per launch
     ("D2Q9", "f64", (64, 64, 1), 0, 4),
     ("D2Q9", "f16s", (8192, 8192, 1), 0, 2),     # shifted FP16: two steps per launch

@@ -2,7 +2,8 @@
 
 For n_steps >= 4, lbm_step runs pairs of steps as one LDS-blocked launch on 3D grids
 (FP32 and shifted-FP32 words with nx a multiple of 32 and ny of 8, shifted FP16 with nx
-a multiple of 64 and ny of 4; the first n_steps mod 4 steps run singly).  Each collision of that kernel is the one-step
+a multiple of 64 and ny of 4, FP64 with nx a multiple of 32 and ny of 4; the first
+n_steps mod 4 steps run singly).  Each collision of that kernel is the one-step
 kernel's, applied to the same rounded storage words, so the result must equal the same
 number of single-step launches bit for bit; the single steps are tied to the oracle
 (Eqs. 1-4) by the one-step parity tests, and the last test here ties the paired
@@ -37,6 +38,8 @@ CASES = [  # lattice, (nx, ny, nz), pitch (None = nx)
     ("D3Q27", (32, 8, 2), None),   # nz < 3
     ("D3Q27", (64, 4, 9), 128),    # 2-byte words: one 64 x 4 tile, padded rows
     ("D3Q27", (128, 12, 5), None),
+    ("D3Q27", (32, 4, 7), None),     # 8-byte words: one 32 x 4 tile
+    ("D3Q27", (64, 12, 4), 96),      # 8-byte words: 32 x 4 tiles, padded rows
     ("D2Q9", (256, 20, 1), None),  # 2D: one 256-cell segment per row, chunks of rows
     ("D2Q9", (64, 37, 1), None),   # 64-cell segments, odd ny
     ("D2Q9", (128, 3, 1), 192),    # ny = 3, padded rows
@@ -141,11 +144,11 @@ def test_paired_steps_leave_pad_words_alone():
     assert torch.all(torch.isfinite(rows[:, :, :32]))
 
 
-@pytest.mark.parametrize("kind", ["f32", "f32s", "f16s"])
+@pytest.mark.parametrize("kind", ["f32", "f32s", "f16s", "f64"])
 def test_paired_steps_full_size_equal_single_steps(kind):
     """256^3 in the launch shape of the benchmark (one chunk of 256 planes per tile,
-    tiles of 32 x 8 columns, 64 x 4 for FP16): four steps as two paired launches
-    against four single steps, every word compared."""
+    tiles of 32 x 8 columns, 64 x 4 for FP16, 32 x 4 for FP64): four steps as two paired
+    launches against four single steps, every word compared."""
     need_gpu()
     B = binding()
     n = 256
@@ -169,10 +172,11 @@ def test_paired_steps_full_size_equal_single_steps(kind):
     assert torch.equal(bits(p), bits(ref))
 
 
-@pytest.mark.parametrize("kind,bound", [("f32", 1e-5), ("f32s", 1e-5), ("f16s", 1e-2)])
+@pytest.mark.parametrize("kind,bound", [("f32", 1e-5), ("f32s", 1e-5), ("f16s", 1e-2), ("f64", 1e-12)])
 def test_paired_steps_vs_oracle(kind, bound):
     """A decaying Taylor-Green vortex on 64 x 32 x 24 cells, 200 steps (100 paired
-    launches) against the FP64 oracle (FP16: a sanity bound on the storage noise)."""
+    launches) against the FP64 oracle (FP16: a sanity bound on the storage noise; FP64:
+    rounding order only)."""
     need_gpu()
     B = binding()
     nx, ny, nz = 64, 32, 24
