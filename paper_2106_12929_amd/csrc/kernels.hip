@@ -1478,8 +1478,8 @@ static hipError_t launch_step_ls(const void* fin, void* fout, const void* force,
 // two-step form bound by its arithmetic, 4% slower than two single steps.
 template <int L, int S>
 constexpr bool step2_enabled() {
-  if (L == kD2Q9) return S != kBF16S;
-  return (L == kD3Q27 || L == kD3Q19) && (S == kF32 || S == kF32S || S == kF16S || S == kF64);
+  if (L == kD2Q9) return true;
+  return L == kD3Q27 || L == kD3Q19;
 }
 
 // Segment width of the D2Q9 multi-step kernel advancing nst steps (0: none fits).

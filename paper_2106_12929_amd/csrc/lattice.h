@@ -122,10 +122,8 @@ __device__ __forceinline__ float f16_bits_to_f32(uint16_t b) {
   return static_cast<float>(__builtin_bit_cast(_Float16, b));
 }
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
-  uint32_t b = __builtin_bit_cast(uint32_t, x);
-  if ((b & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((b >> 16) | 0x40u);  // quiet NaN
-  b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest, ties to even, on the dropped half
-  return static_cast<uint16_t>(b >> 16);
+  __bf16 h = static_cast<__bf16>(x);  // v_cvt_pk_bf16_f32: RNE; a NaN stays a (quiet) NaN
+  return __builtin_bit_cast(uint16_t, h);
 }
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
   return __builtin_bit_cast(float, static_cast<uint32_t>(b) << 16);

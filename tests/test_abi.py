@@ -378,7 +378,7 @@ def _launches(B, g, n):
     ("D3Q27", "f16s", (256, 256, 256), 0, 2),    # 2-byte words: 64 x 4 tiles
     ("D3Q27", "f16s", (32, 8, 8), 0, 1),
     ("D3Q19", "f16s", (64, 4, 3), 0, 2),
-    ("D3Q27", "bf16s", (256, 256, 256), 0, 1),   # shifted BF16 steps singly
+    ("D3Q27", "bf16s", (256, 256, 256), 0, 2),   # shifted BF16: 64 x 4 tiles, as FP16
     ("D3Q27", "f64", (256, 256, 256), 0, 2),     # 8-byte words: 32 x 4 tiles
     ("D3Q27", "f64", (32, 4, 3), 0, 2),
     ("D3Q19", "f64", (64, 8, 5), 96, 2),
@@ -392,7 +392,7 @@ def _launches(B, g, n):
     ("D2Q9", "f32", (64, 3, 1), 192, 2),
     ("D2Q9", "f32", (96, 8, 1), 0, 1),           # nx off the 64-cell segments
     ("D2Q9", "f32", (64, 2, 1), 0, 1),           # ny < 3
-    ("D2Q9", "bf16s", (256, 256, 1), 0, 1),
+    ("D2Q9", "bf16s", (256, 256, 1), 0, 2),      # shifted BF16: two steps per launch
     ("D3Q27", "f32", (48, 16, 8), 0, 1),         # nx off the 32-cell tiles
     ("D3Q27", "f32", (32, 12, 8), 0, 1),         # ny off the 8-row tiles
     ("D3Q27", "f32", (32, 8, 2), 0, 1),          # nz < 3
