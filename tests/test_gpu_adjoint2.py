@@ -198,3 +198,36 @@ def test_paired_rollout_gradient_vs_oracle():
     say(f"  loss gpu {float(L):.8e} oracle {float(L_ref):.8e}; dF rel err {eF:.2e}, dg0 rel err {eg:.2e}")
     assert abs(float(L) - float(L_ref)) <= 1e-5 * abs(float(L_ref))
     assert eF < 1e-4 and eg < 1e-4
+
+
+def test_paired_rollout_on_padded_rows_matches_dense():
+    """The paired backward pass on padded rows (pitch 64 for 32 cells): loss, force
+    gradient and state gradient equal the dense layout's bit for bit, and the state
+    gradient's pad entries stay zero (the two-step adjoint writes live cells only)."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd import autograd as AG
+
+    st = olbm.stencil("D3Q27")
+    shape = (32, 8, 5)
+    spatial = _spatial(st, shape)
+    dense = B.Grid("D3Q27", "f32", *shape)
+    pitched = B.Grid("D3Q27", "f32", *shape, 64)
+    assert B.lbm_adjoint_step2_available(dense) and B.lbm_adjoint_step2_available(pitched)
+    s = _state(st, spatial, 71, "f32")
+    F0 = synthetic.random_normal((st.D,) + spatial, 72, 1e-4).float().cuda()
+    out = []
+    for grid in (dense, pitched):
+        say(f"paired rollout, row pitch {grid.row_pitch}")
+        g0 = grid.to_layout(s).cuda().requires_grad_(True)
+        F = F0.clone().requires_grad_(True)
+        gT = AG.rollout(grid, g0, F, 0.57, 9, checkpoint_every=4)
+        rho, u = AG.moments(grid, gT, F)
+        loss = (u.double() ** 2).sum() + (rho.double() - 1).pow(2).sum()
+        loss.backward()
+        out.append((loss.detach(), F.grad, g0.grad))
+    (l0, f0, s0), (l1, f1, s1) = out
+    assert torch.equal(bits(l0), bits(l1))
+    assert torch.equal(bits(f0), bits(f1))
+    assert torch.equal(bits(pitched.from_layout(s1.cpu())), bits(dense.from_layout(s0.cpu())))
+    assert bool((s1.view(5 * 8, 27, 64)[:, :, 32:] == 0).all())
