@@ -96,10 +96,10 @@ def test_paired_steps_equal_single_steps(lat, shape, pitch, kind, mode):
         assert same, f"n_steps={n}"
 
 
-@pytest.mark.parametrize("kind", ["f32", "f64", "f16s"])
+@pytest.mark.parametrize("kind", ["f32", "f64", "f16s", "bf16s"])
 def test_paired_steps_d2q9_full_size_equal_single_steps(kind):
     """8192^2 D2Q9 (the 2D benchmark grid): eight steps as two four-step launches (64
-    segments of 128 cells per row; four two-step launches for shifted FP16) and four
+    segments of 128 cells per row; four two-step launches for shifted FP16 and BF16) and four
     steps as two two-step launches (32 segments of 256 cells), against single steps,
     every word compared."""
     need_gpu()
@@ -114,7 +114,7 @@ def test_paired_steps_d2q9_full_size_equal_single_steps(kind):
     b = grid.empty_populations()
     assert B.lbm_step(grid, a, b, 0.6, None, 1) == 0
     start = b.clone()
-    for n, plan in ((4, (0, 2, 0)), (8, (0, 4, 0) if kind == "f16s" else (0, 0, 2))):
+    for n, plan in ((4, (0, 2, 0)), (8, (0, 4, 0) if kind in ("f16s", "bf16s") else (0, 0, 2))):
         x, y = start.clone(), a
         for _ in range(n):
             B.lbm_step(grid, x, y, 0.6, None, 1)
@@ -144,10 +144,10 @@ def test_paired_steps_leave_pad_words_alone():
     assert torch.all(torch.isfinite(rows[:, :, :32]))
 
 
-@pytest.mark.parametrize("kind", ["f32", "f32s", "f16s", "f64"])
+@pytest.mark.parametrize("kind", ["f32", "f32s", "f16s", "bf16s", "f64"])
 def test_paired_steps_full_size_equal_single_steps(kind):
     """256^3 in the launch shape of the benchmark (one chunk of 256 planes per tile,
-    tiles of 32 x 8 columns, 64 x 4 for FP16, 32 x 4 for FP64): four steps as two paired
+    tiles of 32 x 8 columns, 64 x 4 for FP16 and BF16, 32 x 4 for FP64): four steps as two paired
     launches against four single steps, every word compared."""
     need_gpu()
     B = binding()
@@ -172,10 +172,10 @@ def test_paired_steps_full_size_equal_single_steps(kind):
     assert torch.equal(bits(p), bits(ref))
 
 
-@pytest.mark.parametrize("kind,bound", [("f32", 1e-5), ("f32s", 1e-5), ("f16s", 1e-2), ("f64", 1e-12)])
+@pytest.mark.parametrize("kind,bound", [("f32", 1e-5), ("f32s", 1e-5), ("f16s", 1e-2), ("bf16s", 2e-2), ("f64", 1e-12)])
 def test_paired_steps_vs_oracle(kind, bound):
     """A decaying Taylor-Green vortex on 64 x 32 x 24 cells, 200 steps (100 paired
-    launches) against the FP64 oracle (FP16: a sanity bound on the storage noise; FP64:
+    launches) against the FP64 oracle (FP16, BF16: a sanity bound on the storage noise; FP64:
     rounding order only)."""
     need_gpu()
     B = binding()
