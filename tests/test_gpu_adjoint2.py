@@ -102,19 +102,20 @@ def test_two_adjoint_steps_reject_other_grids():
             B.lbm_adjoint_step2_local(grid, g, g, c, torch.zeros_like(c), 0.6)
 
 
-@pytest.mark.parametrize("kind,mode", [("f32", "grad"), ("f16s", "none")])
-def test_two_adjoint_steps_full_size(kind, mode):
-    """256^3 in the launch shape of the full-scale adjoint (tiles of 32 x 8 columns, the
-    z chunks the occupancy gives): every word of chi and of the force gradient compared
-    with two one-step launches."""
+@pytest.mark.parametrize("kind,mode,n,tuned", [("f32", "grad", 256, False), ("f16s", "none", 256, False),
+                                               ("f16s", "grad", 512, True)])
+def test_two_adjoint_steps_full_size(kind, mode, n, tuned):
+    """256^3, and 512^3 on the rows of the full-scale adjoint workload (Grid.tuned, FP16
+    state, force gradient), in the launch shape the rollout uses (tiles of 32 x 8
+    columns, the z chunks the occupancy gives): every word of chi and of the force
+    gradient compared with two one-step launches."""
     need_gpu()
     B = binding()
-    n = 256
-    grid = B.Grid("D3Q27", kind, n, n, n)
-    say(f"two adjoint steps full size {kind} {mode} {n}^3")
-    u = synthetic.taylor_green_3d(n, n, n, 0.05)
+    grid = B.Grid.tuned("D3Q27", kind, n, n, n) if tuned else B.Grid("D3Q27", kind, n, n, n)
+    say(f"two adjoint steps full size {kind} {mode} {n}^3 pitch {grid.row_pitch}")
+    u = synthetic.taylor_green_3d_on("cuda", n, n, n, 0.05)
     gtm1 = grid.empty_populations()
-    B.lbm_init_equilibrium(grid, None, u.cuda(), gtm1)
+    B.lbm_init_equilibrium(grid, None, u, gtm1)
     del u
     F = dF = None
     if mode == "grad":
@@ -129,7 +130,7 @@ def test_two_adjoint_steps_full_size(kind, mode):
     out = torch.empty_like(chi)
     B.lbm_adjoint_step2_local(grid, gt, gtm1, chi, out, 0.51, F, dF)
     torch.cuda.synchronize()
-    assert torch.equal(bits(out), bits(ref))
+    assert torch.equal(bits(grid.from_layout(out)), bits(grid.from_layout(ref)))
     if dF is not None:
         assert torch.equal(bits(dF), bits(dF_ref))
 
