@@ -336,11 +336,13 @@ int lbm_adjoint_step_local(const lbm_grid* grid, const void* g_t, const void* ad
  *             first), so that the result equals lbm_adjoint_step_local(g_t, chi_next,
  *             1, tmp) followed by lbm_adjoint_step_local(g_tm1, tmp, 1, chi_out) bit for
  *             bit.
- * g_t, g_tm1: the states of steps t and t-1 (Q*N storage words each).  chi_next,
- * chi_out: Q*N reals.  tau, force, dforce as lbm_adjoint_step.  chi_out must not
- * overlap any other argument, dforce none but chi_out's.  LBM_EUNSUP where the grid or
- * storage kind is not taken (3D lattices, every kind but FP64, nx a multiple of 32, ny
- * of 8, nz >= 3: lbm_adjoint_step2_available). */
+ * g_t, g_tm1: the states of steps t and t-1 (Q*N storage words each, read only).
+ * chi_next: Q*N reals (read only).  chi_out: Q*N reals, live cells overwritten, pad
+ * words untouched.  tau, force, dforce as lbm_adjoint_step (the one force field of both
+ * steps).  LBM_EALIAS if chi_out or dforce overlaps another argument.  LBM_EUNSUP for
+ * dforce without force, and where the grid or storage kind is not taken: the kernel
+ * takes D3Q27 and D3Q19 grids with any storage kind but FP64, nx a multiple of 32, ny
+ * of 8, nz >= 3 and one z plane of reals < 4 GiB (lbm_adjoint_step2_available). */
 int lbm_adjoint_step2_local(const lbm_grid* grid, const void* g_t, const void* g_tm1, const void* chi_next,
                             void* chi_out, double tau, const void* force, void* dforce, void* stream);
 
