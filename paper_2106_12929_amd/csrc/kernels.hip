@@ -103,16 +103,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWave
 // per plane separates the two slots' uses.  A consumer keeps the populations of the
 // two planes above its current output that it has already read (9 and 18 values): a
 // plane contributes the c_z = -1 directions to the output plane below it, c_z = 0 to
-// its own plane and c_z = +1 to the plane above.  The producers load plane k+1 while
-// they collide plane k.
+// its own plane and c_z = +1 to the plane above.  The producers load plane k+1 (words
+// and force) while they collide plane k; the consumers load the force of their next
+// output plane one plane ahead.
 //
 // Each collision is bgk_collide on the words the one-step kernel would have read, and
 // the intermediate words are rounded to storage exactly as its stores are, so the
 // result equals two launches of step_kernel bit for bit.
 //
 // Tiles are 32 x 8 cells for 4-byte words and 64 x 4 for 2-byte words (a direction row
-// of a tile is one 128-byte line).  Consecutive tiles of a chunk go to the same XCD (blocks are dealt to the 8
-// XCDs in turn), so the ring rows and line ends a block shares with its neighbours
+// of a tile is one 128-byte line), 32 x 4 for 8-byte words.  Consecutive tiles of a
+// chunk go to the same XCD (blocks are dealt to the 8 XCDs in turn), so the ring rows and line ends a block shares with its neighbours
 // are mostly served by that XCD's L2: a launch fetches about 1.4 times the state's
 // bytes (two single steps fetch them twice); the excess is ring rows read again when
 // a neighbouring tile is at another plane.
@@ -190,22 +191,22 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
     const uint32_t xb[3] = {wrap_inc(x, g.nx) * (uint32_t)sizeof(W), x * (uint32_t)sizeof(W),
                             wrap_dec(x, g.nx) * (uint32_t)sizeof(W)};
     const uint32_t yb[3] = {wrap_inc(y, g.ny) * a.yrow_bytes, y * a.yrow_bytes, wrap_dec(y, g.ny) * a.yrow_bytes};
-    auto load = [&](int pz, W (&r)[Q]) {
+    // the gathers of plane pz: the pulled words and the force
+    auto load = [&](int pz, W (&r)[Q], real (&rf)[3]) {
       const char* base[3] = {fb + (uint64_t)wrapz(pz + 1) * a.plane_bytes, fb + (uint64_t)wrapz(pz) * a.plane_bytes,
                              fb + (uint64_t)wrapz(pz - 1) * a.plane_bytes};
 #pragma unroll
       for (int i = 0; i < Q; ++i)
         r[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * a.row_bytes +
                                            (yb[LT::cy(i) + 1] + xb[LT::cx(i) + 1]));
+      load_force(wrapz(pz), col, rf[0], rf[1], rf[2]);
     };
-    auto produce = [&](int pz, W (&r)[Q], auto sl) {
+    auto produce = [&](W (&r)[Q], const real (&rf)[3], auto sl) {
       constexpr int SL = decltype(sl)::value;
       real d[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
-      real Fx = 0, Fy = 0, Fz = 0;
-      load_force(wrapz(pz), col, Fx, Fy, Fz);
-      bgk_collide<L, real, FM>(d, Fx, Fy, Fz, omega);
+      bgk_collide<L, real, FM>(d, rf[0], rf[1], rf[2], omega);
       if (live) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) slot[SL][i][s] = ST::from_dev(d[i], CO::W(i));
@@ -214,18 +215,19 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     W r0[Q], r1[Q];
-    load((int)zb - 1, r0);
+    real f0[3] = {0, 0, 0}, f1[3] = {0, 0, 0};
+    load((int)zb - 1, r0, f0);
     uint32_t k = 0;
     for (; k + 1 < nplanes; k += 2) {  // plane zb-1+k into slot 0, the next into slot 1
-      load((int)(zb + k), r1);
-      produce((int)(zb + k) - 1, r0, I0());
+      load((int)(zb + k), r1, f1);
+      produce(r0, f0, I0());
       __syncthreads();
-      load((int)(zb + k) + 1, r0);  // one plane past ze on the last pass: read, unused
-      produce((int)(zb + k), r1, I1());
+      load((int)(zb + k) + 1, r0, f0);  // one plane past ze on the last pass: read, unused
+      produce(r1, f1, I1());
       __syncthreads();
     }
     if (k < nplanes) {
-      produce((int)(zb + k) - 1, r0, I0());
+      produce(r0, f0, I0());
       __syncthreads();
     }
     __syncthreads();  // the consumers' last plane
@@ -239,6 +241,7 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
     real dA[Q], dB[Q], dC[Q];  // outputs q - 1, q, q + 1 of the plane q just read
 #pragma unroll
     for (int i = 0; i < Q; ++i) dA[i] = dB[i] = dC[i] = 0;
+    real cf[3] = {0, 0, 0};  // force of the next output plane, read a plane ahead
     auto consume = [&](int q, auto sl, auto emit) {
       constexpr int SL = decltype(sl)::value;
       constexpr bool EMIT = decltype(emit)::value;
@@ -250,13 +253,12 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
         if (LT::cz(i) > 0) dC[i] = v;
       }
       if constexpr (EMIT) {
-        real Fx = 0, Fy = 0, Fz = 0;
-        load_force((uint32_t)(q - 1), col, Fx, Fy, Fz);
-        bgk_collide<L, real, FM>(dA, Fx, Fy, Fz, omega);
+        bgk_collide<L, real, FM>(dA, cf[0], cf[1], cf[2], omega);
         char* o = ob + (uint64_t)(q - 1) * a.plane_bytes + out_off;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
           store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes), ST::from_dev(dA[i], CO::W(i)));
+        if (q < (int)ze) load_force((uint32_t)q, col, cf[0], cf[1], cf[2]);  // the next output plane's
       }
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
@@ -266,6 +268,7 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
+    load_force(zb, col, cf[0], cf[1], cf[2]);  // the first output plane's force
     __syncthreads();  // plane zb-1 written
     consume((int)zb - 1, I0(), std::false_type());
     __syncthreads();
