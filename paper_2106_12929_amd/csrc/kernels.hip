@@ -299,7 +299,8 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
 // iteration k - 1 (a row gives the c_y = -1 directions to the row below it, c_y = 0 to
 // itself, c_y = +1 to the row above; a lane keeps 3 + 6 values it has already read),
 // completes the row below it and writes it to its own ring (slot k & 1).  One barrier
-// per iteration.  Stage 1 loads the next row while it collides the current one.  The
+// per iteration.  Stage 1 loads the next row (words and force) while it collides the
+// current one; the other stages read the force of their next row a row ahead.  The
 // intermediate words are rounded to storage as step_kernel stores them and each
 // collision is bgk_collide, so the result equals NST launches of step_kernel bit for
 // bit.  The widened segments recompute 2 (NST - s) cells per row and stage: 1.008x of
@@ -372,23 +373,23 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
     const uint32_t xb[3] = {wrap_inc(x, g.nx) * (uint32_t)sizeof(W), x * (uint32_t)sizeof(W),
                             wrap_dec(x, g.nx) * (uint32_t)sizeof(W)};
     const uint32_t rows = (ye - yb) + 2 * (NST - 1);
-    auto load = [&](int py, W (&r)[Q]) {
+    // the gathers of row py: the pulled words and the force
+    auto load = [&](int py, W (&r)[Q], real (&rf)[2]) {
       py = min(py, r0 + (int)rows - 1);  // the loads past the last row read that row again
       const char* base[3] = {fb + (uint64_t)wrapy(py + 1) * a.yrow_bytes, fb + (uint64_t)wrapy(py) * a.yrow_bytes,
                              fb + (uint64_t)wrapy(py - 1) * a.yrow_bytes};
 #pragma unroll
       for (int i = 0; i < Q; ++i)
         r[i] = *reinterpret_cast<const W*>(base[LT::cy(i) + 1] + (uint64_t)i * a.row_bytes + xb[LT::cx(i) + 1]);
+      load_force(wrapy(py), x, rf[0], rf[1]);
     };
-    auto produce = [&](uint32_t k, W (&r)[Q], auto sl) {
+    auto produce = [&](uint32_t k, W (&r)[Q], const real (&rf)[2], auto sl) {
       constexpr int SL = decltype(sl)::value;
       if (k < rows) {
         real d[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
-        real Fx = 0, Fy = 0;
-        load_force(wrapy(r0 + (int)k), x, Fx, Fy);
-        bgk_collide<kD2Q9, real, FM>(d, Fx, Fy, real(0), omega);
+        bgk_collide<kD2Q9, real, FM>(d, rf[0], rf[1], real(0), omega);
         if (live) {
 #pragma unroll
           for (int i = 0; i < Q; ++i) ring_at(1, SL, i, j) = ST::from_dev(d[i], CO::W(i));
@@ -396,18 +397,19 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
       }
     };
     W ra[Q], rb[Q];
-    load(r0, ra);
+    real fa[2] = {0, 0}, fb2[2] = {0, 0};
+    load(r0, ra, fa);
     uint32_t k = 0;
     for (; k + 1 < iters; k += 2) {
-      load(r0 + (int)k + 1, rb);
-      produce(k, ra, I0());
+      load(r0 + (int)k + 1, rb, fb2);
+      produce(k, ra, fa, I0());
       __syncthreads();
-      load(r0 + (int)k + 2, ra);
-      produce(k + 1, rb, I1());
+      load(r0 + (int)k + 2, ra, fa);
+      produce(k + 1, rb, fb2, I1());
       __syncthreads();
     }
     if (k < iters) {
-      produce(k, ra, I0());
+      produce(k, ra, fa, I0());
       __syncthreads();
     }
   } else {
@@ -428,6 +430,9 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
       real dA[Q], dB[Q], dC[Q];  // rows q - 1, q, q + 1 of the row q just read
 #pragma unroll
       for (int i = 0; i < Q; ++i) dA[i] = dB[i] = dC[i] = 0;
+      // force of the next row this stage completes, read a row ahead
+      real cf[2] = {0, 0};
+      load_force(wrapy(r0 + (int)(k0 + 2) - 2 * (ST_ - 1)), x, cf[0], cf[1]);
       auto step = [&](uint32_t k, auto sl) {
         constexpr int SL = decltype(sl)::value;  // slot written in iteration k (k & 1)
         if (k < k0 || k >= k0 + 2 + rows) return;
@@ -441,9 +446,8 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
         if (k >= k0 + 2) {
           // the row completed here: stage ST_ produces row r0 + k - 2 (ST_ - 1)
           const int row = r0 + (int)k - 2 * (ST_ - 1);
-          real Fx = 0, Fy = 0;
-          load_force(wrapy(row), x, Fx, Fy);
-          bgk_collide<kD2Q9, real, FM>(dA, Fx, Fy, real(0), omega);
+          bgk_collide<kD2Q9, real, FM>(dA, cf[0], cf[1], real(0), omega);
+          if (k + 1 < k0 + 2 + rows) load_force(wrapy(row + 1), x, cf[0], cf[1]);
           if constexpr (LAST) {
             if (live) {
               char* o = ob + (uint64_t)row * a.yrow_bytes + out_off;
