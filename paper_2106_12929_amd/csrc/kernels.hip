@@ -1646,7 +1646,7 @@ static hipError_t launch_stepn_ls(int nst, const void* fin, void* fout, const vo
 // pipeline arithmetic-bound) and takes two.
 template <int L, int S>
 static hipError_t max_steps_ls(const GridArgs& g, int* n) {
-  constexpr bool FOUR = L == kD2Q9 && (S == kF64 || S == kF32 || S == kF32S);
+  constexpr bool FOUR = L == kD2Q9;
   *n = !step2_fits<L, S>(g) ? 1 : (FOUR && stepn_2d_width(g, 4) != 0) ? 4 : 2;
   return hipSuccess;
 }

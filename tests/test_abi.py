@@ -387,12 +387,12 @@ def _launches(B, g, n):
     ("D3Q27", "f64", (32, 4, 4), 4971026, 2),    # 2^32 - 832 bytes
     ("D2Q9", "f32", (256, 256, 1), 0, 4),        # 2D: four steps per launch
     ("D2Q9", "f64", (64, 64, 1), 0, 4),
-    ("D2Q9", "f16s", (8192, 8192, 1), 0, 2),     # shifted FP16: two steps per launch
+    ("D2Q9", "f16s", (8192, 8192, 1), 0, 4),     # every kind: four steps per launch
     ("D2Q9", "f32", (128, 4, 1), 0, 2),          # ny < 5: two steps per launch
     ("D2Q9", "f32", (64, 3, 1), 192, 2),
     ("D2Q9", "f32", (96, 8, 1), 0, 1),           # nx off the 64-cell segments
     ("D2Q9", "f32", (64, 2, 1), 0, 1),           # ny < 3
-    ("D2Q9", "bf16s", (256, 256, 1), 0, 2),      # shifted BF16: two steps per launch
+    ("D2Q9", "bf16s", (256, 256, 1), 0, 4),
     ("D3Q27", "f32", (48, 16, 8), 0, 1),         # nx off the 32-cell tiles
     ("D3Q27", "f32", (32, 12, 8), 0, 1),         # ny off the 8-row tiles
     ("D3Q27", "f32", (32, 8, 2), 0, 1),          # nz < 3

@@ -99,7 +99,7 @@ def test_paired_steps_equal_single_steps(lat, shape, pitch, kind, mode):
 @pytest.mark.parametrize("kind", ["f32", "f64", "f16s", "bf16s"])
 def test_paired_steps_d2q9_full_size_equal_single_steps(kind):
     """8192^2 D2Q9 (the 2D benchmark grid): eight steps as two four-step launches (64
-    segments of 128 cells per row; four two-step launches for shifted FP16 and BF16) and four
+    segments of 128 cells per row) and four
     steps as two two-step launches (32 segments of 256 cells), against single steps,
     every word compared."""
     need_gpu()
@@ -114,7 +114,7 @@ def test_paired_steps_d2q9_full_size_equal_single_steps(kind):
     b = grid.empty_populations()
     assert B.lbm_step(grid, a, b, 0.6, None, 1) == 0
     start = b.clone()
-    for n, plan in ((4, (0, 2, 0)), (8, (0, 4, 0) if kind in ("f16s", "bf16s") else (0, 0, 2))):
+    for n, plan in ((4, (0, 2, 0)), (8, (0, 0, 2))):
         x, y = start.clone(), a
         for _ in range(n):
             B.lbm_step(grid, x, y, 0.6, None, 1)
