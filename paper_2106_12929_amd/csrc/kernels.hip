@@ -1120,11 +1120,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const typename Storage<S>:
 // along z, producer and consumer waves, two LDS slots, one barrier per plane), with the
 // adjoint's transposed streaming: lambda_i(x) = chi_i(x + c_i), so a plane of chi_t
 // gives its c_z = +1 directions to the output plane below it.  Producers gather the
-// state g_t (pull) and chi_t+1 (transposed) from HBM, one plane ahead; consumers gather
-// g_t-1 from HBM (also one plane ahead) and chi_t from LDS.  The producers also leave a_t of the
-// tile's own cells in LDS for the consumers.  Each cell's arithmetic is
-// adjoint_collide, as in adjoint_kernel, so the result equals two of its launches bit
-// for bit.
+// state g_t (pull), chi_t+1 (transposed) and the force from HBM, one plane ahead;
+// consumers gather g_t-1, the force and the force gradient from HBM (also one plane
+// ahead) and chi_t from LDS.  The producers also leave a_t of the tile's own cells in
+// LDS for the consumers.  Each cell's arithmetic is that of adjoint_collide, as in
+// adjoint_kernel, so the result equals two of its launches bit for bit.
 // ---------------------------------------------------------------------------------
 template <int L, int S, bool FORCED>
 __global__ __launch_bounds__((Step2Shape<L, kF32>::NT)) __attribute__((amdgpu_waves_per_eu(3))) void adjoint2_kernel(
