@@ -221,7 +221,16 @@ def run_shard(B, steps: int, warmup: int, nx: int = 512, ny: int = 512, nz: int 
             row["gbs"] = 2 * halo_bytes / (ms * 1e-3) / 1e9
         out[name] = row
     out["halo_bytes_per_face"] = halo_bytes // 2
-    del bufs, f, S
+    # two ghost planes on each side: one exchange and one two-step launch per two steps
+    S2 = SlabSet(grid, 1, ghost=2)
+    S2.scatter(f)
+    ms2 = time_launches(lambda: S2.step_pair(TAU), max(1, steps // 2), warmup)
+    halo2 = 2 * 27 * nx * ny * torch.tensor([], dtype=grid.word_dtype).element_size()  # both faces
+    out["slab2_step_pair"] = {"ms_per_two_steps": ms2, "mlups": 2 * grid.ncells / (ms2 * 1e-3) / 1e6,
+                              "hbm_gbs_per_step": bpc * grid.ncells / (ms2 / 2 * 1e-3) / 1e9}
+    out["halo2_exchange_only"] = {"ms": time_launches(lambda: S2.exchange(), steps, warmup),
+                                  "bytes_each_way": halo2}
+    del bufs, f, S, S2
     torch.cuda.empty_cache()
     return out
 
@@ -877,9 +886,10 @@ def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic
         summ[f"d3q19_{k}_mlups"] = _r(v["mlups"])
     for k, v in (detail.get("forward_forced") or {}).items():
         summ[f"forced_{k}_mlups"] = _r(v["mlups"])
-    # (the scatter form and the bandwidth fractions are in the detail file)
-    for name, key in (("adjoint_local", "adjoint"), ("adjoint_local_forced", "adjoint_forced"),
-                      ("adjoint_paired", "adjoint_paired"), ("adjoint_paired_forced", "adjoint_paired_forced")):
+    # (the scatter form, the forced one-step adjoint and the bandwidth fractions are in the
+    # detail file)
+    for name, key in (("adjoint_local", "adjoint"), ("adjoint_paired", "adjoint_paired"),
+                      ("adjoint_paired_forced", "adjoint_paired_forced")):
         for k, v in (detail.get(key) or {}).items():
             summ[f"{name}_{k}_mlups"] = _r(v["mlups"])
     d2 = detail.get("d2q9_8192") or {}
@@ -893,6 +903,8 @@ def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic
         summ["headline_frac_of_copy"] = _r(head["hbm_gbs"] / detail["device_copy"]["gbs"])
     if "shard_512x512x64_f16s" in detail:
         summ["shard_512x512x64_f16s_slab_mlups"] = _r(detail["shard_512x512x64_f16s"]["slab_step_sequential"]["mlups"])
+        if "slab2_step_pair" in detail["shard_512x512x64_f16s"]:
+            summ["shard_512x512x64_f16s_slab2_mlups"] = _r(detail["shard_512x512x64_f16s"]["slab2_step_pair"]["mlups"])
     if "tgv2d_64_f64" in detail:
         summ["tgv2d_64_f64_graph_us_per_step"] = _r(detail["tgv2d_64_f64"]["graph_us_per_step"])
     wl = detail.get("workloads") or {}

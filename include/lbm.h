@@ -227,6 +227,44 @@ int lbm_step_slab(const lbm_grid* slab, const void* f_in, void* f_out, double ta
 int lbm_slab_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid* dst_slab,
                        void* dst, int face, void* stream);
 
+/* Two steps (Eqs. 1-4, as lbm_step with n_steps = 2) of a whole z-slab in one launch
+ * that keeps the intermediate state on chip, for slabs with two ghost planes on each
+ * side: the halo of two steps is two planes deep, so the slabs exchange once per two
+ * steps.
+ * slab: as lbm_step_slab, nz >= 2 (LBM_EINVAL otherwise).
+ * f_in, f_out: slab buffers of (nz + 4) planes in the population layout: buffer
+ *   planes 0 and 1 are the ghost planes -2 and -1 below the slab, planes 2 .. nz + 1 hold
+ *   slab planes 0 .. nz-1, planes nz + 2 and nz + 3 the ghost planes nz and nz + 1
+ *   above.  The intermediate step is computed on planes -1 .. nz, which reads the
+ *   directions with c_z = +1 of ghost plane -2, those with c_z = 0 and +1 of ghost plane
+ *   -1, those with c_z = 0 and -1 of ghost plane nz and those with c_z = -1 of ghost plane
+ *   nz + 1 (what lbm_slab2_halo_copy fills); no other ghost words are read.  Own planes
+ *   of f_out are written, its ghost planes are left alone.
+ * force: NULL, or D * nx * ny * (nz + 2) reals: the force of slab planes -1 .. nz (one
+ *   ghost plane each side, which the caller fills from the neighbours' force).
+ * The result equals two steps of the periodic grid the slabs make up bit for bit.
+ * LBM_EUNSUP where the slab or storage kind does not take the two-step kernel (3D
+ * lattices; nx and ny on lbm_step's two-step tiles; lbm_step_slab2_available).  f_in and
+ * f_out must not overlap, nor force either of them. */
+int lbm_step_slab2(const lbm_grid* slab, const void* f_in, void* f_out, double tau, const void* force,
+                   void* stream);
+
+/* *available = 1 if lbm_step_slab2 takes this slab and storage kind, else 0.
+ * Host-only.  Grid errors as lbm_step; LBM_ENULL for a NULL output. */
+int lbm_step_slab2_available(const lbm_grid* slab, int* available);
+
+/* Halo exchange of lbm_step_slab2 (Eq. 1's streaming across the cut, two planes deep):
+ *   LBM_FACE_LOW:  src's slab plane 0, directions with c_z = -1 and 0, into dst's ghost
+ *                  plane nz_dst, and src's plane 1, c_z = -1, into dst's ghost plane
+ *                  nz_dst + 1 (dst is the slab below src);
+ *   LBM_FACE_HIGH: src's plane nz_src - 1, c_z = 0 and +1, into dst's ghost plane -1,
+ *                  and src's plane nz_src - 2, c_z = +1, into dst's ghost plane -2 (dst is
+ *                  the slab above).
+ * Buffers of (nz + 4) planes as lbm_step_slab2; both slabs nz >= 2; other rules as
+ * lbm_slab_halo_copy. */
+int lbm_slab2_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid* dst_slab, void* dst,
+                        int face, void* stream);
+
 /* Activation of the neural collision's hidden layer (lbm_step_neural). */
 enum lbm_activation { LBM_ACT_RELU = 0, LBM_ACT_TANH = 1 };
 

@@ -80,6 +80,9 @@ def _load() -> ctypes.CDLL:
         "lbm_copy": (i32, [vp, vp, sz, vp]),
         "lbm_step_slab": (i32, [gp, vp, vp, dbl, vp, ctypes.c_int64, ctypes.c_int64, vp]),
         "lbm_slab_halo_copy": (i32, [gp, vp, gp, vp, i32, vp]),
+        "lbm_step_slab2": (i32, [gp, vp, vp, dbl, vp, vp]),
+        "lbm_step_slab2_available": (i32, [gp, ctypes.POINTER(i32)]),
+        "lbm_slab2_halo_copy": (i32, [gp, vp, gp, vp, i32, vp]),
         "lbm_shell_energy": (i32, [ctypes.POINTER(_CShells), i32, vp, dbl, vp, vp]),
         "lbm_log_spectrum_grad": (i32, [ctypes.POINTER(_CShells), i32, vp, vp, vp, i32, i32, dbl, dbl, vp, vp]),
         "lbm_real_part": (i32, [vp, ctypes.c_int64, dbl, vp, i32, vp]),
@@ -199,15 +202,18 @@ class Grid:
     def empty_populations(self, device="cuda") -> torch.Tensor:
         return torch.empty(self.population_shape(), dtype=self.word_dtype, device=device)
 
-    def slab_population_shape(self) -> tuple:
-        """Shape of a z-slab buffer (lbm_step_slab): the population layout of nz + 2
-        planes, buffer plane 0 and nz + 1 being the ghost planes."""
+    def slab_population_shape(self, ghost: int = 1) -> tuple:
+        """Shape of a z-slab buffer: the population layout of nz + 2 * ghost planes,
+        `ghost` ghost planes below and above the slab's own (1: lbm_step_slab, 2:
+        lbm_step_slab2)."""
         if self.D != 3:
             raise ValueError("z-slabs need a 3D lattice")
-        return (self.nz + 2, self.ny, self.Q, self.row_pitch)
+        if ghost not in (1, 2):
+            raise ValueError("a slab has 1 or 2 ghost planes on each side")
+        return (self.nz + 2 * ghost, self.ny, self.Q, self.row_pitch)
 
-    def empty_slab_populations(self, device="cuda") -> torch.Tensor:
-        return torch.empty(self.slab_population_shape(), dtype=self.word_dtype, device=device)
+    def empty_slab_populations(self, device="cuda", ghost: int = 1) -> torch.Tensor:
+        return torch.empty(self.slab_population_shape(ghost), dtype=self.word_dtype, device=device)
 
     def empty_real(self, components: int, device="cuda") -> torch.Tensor:
         shape = self.spatial if components == 0 else (components,) + self.spatial
@@ -346,6 +352,37 @@ def lbm_slab_halo_copy(src_slab: Grid, src: torch.Tensor, dst_slab: Grid, dst: t
     b = _dev_ptr(dst, "dst", dst_slab.word_dtype, dst_slab.Q * dst_slab.row_pitch * dst_slab.ny * (dst_slab.nz + 2))
     _check(_lib.lbm_slab_halo_copy(ctypes.byref(gs), a, ctypes.byref(gd), b, FACES[face], _stream(stream)),
            "lbm_slab_halo_copy")
+
+
+def lbm_step_slab2(slab: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: float,
+                   force: torch.Tensor | None = None, stream=None) -> None:
+    """Two steps of a whole z-slab with two ghost planes on each side; f_in and f_out
+    are slab buffers (nz + 4 planes), force holds D*nx*ny*(nz + 2) reals (planes -1 .. nz)."""
+    words = slab.Q * slab.row_pitch * slab.ny * (slab.nz + 4)
+    g = slab.c_struct()
+    a = _dev_ptr(f_in, "f_in", slab.word_dtype, words)
+    b = _dev_ptr(f_out, "f_out", slab.word_dtype, words)
+    F = _dev_ptr(force, "force", slab.real_dtype, slab.D * slab.nx * slab.ny * (slab.nz + 2), required=False)
+    _check(_lib.lbm_step_slab2(ctypes.byref(g), a, b, float(tau), F, _stream(stream)), "lbm_step_slab2")
+
+
+def lbm_step_slab2_available(slab: Grid) -> bool:
+    """Whether lbm_step_slab2 takes this slab and storage kind (host-only)."""
+    g = slab.c_struct()
+    v = ctypes.c_int32(0)
+    _check(_lib.lbm_step_slab2_available(ctypes.byref(g), ctypes.byref(v)), "lbm_step_slab2_available")
+    return bool(v.value)
+
+
+def lbm_slab2_halo_copy(src_slab: Grid, src: torch.Tensor, dst_slab: Grid, dst: torch.Tensor, face: str,
+                        stream=None) -> None:
+    """Fills the two ghost planes of dst (the neighbouring slab on `face`'s side of src)
+    from src's two planes at that face."""
+    gs, gd = src_slab.c_struct(), dst_slab.c_struct()
+    a = _dev_ptr(src, "src", src_slab.word_dtype, src_slab.Q * src_slab.row_pitch * src_slab.ny * (src_slab.nz + 4))
+    b = _dev_ptr(dst, "dst", dst_slab.word_dtype, dst_slab.Q * dst_slab.row_pitch * dst_slab.ny * (dst_slab.nz + 4))
+    _check(_lib.lbm_slab2_halo_copy(ctypes.byref(gs), a, ctypes.byref(gd), b, FACES[face], _stream(stream)),
+           "lbm_slab2_halo_copy")
 
 
 def lbm_stream_only(grid: Grid, f_in: torch.Tensor, f_out: torch.Tensor, stream=None) -> None:

@@ -397,6 +397,85 @@ int lbm_slab_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_slab_halo_copy launch");
 }
 
+int lbm_step_slab2_available(const lbm_grid* slab, int* available) {
+  Geometry geo;
+  LBM_TRY(check_grid(slab, &geo));
+  if (!available) return fail(LBM_ENULL, "available is NULL");
+  geo.args.ghost = 2;
+  *available = geo.D == 3 && lbm::step2_slab_supported(slab->lattice, slab->storage, geo.args) ? 1 : 0;
+  return LBM_OK;
+}
+
+int lbm_step_slab2(const lbm_grid* slab, const void* f_in, void* f_out, double tau, const void* force,
+                   void* stream) {
+  Geometry geo;
+  LBM_TRY(check_grid(slab, &geo));
+  if (geo.D != 3) return fail(LBM_EUNSUP, "lbm_step_slab2 needs a 3D lattice (z-slabs)");
+  LBM_TRY(check_tau(tau));
+  if (slab->nz < 2) return fail(LBM_EINVAL, "a slab of two-step launches needs nz >= 2 (got %lld)", (long long)slab->nz);
+  LBM_TRY(check_ptr(f_in, "f_in", true));
+  LBM_TRY(check_ptr(f_out, "f_out", true));
+  LBM_TRY(check_ptr(force, "force", false));
+  const size_t plane = (size_t)geo.Q * geo.args.pitch * geo.args.ny * geo.word;
+  const size_t fbytes = plane * (size_t)(slab->nz + 4);
+  const size_t vbytes = (size_t)geo.D * geo.args.nx * geo.args.ny * (size_t)(slab->nz + 2) * geo.real;
+  if (overlap(f_in, fbytes, f_out, fbytes)) return fail(LBM_EALIAS, "f_in and f_out overlap");
+  if (overlap(force, vbytes, f_in, fbytes) || overlap(force, vbytes, f_out, fbytes))
+    return fail(LBM_EALIAS, "force overlaps a population buffer");
+  geo.args.ghost = 2;
+  if (!lbm::step2_slab_supported(slab->lattice, slab->storage, geo.args))
+    return fail(LBM_EUNSUP, "two steps per launch do not take this slab or storage kind "
+                            "(lbm_step_slab2_available)");
+  const hipError_t e = lbm::launch_step2_slab(slab->lattice, slab->storage, f_in, f_out, force,
+                                              force ? lbm::kGuoForce : lbm::kNoForce, geo.args, 1.0 / tau,
+                                              (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_slab2 launch");
+}
+
+int lbm_slab2_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid* dst_slab, void* dst, int face,
+                        void* stream) {
+  Geometry gs, gd;
+  LBM_TRY(check_grid(src_slab, &gs));
+  LBM_TRY(check_grid(dst_slab, &gd));
+  if (gs.D != 3) return fail(LBM_EUNSUP, "lbm_slab2_halo_copy needs a 3D lattice (z-slabs)");
+  if (src_slab->lattice != dst_slab->lattice || src_slab->storage != dst_slab->storage ||
+      src_slab->nx != dst_slab->nx || src_slab->ny != dst_slab->ny || gs.args.pitch != gd.args.pitch)
+    return fail(LBM_EINVAL, "source and destination slabs differ in lattice, storage, nx, ny or pitch");
+  if (face != LBM_FACE_LOW && face != LBM_FACE_HIGH) return fail(LBM_EINVAL, "face must be 0 or 1 (got %d)", face);
+  if (src_slab->nz < 2 || dst_slab->nz < 2) return fail(LBM_EINVAL, "slabs of two-step launches need nz >= 2");
+  LBM_TRY(check_ptr(src, "src", true));
+  LBM_TRY(check_ptr(dst, "dst", true));
+  // Buffer plane p + 2 holds slab plane p.  LOW: src planes 0 (c_z = -1 and 0) and 1
+  // (c_z = -1) into dst's ghost planes nz and nz + 1.  HIGH: src planes nz - 1 (c_z = 0
+  // and +1) and nz - 2 (c_z = +1) into dst's ghost planes -1 and -2.
+  const bool low = face == LBM_FACE_LOW;
+  const int64_t ns = src_slab->nz, nd = dst_slab->nz;
+  int im, nm, i0, n0, ip, np;
+  face_dirs(src_slab->lattice, -1, &im, &nm);
+  face_dirs(src_slab->lattice, 0, &i0, &n0);
+  face_dirs(src_slab->lattice, 1, &ip, &np);
+  if (i0 != im + nm || ip != i0 + n0) return fail(LBM_EINVAL, "direction groups are not consecutive");
+  struct Part {
+    uint64_t src_plane, dst_plane;
+    int first, count;
+  };
+  const Part parts[2] = {
+      low ? Part{2, (uint64_t)nd + 2, im, nm + n0} : Part{(uint64_t)ns + 1, 1, i0, n0 + np},
+      low ? Part{3, (uint64_t)nd + 3, im, nm} : Part{(uint64_t)ns, 0, ip, np},
+  };
+  const size_t plane = (size_t)gs.Q * gs.args.pitch * gs.args.ny * gs.word;
+  for (const Part& q : parts)
+    for (const Part& r : parts)
+      if (overlap((const char*)src + q.src_plane * plane, plane, (const char*)dst + r.dst_plane * plane, plane))
+        return fail(LBM_EALIAS, "a source plane overlaps a destination ghost plane");
+  for (const Part& q : parts) {
+    const hipError_t e = lbm::launch_halo_copy(gs.Q, (int)gs.word, src, q.src_plane, dst, q.dst_plane, q.first,
+                                               q.count, gs.args.pitch, gs.args.ny, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_slab2_halo_copy launch");
+  }
+  return LBM_OK;
+}
+
 int lbm_stream_only(const lbm_grid* grid, const void* f_in, void* f_out, void* stream) {
   Geometry geo;
   LBM_TRY(check_grid(grid, &geo));

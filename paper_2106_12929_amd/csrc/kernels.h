@@ -18,7 +18,8 @@ struct GridArgs {
   uint64_t ncells;   // nx * ny * nz (< 2^31)
   uint32_t z0, nzl;  // planes [z0, z0 + nzl) handled by the launch (0 and nz: all of them)
   uint32_t ghost;    // 0: periodic in z; 1: z-slab buffer with a ghost plane below and above
-                     // the nz planes (buffer plane = z + 1, no wrap in z)
+                     // the nz planes (buffer plane = z + 1, no wrap in z); 2: two ghost
+                     // planes each side (buffer plane = z + 2), step2_kernel only
   uint32_t pitch;    // words between direction rows of population buffers (>= nx)
 };
 
@@ -32,6 +33,7 @@ struct Step2Args {
   uint32_t row_bytes;         // one direction row: pitch words
   uint32_t yrow_bytes;        // the Q direction rows of one grid row
   uint32_t plane_bytes;       // the ny grid rows of one z plane (< 2^32)
+  uint64_t force_stride;      // reals between the force components (the force field's cells)
 };
 // The most steps one launch can advance for this lattice, storage kind and grid: 4
 // (the D2Q9 multi-step kernel), 2 (the two-step kernels) or 1.  For nst = 2 or 4 up to
@@ -57,6 +59,12 @@ hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, co
 // (adjoint2_kernel), where the grid and storage kind allow; equal to two launch_adjoint
 // calls in mode kAdjLocalChi bit for bit, the force gradient included.
 bool adjoint2_supported(int lattice, int storage, const GridArgs& g);
+// Two steps on a z-slab with two ghost planes on each side (step2_kernel with
+// g.ghost == 2): buffer plane p + 2 holds slab plane p (p = -2 .. nz + 1), the force
+// holds slab planes -1 .. nz at p + 1.  Every own plane is computed; nothing wraps in z.
+bool step2_slab_supported(int lattice, int storage, const GridArgs& g);
+hipError_t launch_step2_slab(int lattice, int storage, const void* fin, void* fout, const void* force,
+                             int force_mode, const GridArgs& g, double omega, hipStream_t s);
 hipError_t launch_adjoint2(int lattice, int storage, const void* gt, const void* gtm1, const void* chi_next,
                            void* chi_out, const void* force, void* dforce, const GridArgs& g, double omega,
                            hipStream_t s);

@@ -163,16 +163,21 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
   const char* fb = reinterpret_cast<const char*>(fin);
   char* ob = reinterpret_cast<char*>(fout);
   const uint32_t plane_cells = g.nx * g.ny;
-  // planes zb-2 .. ze+2 wrapped (nz >= 3)
-  auto wrapz = [&](int z) -> uint32_t {
+  // Buffer plane of plane z (z = zb-2 .. ze+1) and force plane of plane z (zb-1 .. ze):
+  // a periodic grid wraps (nz >= 3); a slab with two ghost planes on each side
+  // (g.ghost == 2) keeps plane z at buffer plane z + 2 and its force at z + 1.
+  const bool slab = g.ghost != 0;
+  auto plane_of = [&](int z) -> uint32_t {
+    if (slab) return (uint32_t)(z + 2);
     return (uint32_t)(z < 0 ? z + (int)g.nz : (z >= (int)g.nz ? z - (int)g.nz : z));
   };
-  auto load_force = [&](uint32_t z, uint32_t col, real& Fx, real& Fy, real& Fz) {
+  auto load_force = [&](int z, uint32_t col, real& Fx, real& Fy, real& Fz) {
     if constexpr (FM != kNoForce) {
-      const real* f = force + (uint64_t)z * plane_cells + col;
+      const uint32_t fz = slab ? (uint32_t)(z + 1) : plane_of(z);
+      const real* f = force + (uint64_t)fz * plane_cells + col;
       Fx = f[0];
-      Fy = f[g.ncells];
-      Fz = f[2 * g.ncells];
+      Fy = f[a.force_stride];
+      Fz = f[2 * a.force_stride];
     }
   };
 
@@ -193,13 +198,15 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
     const uint32_t yb[3] = {wrap_inc(y, g.ny) * a.yrow_bytes, y * a.yrow_bytes, wrap_dec(y, g.ny) * a.yrow_bytes};
     // the gathers of plane pz: the pulled words and the force
     auto load = [&](int pz, W (&r)[Q], real (&rf)[3]) {
-      const char* base[3] = {fb + (uint64_t)wrapz(pz + 1) * a.plane_bytes, fb + (uint64_t)wrapz(pz) * a.plane_bytes,
-                             fb + (uint64_t)wrapz(pz - 1) * a.plane_bytes};
+      if (slab) pz = min(pz, (int)ze);  // the read past plane ze (unused) stays in the buffer
+      const char* base[3] = {fb + (uint64_t)plane_of(pz + 1) * a.plane_bytes,
+                             fb + (uint64_t)plane_of(pz) * a.plane_bytes,
+                             fb + (uint64_t)plane_of(pz - 1) * a.plane_bytes};
 #pragma unroll
       for (int i = 0; i < Q; ++i)
         r[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * a.row_bytes +
                                            (yb[LT::cy(i) + 1] + xb[LT::cx(i) + 1]));
-      load_force(wrapz(pz), col, rf[0], rf[1], rf[2]);
+      load_force(pz, col, rf[0], rf[1], rf[2]);
     };
     auto produce = [&](W (&r)[Q], const real (&rf)[3], auto sl) {
       constexpr int SL = decltype(sl)::value;
@@ -254,11 +261,11 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
       }
       if constexpr (EMIT) {
         bgk_collide<L, real, FM>(dA, cf[0], cf[1], cf[2], omega);
-        char* o = ob + (uint64_t)(q - 1) * a.plane_bytes + out_off;
+        char* o = ob + (uint64_t)plane_of(q - 1) * a.plane_bytes + out_off;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
           store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes), ST::from_dev(dA[i], CO::W(i)));
-        if (q < (int)ze) load_force((uint32_t)q, col, cf[0], cf[1], cf[2]);  // the next output plane's
+        if (q < (int)ze) load_force(q, col, cf[0], cf[1], cf[2]);  // the next output plane's
       }
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
@@ -268,7 +275,7 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
-    load_force(zb, col, cf[0], cf[1], cf[2]);  // the first output plane's force
+    load_force((int)zb, col, cf[0], cf[1], cf[2]);  // the first output plane's force
     __syncthreads();  // plane zb-1 written
     consume((int)zb - 1, I0(), std::false_type());
     __syncthreads();
@@ -1605,11 +1612,33 @@ static hipError_t launch_step2_lsf(const void* fin, void* fout, const void* forc
   a.row_bytes = g.pitch * (uint32_t)sizeof(W);
   a.yrow_bytes = Lattice<L>::Q * a.row_bytes;
   a.plane_bytes = g.ny * a.yrow_bytes;
+  // a slab's force has a ghost plane below and above its own planes
+  a.force_stride = g.ghost ? (uint64_t)g.nx * g.ny * (g.nz + 2) : g.ncells;
   const uint64_t tiles = (uint64_t)a.tiles_x * a.tiles_y;
   a.lz = step2_chunk(tiles, g.nz, (uint64_t)step2_blocks_per_cu<L, S, FM>() * device_cus(), 2);
   const dim3 grid((unsigned)(tiles * ((g.nz + a.lz - 1) / a.lz)));
   step2_kernel<L, S, FM><<<grid, SH::NT, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, a, (R)omega);
   return hipGetLastError();
+}
+
+// Two steps on a z-slab with two ghost planes on each side (g.ghost == 2): the 3D
+// lattices and the tiles of the periodic two-step launches, nz >= 2.
+template <int L, int S>
+static bool step2_slab_fits(const GridArgs& g) {
+  if constexpr (!step2_enabled<L, S>() || L == kD2Q9) {
+    return false;
+  } else {
+    using SH = Step2Shape<L, S>;
+    const uint64_t plane = (uint64_t)g.ny * Lattice<L>::Q * g.pitch * sizeof(typename Storage<S>::word);
+    return g.ghost == 2 && g.z0 == 0 && g.nzl == g.nz && g.nx % SH::TX == 0 && g.ny % SH::TY == 0 && g.nz >= 2 &&
+           plane < (uint64_t(1) << 32);
+  }
+}
+
+template <int L, int S>
+static hipError_t step2_slab_fits_ls(const GridArgs& g, bool* ok) {
+  *ok = step2_slab_fits<L, S>(g);
+  return hipSuccess;
 }
 
 template <int L, int S>
@@ -1644,6 +1673,21 @@ static hipError_t launch_stepn_ls(int nst, const void* fin, void* fout, const vo
 // single steps' rate, against 1.7-1.8x for two steps per launch); shifted FP16 ran
 // slower with four (226.6k against 243.7k MLUPS: its conversions make the deeper
 // pipeline arithmetic-bound) and takes two.
+template <int L, int S>
+static hipError_t launch_step2_slab_ls(const void* fin, void* fout, const void* force, int force_mode,
+                                       const GridArgs& g, double omega, hipStream_t s) {
+  if constexpr (!step2_enabled<L, S>() || L == kD2Q9) {
+    return hipErrorInvalidValue;
+  } else {
+    if (!step2_slab_fits<L, S>(g)) return hipErrorInvalidValue;
+    if (force_mode != kNoForce && force_mode != kGuoForce && force_mode != kShiftForce) return hipErrorInvalidValue;
+    const int fm = force ? force_mode : kNoForce;
+    if (fm == kNoForce) return launch_step2_lsf<L, S, kNoForce>(fin, fout, nullptr, g, omega, s);
+    if (fm == kGuoForce) return launch_step2_lsf<L, S, kGuoForce>(fin, fout, force, g, omega, s);
+    return launch_step2_lsf<L, S, kShiftForce>(fin, fout, force, g, omega, s);
+  }
+}
+
 template <int L, int S>
 static hipError_t max_steps_ls(const GridArgs& g, int* n) {
   constexpr bool FOUR = L == kD2Q9;
@@ -1886,6 +1930,17 @@ int max_steps_per_launch(int lattice, int storage, const GridArgs& g) {
 hipError_t launch_stepn(int lattice, int storage, int nst, const void* fin, void* fout, const void* force,
                         int force_mode, const GridArgs& g, double omega, hipStream_t s) {
   LBM_DISPATCH(launch_stepn_ls, lattice, storage, nst, fin, fout, force, force_mode, g, omega, s);
+}
+
+bool step2_slab_supported(int lattice, int storage, const GridArgs& g) {
+  bool ok = false;
+  auto check = [&]() -> hipError_t { LBM_DISPATCH(step2_slab_fits_ls, lattice, storage, g, &ok); };
+  return check() == hipSuccess && ok;
+}
+
+hipError_t launch_step2_slab(int lattice, int storage, const void* fin, void* fout, const void* force,
+                             int force_mode, const GridArgs& g, double omega, hipStream_t s) {
+  LBM_DISPATCH(launch_step2_slab_ls, lattice, storage, fin, fout, force, force_mode, g, omega, s);
 }
 
 bool adjoint2_supported(int lattice, int storage, const GridArgs& g) {

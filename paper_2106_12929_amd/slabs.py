@@ -16,7 +16,13 @@ keeps its planes in a buffer with one ghost plane below and one above
 `SlabSet` runs the P slabs on one device, each with its own buffers, with the
 exchange on a second stream when `overlap` is set.  The result is bitwise the
 periodic `lbm_step` of the whole grid: every cell runs the same kernel arithmetic on
-the same words.  On several devices each slab would live on its own device and the
+the same words.
+
+With `ghost=2` the slabs keep two ghost planes on each side and advance two steps per
+launch (`lbm_step_slab2`, the two-step kernel with the intermediate state on chip):
+`step_pair` exchanges the two-plane-deep halo (`lbm_slab2_halo_copy`) once and then
+steps every slab twice.  Halving the exchanges halves the latency-bound
+synchronisations between devices, for 1.5 times the exchanged bytes per two steps.  On several devices each slab would live on its own device and the
 exchange would cross xGMI; the buffers, the kernels and the order of operations are
 the ones used here.
 """
@@ -36,17 +42,24 @@ def split_planes(nz: int, parts: int) -> list[int]:
 
 
 class SlabSet:
-    def __init__(self, grid: B.Grid, planes, device="cuda"):
+    def __init__(self, grid: B.Grid, planes, device="cuda", ghost: int = 1):
         if grid.D != 3:
             raise ValueError("z-slabs need a 3D lattice")
+        if ghost not in (1, 2):
+            raise ValueError("a slab has 1 or 2 ghost planes on each side")
         planes = split_planes(grid.nz, planes) if isinstance(planes, int) else [int(p) for p in planes]
-        if sum(planes) != grid.nz or min(planes) < 1:
-            raise ValueError(f"slab plane counts {planes} do not partition nz = {grid.nz}")
+        if sum(planes) != grid.nz or min(planes) < ghost:
+            raise ValueError(f"slab plane counts {planes} do not partition nz = {grid.nz} into slabs of "
+                             f"at least {ghost} planes")
         self.grid = grid
+        self.ghost = ghost
         self.planes = planes
         self.z0 = [sum(planes[:p]) for p in range(len(planes))]
         self.slabs = [B.Grid(grid.lattice, grid.storage, grid.nx, grid.ny, n, grid.pitch) for n in planes]
-        self.bufs = [[s.empty_slab_populations(device), s.empty_slab_populations(device)] for s in self.slabs]
+        if ghost == 2 and not all(B.lbm_step_slab2_available(s) for s in self.slabs):
+            raise ValueError("two steps per launch do not take these slabs (lbm_step_slab2_available)")
+        self.bufs = [[s.empty_slab_populations(device, ghost), s.empty_slab_populations(device, ghost)]
+                     for s in self.slabs]
         self.cur = 0
         self._halo_stream = None
 
@@ -55,9 +68,10 @@ class SlabSet:
         return len(self.slabs)
 
     def interior(self, p: int, which: int | None = None) -> torch.Tensor:
-        """View of slab p's own planes (buffer planes 1..nz) in the current buffer."""
+        """View of slab p's own planes (buffer planes ghost .. ghost + nz - 1) in the
+        current buffer."""
         b = self.bufs[p][self.cur if which is None else which]
-        return b[1:self.planes[p] + 1]
+        return b[self.ghost:self.planes[p] + self.ghost]
 
     def scatter(self, f: torch.Tensor) -> None:
         """Loads a whole-grid population buffer (population layout) into the slabs."""
@@ -69,18 +83,40 @@ class SlabSet:
         return torch.cat([self.interior(p) for p in range(self.P)], dim=0)
 
     def split_field(self, v: torch.Tensor | None):
-        """A whole-grid [D, nz, ny, nx] real field cut into the slabs' own cells."""
+        """A whole-grid [D, nz, ny, nx] real field cut into the slabs' own cells; with
+        two ghost planes, each slab's part also holds the plane below and the plane above
+        it (periodic in z), as lbm_step_slab2 takes its force."""
         if v is None:
             return [None] * self.P
-        return [v[:, self.z0[p]:self.z0[p] + self.planes[p]].contiguous() for p in range(self.P)]
+        if self.ghost == 1:
+            return [v[:, self.z0[p]:self.z0[p] + self.planes[p]].contiguous() for p in range(self.P)]
+        nz = self.grid.nz
+        out = []
+        for p in range(self.P):
+            idx = torch.arange(self.z0[p] - 1, self.z0[p] + self.planes[p] + 1, device=v.device) % nz
+            out.append(v.index_select(1, idx).contiguous())
+        return out
 
     def exchange(self, stream=None) -> None:
         """Fills every slab's ghost planes of the current buffer from its neighbours."""
         c = self.cur
+        copy = B.lbm_slab_halo_copy if self.ghost == 1 else B.lbm_slab2_halo_copy
         for p in range(self.P):
             up, down = (p + 1) % self.P, (p - 1) % self.P
-            B.lbm_slab_halo_copy(self.slabs[p], self.bufs[p][c], self.slabs[up], self.bufs[up][c], "high", stream)
-            B.lbm_slab_halo_copy(self.slabs[p], self.bufs[p][c], self.slabs[down], self.bufs[down][c], "low", stream)
+            copy(self.slabs[p], self.bufs[p][c], self.slabs[up], self.bufs[up][c], "high", stream)
+            copy(self.slabs[p], self.bufs[p][c], self.slabs[down], self.bufs[down][c], "low", stream)
+
+    def step_pair(self, tau: float, forces=None) -> None:
+        """Two steps of the whole grid (slabs with two ghost planes): one exchange, then
+        one two-step launch per slab.  forces: per slab, D x (nz + 2) planes of force
+        (split_field), or None."""
+        if self.ghost != 2:
+            raise ValueError("step_pair needs slabs with two ghost planes (ghost=2)")
+        forces = forces if forces is not None else [None] * self.P
+        self.exchange()
+        for p in range(self.P):
+            B.lbm_step_slab2(self.slabs[p], self.bufs[p][self.cur], self.bufs[p][1 - self.cur], tau, forces[p])
+        self.cur = 1 - self.cur
 
     def _launch(self, p: int, tau: float, force, z_begin: int, z_end: int) -> None:
         if z_begin < z_end:
@@ -91,6 +127,8 @@ class SlabSet:
         """One step of the whole grid: exchange, inner planes, boundary planes.  With
         `overlap` the exchange runs on a second stream concurrently with the inner
         planes; the boundary planes wait for it."""
+        if self.ghost != 1:
+            raise ValueError("slabs with two ghost planes advance two steps at a time (step_pair)")
         forces = forces if forces is not None else [None] * self.P
         main = torch.cuda.current_stream()
         if overlap:

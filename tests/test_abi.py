@@ -284,6 +284,56 @@ def test_slab_halo_validation(B):
     assert halo(dst=ctypes.c_void_p(0x10000 - 8 * plane), face=0) == -4
 
 
+def test_slab2_step_validation(B):
+    lib = B._lib
+    g = _grid(B, nx=32, ny=8, nz=8)  # slab buffers of 12 planes
+
+    def step(grid=g, a=P1, b=P2, tau=0.6, force=None):
+        return lib.lbm_step_slab2(ctypes.byref(grid), a, b, tau, force, None)
+
+    assert step(_grid(B, "D2Q9", nx=64, ny=8, nz=1)) == -5   # z-slabs need a 3D lattice
+    assert step(_grid(B, nx=32, ny=8, nz=1)) == -1           # nz < 2
+    assert step(tau=0.5) == -1
+    assert step(a=None) == -2
+    assert step(b=MIS) == -3
+    assert step(a=P1, b=P1) == -4
+    plane = 27 * 32 * 8 * 4
+    assert step(b=ctypes.c_void_p(0x10000 + 11 * plane)) == -4   # f_out inside f_in's top ghost plane
+    assert step(force=ctypes.c_void_p(0x10000 + 16)) == -4
+    assert step(_grid(B, nx=48, ny=8, nz=8)) == -5            # nx off the 32-cell tiles
+    assert step(_grid(B, nx=32, ny=12, nz=8)) == -5           # ny off the 8-row tiles
+    assert step(_grid(B, storage="f16s", nx=32, ny=8, nz=8)) == -5  # 2-byte words: 64 x 4 tiles
+    v = ctypes.c_int32(7)
+    for grid, ok in ((g, 1), (_grid(B, storage="f16s", nx=64, ny=4, nz=2), 1), (_grid(B, storage="f64", nx=32, ny=4, nz=3), 1),
+                     (_grid(B, nx=32, ny=8, nz=1), 0), (_grid(B, "D2Q9", nx=64, ny=8, nz=1), 0),
+                     (_grid(B, nx=48, ny=8, nz=8), 0)):
+        assert lib.lbm_step_slab2_available(ctypes.byref(grid), ctypes.byref(v)) == 0
+        assert v.value == ok
+    assert lib.lbm_step_slab2_available(ctypes.byref(g), None) == -2
+
+
+def test_slab2_halo_validation(B):
+    lib = B._lib
+    g = _grid(B)  # 8 x 8 x 8: buffers of 12 planes
+
+    def halo(src_grid=g, src=P1, dst_grid=g, dst=P2, face=0):
+        return lib.lbm_slab2_halo_copy(ctypes.byref(src_grid), src, ctypes.byref(dst_grid), dst, face, None)
+
+    assert halo(src_grid=_grid(B, "D2Q9", nz=1), dst_grid=_grid(B, "D2Q9", nz=1)) == -5
+    assert halo(dst_grid=_grid(B, nx=9)) == -1
+    assert halo(dst_grid=_grid(B, nz=1)) == -1           # both slabs need two planes
+    assert halo(src_grid=_grid(B, nz=1)) == -1
+    assert halo(face=3) == -1
+    assert halo(src=None) == -2
+    assert halo(dst=MIS) == -3
+    plane = 27 * 8 * 8 * 4
+    # LOW reads src planes 2, 3 and writes dst planes nz + 2, nz + 3 = 10, 11: a dst 8
+    # planes below src puts ghost plane 10 on source plane 2
+    assert halo(dst=ctypes.c_void_p(0x10000 - 8 * plane), face=0) == -4
+    # HIGH reads src planes nz, nz + 1 = 8, 9 and writes dst planes 0, 1
+    assert halo(dst=ctypes.c_void_p(0x10000 + 8 * plane), face=1) == -4
+
+
 def test_pitch_validation(B):
     lib = B._lib
     assert _step(B, _grid(B, nx=8, pitch=7), P1, P2) == -1      # 0 < pitch < nx

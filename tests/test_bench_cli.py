@@ -44,7 +44,8 @@ def _fake_detail():
                       for k in ("bgk", "bgk_paired", "mrt", "mrt_cell", "neural_relu", "neural_tanh")},
         "row_pitch": {f"case{i}": fw() for i in range(6)},
         "shard_512x512x64_f16s": {"periodic_step": {"ms": v(), "mlups": v()},
-                                  "slab_step_sequential": {"ms": v(), "mlups": v()}},
+                                  "slab_step_sequential": {"ms": v(), "mlups": v()},
+                                  "slab2_step_pair": {"ms_per_two_steps": v(), "mlups": v()}},
         "adjoint": {k: fw() for k in ("f32", "f16s")},
         "adjoint_scatter_form": {k: fw() for k in ("f32", "f16s")},
         "adjoint_forced": {k: fw() for k in ("f32", "f16s")},

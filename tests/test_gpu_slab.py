@@ -1,7 +1,8 @@
 """GPU checks of the z-slab step (one shard of a domain decomposition along z): a
 periodic grid cut into slabs with ghost planes and a halo exchange reproduces the
 periodic step of the whole grid bit for bit, for every storage kind, with and without
-a body force, with the exchange overlapped on a second stream or not."""
+a body force, with the exchange overlapped on a second stream or not; and so do slabs
+with two ghost planes that advance two steps per launch."""
 import pytest
 import torch
 
@@ -151,5 +152,77 @@ def test_full_size_shard_matches_periodic_step(parts):
     S.scatter(g0)
     for t in range(T):
         S.step(0.51, None, overlap=(t % 2 == 1))
+    torch.cuda.synchronize()
+    assert torch.equal(bits(S.gather()), bits(ref))
+
+
+PARTS2 = [[12], [6, 6], [5, 4, 3], [2] * 6, [2, 10]]
+
+
+@pytest.mark.parametrize("parts", PARTS2, ids=lambda p: "x".join(map(str, p)))
+@pytest.mark.parametrize("lat,kind,shape", [("D3Q27", "f32", (64, 16, 12)), ("D3Q27", "f16s", (64, 8, 12)),
+                                            ("D3Q27", "bf16s", (128, 4, 12)), ("D3Q27", "f64", (32, 8, 12)),
+                                            ("D3Q19", "f32", (32, 8, 12)), ("D3Q27", "f32s", (32, 16, 12))])
+@pytest.mark.parametrize("forced", [False, True])
+def test_slabs_two_steps_per_launch_match_periodic_step(parts, lat, kind, shape, forced):
+    """Slabs with two ghost planes on each side, one two-plane-deep exchange and one
+    two-step launch per slab for every two steps: bit for bit the periodic step of the
+    whole grid (3 pairs, 6 steps), with and without a Guo force (the slab's force
+    carries a ghost plane each side)."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd.slabs import SlabSet
+
+    st = olbm.stencil(lat)
+    nx, ny, nz = shape
+    spatial = (nz, ny, nx)
+    grid = B.Grid(lat, kind, nx, ny, nz)
+    say(f"slabs, two steps per launch {lat} {kind} {shape} parts={parts} forced={forced}")
+    g0 = grid.to_layout(_state(st, spatial, 37, kind)).cuda()
+    F = synthetic.random_normal((3,) + spatial, 6, 1e-4).to(grid.real_dtype).cuda() if forced else None
+    ref = _periodic(B, grid, g0, 0.56, F, 6)
+    S = SlabSet(grid, parts, ghost=2)
+    S.scatter(g0)
+    forces = S.split_field(F)
+    for _ in range(3):
+        S.step_pair(0.56, forces)
+    torch.cuda.synchronize()
+    assert torch.equal(bits(S.gather()), bits(ref))
+
+
+def test_two_step_slabs_reject_other_shapes():
+    """Slabs off the two-step tiles, or of one plane, are refused instead of stepping
+    another way."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd.slabs import SlabSet
+
+    with pytest.raises(ValueError):
+        SlabSet(B.Grid("D3Q27", "f32", 48, 8, 8), 2, ghost=2)
+    with pytest.raises(ValueError):
+        SlabSet(B.Grid("D3Q27", "f32", 32, 8, 8), [1, 7], ghost=2)
+    S = SlabSet(B.Grid("D3Q27", "f32", 32, 8, 8), 2, ghost=2)
+    with pytest.raises(ValueError):
+        S.step(0.6)
+
+
+@pytest.mark.parametrize("parts", [1, 2])
+def test_full_size_shard_two_steps_per_launch_matches_periodic_step(parts):
+    """The 512 x 512 x 64 f16s shard of the benchmark with two ghost planes, as one slab
+    (its own neighbour) and as two: 2 pairs, bit for bit 4 periodic steps."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd.slabs import SlabSet
+
+    nx, ny, nz = 512, 512, 64
+    grid = B.Grid("D3Q27", "f16s", nx, ny, nz)
+    say(f"full-size shard 512x512x64 f16s, two steps per launch, parts={parts}")
+    g0 = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, synthetic.taylor_green_3d_on("cuda", nx, ny, nz, 0.05), g0)
+    ref = _periodic(B, grid, g0, 0.51, None, 4)
+    S = SlabSet(grid, parts, ghost=2)
+    S.scatter(g0)
+    for _ in range(2):
+        S.step_pair(0.51)
     torch.cuda.synchronize()
     assert torch.equal(bits(S.gather()), bits(ref))
