@@ -713,8 +713,9 @@ def main():
                     help="only copy 1 GiB to another 1 GiB buffer 3 times (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the step runs on a single MI355X and this build has no "
-              "multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the step runs on a single MI355X; the library's z-slab "
+              "step (lbm_step_slab, lbm_step_slab2) is one GPU's share of a multi-GPU run, timed in the "
+              "shard case of the default run.", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
