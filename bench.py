@@ -20,7 +20,7 @@ measurements: the other storage formats (FP64, shifted FP32, shifted FP16/BF16) 
 their error against the FP64 run after 1000 steps, D3Q19, the forced steps, the
 adjoint step, the moments kernel, a plain device copy for the practical bandwidth
 ceiling, and the workloads with the relaxation time each actually ran at.  The full
-record of every measurement goes to --detail-out (gpurun_out/bench_detail.json).
+record of every measurement goes to the JSON file --detail-out names.
 """
 from __future__ import annotations
 
