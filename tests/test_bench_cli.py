@@ -79,8 +79,8 @@ def _fake_detail():
 
 def test_bench_line_is_small_and_complete():
     """The printed line stays a few KB (a runner that keeps only the last 9 KB of the
-    output, stderr included, still gets it whole) and carries the headline, the roofline, the CPU baseline and the
-    summary; the full record goes to a file."""
+    output, stderr included, still gets it whole) and carries the headline, the
+    roofline, the CPU baseline and the summary; the full record goes to a file."""
     import json
     import importlib.util
 
