@@ -93,7 +93,7 @@ def test_bench_line_is_small_and_complete():
            "sample": "FP64 torch-CPU oracle, D3Q27 TGV tau=0.51 on 256^3 cells (the full grid), 6 steps (21.3 s)",
            "single_thread_value": 1.7, "single_thread_sample": "64^3 cells, 5 steps (4.1 s)",
            "host": "AMD EPYC 9575F 64-Core Processor, 256 logical CPUs visible, 1500 GiB available"}
-    line = bench.summary_line(head, detail, cpu, 200, 10, 3624615676.0, "gpurun_out/bench_detail.json")
+    line = bench.summary_line(head, detail, cpu, 200, 10, 3624615676.0, "bench_detail.json")
     text = json.dumps(line, separators=(",", ":"))
     assert len(text) <= 4096, len(text)
     for k in ("metric", "value", "unit", "ms_per_step", "steps", "warmup", "dtype", "roofline", "cpu_baseline",
