@@ -11,13 +11,18 @@ from _helpers import binding, bits, need_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("lat,shape,plan", [("D3Q27", (40, 12, 9), (10, 0, 0)), ("D3Q27", (64, 16, 9), (2, 4, 0)),
+                                            ("D2Q9", (128, 16, 1), (2, 0, 2))])
+def test_graph_replay_matches_eager(lat, shape, plan):
     """A captured 10-step lbm_step replayed three times, with eager work and
-    synchronisations in between, reproduces the eager result every time."""
+    synchronisations in between, reproduces the eager result every time: single
+    steps, and two- and four-step launches (the launch plan is checked)."""
     need_gpu()
     B = binding()
-    grid = B.Grid("D3Q27", "f32", 40, 12, 9)
-    u = synthetic.random_fields((9, 12, 40), 3, 7, umax=0.05)[1].cuda()
+    grid = B.Grid(lat, "f32", *shape)
+    assert B.lbm_step_launches(grid, 10) == plan
+    spatial = (shape[1], shape[0]) if lat == "D2Q9" else (shape[2], shape[1], shape[0])
+    u = synthetic.random_fields(spatial, grid.D, 7, umax=0.05)[1].cuda()
     a, b = grid.empty_populations(), grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, u, a)
     start = a.clone()
@@ -40,6 +45,46 @@ def test_graph_replay_matches_eager():
         torch.cuda.synchronize()
         _ = (a.float().sum() + 1).item()  # eager work between replays
         assert torch.equal(bits(a), bits(refs[k])), k
+
+
+def test_graph_replay_of_two_adjoint_steps_matches_eager():
+    """Two collision-local adjoint steps per launch (with a force gradient) captured in
+    a graph and replayed three times against eager launches: chi and the accumulated
+    force gradient every time."""
+    need_gpu()
+    B = binding()
+    grid = B.Grid("D3Q27", "f32", 64, 16, 9)
+    spatial = (9, 16, 64)
+    u = synthetic.random_fields(spatial, 3, 8, umax=0.05)[1].cuda()
+    g0, g1 = grid.empty_populations(), grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u, g0)
+    B.lbm_step(grid, g0, g1, 0.55, None, 1)
+    F = synthetic.random_normal((3,) + spatial, 9, 1e-4).float().cuda()
+    chi0 = synthetic.random_normal((27,) + spatial, 10).float()
+    chi0 = grid.to_layout(chi0).cuda()
+    refs = []
+    x, y = chi0.clone(), torch.empty_like(chi0)
+    dF = torch.zeros_like(F)
+    for _ in range(3):
+        B.lbm_adjoint_step2_local(grid, g1, g0, x, y, 0.55, F, dF)
+        x, y = y, x
+        refs.append((x.clone(), dF.clone()))
+    a, b = chi0.clone(), torch.empty_like(chi0)
+    dG = torch.zeros_like(F)
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            B.lbm_adjoint_step2_local(grid, g1, g0, a, b, 0.55, F, dG)
+            B.lbm_copy(b, a)
+    torch.cuda.current_stream().wait_stream(s)
+    for k in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = (a.float().sum() + 1).item()  # eager work between replays
+        assert torch.equal(bits(a), bits(refs[k][0])), k
+        assert torch.equal(bits(dG), bits(refs[k][1])), k
 
 
 def test_resume_from_saved_state_is_bit_identical(tmp_path):
