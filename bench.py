@@ -123,7 +123,9 @@ def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = 
 
 def run_d2q9(B, steps: int, warmup: int, n: int = 8192):
     """D2Q9 throughput on an n x n periodic grid (Taylor-Green start): the BGK step for
-    several storage kinds, the MRT step (Eq. 5) with uniform relaxation times and with
+    several storage kinds (single launches, and one call of several steps that runs
+    four per launch), the MRT step (Eq. 5) with uniform relaxation times (the same two
+    ways) and with
     per-cell ghost-moment times (3 more values read per cell), and the neural collision
     (MRT with ghost times from a 6-53-3 network per cell, Sec. 3.1)."""
     from synthetic import taylor_green_2d
@@ -164,16 +166,19 @@ def run_d2q9(B, steps: int, warmup: int, n: int = 8192):
             gbs = bpc * grid.ncells / (ms * 1e-3) / 1e9
             out[f"{kind}_{storage}"] = {"ms_per_step": ms, "mlups": grid.ncells / (ms * 1e-3) / 1e6,
                                         "bytes_per_cell": bpc, "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
-            if kind == "bgk":  # the BGK step as one lbm_step call of `steps` steps (multi-step launches)
+            if kind in ("bgk", "mrt"):  # one call of `steps` steps (multi-step launches)
                 k4 = 8 * max(1, steps // 8)
 
                 def call():
-                    if B.lbm_step(grid, bufs[cur[0]], bufs[1 - cur[0]], 0.6, None, k4) == 0:
+                    a, b = bufs[cur[0]], bufs[1 - cur[0]]
+                    where = (B.lbm_step(grid, a, b, 0.6, None, k4) if kind == "bgk"
+                             else B.lbm_step_mrt(grid, a, b, taus, None, k4))
+                    if where == 0:
                         cur[0] ^= 1
 
                 ms2 = time_launches(call, 1, 1) / k4
                 gbs2 = bpc * grid.ncells / (ms2 * 1e-3) / 1e9
-                out[f"bgk_paired_{storage}"] = {"ms_per_step": ms2, "mlups": grid.ncells / (ms2 * 1e-3) / 1e6,
+                out[f"{kind}_paired_{storage}"] = {"ms_per_step": ms2, "mlups": grid.ncells / (ms2 * 1e-3) / 1e6,
                                                 "bytes_per_cell": bpc, "hbm_gbs": gbs2,
                                                 "hbm_frac": gbs2 / PEAK_HBM_GBS,
                                                 "launches": dict(zip(("one_step", "two_step", "four_step"),
@@ -894,7 +899,7 @@ def summary_line(head: dict, detail: dict, cpu, steps: int, warmup: int, traffic
         for k, v in (detail.get(key) or {}).items():
             summ[f"{name}_{k}_mlups"] = _r(v["mlups"])
     d2 = detail.get("d2q9_8192") or {}
-    for k in ("bgk_paired_f32", "bgk_paired_f16s", "bgk_paired_f64", "bgk_f32"):
+    for k in ("bgk_paired_f32", "bgk_paired_f16s", "bgk_paired_f64", "bgk_f32", "mrt_paired_f32"):
         if k in d2:
             summ[f"d2q9_8192_{k}_mlups"] = _r(d2[k]["mlups"])
     if "moments_f32" in detail:

@@ -186,8 +186,10 @@ int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, 
  * tau_ghost: NULL, or 3*N reals giving per-cell tau_6, tau_7, tau_8 (N, J_x, J_y) in
  *   place of the uniform ones (the outputs of the paper's neural collision model);
  *   every value must be > 1/2 (not checked on the device).
- * Same ping-pong, return value and buffer rules as lbm_step.  LBM_EUNSUP for lattices
- * other than D2Q9. */
+ * Same ping-pong, return value and buffer rules as lbm_step.  With uniform ghost times
+ * (tau_ghost NULL) the steps run two or four per launch where lbm_step's would
+ * (lbm_step_launches), bit for bit the single steps.  LBM_EUNSUP for lattices other
+ * than D2Q9. */
 int lbm_step_mrt(const lbm_grid* grid, void* f_in, void* f_out, const double* tau_moments,
                  const void* tau_ghost, int n_steps, void* stream);
 

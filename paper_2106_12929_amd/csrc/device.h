@@ -277,4 +277,84 @@ __device__ __forceinline__ void bgk_collide(real (&d)[Lattice<L>::Q], real Fx, r
   }
 }
 
+// ---------------------------------------------------------------------------------
+// D2Q9 multiple-relaxation-time relaxation (Sec. 3.1, Eq. 5) in the Dellar basis, split
+// so that the one-step and the multi-step kernels share it.  With the w-orthogonal
+// rows R = {1, c_x, c_y, 3c_x^2-1, c_x c_y, 3c_y^2-1, g, g c_x, g c_y},
+// g = (3c_x^2-1)(3c_y^2-1), the operator acting on h - f^eq is
+//   f'_i = h_i - w_i sum_{k=3..8} R_k(c_i) s_k n_k,   n_k = sum_i R_k(c_i) (h_i - f^eq_i),
+// s_k = 1/(tau_k |R_k|^2).  mrt_noneq takes the n_k of a cell's pulled deviations
+// d = h - w, mrt_relax applies the update in place.  Products are fused only within an
+// expression, so every kernel that inlines them rounds identically.
+// ---------------------------------------------------------------------------------
+template <typename real>
+struct MrtScales {
+  real s[6];  // s_3 .. s_8, rounded to the kernel's real type on the host
+};
+
+template <typename real>
+struct MrtNoneq {
+  real nxx, nxy, nyy, nN, nJx, nJy;  // n_3 .. n_8
+};
+
+template <typename real>
+__device__ __forceinline__ MrtNoneq<real> mrt_noneq(const real (&d)[9]) {
+#pragma clang fp contract(on)
+  using LT = Lattice<kD2Q9>;
+  // Raw moments of the deviations d = h - w; every R_k is orthogonal to w, so these are
+  // the moments of h.  Lattice factors are 0, +-1, +-2 or 4: every product is exact.
+  real drho = 0, jx = 0, jy = 0, sx = 0, sy = 0, pxy = 0, nN = 0, nJx = 0, nJy = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cx = LT::cx(i), cy = LT::cy(i);
+    drho += d[i];
+    add_times(jx, cx, d[i]);
+    add_times(jy, cy, d[i]);
+    add_times(sx, cx * cx, d[i]);  // sum over c_x != 0
+    add_times(sy, cy * cy, d[i]);
+    add_times(pxy, cx * cy, d[i]);
+    const real gd = real((3 * cx * cx - 1) * (3 * cy * cy - 1)) * d[i];
+    nN += gd;
+    add_times(nJx, cx, gd);
+    add_times(nJy, cy, gd);
+  }
+  const real rho = real(1) + drho;
+  const real inv_rho = real(1) / rho;
+  const real ux = jx * inv_rho, uy = jy * inv_rho;
+  // Subtract the moments of the second-order equilibrium, which have closed forms:
+  // sum (3c_x^2 - 1) f^eq = 3 rho u_x^2, sum c_x c_y f^eq = rho u_x u_y, and the ghost
+  // moments N, J of f^eq vanish.  sum (3c_x^2 - 1) d = 3 sx - drho.
+  MrtNoneq<real> n;
+  n.nxx = real(3) * sx - drho - real(3) * rho * ux * ux;
+  n.nxy = pxy - rho * ux * uy;
+  n.nyy = real(3) * sy - drho - real(3) * rho * uy * uy;
+  n.nN = nN;
+  n.nJx = nJx;
+  n.nJy = nJy;
+  return n;
+}
+
+// s: s_3 .. s_8 (the ghost scales s_6 .. s_8 uniform or the cell's own)
+template <typename real>
+__device__ __forceinline__ void mrt_relax(real (&d)[9], const MrtNoneq<real>& n, const real (&s)[6]) {
+#pragma clang fp contract(on)
+  using LT = Lattice<kD2Q9>;
+  using CO = Coef<kD2Q9, real>;
+  const real axx = n.nxx * s[0], axy = n.nxy * s[1], ayy = n.nyy * s[2];
+  const real aN = n.nN * s[3], aJx = n.nJx * s[4], aJy = n.nJy * s[5];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cx = LT::cx(i), cy = LT::cy(i);
+    const real gi = real((3 * cx * cx - 1) * (3 * cy * cy - 1));
+    real corr = real(3 * cx * cx - 1) * axx;
+    add_times(corr, cx * cy, axy);
+    corr += real(3 * cy * cy - 1) * ayy;
+    real ghost_part = aN;
+    add_times(ghost_part, cx, aJx);
+    add_times(ghost_part, cy, aJy);
+    corr += gi * ghost_part;
+    d[i] = d[i] - CO::W(i) * corr;
+  }
+}
+
 }  // namespace lbm

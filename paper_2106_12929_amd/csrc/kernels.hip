@@ -326,7 +326,8 @@ struct StepNShape2D {
 template <int S, int FM, int TX, int NST>
 __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
     const typename Storage<S>::word* __restrict__ fin, typename Storage<S>::word* __restrict__ fout,
-    const typename Storage<S>::real* __restrict__ force, GridArgs g, Step2Args a, typename Storage<S>::real omega) {
+    const typename Storage<S>::real* __restrict__ force, GridArgs g, Step2Args a, typename Storage<S>::real omega,
+    MrtScales<typename Storage<S>::real> mrt) {
   using LT = Lattice<kD2Q9>;
   using ST = Storage<S>;
   using W = typename ST::word;
@@ -358,10 +359,19 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
     return (uint32_t)(x < 0 ? x + (int)g.nx : (x >= (int)g.nx ? x - (int)g.nx : x));
   };
   auto load_force = [&](uint32_t y, uint32_t x, real& Fx, real& Fy) {
-    if constexpr (FM != kNoForce) {
+    if constexpr (FM == kGuoForce || FM == kShiftForce) {
       const real* f = force + (uint64_t)y * g.nx + x;
       Fx = f[0];
       Fy = f[g.ncells];
+    }
+  };
+  // the collision of one cell: BGK (forced as FM says) or, for kMrtUniform, the MRT
+  // collision with uniform relaxation times
+  auto collide = [&](real (&d)[Q], real Fx, real Fy) {
+    if constexpr (FM == kMrtUniform) {
+      mrt_relax(d, mrt_noneq(d), mrt.s);
+    } else {
+      bgk_collide<kD2Q9, real, FM>(d, Fx, Fy, real(0), omega);
     }
   };
   // word of direction i, column j of the ring of stage s, slot sl
@@ -396,7 +406,7 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
         real d[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
-        bgk_collide<kD2Q9, real, FM>(d, rf[0], rf[1], real(0), omega);
+        collide(d, rf[0], rf[1]);
         if (live) {
 #pragma unroll
           for (int i = 0; i < Q; ++i) ring_at(1, SL, i, j) = ST::from_dev(d[i], CO::W(i));
@@ -453,7 +463,7 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
         if (k >= k0 + 2) {
           // the row completed here: stage ST_ produces row r0 + k - 2 (ST_ - 1)
           const int row = r0 + (int)k - 2 * (ST_ - 1);
-          bgk_collide<kD2Q9, real, FM>(dA, cf[0], cf[1], real(0), omega);
+          collide(dA, cf[0], cf[1]);
           if (k + 1 < k0 + 2 + rows) load_force(wrapy(row + 1), x, cf[0], cf[1]);
           if constexpr (LAST) {
             if (live) {
@@ -523,11 +533,6 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
 //                  come in through scalar loads.
 // ---------------------------------------------------------------------------------
 template <typename real>
-struct MrtScales {
-  real s[6];  // rounded to the kernel's real type on the host
-};
-
-template <typename real>
 __device__ __forceinline__ real act_tanh(real z) {
   return tanh(z);
 }
@@ -571,33 +576,8 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
   real d[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(load_src<LT>(fin, g, src, xb, i), CO::W(i));
-  // Raw moments of the deviations d = h - w; every R_k is orthogonal to w, so these are
-  // the moments of h.  Lattice factors are 0, +-1, +-2 or 4: every product is exact.
-  real drho = 0, jx = 0, jy = 0, sx = 0, sy = 0, pxy = 0, nN = 0, nJx = 0, nJy = 0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int cx = LT::cx(i), cy = LT::cy(i);
-    drho += d[i];
-    add_times(jx, cx, d[i]);
-    add_times(jy, cy, d[i]);
-    add_times(sx, cx * cx, d[i]);  // sum over c_x != 0
-    add_times(sy, cy * cy, d[i]);
-    add_times(pxy, cx * cy, d[i]);
-    const real gd = real((3 * cx * cx - 1) * (3 * cy * cy - 1)) * d[i];
-    nN += gd;
-    add_times(nJx, cx, gd);
-    add_times(nJy, cy, gd);
-  }
-  const real rho = real(1) + drho;
-  const real inv_rho = real(1) / rho;
-  const real ux = jx * inv_rho, uy = jy * inv_rho;
-  // Non-equilibrium moments n_k = sum_i R_k(c_i) (h_i - f^eq_i): the raw moments minus
-  // those of the second-order D2Q9 equilibrium, which have closed forms:
-  // sum (3c_x^2 - 1) f^eq = 3 rho u_x^2, sum c_x c_y f^eq = rho u_x u_y, and the ghost
-  // moments N, J of f^eq vanish.  sum (3c_x^2 - 1) d = 3 sx - drho.
-  const real nxx = real(3) * sx - drho - real(3) * rho * ux * ux;
-  const real nxy = pxy - rho * ux * uy;
-  const real nyy = real(3) * sy - drho - real(3) * rho * uy * uy;
+  const MrtNoneq<real> nq = mrt_noneq(d);
+  const real nxx = nq.nxx, nxy = nq.nxy, nyy = nq.nyy, nN = nq.nN, nJx = nq.nJx, nJy = nq.nJy;
   real s6 = real(sc.s[3]), s7 = real(sc.s[4]), s8 = real(sc.s[5]);
   if constexpr (GM == kGhostField) {
     const uint32_t n = cell_index(g, c);
@@ -624,23 +604,11 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
     s7 = real(3) / (real(8) * (exp_real<real>(t1) + real(0.5)));
     s8 = real(3) / (real(8) * (exp_real<real>(t2) + real(0.5)));
   }
-  const real axx = nxx * real(sc.s[0]), axy = nxy * real(sc.s[1]), ayy = nyy * real(sc.s[2]);
-  const real aN = nN * s6, aJx = nJx * s7, aJy = nJy * s8;
+  const real s[6] = {sc.s[0], sc.s[1], sc.s[2], s6, s7, s8};
+  mrt_relax(d, nq, s);
   const uint32_t xo = c.x * (uint32_t)sizeof(typename ST::word);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int cx = LT::cx(i), cy = LT::cy(i);
-    const real gi = real((3 * cx * cx - 1) * (3 * cy * cy - 1));
-    real corr = real(3 * cx * cx - 1) * axx;
-    add_times(corr, cx * cy, axy);
-    corr += real(3 * cy * cy - 1) * ayy;
-    real ghost_part = aN;
-    add_times(ghost_part, cx, aJx);
-    add_times(ghost_part, cy, aJy);
-    corr += gi * ghost_part;
-    const real dn = d[i] - CO::W(i) * corr;
-    store_stream(at_byte(fout + dir_row<Q>(g, c.y, c.z, i), xo), ST::from_dev(dn, CO::W(i)));
-  }
+  for (int i = 0; i < Q; ++i) store_stream(at_byte(fout + dir_row<Q>(g, c.y, c.z, i), xo), ST::from_dev(d[i], CO::W(i)));
 }
 
 // ---------------------------------------------------------------------------------
@@ -1571,11 +1539,13 @@ static uint32_t step2_blocks_per_cu() {
 
 template <int S, int FM, int TX, int NST>
 static hipError_t launch_stepn_2d(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
-                                  hipStream_t s) {
+                                  hipStream_t s, const double* mrt_scales = nullptr) {
   using ST = Storage<S>;
   using W = typename ST::word;
   using R = typename ST::real;
   static std::atomic<int> cached{0};
+  MrtScales<R> sc;
+  for (int k = 0; k < 6; ++k) sc.s[k] = mrt_scales ? (R)mrt_scales[k] : R(0);
   Step2Args a;
   a.tiles_x = g.nx / TX;
   a.tiles_y = 1;
@@ -1587,16 +1557,26 @@ static hipError_t launch_stepn_2d(const void* fin, void* fout, const void* force
   a.lz = step2_chunk(a.tiles_x, g.ny, slots, 3 * (NST - 1));
   const dim3 grid((unsigned)(a.tiles_x * ((g.ny + a.lz - 1) / a.lz)));
   stepn_2d_kernel<S, FM, TX, NST><<<grid, StepNShape2D<TX, NST>::NT, 0, s>>>((const W*)fin, (W*)fout,
-                                                                             (const R*)force, g, a, (R)omega);
+                                                                             (const R*)force, g, a, (R)omega, sc);
   return hipGetLastError();
 }
 
 template <int S, int FM, int NST>
 static hipError_t launch_stepn_2d_w(const void* fin, void* fout, const void* force, const GridArgs& g, double omega,
-                                    hipStream_t s) {
+                                    hipStream_t s, const double* mrt_scales = nullptr) {
   constexpr int WIDE = NST == 4 ? 128 : 256;
-  if (stepn_2d_width(g, NST) == WIDE) return launch_stepn_2d<S, FM, WIDE, NST>(fin, fout, force, g, omega, s);
-  return launch_stepn_2d<S, FM, 64, NST>(fin, fout, force, g, omega, s);
+  if (stepn_2d_width(g, NST) == WIDE)
+    return launch_stepn_2d<S, FM, WIDE, NST>(fin, fout, force, g, omega, s, mrt_scales);
+  return launch_stepn_2d<S, FM, 64, NST>(fin, fout, force, g, omega, s, mrt_scales);
+}
+
+template <int S>
+static hipError_t launch_stepn_mrt_s(int nst, const void* fin, void* fout, const GridArgs& g, const double* scales,
+                                     hipStream_t s) {
+  if (!step2_fits<kD2Q9, S>(g) || (nst != 2 && nst != 4) || (nst == 4 && stepn_2d_width(g, 4) == 0))
+    return hipErrorInvalidValue;
+  if (nst == 4) return launch_stepn_2d_w<S, kMrtUniform, 4>(fin, fout, nullptr, g, 0.0, s, scales);
+  return launch_stepn_2d_w<S, kMrtUniform, 2>(fin, fout, nullptr, g, 0.0, s, scales);
 }
 
 template <int L, int S, int FM>
@@ -1717,6 +1697,18 @@ static hipError_t launch_mrt_s(const void* fin, void* fout, const void* ghost, i
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_stepn_mrt(int storage, int nst, const void* fin, void* fout, const GridArgs& g,
+                            const double* scales, hipStream_t s) {
+  switch (storage) {
+    case kF64: return launch_stepn_mrt_s<kF64>(nst, fin, fout, g, scales, s);
+    case kF32: return launch_stepn_mrt_s<kF32>(nst, fin, fout, g, scales, s);
+    case kF32S: return launch_stepn_mrt_s<kF32S>(nst, fin, fout, g, scales, s);
+    case kF16S: return launch_stepn_mrt_s<kF16S>(nst, fin, fout, g, scales, s);
+    case kBF16S: return launch_stepn_mrt_s<kBF16S>(nst, fin, fout, g, scales, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_mrt(int storage, const void* fin, void* fout, const void* ghost, int ghost_mode, const GridArgs& g,
