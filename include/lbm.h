@@ -162,7 +162,8 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
 int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force,
              int n_steps, void* stream);
 
-/* How lbm_step (and lbm_step_shifted) split n_steps >= 1 into launches: *single
+/* How lbm_step (and lbm_step_shifted, and lbm_step_mrt with uniform ghost times) split
+ * n_steps >= 1 into launches: *single
  * one-step launches, then *paired two-step launches, then *quad four-step launches
  * (single + 2 paired + 4 quad = n_steps; paired and quad are even).  Host-only (no
  * device work).  LBM_EINVAL for n_steps < 1, LBM_ENULL for NULL outputs, grid errors as
