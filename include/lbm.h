@@ -289,8 +289,8 @@ enum lbm_activation { LBM_ACT_RELU = 0, LBM_ACT_TANH = 1 };
  *   W2 [3][53] row-major; arithmetic in the storage kind's real type.
  * activation: LBM_ACT_RELU or LBM_ACT_TANH.
  * tau_shear > 1/2 sets nu = (tau_shear - 1/2)/3.  Same ping-pong, return value and
- * buffer rules as lbm_step; params must not overlap the population buffers.  LBM_EUNSUP
- * for lattices other than D2Q9. */
+ * buffer rules as lbm_step (one step per launch); params must not overlap the population
+ * buffers.  LBM_EUNSUP for lattices other than D2Q9. */
 int lbm_step_neural(const lbm_grid* grid, void* f_in, void* f_out, double tau_shear,
                     const void* params, int activation, int n_steps, void* stream);
 

@@ -306,7 +306,7 @@ int mrt_common(const lbm_grid* grid, void* f_in, void* f_out, const double* taus
   double scales[6];
   for (int k = 0; k < 6; ++k) scales[k] = 1.0 / (taus[k + 3] * norm2[k]);
   // uniform relaxation times: several steps per launch where lbm_step would take them
-  // (lbm_step_launches); per-cell ghost times step singly
+  // (lbm_step_launches); per-cell ghost times (a field or the network) step singly
   const Plan plan = ghost_mode == lbm::kGhostUniform ? launch_plan(grid, geo, n_steps) : Plan{n_steps, 0, 0};
   void* bufs[2] = {f_in, f_out};
   int cur = 0;

@@ -296,6 +296,79 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
 }
 
 // ---------------------------------------------------------------------------------
+// D2Q9 multiple-relaxation-time step (Sec. 3.1, Eq. 5) in the Dellar basis.
+//
+// The basis {1, c_x, c_y, c_x^2, c_x c_y, c_y^2, g, g c_x, g c_y}, g = (3c_x^2-1)(3c_y^2-1),
+// spans the same moment subspaces as the w-orthogonal set
+//   R = {1, c_x, c_y, 3c_x^2-1, c_x c_y, 3c_y^2-1, g, g c_x, g c_y}
+// (the second-order rows differ from Dellar's only by multiples of the conserved rho),
+// so Eq. 5's operator -M^{-1} S^{-1} (M f - m^eq) acting on f - f^eq (zero conserved
+// part) is  f'_i = h_i - w_i sum_{k=3..8} R_k(c_i) n_k / (tau_k |R_k|^2),
+// n_k = sum_i R_k(c_i) (h_i - f^eq_i),  |R_k|^2 = sum_i w_i R_k(c_i)^2 = 2, 1/9, 2, 4,
+// 8/3, 8/3.  scale[k-3] = 1/(tau_k |R_k|^2) for uniform times.  GM selects where the
+// ghost times tau_6..8 come from:
+//   kGhostUniform  the uniform scales
+//   kGhostField    a per-cell field ghost[3][N]
+//   kGhostRelu,    the neural collision of Sec. 3.1: per cell, a network with inputs
+//   kGhostTanh     x = (Pi_xx, Pi_xy, Pi_yy, N, J_x, J_y) of h - f^eq, i.e.
+//                  (n_3/3, n_4, n_5/3, n_6, n_7, n_8), 53 hidden units
+//                  a_j = act(b1_j + sum_k W1_jk x_k) and outputs t_n = sum_j W2_nj a_j,
+//                  tau_{6+n} = exp(t_n) + 1/2.  ghost = the 530 parameters, W1 [53][6],
+//                  b1 [53], W2 [3][53]; every lane reads the same addresses, so they
+//                  come in through scalar loads.
+// ---------------------------------------------------------------------------------
+template <typename real>
+__device__ __forceinline__ real act_tanh(real z) {
+  return tanh(z);
+}
+// FP32: tanh z = 1 - 2/(e^{2z} + 1) with the hardware base-2 exponential of
+// z * 2 log2(e) and the hardware reciprocal (each about 1 ulp; the reciprocal's
+// argument is >= 1, never denormal).  Absolute error a few 1e-8 (relative error grows
+// only where tanh z itself is below that), saturating cleanly to +-1 where e^{2z}
+// overflows (1/inf = 0) or underflows.  An IEEE division here would cost a dozen VALU
+// instructions per hidden unit, most of the network's cost in this VALU-bound kernel.
+template <>
+__device__ __forceinline__ float act_tanh<float>(float z) {
+  constexpr float two_log2e = 2.0f * 1.44269504088896341f;  // exact: a power-of-two multiple
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z * two_log2e) + 1.0f);
+}
+template <typename real>
+__device__ __forceinline__ real exp_real(real z) {
+  return exp(z);
+}
+template <>
+__device__ __forceinline__ float exp_real<float>(float z) {
+  return expf(z);
+}
+
+// The neural collision's ghost scales s_6 .. s_8 of one cell (Sec. 3.1): the network
+// on x = (n_3/3, n_4, n_5/3, n_6, n_7, n_8), tau_{6+n} = exp(t_n) + 1/2,
+// s = 1/(tau |R|^2).  params: the 530 parameters (W1 [53][6], b1 [53], W2 [3][53]).
+template <typename real, bool RELU>
+__device__ __forceinline__ void neural_scales(const MrtNoneq<real>& nq, const real* __restrict__ params, real& s6,
+                                              real& s7, real& s8) {
+#pragma clang fp contract(on)
+  const real x[6] = {nq.nxx * real(1.0 / 3.0), nq.nxy, nq.nyy * real(1.0 / 3.0), nq.nN, nq.nJx, nq.nJy};
+  const real* __restrict__ W1 = params;
+  const real* __restrict__ b1 = params + kNeuralHidden * 6;
+  const real* __restrict__ W2 = b1 + kNeuralHidden;
+  real t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+  for (int j = 0; j < kNeuralHidden; ++j) {
+    real z = b1[j];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) z += W1[6 * j + k] * x[k];
+    const real act = RELU ? (z > real(0) ? z : real(0)) : act_tanh<real>(z);
+    t0 += W2[j] * act;
+    t1 += W2[kNeuralHidden + j] * act;
+    t2 += W2[2 * kNeuralHidden + j] * act;
+  }
+  s6 = real(1) / (real(4) * (exp_real<real>(t0) + real(0.5)));
+  s7 = real(3) / (real(8) * (exp_real<real>(t1) + real(0.5)));
+  s8 = real(3) / (real(8) * (exp_real<real>(t2) + real(0.5)));
+}
+
+// ---------------------------------------------------------------------------------
 // NST time steps per launch for D2Q9 (NST = 2 or 4): the 2D form of step2_kernel, with
 // a pipeline of NST stages.  A block owns a segment of TX cells of x and a chunk of
 // rows [yb, ye), and marches along y.  Stage s (s = 1..NST) advances the state by its
@@ -510,52 +583,7 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
   }
 }
 
-// ---------------------------------------------------------------------------------
-// D2Q9 multiple-relaxation-time step (Sec. 3.1, Eq. 5) in the Dellar basis.
-//
-// The basis {1, c_x, c_y, c_x^2, c_x c_y, c_y^2, g, g c_x, g c_y}, g = (3c_x^2-1)(3c_y^2-1),
-// spans the same moment subspaces as the w-orthogonal set
-//   R = {1, c_x, c_y, 3c_x^2-1, c_x c_y, 3c_y^2-1, g, g c_x, g c_y}
-// (the second-order rows differ from Dellar's only by multiples of the conserved rho),
-// so Eq. 5's operator -M^{-1} S^{-1} (M f - m^eq) acting on f - f^eq (zero conserved
-// part) is  f'_i = h_i - w_i sum_{k=3..8} R_k(c_i) n_k / (tau_k |R_k|^2),
-// n_k = sum_i R_k(c_i) (h_i - f^eq_i),  |R_k|^2 = sum_i w_i R_k(c_i)^2 = 2, 1/9, 2, 4,
-// 8/3, 8/3.  scale[k-3] = 1/(tau_k |R_k|^2) for uniform times.  GM selects where the
-// ghost times tau_6..8 come from:
-//   kGhostUniform  the uniform scales
-//   kGhostField    a per-cell field ghost[3][N]
-//   kGhostRelu,    the neural collision of Sec. 3.1: per cell, a network with inputs
-//   kGhostTanh     x = (Pi_xx, Pi_xy, Pi_yy, N, J_x, J_y) of h - f^eq, i.e.
-//                  (n_3/3, n_4, n_5/3, n_6, n_7, n_8), 53 hidden units
-//                  a_j = act(b1_j + sum_k W1_jk x_k) and outputs t_n = sum_j W2_nj a_j,
-//                  tau_{6+n} = exp(t_n) + 1/2.  ghost = the 530 parameters, W1 [53][6],
-//                  b1 [53], W2 [3][53]; every lane reads the same addresses, so they
-//                  come in through scalar loads.
-// ---------------------------------------------------------------------------------
-template <typename real>
-__device__ __forceinline__ real act_tanh(real z) {
-  return tanh(z);
-}
-// FP32: tanh z = 1 - 2/(e^{2z} + 1) with the hardware base-2 exponential of
-// z * 2 log2(e) and the hardware reciprocal (each about 1 ulp; the reciprocal's
-// argument is >= 1, never denormal).  Absolute error a few 1e-8 (relative error grows
-// only where tanh z itself is below that), saturating cleanly to +-1 where e^{2z}
-// overflows (1/inf = 0) or underflows.  An IEEE division here would cost a dozen VALU
-// instructions per hidden unit, most of the network's cost in this VALU-bound kernel.
-template <>
-__device__ __forceinline__ float act_tanh<float>(float z) {
-  constexpr float two_log2e = 2.0f * 1.44269504088896341f;  // exact: a power-of-two multiple
-  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z * two_log2e) + 1.0f);
-}
-template <typename real>
-__device__ __forceinline__ real exp_real(real z) {
-  return exp(z);
-}
-template <>
-__device__ __forceinline__ float exp_real<float>(float z) {
-  return expf(z);
-}
-
+// One D2Q9 MRT step (the collision and GM as described above the D2Q9 multi-step kernel).
 template <int S, int GM>
 __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>::word* __restrict__ fin,
                                                        typename Storage<S>::word* __restrict__ fout,
@@ -577,7 +605,6 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(load_src<LT>(fin, g, src, xb, i), CO::W(i));
   const MrtNoneq<real> nq = mrt_noneq(d);
-  const real nxx = nq.nxx, nxy = nq.nxy, nyy = nq.nyy, nN = nq.nN, nJx = nq.nJx, nJy = nq.nJy;
   real s6 = real(sc.s[3]), s7 = real(sc.s[4]), s8 = real(sc.s[5]);
   if constexpr (GM == kGhostField) {
     const uint32_t n = cell_index(g, c);
@@ -585,24 +612,7 @@ __global__ __launch_bounds__(256) void mrt_step_kernel(const typename Storage<S>
     s7 = real(3) / (real(8) * ghost[N + n]);
     s8 = real(3) / (real(8) * ghost[2 * N + n]);
   } else if constexpr (GM == kGhostRelu || GM == kGhostTanh) {
-    const real x[6] = {nxx * real(1.0 / 3.0), nxy, nyy * real(1.0 / 3.0), nN, nJx, nJy};
-    const real* __restrict__ W1 = ghost;
-    const real* __restrict__ b1 = ghost + kNeuralHidden * 6;
-    const real* __restrict__ W2 = b1 + kNeuralHidden;
-    real t0 = 0, t1 = 0, t2 = 0;
-#pragma unroll
-    for (int j = 0; j < kNeuralHidden; ++j) {
-      real z = b1[j];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) z += W1[6 * j + k] * x[k];
-      const real a = GM == kGhostRelu ? (z > real(0) ? z : real(0)) : act_tanh<real>(z);
-      t0 += W2[j] * a;
-      t1 += W2[kNeuralHidden + j] * a;
-      t2 += W2[2 * kNeuralHidden + j] * a;
-    }
-    s6 = real(1) / (real(4) * (exp_real<real>(t0) + real(0.5)));
-    s7 = real(3) / (real(8) * (exp_real<real>(t1) + real(0.5)));
-    s8 = real(3) / (real(8) * (exp_real<real>(t2) + real(0.5)));
+    neural_scales<real, GM == kGhostRelu>(nq, ghost, s6, s7, s8);
   }
   const real s[6] = {sc.s[0], sc.s[1], sc.s[2], s6, s7, s8};
   mrt_relax(d, nq, s);

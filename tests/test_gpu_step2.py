@@ -251,3 +251,4 @@ def test_mrt_multi_step_full_size_equal_single_steps(kind):
     assert B.lbm_step_mrt(grid, p, q, MRT_TAUS, None, 8) == 1
     torch.cuda.synchronize()
     assert torch.equal(bits(p), bits(ref))
+
