@@ -233,6 +233,8 @@ def run_shard(B, steps: int, warmup: int, nx: int = 512, ny: int = 512, nz: int 
     halo2 = 2 * 27 * nx * ny * torch.tensor([], dtype=grid.word_dtype).element_size()  # both faces
     out["slab2_step_pair"] = {"ms_per_two_steps": ms2, "mlups": 2 * grid.ncells / (ms2 * 1e-3) / 1e6,
                               "hbm_gbs_per_step": bpc * grid.ncells / (ms2 / 2 * 1e-3) / 1e9}
+    ms2o = time_launches(lambda: S2.step_pair(TAU, overlap=True), max(1, steps // 2), warmup)
+    out["slab2_step_pair_overlapped"] = {"ms_per_two_steps": ms2o, "mlups": 2 * grid.ncells / (ms2o * 1e-3) / 1e6}
     out["halo2_exchange_only"] = {"ms": time_launches(lambda: S2.exchange(), steps, warmup),
                                   "bytes_each_way": halo2}
     del bufs, f, S, S2

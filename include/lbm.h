@@ -234,23 +234,28 @@ int lbm_slab_halo_copy(const lbm_grid* src_slab, const void* src, const lbm_grid
  * that keeps the intermediate state on chip, for slabs with two ghost planes on each
  * side: the halo of two steps is two planes deep, so the slabs exchange once per two
  * steps.
- * slab: as lbm_step_slab, nz >= 2 (LBM_EINVAL otherwise).
+ * slab: as lbm_step_slab, nz >= 2 (LBM_EINVAL otherwise, and for an empty or
+ *   out-of-range plane range).
  * f_in, f_out: slab buffers of (nz + 4) planes in the population layout: buffer
  *   planes 0 and 1 are the ghost planes -2 and -1 below the slab, planes 2 .. nz + 1 hold
  *   slab planes 0 .. nz-1, planes nz + 2 and nz + 3 the ghost planes nz and nz + 1
  *   above.  The intermediate step is computed on planes -1 .. nz, which reads the
  *   directions with c_z = +1 of ghost plane -2, those with c_z = 0 and +1 of ghost plane
  *   -1, those with c_z = 0 and -1 of ghost plane nz and those with c_z = -1 of ghost plane
- *   nz + 1 (what lbm_slab2_halo_copy fills); no other ghost words are read.  Own planes
- *   of f_out are written, its ghost planes are left alone.
+ *   nz + 1 (what lbm_slab2_halo_copy fills); no other ghost words are read.  The ghost
+ *   planes of f_out are left alone.
  * force: NULL, or D * nx * ny * (nz + 2) reals: the force of slab planes -1 .. nz (one
  *   ghost plane each side, which the caller fills from the neighbours' force).
+ * z_begin, z_end: the slab planes [z_begin, z_end) to compute, 0 <= z_begin < z_end
+ *   <= nz; only those planes of f_out are written.  The inner planes [2, nz-2) read no
+ *   ghost data, so they can run while the halo exchange of the previous launch is in
+ *   flight, and the four boundary planes after it.
  * The result equals two steps of the periodic grid the slabs make up bit for bit.
  * LBM_EUNSUP where the slab or storage kind does not take the two-step kernel (3D
  * lattices; nx and ny on lbm_step's two-step tiles; lbm_step_slab2_available).  f_in and
  * f_out must not overlap, nor force either of them. */
 int lbm_step_slab2(const lbm_grid* slab, const void* f_in, void* f_out, double tau, const void* force,
-                   void* stream);
+                   int64_t z_begin, int64_t z_end, void* stream);
 
 /* *available = 1 if lbm_step_slab2 takes this slab and storage kind, else 0.
  * Host-only.  Grid errors as lbm_step; LBM_ENULL for a NULL output. */

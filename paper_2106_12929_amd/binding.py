@@ -80,7 +80,7 @@ def _load() -> ctypes.CDLL:
         "lbm_copy": (i32, [vp, vp, sz, vp]),
         "lbm_step_slab": (i32, [gp, vp, vp, dbl, vp, ctypes.c_int64, ctypes.c_int64, vp]),
         "lbm_slab_halo_copy": (i32, [gp, vp, gp, vp, i32, vp]),
-        "lbm_step_slab2": (i32, [gp, vp, vp, dbl, vp, vp]),
+        "lbm_step_slab2": (i32, [gp, vp, vp, dbl, vp, ctypes.c_int64, ctypes.c_int64, vp]),
         "lbm_step_slab2_available": (i32, [gp, ctypes.POINTER(i32)]),
         "lbm_slab2_halo_copy": (i32, [gp, vp, gp, vp, i32, vp]),
         "lbm_shell_energy": (i32, [ctypes.POINTER(_CShells), i32, vp, dbl, vp, vp]),
@@ -355,15 +355,19 @@ def lbm_slab_halo_copy(src_slab: Grid, src: torch.Tensor, dst_slab: Grid, dst: t
 
 
 def lbm_step_slab2(slab: Grid, f_in: torch.Tensor, f_out: torch.Tensor, tau: float,
-                   force: torch.Tensor | None = None, stream=None) -> None:
-    """Two steps of a whole z-slab with two ghost planes on each side; f_in and f_out
-    are slab buffers (nz + 4 planes), force holds D*nx*ny*(nz + 2) reals (planes -1 .. nz)."""
+                   force: torch.Tensor | None = None, z_begin: int = 0, z_end: int | None = None,
+                   stream=None) -> None:
+    """Two steps of slab planes [z_begin, z_end) (default: all) of a z-slab with two ghost
+    planes on each side; f_in and f_out are slab buffers (nz + 4 planes), force holds
+    D*nx*ny*(nz + 2) reals (planes -1 .. nz)."""
     words = slab.Q * slab.row_pitch * slab.ny * (slab.nz + 4)
     g = slab.c_struct()
     a = _dev_ptr(f_in, "f_in", slab.word_dtype, words)
     b = _dev_ptr(f_out, "f_out", slab.word_dtype, words)
     F = _dev_ptr(force, "force", slab.real_dtype, slab.D * slab.nx * slab.ny * (slab.nz + 2), required=False)
-    _check(_lib.lbm_step_slab2(ctypes.byref(g), a, b, float(tau), F, _stream(stream)), "lbm_step_slab2")
+    z1 = slab.nz if z_end is None else int(z_end)
+    _check(_lib.lbm_step_slab2(ctypes.byref(g), a, b, float(tau), F, int(z_begin), z1, _stream(stream)),
+           "lbm_step_slab2")
 
 
 def lbm_step_slab2_available(slab: Grid) -> bool:

@@ -418,12 +418,15 @@ int lbm_step_slab2_available(const lbm_grid* slab, int* available) {
 }
 
 int lbm_step_slab2(const lbm_grid* slab, const void* f_in, void* f_out, double tau, const void* force,
-                   void* stream) {
+                   int64_t z_begin, int64_t z_end, void* stream) {
   Geometry geo;
   LBM_TRY(check_grid(slab, &geo));
   if (geo.D != 3) return fail(LBM_EUNSUP, "lbm_step_slab2 needs a 3D lattice (z-slabs)");
   LBM_TRY(check_tau(tau));
   if (slab->nz < 2) return fail(LBM_EINVAL, "a slab of two-step launches needs nz >= 2 (got %lld)", (long long)slab->nz);
+  if (z_begin < 0 || z_end > slab->nz || z_begin >= z_end)
+    return fail(LBM_EINVAL, "plane range [%lld, %lld) is empty or outside [0, %lld)", (long long)z_begin,
+                (long long)z_end, (long long)slab->nz);
   LBM_TRY(check_ptr(f_in, "f_in", true));
   LBM_TRY(check_ptr(f_out, "f_out", true));
   LBM_TRY(check_ptr(force, "force", false));
@@ -434,6 +437,8 @@ int lbm_step_slab2(const lbm_grid* slab, const void* f_in, void* f_out, double t
   if (overlap(force, vbytes, f_in, fbytes) || overlap(force, vbytes, f_out, fbytes))
     return fail(LBM_EALIAS, "force overlaps a population buffer");
   geo.args.ghost = 2;
+  geo.args.z0 = (uint32_t)z_begin;
+  geo.args.nzl = (uint32_t)(z_end - z_begin);
   if (!lbm::step2_slab_supported(slab->lattice, slab->storage, geo.args))
     return fail(LBM_EUNSUP, "two steps per launch do not take this slab or storage kind "
                             "(lbm_step_slab2_available)");

@@ -68,7 +68,8 @@ hipError_t launch_adjoint(int lattice, int storage, int mode, const void* gt, co
 bool adjoint2_supported(int lattice, int storage, const GridArgs& g);
 // Two steps on a z-slab with two ghost planes on each side (step2_kernel with
 // g.ghost == 2): buffer plane p + 2 holds slab plane p (p = -2 .. nz + 1), the force
-// holds slab planes -1 .. nz at p + 1.  Every own plane is computed; nothing wraps in z.
+// holds slab planes -1 .. nz at p + 1.  Planes [g.z0, g.z0 + g.nzl) are computed;
+// nothing wraps in z.
 bool step2_slab_supported(int lattice, int storage, const GridArgs& g);
 hipError_t launch_step2_slab(int lattice, int storage, const void* fin, void* fout, const void* force,
                              int force_mode, const GridArgs& g, double omega, hipStream_t s);

@@ -155,8 +155,9 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
   const uint32_t lin = xcd < extra ? xcd * (per + 1) + pos : extra * (per + 1) + (xcd - extra) * per + pos;
   const uint32_t tx = lin % a.tiles_x, ty = (lin / a.tiles_x) % a.tiles_y, zc = lin / (a.tiles_x * a.tiles_y);
   const uint32_t x0 = tx * TX, y0 = ty * SH::TY;
-  const uint32_t zb = zc * a.lz;
-  const uint32_t ze = min(zb + a.lz, g.nz);
+  // the launch's planes [z0, z0 + nzl) in chunks of lz (all of them on a periodic grid)
+  const uint32_t zb = g.z0 + zc * a.lz;
+  const uint32_t ze = min(zb + a.lz, g.z0 + g.nzl);
   const uint32_t nplanes = ze - zb + 2;  // step t+1 on planes zb-1 .. ze
   const uint32_t t = threadIdx.x;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(t / 64);
@@ -1605,14 +1606,15 @@ static hipError_t launch_step2_lsf(const void* fin, void* fout, const void* forc
   // a slab's force has a ghost plane below and above its own planes
   a.force_stride = g.ghost ? (uint64_t)g.nx * g.ny * (g.nz + 2) : g.ncells;
   const uint64_t tiles = (uint64_t)a.tiles_x * a.tiles_y;
-  a.lz = step2_chunk(tiles, g.nz, (uint64_t)step2_blocks_per_cu<L, S, FM>() * device_cus(), 2);
-  const dim3 grid((unsigned)(tiles * ((g.nz + a.lz - 1) / a.lz)));
+  a.lz = step2_chunk(tiles, g.nzl, (uint64_t)step2_blocks_per_cu<L, S, FM>() * device_cus(), 2);
+  const dim3 grid((unsigned)(tiles * ((g.nzl + a.lz - 1) / a.lz)));
   step2_kernel<L, S, FM><<<grid, SH::NT, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, a, (R)omega);
   return hipGetLastError();
 }
 
 // Two steps on a z-slab with two ghost planes on each side (g.ghost == 2): the 3D
-// lattices and the tiles of the periodic two-step launches, nz >= 2.
+// lattices and the tiles of the periodic two-step launches, nz >= 2, the planes
+// [z0, z0 + nzl) of the slab.
 template <int L, int S>
 static bool step2_slab_fits(const GridArgs& g) {
   if constexpr (!step2_enabled<L, S>() || L == kD2Q9) {
@@ -1620,8 +1622,8 @@ static bool step2_slab_fits(const GridArgs& g) {
   } else {
     using SH = Step2Shape<L, S>;
     const uint64_t plane = (uint64_t)g.ny * Lattice<L>::Q * g.pitch * sizeof(typename Storage<S>::word);
-    return g.ghost == 2 && g.z0 == 0 && g.nzl == g.nz && g.nx % SH::TX == 0 && g.ny % SH::TY == 0 && g.nz >= 2 &&
-           plane < (uint64_t(1) << 32);
+    return g.ghost == 2 && g.nzl >= 1 && g.z0 + g.nzl <= g.nz && g.nx % SH::TX == 0 && g.ny % SH::TY == 0 &&
+           g.nz >= 2 && plane < (uint64_t(1) << 32);
   }
 }
 

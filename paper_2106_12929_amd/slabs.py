@@ -106,16 +106,43 @@ class SlabSet:
             copy(self.slabs[p], self.bufs[p][c], self.slabs[up], self.bufs[up][c], "high", stream)
             copy(self.slabs[p], self.bufs[p][c], self.slabs[down], self.bufs[down][c], "low", stream)
 
-    def step_pair(self, tau: float, forces=None) -> None:
+    def _launch2(self, p: int, tau: float, force, z_begin: int, z_end: int) -> None:
+        if z_begin < z_end:
+            B.lbm_step_slab2(self.slabs[p], self.bufs[p][self.cur], self.bufs[p][1 - self.cur], tau, force,
+                             z_begin, z_end)
+
+    def step_pair(self, tau: float, forces=None, overlap: bool = False) -> None:
         """Two steps of the whole grid (slabs with two ghost planes): one exchange, then
-        one two-step launch per slab.  forces: per slab, D x (nz + 2) planes of force
-        (split_field), or None."""
+        two-step launches: the inner planes [2, nz-2), which read no ghost data, and the
+        four boundary planes (slabs of fewer than 5 planes: one launch of all).  With
+        `overlap` the exchange runs on a second stream concurrently with the inner
+        planes.  forces: per slab, D x (nz + 2) planes of force (split_field), or None."""
         if self.ghost != 2:
             raise ValueError("step_pair needs slabs with two ghost planes (ghost=2)")
         forces = forces if forces is not None else [None] * self.P
-        self.exchange()
+        main = torch.cuda.current_stream()
+        split = [n >= 5 for n in self.planes]
+        if overlap:
+            if self._halo_stream is None:
+                self._halo_stream = torch.cuda.Stream()
+            hs = self._halo_stream
+            hs.wait_stream(main)  # the previous launch has written the planes being sent
+            with torch.cuda.stream(hs):
+                self.exchange(hs)
+        else:
+            self.exchange()
         for p in range(self.P):
-            B.lbm_step_slab2(self.slabs[p], self.bufs[p][self.cur], self.bufs[p][1 - self.cur], tau, forces[p])
+            if split[p]:
+                self._launch2(p, tau, forces[p], 2, self.planes[p] - 2)
+        if overlap:
+            main.wait_stream(hs)
+        for p in range(self.P):
+            n = self.planes[p]
+            if split[p]:
+                self._launch2(p, tau, forces[p], 0, 2)
+                self._launch2(p, tau, forces[p], n - 2, n)
+            else:
+                self._launch2(p, tau, forces[p], 0, n)
         self.cur = 1 - self.cur
 
     def _launch(self, p: int, tau: float, force, z_begin: int, z_end: int) -> None:

@@ -288,11 +288,14 @@ def test_slab2_step_validation(B):
     lib = B._lib
     g = _grid(B, nx=32, ny=8, nz=8)  # slab buffers of 12 planes
 
-    def step(grid=g, a=P1, b=P2, tau=0.6, force=None):
-        return lib.lbm_step_slab2(ctypes.byref(grid), a, b, tau, force, None)
+    def step(grid=g, a=P1, b=P2, tau=0.6, force=None, z0=0, z1=None):
+        z1 = grid.nz if z1 is None else z1
+        return lib.lbm_step_slab2(ctypes.byref(grid), a, b, tau, force, z0, z1, None)
 
     assert step(_grid(B, "D2Q9", nx=64, ny=8, nz=1)) == -5   # z-slabs need a 3D lattice
     assert step(_grid(B, nx=32, ny=8, nz=1)) == -1           # nz < 2
+    for z0, z1 in ((0, 0), (-1, 4), (0, 9), (5, 3)):
+        assert step(z0=z0, z1=z1) == -1                     # empty or out-of-range plane range
     assert step(tau=0.5) == -1
     assert step(a=None) == -2
     assert step(b=MIS) == -3

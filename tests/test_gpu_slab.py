@@ -184,10 +184,37 @@ def test_slabs_two_steps_per_launch_match_periodic_step(parts, lat, kind, shape,
     S = SlabSet(grid, parts, ghost=2)
     S.scatter(g0)
     forces = S.split_field(F)
-    for _ in range(3):
-        S.step_pair(0.56, forces)
+    for t in range(3):
+        S.step_pair(0.56, forces, overlap=(t % 2 == 1))
     torch.cuda.synchronize()
     assert torch.equal(bits(S.gather()), bits(ref))
+
+
+@pytest.mark.parametrize("kind", ["f32", "f16s"])
+def test_two_step_slab_plane_ranges_compose(kind):
+    """lbm_step_slab2 over the plane ranges [0, 3), [3, 7), [7, 9), [9, 12) writes what one
+    launch over [0, 12) writes, word for word (the launches read the same input)."""
+    need_gpu()
+    B = binding()
+    from paper_2106_12929_amd.slabs import SlabSet
+
+    lat = "D3Q27"
+    shape = (64, 8, 12)
+    st = olbm.stencil(lat)
+    grid = B.Grid(lat, kind, *shape)
+    spatial = (shape[2], shape[1], shape[0])
+    S = SlabSet(grid, 1, ghost=2)
+    S.scatter(grid.to_layout(_state(st, spatial, 41, kind)).cuda())
+    S.exchange()
+    slab, src = S.slabs[0], S.bufs[0][S.cur]
+    whole = torch.zeros_like(src)
+    B.lbm_step_slab2(slab, src, whole, 0.56)
+    parts = torch.zeros_like(src)
+    for z0, z1 in ((0, 3), (3, 7), (7, 9), (9, 12)):
+        B.lbm_step_slab2(slab, src, parts, 0.56, None, z0, z1)
+    torch.cuda.synchronize()
+    assert torch.equal(bits(parts), bits(whole))
+    assert (whole[:2] == 0).all() and (whole[-2:] == 0).all()  # ghost planes untouched
 
 
 def test_two_step_slabs_reject_other_shapes():
@@ -222,7 +249,7 @@ def test_full_size_shard_two_steps_per_launch_matches_periodic_step(parts):
     ref = _periodic(B, grid, g0, 0.51, None, 4)
     S = SlabSet(grid, parts, ghost=2)
     S.scatter(g0)
-    for _ in range(2):
-        S.step_pair(0.51)
+    for t in range(2):
+        S.step_pair(0.51, overlap=(t == 1))
     torch.cuda.synchronize()
     assert torch.equal(bits(S.gather()), bits(ref))
