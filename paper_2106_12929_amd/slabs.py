@@ -113,15 +113,16 @@ class SlabSet:
 
     def step_pair(self, tau: float, forces=None, overlap: bool = False) -> None:
         """Two steps of the whole grid (slabs with two ghost planes): one exchange, then
-        two-step launches: the inner planes [2, nz-2), which read no ghost data, and the
-        four boundary planes (slabs of fewer than 5 planes: one launch of all).  With
-        `overlap` the exchange runs on a second stream concurrently with the inner
-        planes.  forces: per slab, D x (nz + 2) planes of force (split_field), or None."""
+        one two-step launch per slab.  With `overlap` the exchange runs on a second
+        stream concurrently with a launch of the inner planes [2, nz-2), which read no
+        ghost data, and the four boundary planes follow once it has landed (slabs of
+        fewer than 5 planes: one launch of all after the exchange).  forces: per slab,
+        D x (nz + 2) planes of force (split_field), or None."""
         if self.ghost != 2:
             raise ValueError("step_pair needs slabs with two ghost planes (ghost=2)")
         forces = forces if forces is not None else [None] * self.P
         main = torch.cuda.current_stream()
-        split = [n >= 5 for n in self.planes]
+        split = [overlap and n >= 5 for n in self.planes]
         if overlap:
             if self._halo_stream is None:
                 self._halo_stream = torch.cuda.Stream()
