@@ -1465,10 +1465,9 @@ static hipError_t launch_step_ls(const void* fin, void* fout, const void* force,
   return hipGetLastError();
 }
 
-// Two-step launches (step2_kernel) on the 3D lattices: FP32 and shifted-FP32 words
-// (one launch 1.47-1.59x faster than two of step_kernel at 256^3) and shifted FP16
-// (1.13-1.30x).  Shifted BF16 is left to step_kernel: its software rounding makes the
-// two-step form bound by its arithmetic, 4% slower than two single steps.
+// Multi-step launches for every storage kind: on the 3D lattices step2_kernel (one
+// launch at 256^3 against two of step_kernel: FP32 and shifted FP32 1.47-1.59x, shifted
+// FP16 and BF16 1.10-1.30x, FP64 1.5x), on D2Q9 stepn_2d_kernel.
 template <int L, int S>
 constexpr bool step2_enabled() {
   if (L == kD2Q9) return true;
@@ -1529,9 +1528,9 @@ static uint32_t step2_chunk(uint64_t tiles, uint32_t nz, uint64_t slots, uint32_
   return best;
 }
 
-// Blocks of one two-step instantiation resident per CU (its registers and LDS decide;
-// the D3Q27 forms take one block of 10 or 11 waves per CU at 99-168 registers, the
-// D3Q19 forms up to two).
+// Blocks of one multi-step instantiation resident per CU (its registers and LDS decide;
+// the D3Q27 forms take one block of 10 or 11 waves per CU at 99-168 registers, 6 waves
+// at up to 256 for FP64, the D3Q19 forms up to two).
 template <typename K>
 static uint32_t blocks_per_cu(std::atomic<int>& cached, K kernel, int threads) {
   int n = cached.load(std::memory_order_relaxed);
