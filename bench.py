@@ -595,9 +595,12 @@ def profile_set(B, steps: int, warmup: int):
     # launches, after a warm-up call as long: the first launches of a run are slower);
     # the bytes it must move are the state read and written once per launch
     n2s = 4 * max(1, steps)
-    r = run_forward(B, "f32", n2s, warmup, u3)
-    report(f"two-step D3Q27 f32 {N}^3", "step2_kernel<D3Q27, F32, unforced>", B.Grid("D3Q27", "f32", N, N, N),
-           r["ms_per_two_step_launch"], r["bytes_per_cell"])
+    for storage, kname in (("f32", "step2_kernel<D3Q27, F32, unforced>"),
+                           ("f16s", "step2_kernel<D3Q27, F16S, unforced>"),
+                           ("f64", "step2_kernel<D3Q27, F64, unforced>")):
+        r = run_forward(B, storage, n2s, warmup, u3)
+        report(f"two-step D3Q27 {storage} {N}^3", kname, B.Grid("D3Q27", storage, N, N, N),
+               r["ms_per_two_step_launch"], r["bytes_per_cell"])
     for storage, kname in (("f32", "step_kernel<D3Q27, F32, unforced>"), ("f16s", "step_kernel<D3Q27, F16S, unforced>"),
                            ("f64", "step_kernel<D3Q27, F64, unforced>")):
         r = run_forward(B, storage, steps, warmup, u3, one_call=False)
