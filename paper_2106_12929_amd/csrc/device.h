@@ -25,6 +25,43 @@ __device__ __forceinline__ void store_stream(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
+// A wave-uniform region [base, base + bytes) as a raw buffer resource (stride 0, no
+// swizzle; word 3 is the gfx9 32-bit data format).  Stores through it take the lane's
+// 32-bit offset and a wave-uniform offset, so a run of stores at uniform distances
+// needs no per-store address arithmetic.  A store at or past `bytes` is dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t region_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// The T at byte voff + soff of a region (voff per lane, soff uniform); 0 at or past
+// the region's end.
+template <typename T>
+__device__ __forceinline__ T region_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 2) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  } else if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    static_assert(sizeof(T) == 8, "2-, 4- or 8-byte words");
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+}
+
+// Nontemporal store of v at byte voff + soff of a region (voff per lane, soff uniform).
+template <typename T>
+__device__ __forceinline__ void store_stream(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v) {
+  constexpr int kNontemporal = 2;  // the cache-policy bit of a streaming store
+  if constexpr (sizeof(T) == 2) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, kNontemporal);
+  } else if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, kNontemporal);
+  } else {
+    static_assert(sizeof(T) == 8, "2-, 4- or 8-byte words");
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, kNontemporal);
+  }
+}
+
 struct Cell {
   uint32_t x, y, z;
 };

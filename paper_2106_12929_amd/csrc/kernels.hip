@@ -203,10 +203,21 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
       const char* base[3] = {fb + (uint64_t)plane_of(pz + 1) * a.plane_bytes,
                              fb + (uint64_t)plane_of(pz) * a.plane_bytes,
                              fb + (uint64_t)plane_of(pz - 1) * a.plane_bytes};
+      if constexpr (sizeof(W) == 8) {
+        // FP64 (at its scalar-register limit; the resources below would spill): plain loads
 #pragma unroll
-      for (int i = 0; i < Q; ++i)
-        r[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * a.row_bytes +
-                                           (yb[LT::cy(i) + 1] + xb[LT::cx(i) + 1]));
+        for (int i = 0; i < Q; ++i)
+          r[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * a.row_bytes +
+                                             (yb[LT::cy(i) + 1] + xb[LT::cx(i) + 1]));
+      } else {
+        // the three source planes as buffer resources: a load takes the lane's 32-bit
+        // offset and the direction row's uniform offset, no 64-bit address per load
+        const __amdgpu_buffer_rsrc_t src[3] = {region_rsrc(base[0], a.plane_bytes), region_rsrc(base[1], a.plane_bytes),
+                                               region_rsrc(base[2], a.plane_bytes)};
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          r[i] = region_load<W>(src[LT::cz(i) + 1], yb[LT::cy(i) + 1] + xb[LT::cx(i) + 1], (uint32_t)i * a.row_bytes);
+      }
       load_force(pz, col, rf[0], rf[1], rf[2]);
     };
     auto produce = [&](W (&r)[Q], const real (&rf)[3], auto sl) {
@@ -262,10 +273,16 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
       }
       if constexpr (EMIT) {
         bgk_collide<L, real, FM>(dA, cf[0], cf[1], cf[2], omega);
-        char* o = ob + (uint64_t)plane_of(q - 1) * a.plane_bytes + out_off;
+        char* o = ob + (uint64_t)plane_of(q - 1) * a.plane_bytes;
+        if constexpr (sizeof(W) == 8) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-          store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes), ST::from_dev(dA[i], CO::W(i)));
+          for (int i = 0; i < Q; ++i)
+            store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes + out_off), ST::from_dev(dA[i], CO::W(i)));
+        } else {
+          const auto ro = region_rsrc(o, a.plane_bytes);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) store_stream(ro, out_off, (uint32_t)i * a.row_bytes, ST::from_dev(dA[i], CO::W(i)));
+        }
         if (q < (int)ze) load_force(q, col, cf[0], cf[1], cf[2]);  // the next output plane's
       }
 #pragma unroll
@@ -467,11 +484,11 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
     // the gathers of row py: the pulled words and the force
     auto load = [&](int py, W (&r)[Q], real (&rf)[2]) {
       py = min(py, r0 + (int)rows - 1);  // the loads past the last row read that row again
-      const char* base[3] = {fb + (uint64_t)wrapy(py + 1) * a.yrow_bytes, fb + (uint64_t)wrapy(py) * a.yrow_bytes,
-                             fb + (uint64_t)wrapy(py - 1) * a.yrow_bytes};
+      const __amdgpu_buffer_rsrc_t src[3] = {region_rsrc(fb + (uint64_t)wrapy(py + 1) * a.yrow_bytes, a.yrow_bytes),
+                                             region_rsrc(fb + (uint64_t)wrapy(py) * a.yrow_bytes, a.yrow_bytes),
+                                             region_rsrc(fb + (uint64_t)wrapy(py - 1) * a.yrow_bytes, a.yrow_bytes)};
 #pragma unroll
-      for (int i = 0; i < Q; ++i)
-        r[i] = *reinterpret_cast<const W*>(base[LT::cy(i) + 1] + (uint64_t)i * a.row_bytes + xb[LT::cx(i) + 1]);
+      for (int i = 0; i < Q; ++i) r[i] = region_load<W>(src[LT::cy(i) + 1], xb[LT::cx(i) + 1], (uint32_t)i * a.row_bytes);
       load_force(wrapy(py), x, rf[0], rf[1]);
     };
     auto produce = [&](uint32_t k, W (&r)[Q], const real (&rf)[2], auto sl) {
@@ -541,10 +558,10 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
           if (k + 1 < k0 + 2 + rows) load_force(wrapy(row + 1), x, cf[0], cf[1]);
           if constexpr (LAST) {
             if (live) {
-              char* o = ob + (uint64_t)row * a.yrow_bytes + out_off;
+              const auto o = region_rsrc(ob + (uint64_t)row * a.yrow_bytes, a.yrow_bytes);
 #pragma unroll
               for (int i = 0; i < Q; ++i)
-                store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes), ST::from_dev(dA[i], CO::W(i)));
+                store_stream(o, out_off, (uint32_t)i * a.row_bytes, ST::from_dev(dA[i], CO::W(i)));
             }
           } else if (live) {
 #pragma unroll
