@@ -131,6 +131,16 @@ struct Step2Shape {
   static constexpr int NC = TX * TY / 64;                   // consumer waves
   static constexpr int NT = 64 * (NP + NC);
   static constexpr int WAVES_PER_EU = WB == 8 ? 2 : 3;
+  static constexpr int LDS = 2 * Lattice<L>::Q * NS * WB;   // the two plane slots
+  // Gathers and stores through buffer resources (a 32-bit lane offset and a uniform
+  // offset per access instead of a 64-bit address; 256^3, against plain pointers:
+  // D3Q27 FP32 +3%, FP16 and BF16 +2%, D3Q19 FP32 +2%, BF16 +1%): every form but
+  // FP64, whose resources would spill, and two that ran slower with them, shifted FP32
+  // D3Q27 (-4%) and D3Q19 FP16 (-2%).
+  static constexpr bool BUFFER = WB != 8 && !(L == kD3Q27 && S == kF32S) && !(L == kD3Q19 && S == kF16S);
+  // Blocks per CU the launch allows (0: as many as registers and LDS allow).  The FP32
+  // D3Q27 form, whose registers allow two, runs 1.4% faster at one.
+  static constexpr int CAP = L == kD3Q27 && S == kF32 ? 1 : 0;
 };
 
 template <int L, int S, int FM>
@@ -203,8 +213,7 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
       const char* base[3] = {fb + (uint64_t)plane_of(pz + 1) * a.plane_bytes,
                              fb + (uint64_t)plane_of(pz) * a.plane_bytes,
                              fb + (uint64_t)plane_of(pz - 1) * a.plane_bytes};
-      if constexpr (sizeof(W) == 8) {
-        // FP64 (at its scalar-register limit; the resources below would spill): plain loads
+      if constexpr (!SH::BUFFER) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
           r[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * a.row_bytes +
@@ -274,7 +283,7 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
       if constexpr (EMIT) {
         bgk_collide<L, real, FM>(dA, cf[0], cf[1], cf[2], omega);
         char* o = ob + (uint64_t)plane_of(q - 1) * a.plane_bytes;
-        if constexpr (sizeof(W) == 8) {
+        if constexpr (!SH::BUFFER) {
 #pragma unroll
           for (int i = 0; i < Q; ++i)
             store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes + out_off), ST::from_dev(dA[i], CO::W(i)));
@@ -1549,19 +1558,27 @@ static uint32_t step2_chunk(uint64_t tiles, uint32_t nz, uint64_t slots, uint32_
 // the D3Q27 forms take one block of 10 or 11 waves per CU at 99-168 registers, 6 waves
 // at up to 256 for FP64, the D3Q19 forms up to two).
 template <typename K>
-static uint32_t blocks_per_cu(std::atomic<int>& cached, K kernel, int threads) {
+static uint32_t blocks_per_cu(std::atomic<int>& cached, K kernel, int threads, size_t dyn_lds = 0) {
   int n = cached.load(std::memory_order_relaxed);
   if (n <= 0) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n <= 0) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, dyn_lds) != hipSuccess || n <= 0) n = 1;
     cached.store(n, std::memory_order_relaxed);
   }
   return (uint32_t)n;
 }
 
+// The dynamic LDS a two-step launch reserves (untouched) to hold it to its block cap.
+template <int L, int S>
+constexpr size_t step2_reserve() {
+  using SH = Step2Shape<L, S>;
+  static_assert(SH::CAP == 0 || SH::CAP == 1, "a cap of one block");
+  return SH::CAP == 1 && (size_t)SH::LDS <= kLdsPerCu / 2 ? kLdsPerCu / 2 + 1024 - SH::LDS : 0;
+}
+
 template <int L, int S, int FM>
 static uint32_t step2_blocks_per_cu() {
   static std::atomic<int> cached{0};
-  return blocks_per_cu(cached, step2_kernel<L, S, FM>, Step2Shape<L, S>::NT);
+  return blocks_per_cu(cached, step2_kernel<L, S, FM>, Step2Shape<L, S>::NT, step2_reserve<L, S>());
 }
 
 template <int S, int FM, int TX, int NST>
@@ -1624,7 +1641,8 @@ static hipError_t launch_step2_lsf(const void* fin, void* fout, const void* forc
   const uint64_t tiles = (uint64_t)a.tiles_x * a.tiles_y;
   a.lz = step2_chunk(tiles, g.nzl, (uint64_t)step2_blocks_per_cu<L, S, FM>() * device_cus(), 2);
   const dim3 grid((unsigned)(tiles * ((g.nzl + a.lz - 1) / a.lz)));
-  step2_kernel<L, S, FM><<<grid, SH::NT, 0, s>>>((const W*)fin, (W*)fout, (const R*)force, g, a, (R)omega);
+  step2_kernel<L, S, FM><<<grid, SH::NT, step2_reserve<L, S>(), s>>>((const W*)fin, (W*)fout, (const R*)force, g, a,
+                                                                     (R)omega);
   return hipGetLastError();
 }
 
