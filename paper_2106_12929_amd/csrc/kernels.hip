@@ -139,7 +139,8 @@ struct Step2Shape {
   // D3Q27 (-4%) and D3Q19 FP16 (-2%).
   static constexpr bool BUFFER = WB != 8 && !(L == kD3Q27 && S == kF32S) && !(L == kD3Q19 && S == kF16S);
   // Blocks per CU the launch allows (0: as many as registers and LDS allow).  The FP32
-  // D3Q27 form, whose registers allow two, runs 1.4% faster at one.
+  // D3Q27 form, whose registers allow two, runs faster at one when its tiles fit the
+  // CUs (the launch decides).
   static constexpr int CAP = L == kD3Q27 && S == kF32 ? 1 : 0;
 };
 
@@ -1576,9 +1577,10 @@ constexpr size_t step2_reserve() {
 }
 
 template <int L, int S, int FM>
-static uint32_t step2_blocks_per_cu() {
-  static std::atomic<int> cached{0};
-  return blocks_per_cu(cached, step2_kernel<L, S, FM>, Step2Shape<L, S>::NT, step2_reserve<L, S>());
+static uint32_t step2_blocks_per_cu(bool capped) {
+  static std::atomic<int> cached[2] = {{0}, {0}};
+  return blocks_per_cu(cached[capped], step2_kernel<L, S, FM>, Step2Shape<L, S>::NT,
+                       capped ? step2_reserve<L, S>() : 0);
 }
 
 template <int S, int FM, int TX, int NST>
@@ -1639,10 +1641,14 @@ static hipError_t launch_step2_lsf(const void* fin, void* fout, const void* forc
   // a slab's force has a ghost plane below and above its own planes
   a.force_stride = g.ghost ? (uint64_t)g.nx * g.ny * (g.nz + 2) : g.ncells;
   const uint64_t tiles = (uint64_t)a.tiles_x * a.tiles_y;
-  a.lz = step2_chunk(tiles, g.nzl, (uint64_t)step2_blocks_per_cu<L, S, FM>() * device_cus(), 2);
+  // The block cap holds where every tile then runs its whole plane range in one round
+  // (FP32 D3Q27 256^3: +1.6%); with more tiles than CUs a second resident block fills
+  // the rounds' tails (384^3: 3% faster uncapped; 320^3 and 512^3 alike either way).
+  const bool capped = SH::CAP == 1 && tiles <= device_cus();
+  a.lz = step2_chunk(tiles, g.nzl, (uint64_t)step2_blocks_per_cu<L, S, FM>(capped) * device_cus(), 2);
   const dim3 grid((unsigned)(tiles * ((g.nzl + a.lz - 1) / a.lz)));
-  step2_kernel<L, S, FM><<<grid, SH::NT, step2_reserve<L, S>(), s>>>((const W*)fin, (W*)fout, (const R*)force, g, a,
-                                                                     (R)omega);
+  step2_kernel<L, S, FM><<<grid, SH::NT, capped ? step2_reserve<L, S>() : 0, s>>>((const W*)fin, (W*)fout,
+                                                                                  (const R*)force, g, a, (R)omega);
   return hipGetLastError();
 }
 
