@@ -136,7 +136,8 @@ struct Step2Shape {
   // offset per access instead of a 64-bit address; 256^3, against plain pointers:
   // D3Q27 FP32 +3%, FP16 and BF16 +2%, D3Q19 FP32 +2%, BF16 +1%): every form but
   // FP64, whose resources would spill, and two that ran slower with them, shifted FP32
-  // D3Q27 (-4%) and D3Q19 FP16 (-2%).
+  // D3Q27 (-4%) and D3Q19 FP16 (-2%); the kernel also leaves out the velocity-shift
+  // force on 16-bit words (-1.7%).
   static constexpr bool BUFFER = WB != 8 && !(L == kD3Q27 && S == kF32S) && !(L == kD3Q19 && S == kF16S);
   // Blocks per CU the launch allows (0: as many as registers and LDS allow).  The FP32
   // D3Q27 form, whose registers allow two, runs faster at one when its tiles fit the
@@ -157,6 +158,7 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
   using SH = Step2Shape<L, S>;
   constexpr int Q = LT::Q;
   constexpr int TX = SH::TX, NSX = SH::NSX, NS = SH::NS, NP = SH::NP;
+  constexpr bool BUF = SH::BUFFER && !(FM == kShiftForce && SH::WB == 2);
   __shared__ W slot[2][Q][NS];
 
   // XCD-aware block order: blocks b, b + 8, b + 16, ... run on one XCD and take
@@ -214,7 +216,7 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
       const char* base[3] = {fb + (uint64_t)plane_of(pz + 1) * a.plane_bytes,
                              fb + (uint64_t)plane_of(pz) * a.plane_bytes,
                              fb + (uint64_t)plane_of(pz - 1) * a.plane_bytes};
-      if constexpr (!SH::BUFFER) {
+      if constexpr (!BUF) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
           r[i] = *reinterpret_cast<const W*>(base[LT::cz(i) + 1] + (uint64_t)i * a.row_bytes +
@@ -284,7 +286,7 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
       if constexpr (EMIT) {
         bgk_collide<L, real, FM>(dA, cf[0], cf[1], cf[2], omega);
         char* o = ob + (uint64_t)plane_of(q - 1) * a.plane_bytes;
-        if constexpr (!SH::BUFFER) {
+        if constexpr (!BUF) {
 #pragma unroll
           for (int i = 0; i < Q; ++i)
             store_stream(reinterpret_cast<W*>(o + (uint64_t)i * a.row_bytes + out_off), ST::from_dev(dA[i], CO::W(i)));
