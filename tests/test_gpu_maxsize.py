@@ -2,7 +2,9 @@
 arithmetic past 2^32 words and up to the 2^31 - 1 cell limit.
 
   * D3Q27 FP16-shifted on 1024^3 (2^30 cells, 2.9e10 words, 58 GB per buffer);
-  * D2Q9 FP16-shifted on 46340^2 (2,147,395,600 cells, just under 2^31 - 1).
+  * D2Q9 FP16-shifted on 46340^2 (2,147,395,600 cells, just under 2^31 - 1);
+  * the two-step kernel on z planes of more than 2^31 bytes (4096 x 4864 x 3 FP32,
+    4096 x 9728 x 3 FP16-shifted), bit for bit against single steps.
 
 After a few steps from a Taylor-Green start, one more step is compared with the
 oracle's collision at sampled cells (and at the corners of the box, where the
@@ -100,3 +102,41 @@ def test_d2q9_f16s_at_the_cell_limit():
     grid = B.Grid("D2Q9", "f16s", n, n)
     say(f"max size: D2Q9 f16s {n}^2 = {n * n} cells")
     _run(B, grid, st, synthetic.taylor_green_2d_on("cuda", n, n, u0), 0.6, u0)
+
+
+@pytest.mark.parametrize("kind,ny", [("f32", 4864), ("f16s", 9728)])
+def test_two_step_launch_on_planes_past_2_gib(kind, ny):
+    """The two-step kernel addresses each z plane through 32-bit offsets from the
+    plane's base: on a 4096 x ny x 3 grid whose z plane holds more than 2^31 bytes
+    (27 direction rows per grid row), four steps as two two-step launches equal four
+    one-step launches bit for bit."""
+    need_gpu()
+    B = binding()
+    nx, nz, u0, tau = 4096, 3, 0.05, 0.6
+    grid = B.Grid("D3Q27", kind, nx, ny, nz)
+    word = torch.empty((), dtype=grid.word_dtype).element_size()
+    plane = 27 * ny * nx * word
+    assert 2 ** 31 < plane < 2 ** 32
+    assert B.lbm_step_launches(grid, 4) == (0, 2, 0)
+    say(f"two-step launch, D3Q27 {kind} {nx}x{ny}x{nz}: {plane / 2 ** 30:.2f} GiB per z plane")
+    u = synthetic.taylor_green_3d_on("cuda", nx, ny, nz, u0)
+    u[2] = 0.5 * u[0].flip(-1)  # a z velocity too, so every direction carries a deviation
+    a = grid.empty_populations()
+    B.lbm_init_equilibrium(grid, None, u, a)
+    del u
+    ref = a.clone()
+    b = grid.empty_populations()
+    where = B.lbm_step(grid, a, b, tau, None, 4)
+    paired = b if where == 0 else a
+    tmp = b if where != 0 else a  # the other buffer: reused for the single steps
+    x, y = ref, torch.empty_like(ref)
+    for _ in range(4):
+        B.lbm_step(grid, x, y, tau, None, 1)
+        x, y = y, x
+    torch.cuda.synchronize()
+    del tmp, y
+    same = torch.equal(paired, x)
+    say(f"  two-step launches bit-identical to single steps: {same}")
+    assert same
+    del a, b, ref, x, paired
+    torch.cuda.empty_cache()
