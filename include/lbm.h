@@ -154,7 +154,7 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
  * of 32 and ny of 8, shifted-FP16 or shifted-BF16 words with nx a multiple of 64 and
  * ny of 4, or FP64 words with nx a multiple of 32 and ny of 4; nz >= 3; one z plane of
  * words < 4 GiB), two or four on D2Q9 (every kind; nx a multiple of 64; ny >= 3 for
- * two, ny >= 5 for four).  Results equal single
+ * two, ny >= 5 for four; the 9 direction rows of a grid row < 4 GiB).  Results equal single
  * steps bit for bit.  Multi-step launches come in pairs of one kind (n_steps = 8 a + 4 b + c:
  * 2a launches of four steps, 2b of two, c < 4 single steps first), so the result stays
  * in the buffer named above.  Multi-step launches leave pad words untouched.

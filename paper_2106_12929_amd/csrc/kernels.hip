@@ -1515,7 +1515,9 @@ static bool step2_fits(const GridArgs& g) {
   if constexpr (!step2_enabled<L, S>()) {
     return false;
   } else if constexpr (L == kD2Q9) {
-    return g.ghost == 0 && g.z0 == 0 && g.nzl == g.nz && stepn_2d_width(g, 2) != 0;
+    // the Q direction rows of a grid row are one region with 32-bit offsets
+    const uint64_t yrow = (uint64_t)Lattice<L>::Q * g.pitch * sizeof(typename Storage<S>::word);
+    return g.ghost == 0 && g.z0 == 0 && g.nzl == g.nz && stepn_2d_width(g, 2) != 0 && yrow < (uint64_t(1) << 32);
   } else {
     using SH = Step2Shape<L, S>;
     const uint64_t plane = (uint64_t)g.ny * Lattice<L>::Q * g.pitch * sizeof(typename Storage<S>::word);

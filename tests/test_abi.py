@@ -446,6 +446,8 @@ def _launches(B, g, n):
     ("D2Q9", "f32", (96, 8, 1), 0, 1),           # nx off the 64-cell segments
     ("D2Q9", "f32", (64, 2, 1), 0, 1),           # ny < 3
     ("D2Q9", "bf16s", (256, 256, 1), 0, 4),
+    ("D2Q9", "f64", (64, 8, 1), 59652324, 1),    # the 9 direction rows of a grid row: 2^32 + 32 bytes
+    ("D2Q9", "f64", (64, 8, 1), 59652320, 4),    # 2^32 - 256 bytes
     ("D3Q27", "f32", (48, 16, 8), 0, 1),         # nx off the 32-cell tiles
     ("D3Q27", "f32", (32, 12, 8), 0, 1),         # ny off the 8-row tiles
     ("D3Q27", "f32", (32, 8, 2), 0, 1),          # nz < 3
