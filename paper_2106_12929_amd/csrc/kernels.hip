@@ -135,7 +135,8 @@ struct Step2Shape {
   // Gathers and stores through buffer resources (a 32-bit lane offset and a uniform
   // offset per access instead of a 64-bit address; 256^3, against plain pointers:
   // D3Q27 FP32 +3%, FP16 and BF16 +2%, D3Q19 FP32 +2%, BF16 +1%): every form but
-  // FP64, whose resources would spill, and two that ran slower with them, shifted FP32
+  // FP64 (its resources spill scalar registers: 10% slower), and two that ran slower
+  // with them, shifted FP32
   // D3Q27 (-4%) and D3Q19 FP16 (-2%); the kernel also leaves out the velocity-shift
   // force on 16-bit words (-1.7%).
   static constexpr bool BUFFER = WB != 8 && !(L == kD3Q27 && S == kF32S) && !(L == kD3Q19 && S == kF16S);
