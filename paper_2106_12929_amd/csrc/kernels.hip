@@ -131,6 +131,15 @@ struct Step2Shape {
   static constexpr int NC = TX * TY / 64;                   // consumer waves
   static constexpr int NT = 64 * (NP + NC);
   static constexpr int WAVES_PER_EU = WB == 8 ? 2 : 3;
+  // The producers' plane loop.  ROTATE: passes over DEPTH rotating register sets of
+  // gathers (plane p + DEPTH - 1 loading while plane p is collided); otherwise the loop
+  // unrolled over two planes with a separate last plane.  Measured at 256^3 (MLUPS):
+  // D3Q27 FP32 42.7k -> 43.3k rotating with two sets, shifted FP16 64.1k -> 65.3k with
+  // three; the unrolled loop kept D3Q19 FP32 at 58.8k (57.4k rotating) and shifted
+  // FP32 at 42.2k (41.6k).  Three sets were neutral or slower for the other forms (FP32
+  // D3Q27 at 384^3 -2%: the extra registers cost its second resident block).
+  static constexpr bool ROTATE = L == kD3Q27 && (S == kF32 || S == kF16S);
+  static constexpr int DEPTH = L == kD3Q27 && S == kF16S ? 3 : 2;
   static constexpr int LDS = 2 * Lattice<L>::Q * NS * WB;   // the two plane slots
   // Gathers and stores through buffer resources (a 32-bit lane offset and a uniform
   // offset per access instead of a 64-bit address; 256^3, against plain pointers:
@@ -213,7 +222,9 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
     const uint32_t yb[3] = {wrap_inc(y, g.ny) * a.yrow_bytes, y * a.yrow_bytes, wrap_dec(y, g.ny) * a.yrow_bytes};
     // the gathers of plane pz: the pulled words and the force
     auto load = [&](int pz, W (&r)[Q], real (&rf)[3]) {
-      if (slab) pz = min(pz, (int)ze);  // the read past plane ze (unused) stays in the buffer
+      // the reads past plane ze (unused) read plane ze again: on a slab they stay in the
+      // buffer, and the rotating loop reads up to two planes past ze
+      if (SH::ROTATE || slab) pz = min(pz, (int)ze);
       const char* base[3] = {fb + (uint64_t)plane_of(pz + 1) * a.plane_bytes,
                              fb + (uint64_t)plane_of(pz) * a.plane_bytes,
                              fb + (uint64_t)plane_of(pz - 1) * a.plane_bytes};
@@ -233,34 +244,56 @@ __attribute__((amdgpu_waves_per_eu(Step2Shape<L, S>::WAVES_PER_EU))) void step2_
       }
       load_force(pz, col, rf[0], rf[1], rf[2]);
     };
-    auto produce = [&](W (&r)[Q], const real (&rf)[3], auto sl) {
-      constexpr int SL = decltype(sl)::value;
+    auto produce = [&](W (&r)[Q], const real (&rf)[3], uint32_t sl) {
       real d[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
       bgk_collide<L, real, FM>(d, rf[0], rf[1], rf[2], omega);
       if (live) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) slot[SL][i][s] = ST::from_dev(d[i], CO::W(i));
+        for (int i = 0; i < Q; ++i) slot[sl][i][s] = ST::from_dev(d[i], CO::W(i));
       }
     };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    W r0[Q], r1[Q];
-    real f0[3] = {0, 0, 0}, f1[3] = {0, 0, 0};
-    load((int)zb - 1, r0, f0);
-    uint32_t k = 0;
-    for (; k + 1 < nplanes; k += 2) {  // plane zb-1+k into slot 0, the next into slot 1
-      load((int)(zb + k), r1, f1);
-      produce(r0, f0, I0());
-      __syncthreads();
-      load((int)(zb + k) + 1, r0, f0);  // one plane past ze on the last pass: read, unused
-      produce(r1, f1, I1());
-      __syncthreads();
-    }
-    if (k < nplanes) {
-      produce(r0, f0, I0());
-      __syncthreads();
+    if constexpr (SH::ROTATE) {
+      // DEPTH register sets of gathers: plane p + DEPTH - 1 is loading while plane p is
+      // collided (into slot p & 1) and the planes between are in flight.
+      constexpr int D = SH::DEPTH;
+      W r[D][Q];
+      real f[D][3] = {};
+#pragma unroll
+      for (int d = 0; d + 1 < D; ++d) load((int)zb - 1 + d, r[d], f[d]);
+      auto pass = [&](uint32_t k, auto qc) {  // plane zb-1+k, k = q mod D
+        constexpr int q = decltype(qc)::value;
+        load((int)(zb + k) + D - 2, r[(q + D - 1) % D], f[(q + D - 1) % D]);
+        produce(r[q], f[q], D == 2 ? (uint32_t)q : k & 1);  // slot of the plane's parity
+        __syncthreads();
+      };
+      for (uint32_t k = 0; k < nplanes; k += D) {
+        pass(k, std::integral_constant<int, 0>());
+        if (k + 1 >= nplanes) break;
+        pass(k + 1, std::integral_constant<int, 1>());
+        if constexpr (D == 3) {
+          if (k + 2 >= nplanes) break;
+          pass(k + 2, std::integral_constant<int, 2>());
+        }
+      }
+    } else {
+      W r0[Q], r1[Q];
+      real f0[3] = {0, 0, 0}, f1[3] = {0, 0, 0};
+      load((int)zb - 1, r0, f0);
+      uint32_t k = 0;
+      for (; k + 1 < nplanes; k += 2) {  // plane zb-1+k into slot 0, the next into slot 1
+        load((int)(zb + k), r1, f1);
+        produce(r0, f0, 0);
+        __syncthreads();
+        load((int)(zb + k) + 1, r0, f0);  // one plane past ze on the last pass: read, unused
+        produce(r1, f1, 1);
+        __syncthreads();
+      }
+      if (k < nplanes) {
+        produce(r0, f0, 0);
+        __syncthreads();
+      }
     }
     __syncthreads();  // the consumers' last plane
   } else {
