@@ -38,6 +38,8 @@ CASES = [  # lattice, (nx, ny, nz), pitch (None = nx)
     ("D3Q27", (32, 8, 2), None),   # nz < 3
     ("D3Q27", (64, 4, 9), 128),    # 2-byte words: one 64 x 4 tile, padded rows
     ("D3Q27", (128, 12, 5), None),
+    ("D3Q27", (64, 4, 3), None),     # 2-byte words: 5 planes per block (the three-set
+    ("D3Q27", (64, 8, 6), None),     # producer loop's tails), 8 planes
     ("D3Q27", (32, 4, 7), None),     # 8-byte words: one 32 x 4 tile
     ("D3Q27", (64, 12, 4), 96),      # 8-byte words: 32 x 4 tiles, padded rows
     ("D2Q9", (256, 20, 1), None),  # 2D: one 256-cell segment per row, chunks of rows
