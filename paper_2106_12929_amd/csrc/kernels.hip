@@ -104,8 +104,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWave
 // two planes above its current output that it has already read (9 and 18 values): a
 // plane contributes the c_z = -1 directions to the output plane below it, c_z = 0 to
 // its own plane and c_z = +1 to the plane above.  The producers load plane k+1 (words
-// and force) while they collide plane k; the consumers load the force of their next
-// output plane one plane ahead.
+// and force; up to k+2 with three register sets) while they collide plane k; the
+// consumers load the force of their next output plane one plane ahead.
 //
 // Each collision is bgk_collide on the words the one-step kernel would have read, and
 // the intermediate words are rounded to storage exactly as its stores are, so the
@@ -113,10 +113,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepMinWave
 //
 // Tiles are 32 x 8 cells for 4-byte words and 64 x 4 for 2-byte words (a direction row
 // of a tile is one 128-byte line), 32 x 4 for 8-byte words.  Consecutive tiles of a
-// chunk go to the same XCD (blocks are dealt to the 8 XCDs in turn), so the ring rows and line ends a block shares with its neighbours
-// are mostly served by that XCD's L2: a launch fetches about 1.4 times the state's
-// bytes (two single steps fetch them twice); the excess is ring rows read again when
-// a neighbouring tile is at another plane.
+// chunk go to the same XCD (blocks are dealt to the 8 XCDs in turn), so the ring rows
+// and line ends a block shares with its neighbours are mostly served by that XCD's
+// L2: a launch fetches about 1.4 times the state's bytes (two single steps fetch them
+// twice); the excess is ring rows read again when a neighbouring tile is at another
+// plane.
 // ---------------------------------------------------------------------------------
 template <int L, int S>
 struct Step2Shape {
@@ -144,10 +145,9 @@ struct Step2Shape {
   // Gathers and stores through buffer resources (a 32-bit lane offset and a uniform
   // offset per access instead of a 64-bit address; 256^3, against plain pointers:
   // D3Q27 FP32 +3%, FP16 and BF16 +2%, D3Q19 FP32 +2%, BF16 +1%): every form but
-  // FP64 (its resources spill scalar registers: 10% slower), and two that ran slower
-  // with them, shifted FP32
-  // D3Q27 (-4%) and D3Q19 FP16 (-2%); the kernel also leaves out the velocity-shift
-  // force on 16-bit words (-1.7%).
+  // FP64 (its resources spill scalar registers: 10% slower) and two that ran slower
+  // with them, shifted FP32 D3Q27 (-4%) and D3Q19 FP16 (-2%); the kernel also leaves
+  // out the velocity-shift force on 16-bit words (-1.7%).
   static constexpr bool BUFFER = WB != 8 && !(L == kD3Q27 && S == kF32S) && !(L == kD3Q19 && S == kF16S);
   // Blocks per CU the launch allows (0: as many as registers and LDS allow).  The FP32
   // D3Q27 form, whose registers allow two, runs faster at one when its tiles fit the
