@@ -26,9 +26,10 @@ __device__ __forceinline__ void store_stream(T* p, T v) {
 }
 
 // A wave-uniform region [base, base + bytes) as a raw buffer resource (stride 0, no
-// swizzle; word 3 is the gfx9 32-bit data format).  Stores through it take the lane's
-// 32-bit offset and a wave-uniform offset, so a run of stores at uniform distances
-// needs no per-store address arithmetic.  A store at or past `bytes` is dropped.
+// swizzle; word 3 is the gfx9 32-bit data format).  Loads and stores through it take
+// the lane's 32-bit offset and a wave-uniform offset, so a run of accesses at uniform
+// distances needs no per-access address arithmetic.  The hardware drops a store at or
+// past `bytes` and returns 0 for such a load; the kernels keep every access inside.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t region_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
