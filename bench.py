@@ -124,10 +124,10 @@ def run_forward(B, storage: str, steps: int, warmup: int, u_dev, lattice: str = 
 def run_d2q9(B, steps: int, warmup: int, n: int = 8192):
     """D2Q9 throughput on an n x n periodic grid (Taylor-Green start): the BGK step for
     several storage kinds (single launches, and one call of several steps that runs
-    four per launch), the MRT step (Eq. 5) with uniform relaxation times (the same two
-    ways) and with
-    per-cell ghost-moment times (3 more values read per cell), and the neural collision
-    (MRT with ghost times from a 6-53-3 network per cell, Sec. 3.1)."""
+    four per launch), the MRT step (Eq. 5) with uniform relaxation times and with
+    per-cell ghost-moment times (3 more values read per cell; both the same two ways),
+    and the neural collision (MRT with ghost times from a 6-53-3 network per cell,
+    Sec. 3.1)."""
     from synthetic import taylor_green_2d
     u = taylor_green_2d(n, n, 0.05).cuda()
     taus = [1, 1, 1, 0.6, 0.6, 0.6, 0.9, 0.8, 0.7]
@@ -166,13 +166,13 @@ def run_d2q9(B, steps: int, warmup: int, n: int = 8192):
             gbs = bpc * grid.ncells / (ms * 1e-3) / 1e9
             out[f"{kind}_{storage}"] = {"ms_per_step": ms, "mlups": grid.ncells / (ms * 1e-3) / 1e6,
                                         "bytes_per_cell": bpc, "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
-            if kind in ("bgk", "mrt"):  # one call of `steps` steps (multi-step launches)
+            if kind in ("bgk", "mrt", "mrt_cell"):  # one call of `steps` steps (multi-step launches)
                 k4 = 8 * max(1, steps // 8)
 
                 def call():
                     a, b = bufs[cur[0]], bufs[1 - cur[0]]
                     where = (B.lbm_step(grid, a, b, 0.6, None, k4) if kind == "bgk"
-                             else B.lbm_step_mrt(grid, a, b, taus, None, k4))
+                             else B.lbm_step_mrt(grid, a, b, taus, tg if kind == "mrt_cell" else None, k4))
                     if where == 0:
                         cur[0] ^= 1
 

@@ -162,7 +162,7 @@ int lbm_init_equilibrium(const lbm_grid* grid, const double* rho, const double* 
 int lbm_step(const lbm_grid* grid, void* f_in, void* f_out, double tau, const void* force,
              int n_steps, void* stream);
 
-/* How lbm_step (and lbm_step_shifted, and lbm_step_mrt with uniform ghost times) split
+/* How lbm_step (and lbm_step_shifted, and lbm_step_mrt) split
  * n_steps >= 1 into launches: *single
  * one-step launches, then *paired two-step launches, then *quad four-step launches
  * (single + 2 paired + 4 quad = n_steps; paired and quad are even).  Host-only (no
@@ -188,9 +188,9 @@ int lbm_step_shifted(const lbm_grid* grid, void* f_in, void* f_out, double tau, 
  *   place of the uniform ones (the outputs of the paper's neural collision model);
  *   every value must be > 1/2 (not checked on the device).
  * Same ping-pong, return value and buffer rules as lbm_step.  With uniform ghost times
- * (tau_ghost NULL) the steps run two or four per launch where lbm_step's would
- * (lbm_step_launches), bit for bit the single steps.  LBM_EUNSUP for lattices other
- * than D2Q9. */
+ * or a tau_ghost field the steps run two or four per launch where lbm_step's would
+ * (lbm_step_launches; the field is read a row ahead, as a force), bit for bit the
+ * single steps.  LBM_EUNSUP for lattices other than D2Q9. */
 int lbm_step_mrt(const lbm_grid* grid, void* f_in, void* f_out, const double* tau_moments,
                  const void* tau_ghost, int n_steps, void* stream);
 

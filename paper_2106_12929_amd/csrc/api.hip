@@ -305,9 +305,10 @@ int mrt_common(const lbm_grid* grid, void* f_in, void* f_out, const double* taus
   const double norm2[6] = {2.0, 1.0 / 9.0, 2.0, 4.0, 8.0 / 3.0, 8.0 / 3.0};
   double scales[6];
   for (int k = 0; k < 6; ++k) scales[k] = 1.0 / (taus[k + 3] * norm2[k]);
-  // uniform relaxation times: several steps per launch where lbm_step would take them
-  // (lbm_step_launches); per-cell ghost times (a field or the network) step singly
-  const Plan plan = ghost_mode == lbm::kGhostUniform ? launch_plan(grid, geo, n_steps) : Plan{n_steps, 0, 0};
+  // uniform relaxation times or a ghost-time field: several steps per launch where
+  // lbm_step would take them (lbm_step_launches); the network's times step singly
+  const bool multi = ghost_mode == lbm::kGhostUniform || ghost_mode == lbm::kGhostField;
+  const Plan plan = multi ? launch_plan(grid, geo, n_steps) : Plan{n_steps, 0, 0};
   void* bufs[2] = {f_in, f_out};
   int cur = 0;
   for (int k = 0; k < plan.single; ++k, cur ^= 1) {
@@ -318,7 +319,7 @@ int mrt_common(const lbm_grid* grid, void* f_in, void* f_out, const double* taus
   for (int nst : {2, 4}) {
     for (int k = 0; k < (nst == 2 ? plan.paired : plan.quad); ++k, cur ^= 1) {
       const hipError_t e = lbm::launch_stepn_mrt(grid->storage, nst, bufs[cur], bufs[cur ^ 1], geo.args, scales,
-                                                 (hipStream_t)stream);
+                                                 ghost_mode == lbm::kGhostField ? ghost : nullptr, (hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, name);
     }
   }

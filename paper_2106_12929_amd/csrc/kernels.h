@@ -9,9 +9,11 @@ namespace lbm {
 constexpr int kNred = 8;              // reduction results of lbm_moments
 enum AdjointMode { kAdjScatter = 0, kAdjLocalLam = 1, kAdjLocalChi = 2 };
 enum ForceMode { kNoForce = 0, kGuoForce = 1, kShiftForce = 2 };
-// Collision of the D2Q9 multi-step kernel in place of BGK (its force-mode parameter):
-// the MRT collision with uniform relaxation times, unforced.
+// Collisions of the D2Q9 multi-step kernel in place of BGK (its force-mode parameter):
+// the MRT collision, unforced, with uniform relaxation times or with per-cell ghost
+// times read from a field (tau_6, tau_7, tau_8 at a stride of the cell count).
 constexpr int kMrtUniform = 3;
+constexpr int kMrtField = 4;
 constexpr int kFoldBlock = 2048;  // block partials folded by one block of the second reduction stage
 
 // Grid geometry passed by value to every cell-parallel kernel.
@@ -44,10 +46,11 @@ struct Step2Args {
 int max_steps_per_launch(int lattice, int storage, const GridArgs& g);
 hipError_t launch_stepn(int lattice, int storage, int nst, const void* fin, void* fout, const void* force,
                         int force_mode, const GridArgs& g, double omega, hipStream_t s);
-// nst = 2 or 4 steps of the D2Q9 MRT collision with uniform relaxation times in one
-// launch (stepn_2d_kernel), where launch_stepn would take the grid; scales as launch_mrt.
+// nst = 2 or 4 steps of the D2Q9 MRT collision in one launch (stepn_2d_kernel), where
+// launch_stepn would take the grid; scales as launch_mrt; ghost: NULL for uniform
+// relaxation times, else the per-cell ghost-time field.
 hipError_t launch_stepn_mrt(int storage, int nst, const void* fin, void* fout, const GridArgs& g,
-                            const double* scales, hipStream_t s);
+                            const double* scales, const void* ghost, hipStream_t s);
 hipError_t launch_stream(int lattice, int word_bytes, const void* fin, void* fout, const GridArgs& g, hipStream_t s);
 hipError_t launch_init(int lattice, int storage, const double* rho, const double* u, void* fout, const GridArgs& g,
                        hipStream_t s);

@@ -495,20 +495,29 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
   auto wrapx = [&](int x) -> uint32_t {
     return (uint32_t)(x < 0 ? x + (int)g.nx : (x >= (int)g.nx ? x - (int)g.nx : x));
   };
-  auto load_force = [&](uint32_t y, uint32_t x, real& Fx, real& Fy) {
-    if constexpr (FM == kGuoForce || FM == kShiftForce) {
+  // the per-cell field a collision reads: the force (Fx, Fy) or, for kMrtField, the
+  // three ghost relaxation times (tau_6, tau_7, tau_8)
+  auto load_force = [&](uint32_t y, uint32_t x, real (&F)[3]) {
+    if constexpr (FM == kGuoForce || FM == kShiftForce || FM == kMrtField) {
       const real* f = force + (uint64_t)y * g.nx + x;
-      Fx = f[0];
-      Fy = f[g.ncells];
+      F[0] = f[0];
+      F[1] = f[g.ncells];
+      if constexpr (FM == kMrtField) F[2] = f[2 * (uint64_t)g.ncells];
     }
   };
-  // the collision of one cell: BGK (forced as FM says) or, for kMrtUniform, the MRT
-  // collision with uniform relaxation times
-  auto collide = [&](real (&d)[Q], real Fx, real Fy) {
+  // the collision of one cell: BGK (forced as FM says) or the MRT collision with
+  // uniform relaxation times (kMrtUniform) or per-cell ghost times (kMrtField, the
+  // scales as the one-step MRT kernel forms them)
+  auto collide = [&](real (&d)[Q], const real (&F)[3]) {
     if constexpr (FM == kMrtUniform) {
       mrt_relax(d, mrt_noneq(d), mrt.s);
+    } else if constexpr (FM == kMrtField) {
+      const MrtNoneq<real> nq = mrt_noneq(d);
+      const real s[6] = {mrt.s[0], mrt.s[1], mrt.s[2], real(1) / (real(4) * F[0]), real(3) / (real(8) * F[1]),
+                         real(3) / (real(8) * F[2])};
+      mrt_relax(d, nq, s);
     } else {
-      bgk_collide<kD2Q9, real, FM>(d, Fx, Fy, real(0), omega);
+      bgk_collide<kD2Q9, real, FM>(d, F[0], F[1], real(0), omega);
     }
   };
   // word of direction i, column j of the ring of stage s, slot sl
@@ -528,22 +537,22 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
                             wrap_dec(x, g.nx) * (uint32_t)sizeof(W)};
     const uint32_t rows = (ye - yb) + 2 * (NST - 1);
     // the gathers of row py: the pulled words and the force
-    auto load = [&](int py, W (&r)[Q], real (&rf)[2]) {
+    auto load = [&](int py, W (&r)[Q], real (&rf)[3]) {
       py = min(py, r0 + (int)rows - 1);  // the loads past the last row read that row again
       const __amdgpu_buffer_rsrc_t src[3] = {region_rsrc(fb + (uint64_t)wrapy(py + 1) * a.yrow_bytes, a.yrow_bytes),
                                              region_rsrc(fb + (uint64_t)wrapy(py) * a.yrow_bytes, a.yrow_bytes),
                                              region_rsrc(fb + (uint64_t)wrapy(py - 1) * a.yrow_bytes, a.yrow_bytes)};
 #pragma unroll
       for (int i = 0; i < Q; ++i) r[i] = region_load<W>(src[LT::cy(i) + 1], xb[LT::cx(i) + 1], (uint32_t)i * a.row_bytes);
-      load_force(wrapy(py), x, rf[0], rf[1]);
+      load_force(wrapy(py), x, rf);
     };
-    auto produce = [&](uint32_t k, W (&r)[Q], const real (&rf)[2], auto sl) {
+    auto produce = [&](uint32_t k, W (&r)[Q], const real (&rf)[3], auto sl) {
       constexpr int SL = decltype(sl)::value;
       if (k < rows) {
         real d[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = ST::to_dev(r[i], CO::W(i));
-        collide(d, rf[0], rf[1]);
+        collide(d, rf);
         if (live) {
 #pragma unroll
           for (int i = 0; i < Q; ++i) ring_at(1, SL, i, j) = ST::from_dev(d[i], CO::W(i));
@@ -551,7 +560,7 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
       }
     };
     W ra[Q], rb[Q];
-    real fa[2] = {0, 0}, fb2[2] = {0, 0};
+    real fa[3] = {0, 0, 0}, fb2[3] = {0, 0, 0};
     load(r0, ra, fa);
     uint32_t k = 0;
     for (; k + 1 < iters; k += 2) {
@@ -585,8 +594,8 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
 #pragma unroll
       for (int i = 0; i < Q; ++i) dA[i] = dB[i] = dC[i] = 0;
       // force of the next row this stage completes, read a row ahead
-      real cf[2] = {0, 0};
-      load_force(wrapy(r0 + (int)(k0 + 2) - 2 * (ST_ - 1)), x, cf[0], cf[1]);
+      real cf[3] = {0, 0, 0};
+      load_force(wrapy(r0 + (int)(k0 + 2) - 2 * (ST_ - 1)), x, cf);
       auto step = [&](uint32_t k, auto sl) {
         constexpr int SL = decltype(sl)::value;  // slot written in iteration k (k & 1)
         if (k < k0 || k >= k0 + 2 + rows) return;
@@ -600,8 +609,8 @@ __global__ __launch_bounds__((StepNShape2D<TX, NST>::NT)) void stepn_2d_kernel(
         if (k >= k0 + 2) {
           // the row completed here: stage ST_ produces row r0 + k - 2 (ST_ - 1)
           const int row = r0 + (int)k - 2 * (ST_ - 1);
-          collide(dA, cf[0], cf[1]);
-          if (k + 1 < k0 + 2 + rows) load_force(wrapy(row + 1), x, cf[0], cf[1]);
+          collide(dA, cf);
+          if (k + 1 < k0 + 2 + rows) load_force(wrapy(row + 1), x, cf);
           if constexpr (LAST) {
             if (live) {
               const auto o = region_rsrc(ob + (uint64_t)row * a.yrow_bytes, a.yrow_bytes);
@@ -1656,9 +1665,13 @@ static hipError_t launch_stepn_2d_w(const void* fin, void* fout, const void* for
 
 template <int S>
 static hipError_t launch_stepn_mrt_s(int nst, const void* fin, void* fout, const GridArgs& g, const double* scales,
-                                     hipStream_t s) {
+                                     const void* ghost, hipStream_t s) {
   if (!step2_fits<kD2Q9, S>(g) || (nst != 2 && nst != 4) || (nst == 4 && stepn_2d_width(g, 4) == 0))
     return hipErrorInvalidValue;
+  if (ghost) {
+    if (nst == 4) return launch_stepn_2d_w<S, kMrtField, 4>(fin, fout, ghost, g, 0.0, s, scales);
+    return launch_stepn_2d_w<S, kMrtField, 2>(fin, fout, ghost, g, 0.0, s, scales);
+  }
   if (nst == 4) return launch_stepn_2d_w<S, kMrtUniform, 4>(fin, fout, nullptr, g, 0.0, s, scales);
   return launch_stepn_2d_w<S, kMrtUniform, 2>(fin, fout, nullptr, g, 0.0, s, scales);
 }
@@ -1790,13 +1803,13 @@ static hipError_t launch_mrt_s(const void* fin, void* fout, const void* ghost, i
 }
 
 hipError_t launch_stepn_mrt(int storage, int nst, const void* fin, void* fout, const GridArgs& g,
-                            const double* scales, hipStream_t s) {
+                            const double* scales, const void* ghost, hipStream_t s) {
   switch (storage) {
-    case kF64: return launch_stepn_mrt_s<kF64>(nst, fin, fout, g, scales, s);
-    case kF32: return launch_stepn_mrt_s<kF32>(nst, fin, fout, g, scales, s);
-    case kF32S: return launch_stepn_mrt_s<kF32S>(nst, fin, fout, g, scales, s);
-    case kF16S: return launch_stepn_mrt_s<kF16S>(nst, fin, fout, g, scales, s);
-    case kBF16S: return launch_stepn_mrt_s<kBF16S>(nst, fin, fout, g, scales, s);
+    case kF64: return launch_stepn_mrt_s<kF64>(nst, fin, fout, g, scales, ghost, s);
+    case kF32: return launch_stepn_mrt_s<kF32>(nst, fin, fout, g, scales, ghost, s);
+    case kF32S: return launch_stepn_mrt_s<kF32S>(nst, fin, fout, g, scales, ghost, s);
+    case kF16S: return launch_stepn_mrt_s<kF16S>(nst, fin, fout, g, scales, ghost, s);
+    case kBF16S: return launch_stepn_mrt_s<kBF16S>(nst, fin, fout, g, scales, ghost, s);
   }
   return hipErrorInvalidValue;
 }

@@ -41,7 +41,8 @@ def _fake_detail():
         "forward_d3q19": {k: fw() for k in ("f32", "f64", "f16s")},
         "forward_forced": {f"{m}_{s}": fw() for m in ("guo", "shift") for s in ("f32", "f16s")},
         "d2q9_8192": {f"{k}_{s}": fw() for s in ("f32", "f16s", "f64")
-                      for k in ("bgk", "bgk_paired", "mrt", "mrt_paired", "mrt_cell", "neural_relu", "neural_tanh")},
+                      for k in ("bgk", "bgk_paired", "mrt", "mrt_paired", "mrt_cell", "mrt_cell_paired", "neural_relu",
+                                "neural_tanh")},
         "row_pitch": {f"case{i}": fw() for i in range(6)},
         "shard_512x512x64_f16s": {"periodic_step": {"ms": v(), "mlups": v()},
                                   "slab_step_sequential": {"ms": v(), "mlups": v()},

@@ -203,54 +203,66 @@ def test_paired_steps_vs_oracle(kind, bound):
 MRT_TAUS = [1.0, 1.0, 1.0, 0.56, 0.56, 0.56, 0.9, 0.8, 0.7]
 
 
+def _ghost_times(grid, seed):
+    """Per-cell ghost relaxation times tau_6..8 in [0.55, 1.25] ([3, ny, nx] reals)."""
+    gen = torch.Generator().manual_seed(seed)
+    return (0.55 + 0.7 * torch.rand((3, grid.ny, grid.nx), generator=gen, dtype=torch.float64)).to(grid.real_dtype).cuda()
+
+
 @pytest.mark.parametrize("lat,shape,pitch", [c for c in CASES if c[0] == "D2Q9"])
 @pytest.mark.parametrize("kind", ["f32", "f32s", "f16s", "bf16s", "f64"])
-def test_mrt_multi_step_launches_equal_single_steps(lat, shape, pitch, kind):
-    """lbm_step_mrt with uniform relaxation times runs two or four steps per launch
-    where lbm_step would (the same D2Q9 pipeline with the MRT collision of Eq. 5): every
-    word equals single MRT steps, for n_steps whose plans mix single, two-step and
-    four-step launches."""
+@pytest.mark.parametrize("times", ["uniform", "per_cell"])
+def test_mrt_multi_step_launches_equal_single_steps(lat, shape, pitch, kind, times):
+    """lbm_step_mrt with uniform relaxation times or a per-cell ghost-time field runs
+    two or four steps per launch where lbm_step would (the same D2Q9 pipeline with the
+    MRT collision of Eq. 5; the field read a row ahead like a force): every word equals
+    single MRT steps, for n_steps whose plans mix single, two-step and four-step
+    launches."""
     need_gpu()
     B = binding()
-    say(f"MRT multi-step {shape} pitch {pitch} {kind}")
+    say(f"MRT multi-step {shape} pitch {pitch} {kind} {times}")
     st, grid, g, _ = _setup(B, lat, shape, pitch, kind, "none")
+    ghost = _ghost_times(grid, 5) if times == "per_cell" else None
     for n in (4, 7, 8, 10, 19):
         a, b = g.clone(), grid.empty_populations()
-        where = B.lbm_step_mrt(grid, a, b, MRT_TAUS, None, n)
+        where = B.lbm_step_mrt(grid, a, b, MRT_TAUS, ghost, n)
         assert where == (0 if n % 2 else 1), n
         got = b if where == 0 else a
         x, y = g.clone(), grid.empty_populations()
         for _ in range(n):
-            assert B.lbm_step_mrt(grid, x, y, MRT_TAUS, None, 1) == 0
+            assert B.lbm_step_mrt(grid, x, y, MRT_TAUS, ghost, 1) == 0
             x, y = y, x
         same = torch.equal(bits(grid.from_layout(got.cpu())), bits(grid.from_layout(x.cpu())))
         assert same, f"n_steps={n}"
 
 
-@pytest.mark.parametrize("kind", ["f32", "f16s"])
-def test_mrt_multi_step_full_size_equal_single_steps(kind):
-    """8192^2 D2Q9 MRT: eight steps as two four-step launches against single steps."""
+@pytest.mark.parametrize("kind,times", [("f32", "uniform"), ("f16s", "uniform"), ("f32", "per_cell"),
+                                        ("f16s", "per_cell")])
+def test_mrt_multi_step_full_size_equal_single_steps(kind, times):
+    """8192^2 D2Q9 MRT (uniform or per-cell ghost times): eight steps as two four-step
+    launches against single steps."""
     need_gpu()
     B = binding()
     n = 8192
     grid = B.Grid("D2Q9", kind, n, n)
-    say(f"MRT multi-step D2Q9 {kind} {n}^2")
+    say(f"MRT multi-step D2Q9 {kind} {n}^2 {times}")
+    ghost = _ghost_times(grid, 6) if times == "per_cell" else None
     u = synthetic.taylor_green_2d(n, n, 0.05)
     a = grid.empty_populations()
     B.lbm_init_equilibrium(grid, None, u.cuda(), a)
     del u
     b = grid.empty_populations()
-    assert B.lbm_step_mrt(grid, a, b, MRT_TAUS, None, 1) == 0
+    assert B.lbm_step_mrt(grid, a, b, MRT_TAUS, ghost, 1) == 0
     start = b.clone()
     x, y = start.clone(), a
     for _ in range(8):
-        B.lbm_step_mrt(grid, x, y, MRT_TAUS, None, 1)
+        B.lbm_step_mrt(grid, x, y, MRT_TAUS, ghost, 1)
         x, y = y, x
     ref = x.clone()
     del x
     p, q = start.clone(), y
     assert B.lbm_step_launches(grid, 8) == (0, 0, 2)
-    assert B.lbm_step_mrt(grid, p, q, MRT_TAUS, None, 8) == 1
+    assert B.lbm_step_mrt(grid, p, q, MRT_TAUS, ghost, 8) == 1
     torch.cuda.synchronize()
     assert torch.equal(bits(p), bits(ref))
 
